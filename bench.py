@@ -1,0 +1,146 @@
+"""Benchmark of the local affine-body Newton solve on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: 1000 level-3 icospheres (642 vertices, 1280 triangles each,
+radius 0.05-0.15) at seeded non-overlapping positions falling into a
+static open box; h = 0.01, dhat = 1e-3, kappa = 1e5, kappa_A = 1e8,
+FP64, Newton tolerance 1e-6 (relative |dq|_inf / (h l)).  A step is one
+time step (prediction, the full local Newton solve, commit); W steps run
+untimed first, then K steps are timed.  value = Newton iterations per
+second over the timed steps, inputs resident on the device throughout.
+
+The JSON line carries the roofline of the dominant kernel (measured live
+with HIP events on the library's stream) and the CPU oracle timed on a
+bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOAD = ("1000 icospheres (642 verts, 1280 tris each, r 0.05-0.15) "
+            "falling into an open box container, dt 0.01, dhat 1e-3, "
+            "kappa 1e5, kappa_A 1e8, FP64, Newton tol 1e-6")
+
+
+def cpu_baseline(seed, n_steps):
+    """Oracle on the first n_steps time steps of the same scene."""
+    from oracle import oracle as O
+    from paper_2605_15875_amd import scenes
+    sc = scenes.config(1, seed)
+    orc = O.Oracle(sc)
+    iters = 0
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        st = orc.step()
+        iters += st["newton_iters"]
+    dt = time.perf_counter() - t0
+    return dict(value=iters / dt, unit="newton_iters/s", cores=1,
+                kind="oracle",
+                sample=f"first {n_steps} time steps of the workload "
+                       f"({iters} Newton iterations, {dt:.1f} s, "
+                       f"single thread)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--quiet", action="store_true")
+    a = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if a.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the local solve of one worker runs "
+              "on a single device; multi-GPU runs are not part of this "
+              "build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2605_15875_amd import abd, scenes
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+
+    def log(*m):
+        if not a.quiet:
+            print(*m, file=sys.stderr, flush=True)
+
+    sc = scenes.config(1, a.seed)
+    log(f"scene: {len(sc.bodies)} bodies, {sc.n_vertices} verts, "
+        f"{sc.n_triangles} tris")
+    solver = abd.Solver(sc)
+    for i in range(a.warmup):
+        st = solver.step()
+        log(f"warmup {i}: newton={st['newton_iters']} "
+            f"pcg={st['pcg_iters_total']} ms={st['t_solve_ms']:.1f}")
+    solver.set_timing(True)
+    solver.reset_timing()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    newton = pcg = 0
+    for i in range(a.steps):
+        st = solver.step()
+        newton += st["newton_iters"]
+        pcg += st["pcg_iters_total"]
+        log(f"step {i}: newton={st['newton_iters']} pcg={st['pcg_iters_total']}"
+            f" active={st['n_active']} cand={st['n_cand_pt']}+"
+            f"{st['n_cand_ee']} alpha_min={st['min_alpha']:.3g} "
+            f"ms={st['t_solve_ms']:.1f}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = solver.timing()
+    # dominant kernel family with an algorithmic byte count
+    timed = {k: v for k, v in tm.items() if v["bytes"] > 0 and v["launches"]}
+    dom = max(timed, key=lambda k: timed[k]["ms"]) if timed else None
+    roof = None
+    if dom:
+        d = timed[dom]
+        achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        roof = dict(kernel=dom, bound="hbm", achieved=achieved,
+                    peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+                    launches=d["launches"],
+                    avg_launch_ms=d["ms"] / d["launches"])
+    cpu = None
+    if not a.no_cpu_baseline:
+        log("cpu baseline ...")
+        cpu = cpu_baseline(a.seed, a.cpu_steps)
+    out = {
+        "metric": "local Newton iters/s at ~1M tris",
+        "value": newton / elapsed,
+        "unit": "newton_iters/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": elapsed * 1e3 / a.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "bodies": len(sc.bodies) - 1,
+                   "triangles": sc.n_triangles, "vertices": sc.n_vertices,
+                   "seed": a.seed, "precision": "fp64"},
+        "newton_iters": newton,
+        "pcg_iters": pcg,
+        "stage_ms": {k: round(v["ms"], 3) for k, v in tm.items()},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "mixed_vs_fp64_speedup": None,
+    }
+    print(json.dumps(out), flush=True)
+    solver.close()
+
+
+if __name__ == "__main__":
+    main()

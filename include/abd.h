@@ -1,0 +1,219 @@
+/*
+ * libabd -- one worker's local affine-body-dynamics subproblem of the
+ * consensus-ADMM method (Sec. 4.1, Eq. 5), solved by projected Newton on
+ * one gfx950 GPU.
+ *
+ * The problem (Eq. 5 with the local objective of Eq. 3 and the incremental
+ * potential of Eq. 1):
+ *
+ *   q_i^{k+1} = argmin_q  sum_b (1/kappa_b) [ 1/2 |q_b - qt_b|^2_{M_b}
+ *                                             + h^2 E_orth(q_b) ]
+ *                        + h^2 sum_c (1/kappa_c) kappa b(d_c(q))
+ *                        + sum_{b shared} rho_b/2 |q_b - z_b + u_b|^2
+ *
+ * with affine body DoFs q_b = [p (3), A row-major (9)], vertices
+ * x = A xbar + p, prediction qt = q^t + h qdot + h^2 M^-1 f_ext, the
+ * orthogonality energy E_orth = kappa_A V_b |A A^T - I|_F^2, and the IPC log
+ * barrier b(d) = -(d - dhat)^2 ln(d/dhat) on the unsquared distance of
+ * point-triangle, edge-edge (mollified) and point-ground pairs.  Every
+ * Newton iterate stays penetration free: the step is bounded by additive
+ * CCD and accepted by a backtracking line search on the energy.
+ *
+ * Conventions for every call:
+ *  - return value: ABD_OK (0) or a negative ABD_E_* status; the message of
+ *    the last failure is abd_last_error(ctx) (owned by the context, valid
+ *    until the next call on it);
+ *  - every input pointer is a HOST pointer owned by the caller and copied
+ *    during the call; every output pointer is a caller-allocated HOST buffer
+ *    of the documented size;
+ *  - the library owns all device memory (allocated in abd_finalize and
+ *    grown on demand); work is issued on the bound stream (default: the
+ *    null stream) and every call returns after its results are on the host;
+ *  - arrays are FP64 unless stated, array-of-structures: points [n][3],
+ *    body states [n][12], 12x12 blocks [n][144] row-major in the DoF order
+ *    [p0 p1 p2 A00 A01 A02 A10 A11 A12 A20 A21 A22];
+ *  - body ids are dense int32 in insertion order; vertex, triangle and edge
+ *    ids are global, in insertion order; a body's edges are its unique
+ *    (lo, hi) local vertex pairs sorted lexicographically;
+ *  - SI units, y up.
+ * A context is not thread safe; distinct contexts are independent.
+ */
+#ifndef ABD_H
+#define ABD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define ABD_OK 0
+#define ABD_E_INVALID_ARG (-1) /* bad argument or call order */
+#define ABD_E_MESH (-2)        /* dynamic mesh not closed/oriented */
+#define ABD_E_INFEASIBLE (-3)  /* initial state has distance <= 0 */
+#define ABD_E_NOCONV (-4)      /* Newton hit max_newton (state = last iterate) */
+#define ABD_E_LINESEARCH (-5)  /* line search exhausted */
+#define ABD_E_CAPACITY (-6)    /* caller buffer too small (count still set) */
+#define ABD_E_DEVICE (-7)      /* HIP runtime or kernel error */
+#define ABD_E_OOM (-8)         /* device allocation failed */
+
+/* body kinds */
+#define ABD_DYNAMIC 0
+#define ABD_STATIC 1
+
+/* precision of the Newton linear algebra */
+#define ABD_FP64 0
+
+/* candidate kinds */
+#define ABD_PT 0 /* point-triangle: (vertex, triangle) */
+#define ABD_EE 1 /* edge-edge: (lo edge, hi edge) */
+#define ABD_PG 2 /* point-ground: vertex */
+
+/* pair replication rule for kappa_c (Eq. 3) */
+#define ABD_PAIRS_ALL_ONE 0     /* kappa_c = 1 for every pair */
+#define ABD_PAIRS_BY_SHARED 1   /* kappa_c = 2 if every dynamic body of the
+                                   pair is shared, else 1 */
+
+typedef struct abd_params {
+  double dt;           /* time step h (s) */
+  double dhat;         /* barrier activation distance (m) */
+  double kappa;        /* barrier stiffness */
+  double kappa_A;      /* orthogonality stiffness (Pa) */
+  double gravity[3];   /* m/s^2 */
+  double newton_theta; /* stop when |dq|_inf / (h l) < theta (Eq. 8 form) */
+  double pcg_eta;      /* PCG stops at |r|_2 <= eta |g|_2 */
+  double ground_y;     /* analytic ground plane height (if has_ground) */
+  int32_t max_newton, max_pcg, max_ls;
+  int32_t has_ground;  /* vertex-ground pairs against y = ground_y */
+  int32_t mollify_ee;  /* edge-edge mollifier on |ea x eb|^2 */
+  int32_t precision;   /* ABD_FP64 */
+} abd_params;
+
+typedef struct abd_stats {
+  int32_t newton_iters;    /* linear solves performed */
+  int32_t pcg_iters_total;
+  int32_t ls_halvings;
+  int32_t status;
+  double final_eps_N;      /* |dq|_inf / (h l) of the last direction */
+  double min_alpha;        /* smallest accepted step */
+  double min_dist;         /* smallest candidate distance seen */
+  double scene_scale;      /* l: bounding-box diagonal at step start */
+  int64_t n_cand_pt, n_cand_ee, n_cand_pg, n_active; /* last iteration */
+  double t_solve_ms;       /* wall time of the call */
+} abd_stats;
+
+typedef struct abd_ctx abd_ctx;
+
+/* Create a context on the current HIP device. */
+int abd_create(abd_ctx** out, const abd_params* p);
+void abd_destroy(abd_ctx* ctx);
+const char* abd_last_error(const abd_ctx* ctx);
+
+/* Add a body before abd_finalize.  xbar: [nv][3] rest vertices; tris:
+ * [nt][3] local vertex ids (outward oriented and closed for DYNAMIC);
+ * density in kg/m^3; q0, qdot0: [12] initial state (qdot0 may be NULL);
+ * kind: ABD_DYNAMIC or ABD_STATIC (no DoFs, fixed at q0).  Mass properties
+ * (Mhat = int rho [1 xbar^T; xbar xbar xbar^T] dV and volume) come from the
+ * mesh.  *body_id receives the dense id.  Errors: INVALID_ARG, MESH. */
+int abd_add_body(abd_ctx* ctx, const double* xbar, int32_t nv,
+                 const int32_t* tris, int32_t nt, double density,
+                 const double* q0, const double* qdot0, int32_t kind,
+                 int32_t* body_id);
+
+/* Upload the scene to the device and check that the initial state has
+ * every candidate distance > 0.  Errors: INVALID_ARG, INFEASIBLE, OOM,
+ * DEVICE. */
+int abd_finalize(abd_ctx* ctx);
+
+/* sizes[0..3] = bodies, vertices, triangles, edges */
+int abd_sizes(const abd_ctx* ctx, int64_t* sizes);
+
+/* Consensus data of the shared bodies B_{i,d} (Eq. 5): ids [n]; z, u
+ * [n][12]; rho [n] >= 0; kappa_b [n] >= 1 (replica count, Eq. 3).  Replaces
+ * the previous set; n = 0 gives the monolithic problem.  Callable every
+ * ADMM iteration.  Errors: INVALID_ARG (bad id, non-finite z/u, rho < 0). */
+int abd_set_shared(abd_ctx* ctx, const int32_t* ids, int32_t n,
+                   const double* z, const double* u, const double* rho,
+                   const int32_t* kappa_b);
+
+/* kappa_c rule: ABD_PAIRS_ALL_ONE (default) or ABD_PAIRS_BY_SHARED. */
+int abd_set_pair_replication(abd_ctx* ctx, int32_t mode);
+
+/* Start a time step (Eq. 1): store q^t, form the prediction q-tilde and
+ * the scene scale l (bounding-box diagonal of the dynamic vertices). */
+int abd_begin_step(abd_ctx* ctx);
+
+/* Solve Eq. 5 from the current q (warm start).  out may be NULL.
+ * Errors: NOCONV, LINESEARCH, DEVICE, OOM. */
+int abd_local_solve(abd_ctx* ctx, abd_stats* out);
+
+/* Finish the step: qdot = (q - q^t) / h. */
+int abd_end_step(abd_ctx* ctx);
+
+/* State [B][12] (checkpoint / resume); either pointer may be NULL.
+ * abd_set_state ignores static bodies. */
+int abd_get_state(const abd_ctx* ctx, double* q, double* qdot);
+int abd_set_state(abd_ctx* ctx, const double* q, const double* qdot);
+/* q-tilde [B][12] of the current step */
+int abd_get_qtilde(const abd_ctx* ctx, double* qtilde);
+/* Prescribe the step-start data directly: q^t, q-tilde [B][12] and the
+ * scene scale l (for lock-step comparisons from a shared start state). */
+int abd_set_step(abd_ctx* ctx, const double* qt, const double* qtilde,
+                 double scale);
+
+/* Work on a caller stream (a hipStream_t); NULL = null stream. */
+int abd_set_stream(abd_ctx* ctx, void* hip_stream);
+
+/* ---- inspection hooks (used for parity; not needed to simulate) ---- */
+
+/* Vertex positions x = A xbar + p [V][3] at q (NULL = current q) and, if
+ * dq and dx are given, the displacements dx = dA xbar + dp [V][3]; these
+ * are exactly the values the broad phase and CCD use. */
+int abd_get_vertices(abd_ctx* ctx, const double* q, const double* dq,
+                     double* x, double* dx);
+
+/* Candidate pairs at the current q: static boxes, or swept boxes over
+ * [x, x + dx] when dq != NULL.  A pair (P, Q) of primitives of different
+ * bodies, at least one dynamic, is a candidate iff on every axis
+ * lo_P <= hi_Q + dhat and lo_Q <= hi_P + dhat, with exact min/max boxes.
+ * Output sorted lexicographically: PT and EE write [count][2] int32, PG
+ * writes [count].  If count > cap nothing is written and CAPACITY is
+ * returned with *count set. */
+int abd_export_candidates(abd_ctx* ctx, int32_t kind, const double* dq,
+                          int32_t* out, int64_t cap, int64_t* count);
+
+/* Energy, gradient [B][12] and Hessian blocks at q (static bodies get a
+ * zero gradient and an identity block).  Off-diagonal blocks (a < b, rows
+ * a's DoFs) for body pairs with at least one active contact, sorted by
+ * (a, b): off_ij [n][2], Hoff [n][144]; CAPACITY if n > cap (n_off set). */
+int abd_eval(abd_ctx* ctx, const double* q, double* E, double* g,
+             double* Hdiag, int64_t cap, int64_t* n_off, int32_t* off_ij,
+             double* Hoff, int64_t* n_active);
+
+/* One Newton direction at the current q: dq [B][12] solving H dq = -g. */
+int abd_direction(abd_ctx* ctx, double* dq, int32_t* pcg_iters);
+
+/* alpha_max = min(1, min over swept candidates of the additive-CCD
+ * time of impact) for the step dq [B][12] from the current q. */
+int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max);
+
+/* E(q + alpha dq) - E(q) at the current q, summed term by term. */
+int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
+                     double* dE);
+
+/* Per-stage device timing with HIP events on the bound stream.  Stage ids:
+ * 0 body terms, 1 broad phase, 2 barrier assembly, 3 PCG, 4 CCD,
+ * 5 line search, 6 other.  abd_get_timing returns the summed milliseconds,
+ * the number of timed launches and the algorithmic bytes those launches
+ * had to move (sizes as launched).  Timing adds event records; off by
+ * default. */
+int abd_set_timing(abd_ctx* ctx, int32_t on);
+int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms,
+                   int64_t* launches, double* bytes);
+int abd_reset_timing(abd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

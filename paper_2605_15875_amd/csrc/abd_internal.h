@@ -1,0 +1,556 @@
+/*
+ * Internal layout and device math of libabd (gfx950).  Not part of the
+ * public interface (include/abd.h).
+ *
+ * Device data (all FP64 unless noted):
+ *   body arrays  q, qt, qtilde, qdot, dq [B][12]; Mhat [B][16]; vol [B]
+ *   vertices     xbar [3][V] (structure of arrays), vbody [V] int32
+ *   triangles    tri [3][T] int32 global vertex ids
+ *   edges        edge [2][E] int32 global vertex ids, erest2 [E]
+ *   chunks       groups of <= 64 primitives of one kind of one body, with
+ *                a rest-space box; the broad phase culls body pairs, then
+ *                chunk pairs, then tests primitive pairs exactly
+ *   Hessian      Hdiag [B][144], Hoff [slot][144] (slot = body pair a<b)
+ */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define ABD_CHUNK 64
+#define ACCD_S 0.1
+#define ACCD_MAX_IT 100000
+#define MOLL_EPS 1e-3
+#define BOX_PAD_REL 1e-12
+
+namespace abd {
+
+enum { K_VERT = 0, K_TRI = 1, K_EDGE = 2 };
+enum { C_PT = 0, C_EE = 1, C_PG = 2 };
+
+/* device counters, one block of ints/words zeroed per phase */
+struct Counters {
+  int n_bp, n_cp, n_pt, n_ee, n_pg, n_act;
+  int pcg_iters, err;
+  unsigned long long min_dist;  /* bits of a non-negative double */
+  unsigned long long min_toi;   /* bits of a non-negative double */
+  unsigned long long max_dq;    /* bits of a non-negative double */
+  unsigned int bar;             /* grid barrier arrivals */
+  int n_rows_used;
+  double pcg_rr, pcg_bb;
+};
+
+struct Scene {
+  int B, V, T, E, NC;
+  /* parameters */
+  double dt, dhat, kappa, kappa_A, grav[3], ground_y;
+  int has_ground, mollify, pair_mode;
+  /* bodies */
+  double *q, *qt, *qtilde, *qdot, *dq, *Mhat, *vol, *wbody;
+  int *kind;
+  int *shared_slot; /* [B] -> index into z/u/rho or -1 */
+  double *z, *u, *rho;
+  double *body_rest; /* [B][6] rest box centre (3), half extent (3) */
+  int *body_chunk;   /* [B][3][2] chunk ranges per kind */
+  /* geometry */
+  double *xbar;
+  int *vbody, *tri, *edge;
+  double *erest2;
+  /* chunks */
+  int *ch_body, *ch_kind, *ch_start, *ch_count, *ch_prims;
+  double *ch_rest;  /* [NC][6] */
+  double *ch_box;   /* [NC][6] world box lo(3) hi(3) of the current phase */
+  double *body_box; /* [B][6] */
+  /* broad phase outputs */
+  int2 *bp;     /* body pairs (a < b) */
+  int4 *cp;     /* chunk pairs (kind, chunk P, chunk Q, body-pair slot) */
+  int *cand_pt; /* [cap][3] (v, t, slot) */
+  int *cand_ee; /* [cap][3] (e, f, slot) with e < f */
+  int *cand_pg; /* [cap] v */
+  int4 *act;    /* active pairs (kind, i, j, slot) */
+  int cap_bp, cap_cp, cap_pt, cap_ee, cap_pg, cap_act;
+  /* system */
+  double *g, *Hdiag, *Hoff, *Pinv;
+  int *slot_used;
+  int *row_ptr, *row_cnt, *col_slot, *col_body, *col_trans;
+  int cap_col;
+  /* PCG work */
+  double *r, *zv, *p0, *p1, *Ap, *acc; /* acc: [4][4] ring of dots */
+  /* reductions */
+  double *partials; /* [cap_partials] */
+  int cap_partials;
+  Counters *cnt;
+};
+
+/* ------------------------------------------------------------------ */
+/* canonical vertex transform: x_i = p_i + A_i0 xb0 + A_i1 xb1 + A_i2 xb2
+ * evaluated with explicit fused multiply-adds in this fixed order, so
+ * every kernel (and the export hook) produces bit-identical positions.  */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ void xform(const double* __restrict__ qb,
+                                      double b0, double b1, double b2,
+                                      double* x) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    x[i] = __fma_rn(qb[5 + 3 * i], b2,
+                    __fma_rn(qb[4 + 3 * i], b1,
+                             __fma_rn(qb[3 + 3 * i], b0, qb[i])));
+}
+
+__device__ __forceinline__ void vertex_pos(const Scene& S, int v, double* x) {
+  const double* qb = S.q + 12 * S.vbody[v];
+  xform(qb, S.xbar[v], S.xbar[S.V + v], S.xbar[2 * S.V + v], x);
+}
+
+/* start and end (x + dx) of a vertex over a step dq */
+__device__ __forceinline__ void vertex_pos_swept(const Scene& S, int v,
+                                                 double* x, double* x1) {
+  int b = S.vbody[v];
+  double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
+  xform(S.q + 12 * b, b0, b1, b2, x);
+  double dx[3];
+  xform(S.dq + 12 * b, b0, b1, b2, dx);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x1[i] = __dadd_rn(x[i], dx[i]);
+}
+
+/* position at q + alpha dq */
+__device__ __forceinline__ void vertex_pos_alpha(const Scene& S, int v,
+                                                 double alpha, double* x) {
+  int b = S.vbody[v];
+  const double* qb = S.q + 12 * b;
+  const double* db = S.dq + 12 * b;
+  double qa[12];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) qa[i] = qb[i] + alpha * db[i];
+  xform(qa, S.xbar[v], S.xbar[S.V + v], S.xbar[2 * S.V + v], x);
+}
+
+/* ------------------------------------------------------------------ */
+/* boxes                                                                */
+/* ------------------------------------------------------------------ */
+/* lo_P <= hi_Q + dhat and lo_Q <= hi_P + dhat on every axis; each bound is
+ * one rounded add, compared exactly */
+__device__ __forceinline__ bool box_overlap(const double* P, const double* Q,
+                                            double dh) {
+  bool ok = true;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    ok = ok && (P[k] <= __dadd_rn(Q[3 + k], dh));
+    ok = ok && (Q[k] <= __dadd_rn(P[3 + k], dh));
+  }
+  return ok;
+}
+
+/* Conservative world box of a rest box (centre c, half extent e) under the
+ * affine map q: centre A c + p, half extent |A| e, padded by a relative
+ * 1e-12 of the magnitudes involved, which dominates every rounding error of
+ * the vertex transform; mag adds the magnitude of a second map (a step). */
+__device__ __forceinline__ void world_box(const double* qb, const double* ce,
+                                          double extra_mag, double* box) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double c = qb[i], e = 0.0, m = fabs(qb[i]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      double a = qb[3 + 3 * i + j];
+      c += a * ce[j];
+      e += fabs(a) * ce[3 + j];
+      m += fabs(a) * (fabs(ce[j]) + ce[3 + j]);
+    }
+    double pad = BOX_PAD_REL * (m + extra_mag) + 1e-300;
+    box[i] = c - e - pad;
+    box[3 + i] = c + e + pad;
+  }
+}
+
+__device__ __forceinline__ double map_mag(const double* qb, const double* ce) {
+  double m = 0.0;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    double mi = fabs(qb[i]);
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      mi += fabs(qb[3 + 3 * i + j]) * (fabs(ce[j]) + ce[3 + j]);
+    m = fmax(m, mi);
+  }
+  return m;
+}
+
+/* ------------------------------------------------------------------ */
+/* IPC barrier b(d) = -(d - dhat)^2 ln(d/dhat), 0 < d < dhat            */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ void barrier3(double d, double dh, double& b,
+                                         double& b1, double& b2) {
+  if (!(d < dh)) {
+    b = b1 = b2 = 0.0;
+    return;
+  }
+  double t = d - dh;
+  double L = log(d / dh);
+  double id = 1.0 / d;
+  b = -t * t * L;
+  b1 = -t * (2.0 * L + t * id);
+  b2 = -2.0 * L - 4.0 * t * id + t * t * id * id;
+}
+
+__device__ __forceinline__ double barrier_val(double d, double dh) {
+  if (!(d < dh)) return 0.0;
+  double t = d - dh;
+  return -t * t * log(d / dh);
+}
+
+/* ------------------------------------------------------------------ */
+/* small vector helpers                                                 */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+__device__ __forceinline__ void cross3(const double* a, const double* b,
+                                       double* c) {
+  c[0] = a[1] * b[2] - a[2] * b[1];
+  c[1] = a[2] * b[0] - a[0] * b[2];
+  c[2] = a[0] * b[1] - a[1] * b[0];
+}
+/* v = sum_s l[s] x_s over the 4 pair vertices */
+__device__ __forceinline__ void comb4(const signed char* l, const double* x,
+                                      double* v) {
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    v[i] = l[0] * x[i] + l[1] * x[3 + i] + l[2] * x[6 + i] + l[3] * x[9 + i];
+}
+
+/* ------------------------------------------------------------------ */
+/* primitive distance features                                          */
+/* A feature is a function of difference vectors of the 4 pair slots:  */
+/*   PP:  |r|^2                       (1 vector)                         */
+/*   PE:  |a x e|^2 / |e|^2           (point offset a, edge e)           */
+/*   TRI: (a . (b x c))^2 / |b x c|^2 (point-plane or line-line)         */
+/* Slots are (p, t0, t1, t2) for PT and (a0, a1, b0, b1) for EE.        */
+/* ------------------------------------------------------------------ */
+enum { F_PP = 0, F_PE = 1, F_TRI = 2 };
+struct Feat {
+  int type, code;
+  signed char l[3][4]; /* slot coefficients of the feature's vectors */
+};
+
+__device__ __forceinline__ void set_l(signed char* l, int a, int b, int c,
+                                      int d) {
+  l[0] = (signed char)a; l[1] = (signed char)b;
+  l[2] = (signed char)c; l[3] = (signed char)d;
+}
+
+__device__ __forceinline__ double feat_sqd(const Feat& f, const double* x) {
+  if (f.type == F_PP) {
+    double r[3];
+    comb4(f.l[0], x, r);
+    return dot3(r, r);
+  }
+  if (f.type == F_PE) {
+    double a[3], e[3], c[3];
+    comb4(f.l[0], x, a);
+    comb4(f.l[1], x, e);
+    cross3(a, e, c);
+    return dot3(c, c) / dot3(e, e);
+  }
+  double a[3], b[3], c[3], n[3];
+  comb4(f.l[0], x, a);
+  comb4(f.l[1], x, b);
+  comb4(f.l[2], x, c);
+  cross3(b, c, n);
+  double s = dot3(a, n);
+  return s * s / dot3(n, n);
+}
+
+/* closest feature of point slot p to the closed segment (e0, e1) */
+__device__ __forceinline__ Feat point_seg(const double* x, int p, int e0,
+                                          int e1, int c_e0, int c_e1,
+                                          int c_pe) {
+  double a[3], e[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    a[i] = x[3 * p + i] - x[3 * e0 + i];
+    e[i] = x[3 * e1 + i] - x[3 * e0 + i];
+  }
+  double ee = dot3(e, e);
+  double t = ee > 0.0 ? dot3(a, e) / ee : 0.0;
+  Feat f;
+  signed char z[4] = {0, 0, 0, 0};
+  for (int k = 0; k < 4; ++k) f.l[0][k] = f.l[1][k] = f.l[2][k] = z[k];
+  if (!(ee > 0.0) || t <= 0.0) {
+    f.type = F_PP; f.code = c_e0;
+    f.l[0][p] = 1; f.l[0][e0] = -1;
+  } else if (t >= 1.0) {
+    f.type = F_PP; f.code = c_e1;
+    f.l[0][p] = 1; f.l[0][e1] = -1;
+  } else {
+    f.type = F_PE; f.code = c_pe;
+    f.l[0][p] = 1; f.l[0][e0] = -1;
+    f.l[1][e1] = 1; f.l[1][e0] = -1;
+  }
+  return f;
+}
+
+/* Classify a PT (kind 0) or EE (kind 1) pair: minimum over features in the
+ * fixed order (segment features by index, then the interior feature), the
+ * first one winning ties.  Codes: PT 0..2 vertex t_k, 3..5 edge k (t0t1,
+ * t1t2, t2t0), 6 interior; EE 0..3 (a_i, b_j) -> 2i + j, 4..5 a_i on
+ * segment b, 6..7 b_j on segment a, 8 interior. */
+__device__ inline Feat classify(int kind, const double* x, double& Dout) {
+  Feat best;
+  double bestD = INFINITY;
+  if (kind == C_PT) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      int e0 = 1 + k, e1 = 1 + (k + 1) % 3;
+      Feat f = point_seg(x, 0, e0, e1, e0 - 1, e1 - 1, 3 + k);
+      double D = feat_sqd(f, x);
+      if (D < bestD) { bestD = D; best = f; }
+    }
+    double a[3], b[3], c[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      a[i] = x[i] - x[3 + i];
+      b[i] = x[6 + i] - x[3 + i];
+      c[i] = x[9 + i] - x[3 + i];
+    }
+    double bb = dot3(b, b), bc = dot3(b, c), cc = dot3(c, c);
+    double ab = dot3(a, b), ac = dot3(a, c);
+    double det = bb * cc - bc * bc;
+    if (det > 0.0) {
+      double u = (ab * cc - ac * bc) / det;
+      double v = (ac * bb - ab * bc) / det;
+      if (u > 0.0 && v > 0.0 && u + v < 1.0) {
+        Feat f;
+        f.type = F_TRI; f.code = 6;
+        set_l(f.l[0], 1, -1, 0, 0);
+        set_l(f.l[1], 0, -1, 1, 0);
+        set_l(f.l[2], 0, -1, 0, 1);
+        double D = feat_sqd(f, x);
+        if (D < bestD) { bestD = D; best = f; }
+      }
+    }
+  } else {
+    Feat f4[4] = {point_seg(x, 0, 2, 3, 0, 1, 4), point_seg(x, 1, 2, 3, 2, 3, 5),
+                  point_seg(x, 2, 0, 1, 0, 2, 6), point_seg(x, 3, 0, 1, 1, 3, 7)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double D = feat_sqd(f4[k], x);
+      if (D < bestD) { bestD = D; best = f4[k]; }
+    }
+    double u[3], v[3], w[3], n[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[i] = x[3 + i] - x[i];
+      v[i] = x[9 + i] - x[6 + i];
+      w[i] = x[i] - x[6 + i];
+    }
+    cross3(u, v, n);
+    double N = dot3(n, n);
+    if (N > 0.0) {
+      double uu = dot3(u, u), uv = dot3(u, v), vv = dot3(v, v);
+      double uw = dot3(u, w), vw = dot3(v, w);
+      double s = (uv * vw - vv * uw) / N;
+      double t = (uu * vw - uv * uw) / N;
+      if (s > 0.0 && s < 1.0 && t > 0.0 && t < 1.0) {
+        Feat f;
+        f.type = F_TRI; f.code = 8;
+        set_l(f.l[0], 1, 0, -1, 0);  /* w = a0 - b0 */
+        set_l(f.l[1], -1, 1, 0, 0);  /* u = a1 - a0 */
+        set_l(f.l[2], 0, 0, -1, 1);  /* v = b1 - b0 */
+        double D = feat_sqd(f, x);
+        if (D < bestD) { bestD = D; best = f; }
+      }
+    }
+  }
+  Dout = bestD;
+  return best;
+}
+
+__device__ __forceinline__ double pair_dist(int kind, const double* x) {
+  double D;
+  classify(kind, x, D);
+  return sqrt(D);
+}
+
+/* ------------------------------------------------------------------ */
+/* reduced frame                                                        */
+/* The pair energy depends only on vertex differences; it is written in  */
+/* three difference vectors y_r = sum_s f_r[s] x_s whose slot rows are   */
+/* mutually orthogonal:                                                  */
+/*   PT: p - (t0+t1+t2)/3, t1 - t0, t2 - (t0+t1)/2  (|f|^2 = 4/3, 2, 3/2)*/
+/*   EE: mid(a) - mid(b),  a1 - a0,  b1 - b0         (|f|^2 = 1, 2, 2)   */
+/* so the vertex Hessian is f^T H_y f = U^T (G H_y G) U with U = G^-1 f  */
+/* orthonormal and G = diag|f_r|: PSD projection of the 9x9 G H_y G     */
+/* equals the projection of the 12x12 vertex Hessian.                   */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ double frame_row(int kind, int r, int s) {
+  if (kind == C_PT) {
+    if (r == 0) return s == 0 ? 1.0 : -1.0 / 3.0;
+    if (r == 1) return s == 1 ? -1.0 : (s == 2 ? 1.0 : 0.0);
+    return s == 3 ? 1.0 : (s == 0 ? 0.0 : -0.5);
+  }
+  if (r == 0) return s < 2 ? 0.5 : -0.5;
+  if (r == 1) return s == 0 ? -1.0 : (s == 1 ? 1.0 : 0.0);
+  return s == 2 ? -1.0 : (s == 3 ? 1.0 : 0.0);
+}
+__device__ __forceinline__ double frame_norm2(int kind, int r) {
+  if (kind == C_PT) return r == 0 ? 4.0 / 3.0 : (r == 1 ? 2.0 : 1.5);
+  return r == 0 ? 1.0 : 2.0;
+}
+/* y-coordinates of a difference vector with slot coefficients l */
+__device__ __forceinline__ void frame_coef(int kind, const signed char* l,
+                                           double* C) {
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) s += l[k] * frame_row(kind, r, k);
+    C[r] = s / frame_norm2(kind, r);
+  }
+}
+
+/* packed symmetric 9x9 index, p <= q */
+__device__ __forceinline__ int sidx(int p, int q) {
+  if (p > q) { int t = p; p = q; q = t; }
+  return 9 * p - (p * (p - 1)) / 2 + (q - p);
+}
+
+/* ------------------------------------------------------------------ */
+/* cyclic Jacobi on a packed symmetric 9x9 held per thread in LDS        */
+/* (element-major: K[idx * ld + lane]) and projection to PSD in place:  */
+/* K <- V max(Lambda, 0) V^T.  V is scratch [81][ld].                    */
+/* ------------------------------------------------------------------ */
+__device__ inline void psd9_lds(double* K, double* V, int ld, int lane) {
+#define KK(p, q) K[sidx(p, q) * ld + lane]
+#define VV(p, q) V[((p) * 9 + (q)) * ld + lane]
+  for (int p = 0; p < 9; ++p)
+    for (int q = 0; q < 9; ++q) VV(p, q) = (p == q) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, dia = 0.0;
+    for (int p = 0; p < 9; ++p) {
+      double d = KK(p, p);
+      dia += d * d;
+      for (int q = p + 1; q < 9; ++q) {
+        double a = KK(p, q);
+        off += a * a;
+      }
+    }
+    if (off == 0.0 || off <= 1e-30 * (dia + 2.0 * off)) break;
+    for (int p = 0; p < 8; ++p)
+      for (int q = p + 1; q < 9; ++q) {
+        double apq = KK(p, q);
+        if (apq == 0.0) continue;
+        double app = KK(p, p), aqq = KK(q, q);
+        double theta = (aqq - app) / (2.0 * apq);
+        double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+        if (theta < 0.0) t = -t;
+        double c = 1.0 / sqrt(t * t + 1.0);
+        double s = t * c;
+        for (int r = 0; r < 9; ++r) {
+          if (r == p || r == q) continue;
+          double krp = KK(r, p), krq = KK(r, q);
+          KK(r, p) = c * krp - s * krq;
+          KK(r, q) = s * krp + c * krq;
+        }
+        KK(p, p) = app - t * apq;
+        KK(q, q) = aqq + t * apq;
+        KK(p, q) = 0.0;
+        for (int r = 0; r < 9; ++r) {
+          double vrp = VV(r, p), vrq = VV(r, q);
+          VV(r, p) = c * vrp - s * vrq;
+          VV(r, q) = s * vrp + c * vrq;
+        }
+      }
+  }
+  double lam[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) lam[k] = fmax(KK(k, k), 0.0);
+  for (int p = 0; p < 9; ++p)
+    for (int q = p; q < 9; ++q) {
+      double v = 0.0;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) v += VV(p, k) * lam[k] * VV(q, k);
+      KK(p, q) = v;
+    }
+#undef KK
+#undef VV
+}
+
+/* ------------------------------------------------------------------ */
+/* additive CCD on one PT/EE pair along x + t dx                        */
+/* ------------------------------------------------------------------ */
+__device__ inline double accd(int kind, const double* x, const double* dx,
+                              double tmax) {
+  double m[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+    m[i] = 0.25 * (dx[i] + dx[3 + i] + dx[6 + i] + dx[9 + i]);
+  double r[12];
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) r[3 * k + i] = dx[3 * k + i] - m[i];
+  double n[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) n[k] = sqrt(dot3(r + 3 * k, r + 3 * k));
+  double lp = (kind == C_PT) ? n[0] + fmax(n[1], fmax(n[2], n[3]))
+                             : fmax(n[0], n[1]) + fmax(n[2], n[3]);
+  if (lp == 0.0) return tmax;
+  double d0 = pair_dist(kind, x);
+  if (!(d0 > 0.0)) return 0.0;
+  double gap = ACCD_S * d0;
+  double t = 0.0;
+  double tl = (1.0 - ACCD_S) * d0 / lp;
+  double xt[12];
+  for (int it = 0; it < ACCD_MAX_IT; ++it) {
+    double tn = t + tl;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) xt[i] = x[i] + tn * r[i];
+    double d = pair_dist(kind, xt);
+    if (t > 0.0 && d < gap) return t;
+    t = tn;
+    if (t > tmax) return tmax;
+    tl = 0.9 * d / lp;
+  }
+  return t;
+}
+
+/* ------------------------------------------------------------------ */
+/* atomics on non-negative doubles through their bit patterns           */
+/* ------------------------------------------------------------------ */
+__device__ __forceinline__ void atomic_min_pos(unsigned long long* a,
+                                               double v) {
+  atomicMin(a, (unsigned long long)__double_as_longlong(v));
+}
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* a,
+                                               double v) {
+  atomicMax(a, (unsigned long long)__double_as_longlong(v));
+}
+
+/* ------------------------------------------------------------------ */
+/* host-side launchers (kernels.hip)                                    */
+/* ------------------------------------------------------------------ */
+void launch_predict(const Scene& S, hipStream_t st);
+void launch_commit(const Scene& S, hipStream_t st);
+void launch_transform(const Scene& S, double* x, double* dx, hipStream_t st);
+void launch_body_terms(const Scene& S, hipStream_t st);
+void launch_boxes(const Scene& S, int swept, hipStream_t st);
+void launch_body_pairs(const Scene& S, hipStream_t st);
+void launch_chunk_pairs(const Scene& S, hipStream_t st);
+void launch_prim_pairs(const Scene& S, int swept, hipStream_t st);
+void launch_pg(const Scene& S, int swept, hipStream_t st);
+void launch_filter(const Scene& S, hipStream_t st);
+void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st);
+void launch_bsr(const Scene& S, hipStream_t st);
+void launch_block_inverse(const Scene& S, hipStream_t st);
+int launch_pcg(const Scene& S, double eta, int max_it, int grid,
+               hipStream_t st);
+int pcg_max_grid();
+void launch_dq_norm(const Scene& S, hipStream_t st);
+void launch_ccd(const Scene& S, hipStream_t st);
+void launch_energy(const Scene& S, double alpha, int with_pairs, double* out,
+                   hipStream_t st);
+void launch_update_q(const Scene& S, double alpha, hipStream_t st);
+void launch_scale(const Scene& S, double* out6, hipStream_t st);
+
+}  // namespace abd

@@ -1,0 +1,1162 @@
+/*
+ * Host side of libabd: the C-ABI of include/abd.h, device memory, the
+ * chunk hierarchy of the broad phase, and the Newton loop of the local
+ * solve (Eq. 5):
+ *
+ *   repeat
+ *     body terms + static broad phase + barrier assembly  -> g, H
+ *     block-Jacobi PCG                                     -> dq
+ *     stop if |dq|_inf / (h l) < theta                    (Eq. 8 form)
+ *     swept broad phase + additive CCD                     -> alpha_max
+ *     halve alpha while E(q + alpha dq) - E(q) > 0         (line search)
+ *     q += alpha dq
+ *
+ * Two host synchronisations per iteration read back a small counter block
+ * (stop test and capacities; step size and energy difference).
+ */
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/abd.h"
+#include "abd_internal.h"
+
+using namespace abd;
+
+namespace {
+
+struct HBody {
+  int kind;
+  double density;
+  int v0, nv, t0, nt, e0, ne;
+  double Mhat[16];
+  double vol;
+  double q0[12], qd0[12];
+};
+
+struct Pending {
+  int stage;
+  hipEvent_t a, b;
+  double bytes;
+};
+
+}  // namespace
+
+struct abd_ctx {
+  abd_params P;
+  std::string err;
+  hipStream_t st = nullptr;
+  bool finalized = false;
+  std::vector<HBody> bodies;
+  std::vector<double> xbar; /* [V][3] */
+  std::vector<int> vbody, tri /* [T][3] */, edge /* [E][2] */;
+  std::vector<double> erest2;
+  int pair_mode = 0;
+  double scale = 1.0;
+  Scene S;
+  Counters* h_cnt = nullptr; /* pinned */
+  double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
+  std::vector<void*> allocs;
+  int pcg_grid = 0;
+  int n_shared = 0;
+  /* timing */
+  bool timing = false;
+  double t_ms[7] = {0}, t_bytes[7] = {0};
+  int64_t t_n[7] = {0};
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> ev_pool;
+};
+
+namespace {
+
+int fail(abd_ctx* c, int code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+#define HIPCHK(call)                                                     \
+  do {                                                                   \
+    hipError_t e_ = (call);                                              \
+    if (e_ != hipSuccess)                                                \
+      return fail(ctx, ABD_E_DEVICE,                                     \
+                  std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+template <class T>
+int dalloc(abd_ctx* ctx, T** p, size_t n) {
+  size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+  void* q = nullptr;
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, ABD_E_OOM, "device allocation failed");
+  }
+  ctx->allocs.push_back(q);
+  *p = (T*)q;
+  return ABD_OK;
+}
+
+template <class T>
+void dfree(abd_ctx* ctx, T* p) {
+  if (!p) return;
+  auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), (void*)p);
+  if (it != ctx->allocs.end()) ctx->allocs.erase(it);
+  (void)hipFree(p);
+}
+
+template <class T>
+int upload(abd_ctx* ctx, T** p, const std::vector<T>& v) {
+  int rc = dalloc(ctx, p, v.size());
+  if (rc) return rc;
+  if (!v.empty())
+    HIPCHK(hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+  return ABD_OK;
+}
+
+/* ---------------- timing ---------------- */
+hipEvent_t get_event(abd_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  (void)hipEventCreate(&e);
+  return e;
+}
+struct StageTimer {
+  abd_ctx* ctx;
+  int stage;
+  double bytes;
+  hipEvent_t a = nullptr;
+  StageTimer(abd_ctx* c, int s, double b = 0.0) : ctx(c), stage(s), bytes(b) {
+    if (ctx->timing) {
+      a = get_event(ctx);
+      (void)hipEventRecord(a, ctx->st);
+    }
+  }
+  ~StageTimer() {
+    if (ctx->timing) {
+      hipEvent_t b = get_event(ctx);
+      (void)hipEventRecord(b, ctx->st);
+      ctx->pending.push_back({stage, a, b, bytes});
+    }
+  }
+};
+void resolve_timing(abd_ctx* ctx) {
+  for (auto& p : ctx->pending) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      ctx->t_ms[p.stage] += ms;
+      ctx->t_n[p.stage] += 1;
+      ctx->t_bytes[p.stage] += p.bytes;
+    }
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->pending.clear();
+}
+
+/* ---------------- mass properties (divergence theorem) ---------------- */
+void mass_props(const double* xb, const int32_t* tris, int nt, double rho,
+                double* M, double* vol) {
+  double V = 0.0, f[3] = {0, 0, 0}, s2[9] = {0};
+  for (int t = 0; t < nt; ++t) {
+    const double* a = xb + 3 * tris[3 * t];
+    const double* b = xb + 3 * tris[3 * t + 1];
+    const double* c = xb + 3 * tris[3 * t + 2];
+    double bc[3] = {b[1] * c[2] - b[2] * c[1], b[2] * c[0] - b[0] * c[2],
+                    b[0] * c[1] - b[1] * c[0]};
+    double vt = (a[0] * bc[0] + a[1] * bc[1] + a[2] * bc[2]) / 6.0;
+    V += vt;
+    double s[3];
+    for (int i = 0; i < 3; ++i) {
+      s[i] = a[i] + b[i] + c[i];
+      f[i] += vt * s[i] * 0.25;
+    }
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j)
+        s2[3 * i + j] += vt * 0.05 *
+                         (a[i] * a[j] + b[i] * b[j] + c[i] * c[j] + s[i] * s[j]);
+  }
+  *vol = V;
+  M[0] = rho * V;
+  for (int i = 0; i < 3; ++i) {
+    M[1 + i] = M[4 * (1 + i)] = rho * f[i];
+    for (int j = 0; j < 3; ++j) M[4 * (1 + i) + 1 + j] = rho * s2[3 * i + j];
+  }
+}
+
+/* ---------------- chunk hierarchy ---------------- */
+struct Leaf {
+  std::vector<int> ids;
+};
+
+/* Split primitive ids along the longest axis of their rest centroids until
+ * at most ABD_CHUNK per leaf; leaves of static bodies keep splitting while
+ * they hold more than one primitive and their box is much larger than the
+ * primitives in it (large container walls get boxes of their own). */
+void split_leaves(std::vector<int>& ids, const std::vector<double>& cen,
+                  const std::vector<double>& pbox, bool is_static,
+                  std::vector<Leaf>& out) {
+  if (ids.empty()) return;
+  double lo[3] = {INFINITY, INFINITY, INFINITY},
+         hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double blo[3] = {INFINITY, INFINITY, INFINITY},
+         bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  double maxd = 0.0;
+  for (int i : ids)
+    for (int k = 0; k < 3; ++k) {
+      lo[k] = std::min(lo[k], cen[3 * i + k]);
+      hi[k] = std::max(hi[k], cen[3 * i + k]);
+      blo[k] = std::min(blo[k], pbox[6 * i + k]);
+      bhi[k] = std::max(bhi[k], pbox[6 * i + 3 + k]);
+    }
+  for (int i : ids) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double e = pbox[6 * i + 3 + k] - pbox[6 * i + k];
+      d2 += e * e;
+    }
+    maxd = std::max(maxd, std::sqrt(d2));
+  }
+  double diag = 0.0;
+  for (int k = 0; k < 3; ++k) diag += (bhi[k] - blo[k]) * (bhi[k] - blo[k]);
+  diag = std::sqrt(diag);
+  bool small = (int)ids.size() <= ABD_CHUNK;
+  if (small && (!is_static || ids.size() == 1 || diag <= 2.0 * maxd)) {
+    out.push_back({ids});
+    return;
+  }
+  int ax = 0;
+  for (int k = 1; k < 3; ++k)
+    if (hi[k] - lo[k] > hi[ax] - lo[ax]) ax = k;
+  size_t mid = ids.size() / 2;
+  std::nth_element(ids.begin(), ids.begin() + mid, ids.end(),
+                   [&](int a, int b) { return cen[3 * a + ax] < cen[3 * b + ax]; });
+  std::vector<int> L(ids.begin(), ids.begin() + mid), R(ids.begin() + mid, ids.end());
+  split_leaves(L, cen, pbox, is_static, out);
+  split_leaves(R, cen, pbox, is_static, out);
+}
+
+/* ---------------- counters ---------------- */
+Counters fresh_counters() {
+  Counters c;
+  std::memset(&c, 0, sizeof(c));
+  double inf = INFINITY;
+  std::memcpy(&c.min_dist, &inf, 8);
+  std::memcpy(&c.min_toi, &inf, 8);
+  return c;
+}
+
+int reset_counters(abd_ctx* ctx) {
+  *ctx->h_cnt = fresh_counters();
+  HIPCHK(hipMemcpyAsync(ctx->S.cnt, ctx->h_cnt, sizeof(Counters),
+                        hipMemcpyHostToDevice, ctx->st));
+  return ABD_OK;
+}
+
+int read_counters(abd_ctx* ctx) {
+  HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->S.cnt, sizeof(Counters),
+                        hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  resolve_timing(ctx);
+  if (ctx->h_cnt->err)
+    return fail(ctx, ABD_E_DEVICE, "device barrier timed out");
+  return ABD_OK;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, 8);
+  return d;
+}
+
+/* ---------------- capacities ---------------- */
+int grow(abd_ctx* ctx, bool* changed) {
+  Scene& S = ctx->S;
+  const Counters& c = *ctx->h_cnt;
+  *changed = false;
+  auto need = [](int have, int n) { return n > have; };
+  int rc;
+  if (need(S.cap_bp, c.n_bp)) {
+    dfree(ctx, S.bp);
+    dfree(ctx, S.Hoff);
+    dfree(ctx, S.slot_used);
+    S.cap_bp = (int)std::min<long>(2L * c.n_bp + 1024, 1L << 30);
+    if ((rc = dalloc(ctx, &S.bp, S.cap_bp))) return rc;
+    if ((rc = dalloc(ctx, &S.Hoff, 144L * S.cap_bp))) return rc;
+    if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
+    dfree(ctx, S.col_slot);
+    dfree(ctx, S.col_body);
+    dfree(ctx, S.col_trans);
+    S.cap_col = 2 * S.cap_bp;
+    if ((rc = dalloc(ctx, &S.col_slot, S.cap_col))) return rc;
+    if ((rc = dalloc(ctx, &S.col_body, S.cap_col))) return rc;
+    if ((rc = dalloc(ctx, &S.col_trans, S.cap_col))) return rc;
+    *changed = true;
+  }
+  if (need(S.cap_cp, c.n_cp)) {
+    dfree(ctx, S.cp);
+    S.cap_cp = (int)std::min<long>(2L * c.n_cp + 1024, 1L << 30);
+    if ((rc = dalloc(ctx, &S.cp, S.cap_cp))) return rc;
+    *changed = true;
+  }
+  if (need(S.cap_pt, c.n_pt)) {
+    dfree(ctx, S.cand_pt);
+    S.cap_pt = (int)std::min<long>(2L * c.n_pt + 1024, 1L << 29);
+    if ((rc = dalloc(ctx, &S.cand_pt, 3L * S.cap_pt))) return rc;
+    *changed = true;
+  }
+  if (need(S.cap_ee, c.n_ee)) {
+    dfree(ctx, S.cand_ee);
+    S.cap_ee = (int)std::min<long>(2L * c.n_ee + 1024, 1L << 29);
+    if ((rc = dalloc(ctx, &S.cand_ee, 3L * S.cap_ee))) return rc;
+    *changed = true;
+  }
+  if (need(S.cap_pg, c.n_pg)) {
+    dfree(ctx, S.cand_pg);
+    S.cap_pg = (int)std::min<long>(2L * c.n_pg + 1024, 1L << 30);
+    if ((rc = dalloc(ctx, &S.cand_pg, S.cap_pg))) return rc;
+    *changed = true;
+  }
+  if (need(S.cap_act, c.n_act)) {
+    dfree(ctx, S.act);
+    S.cap_act = (int)std::min<long>(2L * c.n_act + 1024, 1L << 30);
+    if ((rc = dalloc(ctx, &S.act, S.cap_act))) return rc;
+    *changed = true;
+  }
+  return ABD_OK;
+}
+
+/* ---------------- phases ---------------- */
+void broad_phase(abd_ctx* ctx, int swept) {
+  StageTimer t(ctx, 1);
+  const Scene& S = ctx->S;
+  launch_boxes(S, swept, ctx->st);
+  launch_body_pairs(S, ctx->st);
+  launch_chunk_pairs(S, ctx->st);
+  launch_prim_pairs(S, swept, ctx->st);
+  if (S.has_ground) launch_pg(S, swept, ctx->st);
+}
+
+__global__ void k_clear_slots(Scene S) {
+  int nbp = min(S.cnt->n_bp, S.cap_bp);
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < 144L * nbp;
+       t += (long)gridDim.x * blockDim.x) {
+    S.Hoff[t] = 0.0;
+    if (t % 144 == 0) S.slot_used[t / 144] = 0;
+  }
+}
+
+/* gradient and Hessian at the current q (static phase), counters read */
+int assemble(abd_ctx* ctx) {
+  const Scene& S = ctx->S;
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    int rc = reset_counters(ctx);
+    if (rc) return rc;
+    {
+      StageTimer t(ctx, 0, (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96));
+      launch_body_terms(S, ctx->st);
+    }
+    broad_phase(ctx, 0);
+    {
+      StageTimer t(ctx, 2);
+      launch_filter(S, ctx->st);
+      hipLaunchKernelGGL(k_clear_slots, dim3(512), dim3(256), 0, ctx->st, S);
+      launch_assemble(S, 0, ctx->st);
+    }
+    if ((rc = read_counters(ctx))) return rc;
+    bool changed = false;
+    if ((rc = grow(ctx, &changed))) return rc;
+    if (!changed) return ABD_OK;
+  }
+  return fail(ctx, ABD_E_OOM, "capacity growth did not settle");
+}
+
+/* PCG on the assembled system; counters read */
+int linear_solve(abd_ctx* ctx, int* iters) {
+  const Scene& S = ctx->S;
+  {
+    StageTimer t(ctx, 6);
+    HIPCHK(hipMemsetAsync(S.row_cnt, 0, sizeof(int) * (S.B + 1), ctx->st));
+    launch_bsr(S, ctx->st);
+    launch_block_inverse(S, ctx->st);
+    /* the barrier counter and dot accumulators start at zero (the
+     * counter block was reset by the assembly) */
+    HIPCHK(hipMemsetAsync(S.acc, 0, sizeof(double) * 16, ctx->st));
+  }
+  int grid = std::min(ctx->pcg_grid, std::max(1, (S.B + 15) / 16));
+  {
+    StageTimer t(ctx, 3);
+    if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, grid, ctx->st))
+      return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
+    launch_dq_norm(S, ctx->st);
+  }
+  int rc = read_counters(ctx);
+  if (rc) return rc;
+  *iters = ctx->h_cnt->pcg_iters;
+  if (ctx->timing) {
+    /* algorithmic bytes of the PCG launch: per iteration the diagonal and
+     * used off-diagonal blocks once, the block inverses once and seven
+     * length-12B vectors */
+    double per = (double)(S.B + ctx->h_cnt->n_rows_used / 2) * 1152.0 +
+                 (double)S.B * 1152.0 + 7.0 * 12.0 * S.B * 8.0;
+    ctx->t_bytes[3] += per * (*iters);
+  }
+  return ABD_OK;
+}
+
+int upload_dq(abd_ctx* ctx, const double* dq) {
+  HIPCHK(hipMemcpyAsync(ctx->S.dq, dq, sizeof(double) * 12 * ctx->S.B,
+                        hipMemcpyHostToDevice, ctx->st));
+  return ABD_OK;
+}
+
+/* swept candidates for the current dq, with capacity growth; counters read */
+int swept_phase(abd_ctx* ctx, bool ccd) {
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    int rc = reset_counters(ctx);
+    if (rc) return rc;
+    broad_phase(ctx, 1);
+    if (ccd) {
+      StageTimer t(ctx, 4);
+      launch_ccd(ctx->S, ctx->st);
+    }
+    if ((rc = read_counters(ctx))) return rc;
+    bool changed = false;
+    if ((rc = grow(ctx, &changed))) return rc;
+    if (!changed) return ABD_OK;
+  }
+  return fail(ctx, ABD_E_OOM, "capacity growth did not settle");
+}
+
+int energy(abd_ctx* ctx, double alpha, int mode, int with_pairs, double* out) {
+  {
+    StageTimer t(ctx, 5);
+    launch_energy(ctx->S, alpha, mode | (with_pairs << 1),
+                  ctx->S.partials + ctx->S.cap_partials - 1, ctx->st);
+  }
+  HIPCHK(hipMemcpyAsync(ctx->h_buf, ctx->S.partials + ctx->S.cap_partials - 1,
+                        sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  resolve_timing(ctx);
+  *out = ctx->h_buf[0];
+  return ABD_OK;
+}
+
+int check_ctx(abd_ctx* ctx, bool need_final) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  if (need_final && !ctx->finalized)
+    return fail(ctx, ABD_E_INVALID_ARG, "context not finalized");
+  HIPCHK(hipGetLastError());
+  return ABD_OK;
+}
+
+}  // namespace
+
+/* ==================================================================== */
+/* C ABI                                                                 */
+/* ==================================================================== */
+extern "C" {
+
+int abd_create(abd_ctx** out, const abd_params* p) {
+  if (!out || !p) return ABD_E_INVALID_ARG;
+  *out = nullptr;
+  if (!(p->dt > 0) || !(p->dhat > 0) || !(p->kappa > 0) || !(p->kappa_A >= 0) ||
+      p->max_newton < 1 || p->max_pcg < 1 || p->max_ls < 0 ||
+      !(p->newton_theta > 0) || !(p->pcg_eta > 0) || p->precision != ABD_FP64)
+    return ABD_E_INVALID_ARG;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    (void)hipGetLastError();
+    return ABD_E_DEVICE;
+  }
+  abd_ctx* c = new abd_ctx();
+  c->P = *p;
+  std::memset(&c->S, 0, sizeof(Scene));
+  *out = c;
+  return ABD_OK;
+}
+
+void abd_destroy(abd_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipDeviceSynchronize();
+  for (void* p : ctx->allocs) (void)hipFree(p);
+  if (ctx->h_cnt) (void)hipHostFree(ctx->h_cnt);
+  if (ctx->h_buf) (void)hipHostFree(ctx->h_buf);
+  for (auto& p : ctx->pending) {
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  delete ctx;
+}
+
+const char* abd_last_error(const abd_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int abd_add_body(abd_ctx* ctx, const double* xbar, int32_t nv,
+                 const int32_t* tris, int32_t nt, double density,
+                 const double* q0, const double* qdot0, int32_t kind,
+                 int32_t* body_id) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  if (ctx->finalized || !xbar || !tris || !q0 || nv <= 0 || nt <= 0 ||
+      (kind != ABD_DYNAMIC && kind != ABD_STATIC) ||
+      (kind == ABD_DYNAMIC && !(density > 0)))
+    return fail(ctx, ABD_E_INVALID_ARG, "bad add_body arguments");
+  for (int i = 0; i < 3 * nv; ++i)
+    if (!std::isfinite(xbar[i])) return fail(ctx, ABD_E_INVALID_ARG, "xbar");
+  for (int i = 0; i < 12; ++i)
+    if (!std::isfinite(q0[i]) || (qdot0 && !std::isfinite(qdot0[i])))
+      return fail(ctx, ABD_E_INVALID_ARG, "non-finite state");
+  for (int i = 0; i < 3 * nt; ++i)
+    if (tris[i] < 0 || tris[i] >= nv) return fail(ctx, ABD_E_MESH, "triangle index");
+  HBody b;
+  std::memset(&b, 0, sizeof(b));
+  b.kind = kind;
+  b.density = density;
+  b.v0 = (int)ctx->vbody.size();
+  b.nv = nv;
+  b.t0 = (int)(ctx->tri.size() / 3);
+  b.nt = nt;
+  std::memcpy(b.q0, q0, sizeof(b.q0));
+  if (qdot0 && kind == ABD_DYNAMIC) std::memcpy(b.qd0, qdot0, sizeof(b.qd0));
+  /* unique edges sorted by local (lo, hi) */
+  std::vector<std::pair<int, int>> E;
+  E.reserve(3 * nt);
+  for (int t = 0; t < nt; ++t)
+    for (int k = 0; k < 3; ++k) {
+      int a = tris[3 * t + k], c = tris[3 * t + (k + 1) % 3];
+      E.push_back({std::min(a, c), std::max(a, c)});
+    }
+  std::sort(E.begin(), E.end());
+  E.erase(std::unique(E.begin(), E.end()), E.end());
+  if (kind == ABD_DYNAMIC) {
+    std::vector<std::pair<int, int>> D;
+    D.reserve(3 * nt);
+    for (int t = 0; t < nt; ++t)
+      for (int k = 0; k < 3; ++k)
+        D.push_back({tris[3 * t + k], tris[3 * t + (k + 1) % 3]});
+    std::sort(D.begin(), D.end());
+    for (size_t i = 0; i < D.size(); ++i) {
+      if (i > 0 && D[i] == D[i - 1])
+        return fail(ctx, ABD_E_MESH, "repeated directed edge");
+      if (!std::binary_search(D.begin(), D.end(),
+                              std::make_pair(D[i].second, D[i].first)))
+        return fail(ctx, ABD_E_MESH, "mesh not closed or not consistently oriented");
+    }
+    mass_props(xbar, tris, nt, density, b.Mhat, &b.vol);
+    if (!(b.vol > 0)) return fail(ctx, ABD_E_MESH, "non-positive volume");
+  }
+  int id = (int)ctx->bodies.size();
+  b.e0 = (int)ctx->erest2.size();
+  b.ne = (int)E.size();
+  for (int v = 0; v < nv; ++v) {
+    for (int k = 0; k < 3; ++k) ctx->xbar.push_back(xbar[3 * v + k]);
+    ctx->vbody.push_back(id);
+  }
+  for (int t = 0; t < 3 * nt; ++t) ctx->tri.push_back(b.v0 + tris[t]);
+  for (auto& e : E) {
+    ctx->edge.push_back(b.v0 + e.first);
+    ctx->edge.push_back(b.v0 + e.second);
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      double d = xbar[3 * e.second + k] - xbar[3 * e.first + k];
+      s += d * d;
+    }
+    ctx->erest2.push_back(s);
+  }
+  ctx->bodies.push_back(b);
+  if (body_id) *body_id = id;
+  return ABD_OK;
+}
+
+int abd_finalize(abd_ctx* ctx) {
+  int rc = check_ctx(ctx, false);
+  if (rc) return rc;
+  if (ctx->finalized || ctx->bodies.empty())
+    return fail(ctx, ABD_E_INVALID_ARG, "finalize: no bodies or already final");
+  Scene& S = ctx->S;
+  const int B = (int)ctx->bodies.size(), V = (int)ctx->vbody.size();
+  const int T = (int)(ctx->tri.size() / 3), E = (int)(ctx->edge.size() / 2);
+  S.B = B; S.V = V; S.T = T; S.E = E;
+  S.dt = ctx->P.dt; S.dhat = ctx->P.dhat; S.kappa = ctx->P.kappa;
+  S.kappa_A = ctx->P.kappa_A;
+  for (int i = 0; i < 3; ++i) S.grav[i] = ctx->P.gravity[i];
+  S.ground_y = ctx->P.ground_y;
+  S.has_ground = ctx->P.has_ground;
+  S.mollify = ctx->P.mollify_ee;
+  S.pair_mode = ctx->pair_mode;
+
+  /* chunks per body and kind */
+  std::vector<int> ch_body, ch_kind, ch_start, ch_count, ch_prims, body_chunk(6 * B);
+  std::vector<double> ch_rest, body_rest(6 * B);
+  const std::vector<double>& xb = ctx->xbar;
+  for (int b = 0; b < B; ++b) {
+    const HBody& hb = ctx->bodies[b];
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int v = hb.v0; v < hb.v0 + hb.nv; ++v)
+      for (int k = 0; k < 3; ++k) {
+        lo[k] = std::min(lo[k], xb[3 * v + k]);
+        hi[k] = std::max(hi[k], xb[3 * v + k]);
+      }
+    for (int k = 0; k < 3; ++k) {
+      body_rest[6 * b + k] = 0.5 * (lo[k] + hi[k]);
+      body_rest[6 * b + 3 + k] = 0.5 * (hi[k] - lo[k]);
+    }
+    for (int kind = 0; kind < 3; ++kind) {
+      int first = kind == 0 ? hb.v0 : kind == 1 ? hb.t0 : hb.e0;
+      int n = kind == 0 ? hb.nv : kind == 1 ? hb.nt : hb.ne;
+      int nvper = kind == 0 ? 1 : kind == 1 ? 3 : 2;
+      std::vector<double> cen(3 * n), pbox(6 * n);
+      std::vector<int> ids(n);
+      for (int i = 0; i < n; ++i) {
+        ids[i] = i;
+        double plo[3] = {INFINITY, INFINITY, INFINITY}, phi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int j = 0; j < nvper; ++j) {
+          int v = kind == 0 ? first + i
+                            : (kind == 1 ? ctx->tri[3 * (first + i) + j]
+                                         : ctx->edge[2 * (first + i) + j]);
+          for (int k = 0; k < 3; ++k) {
+            plo[k] = std::min(plo[k], xb[3 * v + k]);
+            phi[k] = std::max(phi[k], xb[3 * v + k]);
+          }
+        }
+        for (int k = 0; k < 3; ++k) {
+          cen[3 * i + k] = 0.5 * (plo[k] + phi[k]);
+          pbox[6 * i + k] = plo[k];
+          pbox[6 * i + 3 + k] = phi[k];
+        }
+      }
+      std::vector<Leaf> leaves;
+      split_leaves(ids, cen, pbox, hb.kind != ABD_DYNAMIC, leaves);
+      body_chunk[6 * b + 2 * kind] = (int)ch_body.size();
+      for (auto& L : leaves) {
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        ch_body.push_back(b);
+        ch_kind.push_back(kind);
+        ch_start.push_back((int)ch_prims.size());
+        ch_count.push_back((int)L.ids.size());
+        for (int i : L.ids) {
+          ch_prims.push_back(first + i);
+          for (int k = 0; k < 3; ++k) {
+            clo[k] = std::min(clo[k], pbox[6 * i + k]);
+            chi[k] = std::max(chi[k], pbox[6 * i + 3 + k]);
+          }
+        }
+        for (int k = 0; k < 3; ++k) ch_rest.push_back(0.5 * (clo[k] + chi[k]));
+        for (int k = 0; k < 3; ++k) ch_rest.push_back(0.5 * (chi[k] - clo[k]));
+      }
+      body_chunk[6 * b + 2 * kind + 1] = (int)ch_body.size();
+    }
+  }
+  S.NC = (int)ch_body.size();
+
+  /* geometry in structure-of-arrays layout */
+  std::vector<double> xsoa(3L * V);
+  for (int v = 0; v < V; ++v)
+    for (int k = 0; k < 3; ++k) xsoa[(size_t)k * V + v] = xb[3 * v + k];
+  std::vector<int> tsoa(3L * T), esoa(2L * E);
+  for (int t = 0; t < T; ++t)
+    for (int k = 0; k < 3; ++k) tsoa[(size_t)k * T + t] = ctx->tri[3 * t + k];
+  for (int e = 0; e < E; ++e)
+    for (int k = 0; k < 2; ++k) esoa[(size_t)k * E + e] = ctx->edge[2 * e + k];
+  std::vector<double> q(12L * B), qd(12L * B), Mh(16L * B), vol(B), wb(B, 1.0);
+  std::vector<int> kind(B), shs(B, -1);
+  for (int b = 0; b < B; ++b) {
+    const HBody& hb = ctx->bodies[b];
+    std::memcpy(&q[12 * b], hb.q0, 96);
+    std::memcpy(&qd[12 * b], hb.qd0, 96);
+    std::memcpy(&Mh[16 * b], hb.Mhat, 128);
+    vol[b] = hb.vol;
+    kind[b] = hb.kind;
+  }
+  if ((rc = upload(ctx, &S.xbar, xsoa))) return rc;
+  if ((rc = upload(ctx, &S.vbody, ctx->vbody))) return rc;
+  if ((rc = upload(ctx, &S.tri, tsoa))) return rc;
+  if ((rc = upload(ctx, &S.edge, esoa))) return rc;
+  if ((rc = upload(ctx, &S.erest2, ctx->erest2))) return rc;
+  if ((rc = upload(ctx, &S.q, q))) return rc;
+  if ((rc = upload(ctx, &S.qt, q))) return rc;
+  if ((rc = upload(ctx, &S.qtilde, q))) return rc;
+  if ((rc = upload(ctx, &S.qdot, qd))) return rc;
+  if ((rc = upload(ctx, &S.Mhat, Mh))) return rc;
+  if ((rc = upload(ctx, &S.vol, vol))) return rc;
+  if ((rc = upload(ctx, &S.wbody, wb))) return rc;
+  if ((rc = upload(ctx, &S.kind, kind))) return rc;
+  if ((rc = upload(ctx, &S.shared_slot, shs))) return rc;
+  if ((rc = upload(ctx, &S.body_rest, body_rest))) return rc;
+  if ((rc = upload(ctx, &S.body_chunk, body_chunk))) return rc;
+  if ((rc = upload(ctx, &S.ch_body, ch_body))) return rc;
+  if ((rc = upload(ctx, &S.ch_kind, ch_kind))) return rc;
+  if ((rc = upload(ctx, &S.ch_start, ch_start))) return rc;
+  if ((rc = upload(ctx, &S.ch_count, ch_count))) return rc;
+  if ((rc = upload(ctx, &S.ch_prims, ch_prims))) return rc;
+  if ((rc = upload(ctx, &S.ch_rest, ch_rest))) return rc;
+  if ((rc = dalloc(ctx, &S.ch_box, 6L * S.NC))) return rc;
+  if ((rc = dalloc(ctx, &S.body_box, 6L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.dq, 12L * B))) return rc;
+  HIPCHK(hipMemset(S.dq, 0, sizeof(double) * 12 * B));
+  if ((rc = dalloc(ctx, &S.z, 12))) return rc;
+  if ((rc = dalloc(ctx, &S.u, 12))) return rc;
+  if ((rc = dalloc(ctx, &S.rho, 1))) return rc;
+  /* work buffers */
+  S.cap_bp = std::max(4 * B, 4096);
+  S.cap_cp = 1 << 16;
+  S.cap_pt = S.cap_ee = S.cap_pg = S.cap_act = 1 << 16;
+  S.cap_col = 2 * S.cap_bp;
+  S.cap_partials = 1024;
+  if ((rc = dalloc(ctx, &S.bp, S.cap_bp))) return rc;
+  if ((rc = dalloc(ctx, &S.cp, S.cap_cp))) return rc;
+  if ((rc = dalloc(ctx, &S.cand_pt, 3L * S.cap_pt))) return rc;
+  if ((rc = dalloc(ctx, &S.cand_ee, 3L * S.cap_ee))) return rc;
+  if ((rc = dalloc(ctx, &S.cand_pg, S.cap_pg))) return rc;
+  if ((rc = dalloc(ctx, &S.act, S.cap_act))) return rc;
+  if ((rc = dalloc(ctx, &S.g, 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.Hdiag, 144L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.Pinv, 144L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.Hoff, 144L * S.cap_bp))) return rc;
+  if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
+  if ((rc = dalloc(ctx, &S.row_ptr, B + 1))) return rc;
+  if ((rc = dalloc(ctx, &S.row_cnt, B + 1))) return rc;
+  if ((rc = dalloc(ctx, &S.col_slot, S.cap_col))) return rc;
+  if ((rc = dalloc(ctx, &S.col_body, S.cap_col))) return rc;
+  if ((rc = dalloc(ctx, &S.col_trans, S.cap_col))) return rc;
+  if ((rc = dalloc(ctx, &S.r, 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.zv, 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.p0, 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.p1, 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.Ap, 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
+  if ((rc = dalloc(ctx, &S.partials, S.cap_partials))) return rc;
+  if ((rc = dalloc(ctx, &S.cnt, 1))) return rc;
+  if (hipHostMalloc((void**)&ctx->h_cnt, sizeof(Counters)) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
+    return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
+  ctx->pcg_grid = pcg_max_grid();
+  ctx->finalized = true;
+  /* initial feasibility: every candidate distance > 0 */
+  if ((rc = assemble(ctx))) return rc;
+  double md = bits_to_double(ctx->h_cnt->min_dist);
+  if (!(md > 0.0)) {
+    ctx->finalized = false;
+    return fail(ctx, ABD_E_INFEASIBLE, "initial state has a distance <= 0");
+  }
+  return ABD_OK;
+}
+
+int abd_sizes(const abd_ctx* ctx, int64_t* sizes) {
+  if (!ctx || !sizes) return ABD_E_INVALID_ARG;
+  sizes[0] = (int64_t)ctx->bodies.size();
+  sizes[1] = (int64_t)ctx->vbody.size();
+  sizes[2] = (int64_t)(ctx->tri.size() / 3);
+  sizes[3] = (int64_t)(ctx->edge.size() / 2);
+  return ABD_OK;
+}
+
+int abd_set_shared(abd_ctx* ctx, const int32_t* ids, int32_t n,
+                   const double* z, const double* u, const double* rho,
+                   const int32_t* kappa_b) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  const int B = ctx->S.B;
+  if (n < 0 || (n > 0 && (!ids || !z || !u || !rho || !kappa_b)))
+    return fail(ctx, ABD_E_INVALID_ARG, "set_shared arguments");
+  std::vector<int> slot(B, -1);
+  std::vector<double> wb(B, 1.0);
+  for (int i = 0; i < n; ++i) {
+    int b = ids[i];
+    if (b < 0 || b >= B || ctx->bodies[b].kind != ABD_DYNAMIC || slot[b] >= 0)
+      return fail(ctx, ABD_E_INVALID_ARG, "shared id");
+    for (int k = 0; k < 12; ++k)
+      if (!std::isfinite(z[12 * i + k]) || !std::isfinite(u[12 * i + k]))
+        return fail(ctx, ABD_E_INVALID_ARG, "non-finite z or u");
+    if (!(rho[i] >= 0) || !std::isfinite(rho[i]) || kappa_b[i] < 1)
+      return fail(ctx, ABD_E_INVALID_ARG, "rho or kappa_b");
+    slot[b] = i;
+    wb[b] = 1.0 / kappa_b[i];
+  }
+  Scene& S = ctx->S;
+  if (n > ctx->n_shared) {
+    dfree(ctx, S.z);
+    dfree(ctx, S.u);
+    dfree(ctx, S.rho);
+    if ((rc = dalloc(ctx, &S.z, 12L * n))) return rc;
+    if ((rc = dalloc(ctx, &S.u, 12L * n))) return rc;
+    if ((rc = dalloc(ctx, &S.rho, n))) return rc;
+    ctx->n_shared = n;
+  }
+  if (n > 0) {
+    HIPCHK(hipMemcpy(S.z, z, sizeof(double) * 12 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.u, u, sizeof(double) * 12 * n, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S.rho, rho, sizeof(double) * n, hipMemcpyHostToDevice));
+  }
+  HIPCHK(hipMemcpy(S.shared_slot, slot.data(), sizeof(int) * B, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(S.wbody, wb.data(), sizeof(double) * B, hipMemcpyHostToDevice));
+  return ABD_OK;
+}
+
+int abd_set_pair_replication(abd_ctx* ctx, int32_t mode) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  if (mode != ABD_PAIRS_ALL_ONE && mode != ABD_PAIRS_BY_SHARED)
+    return fail(ctx, ABD_E_INVALID_ARG, "pair replication mode");
+  ctx->pair_mode = mode;
+  ctx->S.pair_mode = mode;
+  return ABD_OK;
+}
+
+int abd_begin_step(abd_ctx* ctx) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  const Scene& S = ctx->S;
+  launch_predict(S, ctx->st);
+  /* scene scale from the dynamic vertices */
+  unsigned long long init[6];
+  double pinf = INFINITY, ninf = -INFINITY;
+  unsigned long long bp, bn;
+  std::memcpy(&bp, &pinf, 8);
+  std::memcpy(&bn, &ninf, 8);
+  /* ordered images: +inf -> bp | sign, -inf -> ~bn */
+  for (int k = 0; k < 3; ++k) {
+    init[k] = bp | 0x8000000000000000ull;
+    init[3 + k] = ~bn;
+  }
+  unsigned long long* d6 = (unsigned long long*)S.partials;
+  HIPCHK(hipMemcpyAsync(d6, init, sizeof(init), hipMemcpyHostToDevice, ctx->st));
+  launch_scale(S, (double*)d6, ctx->st);
+  unsigned long long out[6];
+  HIPCHK(hipMemcpyAsync(out, d6, sizeof(out), hipMemcpyDeviceToHost, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  double l2 = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    auto dec = [](unsigned long long o) {
+      unsigned long long b = (o >> 63) ? (o & 0x7fffffffffffffffull) : ~o;
+      return bits_to_double(b);
+    };
+    double lo = dec(out[k]), hi = dec(out[3 + k]);
+    if (std::isfinite(lo) && std::isfinite(hi)) l2 += (hi - lo) * (hi - lo);
+  }
+  ctx->scale = l2 > 0 ? std::sqrt(l2) : 1.0;
+  return ABD_OK;
+}
+
+int abd_set_step(abd_ctx* ctx, const double* qt, const double* qtilde,
+                 double scale) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!qt || !qtilde || !(scale > 0)) return fail(ctx, ABD_E_INVALID_ARG, "set_step");
+  HIPCHK(hipMemcpy(ctx->S.qt, qt, sizeof(double) * 12 * ctx->S.B, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->S.qtilde, qtilde, sizeof(double) * 12 * ctx->S.B,
+                   hipMemcpyHostToDevice));
+  ctx->scale = scale;
+  return ABD_OK;
+}
+
+int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  auto t0 = std::chrono::steady_clock::now();
+  const Scene& S = ctx->S;
+  abd_stats st;
+  std::memset(&st, 0, sizeof(st));
+  st.min_alpha = 1.0;
+  st.min_dist = INFINITY;
+  st.scene_scale = ctx->scale;
+  const double hl = ctx->P.dt * ctx->scale;
+  int status = ABD_E_NOCONV;
+  for (int it = 0; it < ctx->P.max_newton; ++it) {
+    if ((rc = assemble(ctx))) { status = rc; break; }
+    const Counters& c = *ctx->h_cnt;
+    st.n_cand_pt = c.n_pt;
+    st.n_cand_ee = c.n_ee;
+    st.n_cand_pg = c.n_pg;
+    st.n_active = c.n_act;
+    st.min_dist = bits_to_double(c.min_dist);
+    int pit = 0;
+    if ((rc = linear_solve(ctx, &pit))) { status = rc; break; }
+    st.pcg_iters_total += pit;
+    st.newton_iters = it + 1;
+    double eps = bits_to_double(ctx->h_cnt->max_dq) / hl;
+    st.final_eps_N = eps;
+    if (!std::isfinite(eps)) {
+      status = fail(ctx, ABD_E_NOCONV, "non-finite Newton direction");
+      break;
+    }
+    if (eps < ctx->P.newton_theta) { status = ABD_OK; break; }
+    if ((rc = swept_phase(ctx, true))) { status = rc; break; }
+    double amax = std::min(1.0, bits_to_double(ctx->h_cnt->min_toi));
+    double alpha = amax, dE;
+    if ((rc = energy(ctx, alpha, 0, 1, &dE))) { status = rc; break; }
+    int nh = 0;
+    while (dE > 0.0 && nh < ctx->P.max_ls) {
+      alpha *= 0.5;
+      ++nh;
+      if ((rc = energy(ctx, alpha, 0, 1, &dE))) break;
+    }
+    if (rc) { status = rc; break; }
+    st.ls_halvings += nh;
+    if (dE > 0.0) {
+      if (eps < 10.0 * ctx->P.newton_theta) {
+        status = ABD_OK;
+      } else {
+        status = fail(ctx, ABD_E_LINESEARCH, "line search exhausted");
+      }
+      break;
+    }
+    st.min_alpha = std::min(st.min_alpha, alpha);
+    launch_update_q(S, alpha, ctx->st);
+  }
+  if (status == ABD_E_NOCONV && ctx->err.empty()) ctx->err = "Newton did not converge";
+  (void)hipStreamSynchronize(ctx->st);
+  st.status = status;
+  st.t_solve_ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (out) *out = st;
+  return status;
+}
+
+int abd_end_step(abd_ctx* ctx) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  launch_commit(ctx->S, ctx->st);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return ABD_OK;
+}
+
+int abd_get_state(const abd_ctx* cctx, double* q, double* qdot) {
+  abd_ctx* ctx = const_cast<abd_ctx*>(cctx);
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  size_t n = sizeof(double) * 12 * ctx->S.B;
+  if (q) HIPCHK(hipMemcpy(q, ctx->S.q, n, hipMemcpyDeviceToHost));
+  if (qdot) HIPCHK(hipMemcpy(qdot, ctx->S.qdot, n, hipMemcpyDeviceToHost));
+  return ABD_OK;
+}
+
+int abd_set_state(abd_ctx* ctx, const double* q, const double* qdot) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  const int B = ctx->S.B;
+  std::vector<double> hq(12L * B), hqd(12L * B);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  HIPCHK(hipMemcpy(hq.data(), ctx->S.q, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(hqd.data(), ctx->S.qdot, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
+  for (int b = 0; b < B; ++b) {
+    if (ctx->bodies[b].kind != ABD_DYNAMIC) continue;
+    for (int i = 0; i < 12; ++i) {
+      if (q) {
+        if (!std::isfinite(q[12 * b + i])) return fail(ctx, ABD_E_INVALID_ARG, "q");
+        hq[12 * b + i] = q[12 * b + i];
+      }
+      if (qdot) {
+        if (!std::isfinite(qdot[12 * b + i])) return fail(ctx, ABD_E_INVALID_ARG, "qdot");
+        hqd[12 * b + i] = qdot[12 * b + i];
+      }
+    }
+  }
+  HIPCHK(hipMemcpy(ctx->S.q, hq.data(), sizeof(double) * 12 * B, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(ctx->S.qdot, hqd.data(), sizeof(double) * 12 * B, hipMemcpyHostToDevice));
+  return ABD_OK;
+}
+
+int abd_get_qtilde(const abd_ctx* cctx, double* qtilde) {
+  abd_ctx* ctx = const_cast<abd_ctx*>(cctx);
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  HIPCHK(hipMemcpy(qtilde, ctx->S.qtilde, sizeof(double) * 12 * ctx->S.B,
+                   hipMemcpyDeviceToHost));
+  return ABD_OK;
+}
+
+int abd_set_stream(abd_ctx* ctx, void* hip_stream) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  ctx->st = (hipStream_t)hip_stream;
+  return ABD_OK;
+}
+
+int abd_get_vertices(abd_ctx* ctx, const double* q, const double* dq,
+                     double* x, double* dx) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  Scene& S = ctx->S;
+  std::vector<double> save;
+  double *dx_d = nullptr, *x_d = nullptr;
+  if ((rc = dalloc(ctx, &x_d, 3L * S.V))) return rc;
+  if (dq && dx && (rc = dalloc(ctx, &dx_d, 3L * S.V))) { dfree(ctx, x_d); return rc; }
+  if (q) {
+    save.resize(12L * S.B);
+    HIPCHK(hipMemcpy(save.data(), S.q, sizeof(double) * 12 * S.B, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(S.q, q, sizeof(double) * 12 * S.B, hipMemcpyHostToDevice));
+  }
+  if (dq && dx) HIPCHK(hipMemcpy(S.dq, dq, sizeof(double) * 12 * S.B, hipMemcpyHostToDevice));
+  launch_transform(S, x_d, dx_d, ctx->st);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  HIPCHK(hipMemcpy(x, x_d, sizeof(double) * 3 * S.V, hipMemcpyDeviceToHost));
+  if (dx_d) HIPCHK(hipMemcpy(dx, dx_d, sizeof(double) * 3 * S.V, hipMemcpyDeviceToHost));
+  if (q) HIPCHK(hipMemcpy(S.q, save.data(), sizeof(double) * 12 * S.B, hipMemcpyHostToDevice));
+  dfree(ctx, x_d);
+  dfree(ctx, dx_d);
+  return ABD_OK;
+}
+
+int abd_export_candidates(abd_ctx* ctx, int32_t kind, const double* dq,
+                          int32_t* out, int64_t cap, int64_t* count) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (kind < ABD_PT || kind > ABD_PG || !count)
+    return fail(ctx, ABD_E_INVALID_ARG, "export_candidates");
+  const Scene& S = ctx->S;
+  if (dq) {
+    if ((rc = upload_dq(ctx, dq))) return rc;
+    if ((rc = swept_phase(ctx, false))) return rc;
+  } else {
+    for (int attempt = 0; attempt < 8; ++attempt) {
+      if ((rc = reset_counters(ctx))) return rc;
+      broad_phase(ctx, 0);
+      if ((rc = read_counters(ctx))) return rc;
+      bool changed;
+      if ((rc = grow(ctx, &changed))) return rc;
+      if (!changed) break;
+    }
+  }
+  const Counters& c = *ctx->h_cnt;
+  int n = kind == ABD_PT ? c.n_pt : kind == ABD_EE ? c.n_ee : c.n_pg;
+  *count = n;
+  if (!out) return ABD_OK;
+  if (n > cap) return fail(ctx, ABD_E_CAPACITY, "candidate buffer too small");
+  if (kind == ABD_PG) {
+    std::vector<int> v(n);
+    if (n) HIPCHK(hipMemcpy(v.data(), S.cand_pg, sizeof(int) * n, hipMemcpyDeviceToHost));
+    std::sort(v.begin(), v.end());
+    std::copy(v.begin(), v.end(), out);
+  } else {
+    std::vector<int> v(3L * n);
+    if (n)
+      HIPCHK(hipMemcpy(v.data(), kind == ABD_PT ? S.cand_pt : S.cand_ee,
+                       sizeof(int) * 3 * n, hipMemcpyDeviceToHost));
+    std::vector<std::pair<int, int>> pr(n);
+    for (int i = 0; i < n; ++i) pr[i] = {v[3 * i], v[3 * i + 1]};
+    std::sort(pr.begin(), pr.end());
+    for (int i = 0; i < n; ++i) {
+      out[2 * i] = pr[i].first;
+      out[2 * i + 1] = pr[i].second;
+    }
+  }
+  return ABD_OK;
+}
+
+int abd_eval(abd_ctx* ctx, const double* q, double* E, double* g,
+             double* Hdiag, int64_t cap, int64_t* n_off, int32_t* off_ij,
+             double* Hoff, int64_t* n_active) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  Scene& S = ctx->S;
+  const int B = S.B;
+  std::vector<double> save(12L * B);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  HIPCHK(hipMemcpy(save.data(), S.q, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
+  if (q) HIPCHK(hipMemcpy(S.q, q, sizeof(double) * 12 * B, hipMemcpyHostToDevice));
+  rc = assemble(ctx);
+  if (!rc && E) rc = energy(ctx, 0.0, 1, 1, E);
+  if (!rc) {
+    if (n_active) *n_active = ctx->h_cnt->n_act;
+    if (g) HIPCHK(hipMemcpy(g, S.g, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
+    if (Hdiag)
+      HIPCHK(hipMemcpy(Hdiag, S.Hdiag, sizeof(double) * 144 * B, hipMemcpyDeviceToHost));
+    int nbp = ctx->h_cnt->n_bp;
+    std::vector<int> used(nbp);
+    std::vector<int2> bp(nbp);
+    if (nbp) {
+      HIPCHK(hipMemcpy(used.data(), S.slot_used, sizeof(int) * nbp, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(bp.data(), S.bp, sizeof(int2) * nbp, hipMemcpyDeviceToHost));
+    }
+    std::vector<std::pair<std::pair<int, int>, int>> list;
+    for (int p = 0; p < nbp; ++p)
+      if (used[p]) list.push_back({{bp[p].x, bp[p].y}, p});
+    std::sort(list.begin(), list.end());
+    if (n_off) *n_off = (int64_t)list.size();
+    if (off_ij && Hoff) {
+      if ((int64_t)list.size() > cap) {
+        rc = fail(ctx, ABD_E_CAPACITY, "off-diagonal buffer too small");
+      } else {
+        for (size_t i = 0; i < list.size(); ++i) {
+          off_ij[2 * i] = list[i].first.first;
+          off_ij[2 * i + 1] = list[i].first.second;
+          HIPCHK(hipMemcpy(Hoff + 144 * i, S.Hoff + 144L * list[i].second,
+                           sizeof(double) * 144, hipMemcpyDeviceToHost));
+        }
+      }
+    }
+  }
+  HIPCHK(hipMemcpy(S.q, save.data(), sizeof(double) * 12 * B, hipMemcpyHostToDevice));
+  return rc;
+}
+
+int abd_direction(abd_ctx* ctx, double* dq, int32_t* pcg_iters) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if ((rc = assemble(ctx))) return rc;
+  int it = 0;
+  if ((rc = linear_solve(ctx, &it))) return rc;
+  if (pcg_iters) *pcg_iters = it;
+  if (dq)
+    HIPCHK(hipMemcpy(dq, ctx->S.dq, sizeof(double) * 12 * ctx->S.B, hipMemcpyDeviceToHost));
+  return ABD_OK;
+}
+
+int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!dq || !alpha_max) return fail(ctx, ABD_E_INVALID_ARG, "ccd");
+  if ((rc = upload_dq(ctx, dq))) return rc;
+  if ((rc = swept_phase(ctx, true))) return rc;
+  *alpha_max = std::min(1.0, bits_to_double(ctx->h_cnt->min_toi));
+  return ABD_OK;
+}
+
+int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
+                     double* dE) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!dq || !dE) return fail(ctx, ABD_E_INVALID_ARG, "energy_delta");
+  if ((rc = upload_dq(ctx, dq))) return rc;
+  if ((rc = swept_phase(ctx, false))) return rc;
+  return energy(ctx, alpha, 0, 1, dE);
+}
+
+int abd_set_timing(abd_ctx* ctx, int32_t on) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  ctx->timing = on != 0;
+  return ABD_OK;
+}
+
+int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
+                   double* bytes) {
+  if (!ctx || stage < 0 || stage > 6) return ABD_E_INVALID_ARG;
+  (void)hipStreamSynchronize(ctx->st);
+  resolve_timing(ctx);
+  if (ms) *ms = ctx->t_ms[stage];
+  if (launches) *launches = ctx->t_n[stage];
+  if (bytes) *bytes = ctx->t_bytes[stage];
+  return ABD_OK;
+}
+
+int abd_reset_timing(abd_ctx* ctx) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  (void)hipStreamSynchronize(ctx->st);
+  resolve_timing(ctx);
+  for (int i = 0; i < 7; ++i) ctx->t_ms[i] = ctx->t_bytes[i] = 0.0, ctx->t_n[i] = 0;
+  return ABD_OK;
+}
+
+}  // extern "C"
