@@ -409,71 +409,74 @@ __device__ __forceinline__ void frame_coef(int kind, const signed char* l,
   }
 }
 
-/* packed symmetric 9x9 index, p <= q */
-__device__ __forceinline__ int sidx(int p, int q) {
-  if (p > q) { int t = p; p = q; q = t; }
-  return 9 * p - (p * (p - 1)) / 2 + (q - p);
+/* packed symmetric 9x9 index */
+__host__ __device__ constexpr int sidx(int p, int q) {
+  return p <= q ? 9 * p - (p * (p - 1)) / 2 + (q - p)
+                : 9 * q - (q * (q - 1)) / 2 + (p - q);
 }
 
 /* ------------------------------------------------------------------ */
-/* cyclic Jacobi on a packed symmetric 9x9 held per thread in LDS        */
-/* (element-major: K[idx * ld + lane]) and projection to PSD in place:  */
-/* K <- V max(Lambda, 0) V^T.  V is scratch [81][ld].                    */
+/* cyclic Jacobi on a packed symmetric 9x9 held in registers (every     */
+/* index is a compile-time constant after unrolling), then projection   */
+/* to PSD in place: K <- V max(Lambda, 0) V^T.  Rotations in row order, */
+/* stop when the off-diagonal mass is below 1e-30 of the total.         */
 /* ------------------------------------------------------------------ */
-__device__ inline void psd9_lds(double* K, double* V, int ld, int lane) {
-#define KK(p, q) K[sidx(p, q) * ld + lane]
-#define VV(p, q) V[((p) * 9 + (q)) * ld + lane]
-  for (int p = 0; p < 9; ++p)
-    for (int q = 0; q < 9; ++q) VV(p, q) = (p == q) ? 1.0 : 0.0;
+__device__ __forceinline__ void psd9_reg(double* K) {
+  double V[81];
+#pragma unroll
+  for (int i = 0; i < 81; ++i) V[i] = (i / 9 == i % 9) ? 1.0 : 0.0;
   for (int sweep = 0; sweep < 60; ++sweep) {
     double off = 0.0, dia = 0.0;
+#pragma unroll
     for (int p = 0; p < 9; ++p) {
-      double d = KK(p, p);
-      dia += d * d;
-      for (int q = p + 1; q < 9; ++q) {
-        double a = KK(p, q);
-        off += a * a;
-      }
+      dia += K[sidx(p, p)] * K[sidx(p, p)];
+#pragma unroll
+      for (int q = p + 1; q < 9; ++q) off += K[sidx(p, q)] * K[sidx(p, q)];
     }
     if (off == 0.0 || off <= 1e-30 * (dia + 2.0 * off)) break;
+#pragma unroll
     for (int p = 0; p < 8; ++p)
+#pragma unroll
       for (int q = p + 1; q < 9; ++q) {
-        double apq = KK(p, q);
-        if (apq == 0.0) continue;
-        double app = KK(p, p), aqq = KK(q, q);
-        double theta = (aqq - app) / (2.0 * apq);
-        double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
-        if (theta < 0.0) t = -t;
-        double c = 1.0 / sqrt(t * t + 1.0);
-        double s = t * c;
-        for (int r = 0; r < 9; ++r) {
-          if (r == p || r == q) continue;
-          double krp = KK(r, p), krq = KK(r, q);
-          KK(r, p) = c * krp - s * krq;
-          KK(r, q) = s * krp + c * krq;
-        }
-        KK(p, p) = app - t * apq;
-        KK(q, q) = aqq + t * apq;
-        KK(p, q) = 0.0;
-        for (int r = 0; r < 9; ++r) {
-          double vrp = VV(r, p), vrq = VV(r, q);
-          VV(r, p) = c * vrp - s * vrq;
-          VV(r, q) = s * vrp + c * vrq;
+        const double apq = K[sidx(p, q)];
+        if (apq != 0.0) {
+          const double app = K[sidx(p, p)], aqq = K[sidx(q, q)];
+          const double theta = (aqq - app) / (2.0 * apq);
+          double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
+          t = theta < 0.0 ? -t : t;
+          const double c = 1.0 / sqrt(t * t + 1.0);
+          const double s = t * c;
+#pragma unroll
+          for (int r = 0; r < 9; ++r) {
+            if (r == p || r == q) continue;
+            const double krp = K[sidx(r, p)], krq = K[sidx(r, q)];
+            K[sidx(r, p)] = c * krp - s * krq;
+            K[sidx(r, q)] = s * krp + c * krq;
+          }
+          K[sidx(p, p)] = app - t * apq;
+          K[sidx(q, q)] = aqq + t * apq;
+          K[sidx(p, q)] = 0.0;
+#pragma unroll
+          for (int r = 0; r < 9; ++r) {
+            const double vrp = V[9 * r + p], vrq = V[9 * r + q];
+            V[9 * r + p] = c * vrp - s * vrq;
+            V[9 * r + q] = s * vrp + c * vrq;
+          }
         }
       }
   }
   double lam[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) lam[k] = fmax(KK(k, k), 0.0);
+  for (int k = 0; k < 9; ++k) lam[k] = fmax(K[sidx(k, k)], 0.0);
+#pragma unroll
   for (int p = 0; p < 9; ++p)
+#pragma unroll
     for (int q = p; q < 9; ++q) {
       double v = 0.0;
 #pragma unroll
-      for (int k = 0; k < 9; ++k) v += VV(p, k) * lam[k] * VV(q, k);
-      KK(p, q) = v;
+      for (int k = 0; k < 9; ++k) v += V[9 * p + k] * lam[k] * V[9 * q + k];
+      K[sidx(p, q)] = v;
     }
-#undef KK
-#undef VV
 }
 
 /* ------------------------------------------------------------------ */
@@ -548,8 +551,8 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid,
 int pcg_max_grid();
 void launch_dq_norm(const Scene& S, hipStream_t st);
 void launch_ccd(const Scene& S, hipStream_t st);
-void launch_energy(const Scene& S, double alpha, int with_pairs, double* out,
-                   hipStream_t st);
+void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
+                   int alpha_from_toi, double* out, hipStream_t st);
 void launch_update_q(const Scene& S, double alpha, hipStream_t st);
 void launch_scale(const Scene& S, double* out6, hipStream_t st);
 

@@ -117,10 +117,7 @@ __global__ void k_scale(Scene S, unsigned long long* out6) {
  * 1/kappa_b, and the ADMM penalty rho/2 |q - z + u|^2 of a shared body.
  * Writes g [B][12] and Hdiag [B][144] (static bodies: 0 and identity). */
 __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
-  __shared__ double K[45 * 64];
-  __shared__ double V[81 * 64];
-  const int lane = threadIdx.x;
-  const int b = blockIdx.x * 64 + lane;
+  const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= S.B) return;
   double* Hd = S.Hdiag + 144 * b;
   double* g = S.g + 12 * b;
@@ -130,19 +127,24 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
     return;
   }
   double q[12], dq[12];
+#pragma unroll
   for (int i = 0; i < 12; ++i) {
     q[i] = S.q[12 * b + i];
     dq[i] = q[i] - S.qtilde[12 * b + i];
   }
   double M[16];
+#pragma unroll
   for (int i = 0; i < 16; ++i) M[i] = S.Mhat[16 * b + i];
   const double wb = S.wbody[b];
   const double c = wb * S.dt * S.dt * S.kappa_A * S.vol[b];
   const double* A = q + 3;
   double Sm[9], AtA[9];
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int m = 0; m < 3; ++m) {
       double s = 0.0, t = 0.0;
+#pragma unroll
       for (int n = 0; n < 3; ++n) {
         s += A[3 * k + n] * A[3 * m + n];
         t += A[3 * n + k] * A[3 * n + m];
@@ -151,41 +153,55 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
       AtA[3 * k + m] = t;
     }
   /* orthogonality Hessian 4[d_kp (A^T A)_ql + A_kq A_pl + S_kp d_lq] */
+  double K[45];
+#pragma unroll
   for (int a = 0; a < 9; ++a)
+#pragma unroll
     for (int e = a; e < 9; ++e) {
-      int k = a / 3, l = a % 3, p = e / 3, qq = e % 3;
+      const int k = a / 3, l = a % 3, p = e / 3, qq = e % 3;
       double h = A[3 * k + qq] * A[3 * p + l];
       if (k == p) h += AtA[3 * qq + l];
       if (l == qq) h += Sm[3 * k + p];
-      K[sidx(a, e) * 64 + lane] = 4.0 * h;
+      K[sidx(a, e)] = 4.0 * h;
     }
-  psd9_lds(K, V, 64, lane);
+  psd9_reg(K);
   /* gradient */
+  double gl[12];
+#pragma unroll
   for (int i = 0; i < 3; ++i)
+#pragma unroll
     for (int k = 0; k < 4; ++k) {
       double v = 0.0;
+#pragma unroll
       for (int l = 0; l < 4; ++l) v += M[4 * k + l] * dq[dofi(i, l)];
-      g[dofi(i, k)] = wb * v;
+      gl[dofi(i, k)] = wb * v;
     }
+#pragma unroll
   for (int k = 0; k < 3; ++k)
+#pragma unroll
     for (int l = 0; l < 3; ++l) {
       double v = 0.0;
+#pragma unroll
       for (int m = 0; m < 3; ++m) v += Sm[3 * k + m] * A[3 * m + l];
-      g[3 + 3 * k + l] += c * 4.0 * v;
+      gl[3 + 3 * k + l] += c * 4.0 * v;
     }
-  int sh = S.shared_slot[b];
-  double rho = sh >= 0 ? S.rho[sh] : 0.0;
+  const int sh = S.shared_slot[b];
+  const double rho = sh >= 0 ? S.rho[sh] : 0.0;
   if (sh >= 0)
+#pragma unroll
     for (int i = 0; i < 12; ++i)
-      g[i] += rho * (q[i] - S.z[12 * sh + i] + S.u[12 * sh + i]);
+      gl[i] += rho * (q[i] - S.z[12 * sh + i] + S.u[12 * sh + i]);
+#pragma unroll
+  for (int i = 0; i < 12; ++i) g[i] = gl[i];
   /* Hessian */
+#pragma unroll
   for (int r = 0; r < 12; ++r)
+#pragma unroll
     for (int cc = 0; cc < 12; ++cc) {
-      int i, k, j, l;
-      dof_split(r, i, k);
-      dof_split(cc, j, l);
+      const int i = r < 3 ? r : (r - 3) / 3, k = r < 3 ? 0 : (r - 3) % 3 + 1;
+      const int j = cc < 3 ? cc : (cc - 3) / 3, l = cc < 3 ? 0 : (cc - 3) % 3 + 1;
       double h = (i == j) ? wb * M[4 * k + l] : 0.0;
-      if (r >= 3 && cc >= 3) h += c * K[sidx(r - 3, cc - 3) * 64 + lane];
+      if (r >= 3 && cc >= 3) h += c * K[sidx(r - 3, cc - 3)];
       if (r == cc) h += rho;
       Hd[12 * r + cc] = h;
     }
@@ -558,11 +574,11 @@ __device__ inline void d_tri(const double* a, const double* b,
 }
 
 /* Map derivatives over k feature vectors (frame coefficients C[k][3]) into
- * the y frame: g_y (9) and the packed Hessian written to LDS. */
+ * the y frame: g_y (9) and the packed 9x9 Hessian K (45). */
 template <int k>
-__device__ inline void to_frame(const double (*C)[3], const double* G,
-                                const double* H, double* gy, double* K,
-                                int lane) {
+__device__ __forceinline__ void to_frame(const double (*C)[3], const double* G,
+                                         const double* H, double* gy,
+                                         double* K) {
 #pragma unroll
   for (int r = 0; r < 3; ++r)
 #pragma unroll
@@ -576,51 +592,145 @@ __device__ inline void to_frame(const double (*C)[3], const double* G,
   for (int p = 0; p < 9; ++p)
 #pragma unroll
     for (int q = p; q < 9; ++q) {
-      int r = p / 3, i = p % 3, u = q / 3, i2 = q % 3;
+      const int r = p / 3, i = p % 3, u = q / 3, i2 = q % 3;
       double v = 0.0;
 #pragma unroll
       for (int j = 0; j < k; ++j)
 #pragma unroll
         for (int l = 0; l < k; ++l)
           v += C[j][r] * C[l][u] * H[(3 * j + i) * (3 * k) + 3 * l + i2];
-      K[sidx(p, q) * 64 + lane] = v;
+      K[sidx(p, q)] = v;
     }
 }
 
+/* Barrier gradient g_y and PSD-projected Hessian K (packed, reduced frame)
+ * of one PT/EE pair with slot positions x; also returns the distance. */
+__device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int ei,
+                                               int ej, const double* x,
+                                               double w, double* gy,
+                                               double* K) {
+  double D;
+  Feat f = classify(kind, x, D);
+  const double d = sqrt(D);
+  double b, b1, b2;
+  barrier3(d, S.dhat, b, b1, b2);
+  double gD[9];
+  if (f.type == F_PP) {
+    double C[1][3], r[3], G[3], H[9];
+    frame_coef(kind, f.l[0], C[0]);
+    comb4(f.l[0], x, r);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      G[i] = 2.0 * r[i];
+#pragma unroll
+      for (int j = 0; j < 3; ++j) H[i * 3 + j] = i == j ? 2.0 : 0.0;
+    }
+    to_frame<1>(C, G, H, gD, K);
+  } else if (f.type == F_PE) {
+    double C[2][3], av[3], ev[3], F, G[6], H[36];
+    frame_coef(kind, f.l[0], C[0]);
+    frame_coef(kind, f.l[1], C[1]);
+    comb4(f.l[0], x, av);
+    comb4(f.l[1], x, ev);
+    d_pe(av, ev, F, G, H);
+    to_frame<2>(C, G, H, gD, K);
+  } else {
+    double C[3][3], av[3], bv[3], cv[3], F, G[9], H[81];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) frame_coef(kind, f.l[j], C[j]);
+    comb4(f.l[0], x, av);
+    comb4(f.l[1], x, bv);
+    comb4(f.l[2], x, cv);
+    d_tri(av, bv, cv, F, G, H);
+    to_frame<3>(C, G, H, gD, K);
+  }
+  /* mollifier m(c) on c = |u x v|^2 (u = y_1, v = y_2 of the EE frame) */
+  double m = 1.0, m1 = 0.0, m2 = 0.0, gc[9], Hc[36];
+  bool moll = false;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) gc[i] = 0.0;
+  if (kind == C_EE && S.mollify) {
+    const double ex = MOLL_EPS * S.erest2[ei] * S.erest2[ej];
+    double u[3], v[3], cval, G6[6];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      u[i] = x[3 + i] - x[i];
+      v[i] = x[9 + i] - x[6 + i];
+    }
+    d_cross(u, v, cval, G6, Hc);
+    if (cval < ex) {
+      moll = true;
+      const double rr = cval / ex;
+      m = (2.0 - rr) * rr;
+      m1 = 2.0 * (1.0 - rr) / ex;
+      m2 = -2.0 / (ex * ex);
+#pragma unroll
+      for (int i = 0; i < 6; ++i) gc[3 + i] = G6[i];
+    }
+  }
+  const double i2d = 0.5 / d, i4d3 = 0.25 / (d * d * d);
+  double gd[9], Gs[9];
+#pragma unroll
+  for (int p = 0; p < 9; ++p) {
+    gd[p] = gD[p] * i2d;
+    Gs[p] = sqrt(frame_norm2(kind, p / 3));
+    gy[p] = w * (m * b1 * gd[p] + (moll ? b * m1 * gc[p] : 0.0));
+  }
+#pragma unroll
+  for (int p = 0; p < 9; ++p)
+#pragma unroll
+    for (int q = p; q < 9; ++q) {
+      const double hd = K[sidx(p, q)] * i2d - gD[p] * gD[q] * i4d3;
+      double h = m * (b2 * gd[p] * gd[q] + b1 * hd);
+      if (moll) {
+        const double hc = (p >= 3 && q >= 3) ? Hc[(p - 3) * 6 + (q - 3)] : 0.0;
+        h += b1 * m1 * (gc[p] * gd[q] + gd[p] * gc[q]) +
+             b * (m2 * gc[p] * gc[q] + m1 * hc);
+      }
+      K[sidx(p, q)] = w * h * Gs[p] * Gs[q];
+    }
+  psd9_reg(K);
+#pragma unroll
+  for (int p = 0; p < 9; ++p)
+#pragma unroll
+    for (int q = p; q < 9; ++q) K[sidx(p, q)] /= Gs[p] * Gs[q];
+}
+
 /* One wavefront of 64 active pairs.  Phase 1 (a lane per pair): distance
- * feature, barrier gradient and Hessian in the reduced frame, PSD
- * projection (9x9 Jacobi in LDS), and the frame-to-body maps W.  Phase 2
- * (all lanes per pair): body-space gradient and 12x12 blocks, accumulated
- * with FP64 atomics into g, Hdiag and Hoff. */
+ * feature, barrier gradient and Hessian in the reduced frame with its PSD
+ * projection, and the frame-to-body maps W.  Phase 2 (all lanes per pair):
+ * T = H_y W_Y, then the body-space gradient and 12x12 blocks W_X^T T,
+ * accumulated with FP64 atomics into g, Hdiag and Hoff. */
 __global__ __launch_bounds__(64) void k_assemble(Scene S) {
-  __shared__ double K[45 * 64];
-  __shared__ double V[81 * 64];
+  __shared__ double KL[45 * 64];
+  __shared__ double GW[33 * 64]; /* rows 0..8 g_y, 9..20 W_A, 21..32 W_B */
+  __shared__ double TB[216];
   __shared__ int meta[3 * 64];
   const int lane = threadIdx.x;
   const int nact = min(S.cnt->n_act, S.cap_act);
   for (int base = blockIdx.x * 64; base < nact; base += gridDim.x * 64) {
     const int t = base + lane;
-    double gy[9];
-    double Wa[12], Wb[12];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) gy[i] = 0.0;
-#pragma unroll
-    for (int i = 0; i < 12; ++i) Wa[i] = Wb[i] = 0.0;
     int ba = -1, bb = -1, slot = -1;
     if (t < nact) {
-      int4 a = S.act[t];
-      int kind = a.x;
+      const int4 a = S.act[t];
+      const int kind = a.x;
       slot = a.w;
-      for (int p = 0; p < 45; ++p) K[p * 64 + lane] = 0.0;
+      double gy[9], K[45], Wa[12], Wb[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) Wa[i] = Wb[i] = 0.0;
       if (kind == C_PG) {
-        int v = a.y;
+        const int v = a.y;
         double x[3];
         vertex_pos(S, v, x);
         double b, b1, b2;
         barrier3(x[1] - S.ground_y, S.dhat, b, b1, b2);
-        double w = pair_weight(S, &v, 1);
+        const double w = pair_weight(S, &v, 1);
+#pragma unroll
+        for (int i = 0; i < 9; ++i) gy[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < 45; ++i) K[i] = 0.0;
         gy[1] = w * b1;
-        K[sidx(1, 1) * 64 + lane] = w * b2;
+        K[sidx(1, 1)] = w * b2;
         ba = S.vbody[v];
         Wa[0] = 1.0;
         Wa[1] = S.xbar[v]; Wa[2] = S.xbar[S.V + v]; Wa[3] = S.xbar[2 * S.V + v];
@@ -628,108 +738,40 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
         int vid[4];
         pair_vertices(S, kind, a.y, a.z, vid);
         double x[12];
+#pragma unroll
         for (int s = 0; s < 4; ++s) vertex_pos(S, vid[s], x + 3 * s);
-        double D;
-        Feat f = classify(kind, x, D);
-        double d = sqrt(D);
-        double w = pair_weight(S, vid, 4);
-        double b, b1, b2;
-        barrier3(d, S.dhat, b, b1, b2);
-        /* derivatives of D in the frame, Hessian into K */
-        double gD[9];
-        if (f.type == F_PP) {
-          double C[1][3], r[3], G[3], H[9];
-          frame_coef(kind, f.l[0], C[0]);
-          comb4(f.l[0], x, r);
-          for (int i = 0; i < 3; ++i) {
-            G[i] = 2.0 * r[i];
-            for (int j = 0; j < 3; ++j) H[i * 3 + j] = i == j ? 2.0 : 0.0;
-          }
-          to_frame<1>(C, G, H, gD, K, lane);
-        } else if (f.type == F_PE) {
-          double C[2][3], av[3], ev[3], F, G[6], H[36];
-          frame_coef(kind, f.l[0], C[0]);
-          frame_coef(kind, f.l[1], C[1]);
-          comb4(f.l[0], x, av);
-          comb4(f.l[1], x, ev);
-          d_pe(av, ev, F, G, H);
-          to_frame<2>(C, G, H, gD, K, lane);
-        } else {
-          double C[3][3], av[3], bv[3], cv[3], F, G[9], H[81];
-          for (int j = 0; j < 3; ++j) frame_coef(kind, f.l[j], C[j]);
-          comb4(f.l[0], x, av);
-          comb4(f.l[1], x, bv);
-          comb4(f.l[2], x, cv);
-          d_tri(av, bv, cv, F, G, H);
-          to_frame<3>(C, G, H, gD, K, lane);
-        }
-        /* mollifier m(c) on c = |u x v|^2 (u = y_1, v = y_2 of the EE frame) */
-        double m = 1.0, m1 = 0.0, m2 = 0.0, gc[9], Hc[36];
-        bool moll = false;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) gc[i] = 0.0;
-        if (kind == C_EE && S.mollify) {
-          double ex = MOLL_EPS * S.erest2[a.y] * S.erest2[a.z];
-          double u[3], v[3], cval, G6[6];
-          for (int i = 0; i < 3; ++i) {
-            u[i] = x[3 + i] - x[i];
-            v[i] = x[9 + i] - x[6 + i];
-          }
-          d_cross(u, v, cval, G6, Hc);
-          if (cval < ex) {
-            moll = true;
-            double rr = cval / ex;
-            m = (2.0 - rr) * rr;
-            m1 = 2.0 * (1.0 - rr) / ex;
-            m2 = -2.0 / (ex * ex);
-            for (int i = 0; i < 6; ++i) gc[3 + i] = G6[i];
-          }
-        }
-        double i2d = 0.5 / d, i4d3 = 0.25 / (d * d * d);
-        double gd[9], Gs[9];
-#pragma unroll
-        for (int p = 0; p < 9; ++p) {
-          gd[p] = gD[p] * i2d;
-          Gs[p] = sqrt(frame_norm2(kind, p / 3));
-          gy[p] = w * (m * b1 * gd[p] + (moll ? b * m1 * gc[p] : 0.0));
-        }
-        for (int p = 0; p < 9; ++p)
-          for (int q = p; q < 9; ++q) {
-            double hD = K[sidx(p, q) * 64 + lane];
-            double hd = hD * i2d - gD[p] * gD[q] * i4d3;
-            double h = m * (b2 * gd[p] * gd[q] + b1 * hd);
-            if (moll) {
-              double hc = (p >= 3 && q >= 3) ? Hc[(p - 3) * 6 + (q - 3)] : 0.0;
-              h += b1 * m1 * (gc[p] * gd[q] + gd[p] * gc[q]) +
-                   b * (m2 * gc[p] * gc[q] + m1 * hc);
-            }
-            K[sidx(p, q) * 64 + lane] = w * h * Gs[p] * Gs[q];
-          }
-        psd9_lds(K, V, 64, lane);
-        for (int p = 0; p < 9; ++p)
-          for (int q = p; q < 9; ++q) K[sidx(p, q) * 64 + lane] /= Gs[p] * Gs[q];
-        /* W_side[r][k] = sum_{slots s of the side} f_r[s] xhat_s[k] */
-        int sideB0 = kind == C_PT ? 1 : 2;
+        const double w = pair_weight(S, vid, 4);
+        pair_frame_derivs(S, kind, a.y, a.z, x, w, gy, K);
+        /* W_side[r][k] = sum over the side's slots s of f_r[s] xhat_s[k] */
+        const int sideB0 = kind == C_PT ? 1 : 2;
         ba = S.vbody[vid[0]];
         bb = S.vbody[vid[sideB0]];
+#pragma unroll
         for (int s = 0; s < 4; ++s) {
-          double xh[4] = {1.0, S.xbar[vid[s]], S.xbar[S.V + vid[s]],
-                          S.xbar[2 * S.V + vid[s]]};
-          double* W = s < sideB0 ? Wa : Wb;
+          const double xh[4] = {1.0, S.xbar[vid[s]], S.xbar[S.V + vid[s]],
+                                S.xbar[2 * S.V + vid[s]]};
+#pragma unroll
           for (int r = 0; r < 3; ++r) {
-            double fr = frame_row(kind, r, s);
-            for (int k = 0; k < 4; ++k) W[4 * r + k] += fr * xh[k];
+            const double fr = frame_row(kind, r, s);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+              if (s < sideB0) Wa[4 * r + k] += fr * xh[k];
+              else Wb[4 * r + k] += fr * xh[k];
+            }
           }
         }
       }
       if (ba >= 0 && S.kind[ba] != 0) ba = -1;
       if (bb >= 0 && S.kind[bb] != 0) bb = -1;
-    }
-    /* publish per-pair data: g_y and W in V rows 0..32 */
-    for (int i = 0; i < 9; ++i) V[i * 64 + lane] = gy[i];
-    for (int i = 0; i < 12; ++i) {
-      V[(9 + i) * 64 + lane] = Wa[i];
-      V[(21 + i) * 64 + lane] = Wb[i];
+#pragma unroll
+      for (int i = 0; i < 45; ++i) KL[i * 64 + lane] = K[i];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) GW[i * 64 + lane] = gy[i];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) {
+        GW[(9 + i) * 64 + lane] = Wa[i];
+        GW[(21 + i) * 64 + lane] = Wb[i];
+      }
     }
     meta[lane] = ba;
     meta[64 + lane] = bb;
@@ -737,23 +779,36 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
     __syncthreads();
     const int npairs = min(64, nact - base);
     for (int j = 0; j < npairs; ++j) {
-      int A = meta[j], Bq = meta[64 + j], sl = meta[128 + j];
+      const int A = meta[j], Bq = meta[64 + j], sl = meta[128 + j];
       if (A < 0 && Bq < 0) continue;
+      /* T_Y[(r,i)][(i2,l)] = sum_u H[(r,i),(u,i2)] W_Y[u][l] */
+      for (int e = lane; e < 216; e += 64) {
+        const int Y = e / 108, f = e % 108, ri = f / 12, i2 = (f % 12) / 4,
+                  l = f % 4;
+        const int wo = Y ? 21 : 9;
+        double v = 0.0;
+#pragma unroll
+        for (int u = 0; u < 3; ++u)
+          v += KL[sidx(ri, 3 * u + i2) * 64 + j] * GW[(wo + 4 * u + l) * 64 + j];
+        TB[e] = v;
+      }
       /* gradient */
       if (lane < 24) {
-        int side = lane / 12, dd = lane % 12;
-        int body = side ? Bq : A;
+        const int side = lane / 12, dd = lane % 12;
+        const int body = side ? Bq : A;
         if (body >= 0) {
           int i, k;
           dof_split(dd, i, k);
-          int wo = side ? 21 : 9;
+          const int wo = side ? 21 : 9;
           double v = 0.0;
+#pragma unroll
           for (int r = 0; r < 3; ++r)
-            v += V[(wo + 4 * r + k) * 64 + j] * V[(3 * r + i) * 64 + j];
+            v += GW[(wo + 4 * r + k) * 64 + j] * GW[(3 * r + i) * 64 + j];
           atomicAdd(S.g + 12 * body + dd, v);
         }
       }
-      /* blocks: 0 = (A,A), 1 = (B,B), 2 = (lo,hi) */
+      __syncthreads();
+      /* blocks: (A,A), (B,B), (lo,hi) = W_X^T T_Y */
       for (int blk = 0; blk < 3; ++blk) {
         int X, Y;
         double* dst;
@@ -769,21 +824,20 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
           dst = S.Hoff + 144 * (size_t)sl;
           if (lane == 0) S.slot_used[sl] = 1;
         }
-        const int wx = X ? 21 : 9, wy = Y ? 21 : 9;
+        const int wx = X ? 21 : 9;
         for (int e = lane; e < 144; e += 64) {
           int i, k, i2, l;
           dof_split(e / 12, i, k);
           dof_split(e % 12, i2, l);
           double v = 0.0;
-          for (int r = 0; r < 3; ++r) {
-            double wr = V[(wx + 4 * r + k) * 64 + j];
-            for (int u = 0; u < 3; ++u)
-              v += wr * K[sidx(3 * r + i, 3 * u + i2) * 64 + j] *
-                   V[(wy + 4 * u + l) * 64 + j];
-          }
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            v += GW[(wx + 4 * r + k) * 64 + j] *
+                 TB[Y * 108 + (3 * r + i) * 12 + i2 * 4 + l];
           atomicAdd(dst + e, v);
         }
       }
+      __syncthreads();
     }
     __syncthreads();
   }
@@ -1163,8 +1217,15 @@ __device__ double pair_energy_at(const Scene& S, int kind, int i, int j,
 }
 
 __global__ __launch_bounds__(256) void k_energy(Scene S, double alpha,
-                                                int mode, int with_pairs) {
+                                                int mode, int with_pairs,
+                                                int alpha_from_toi) {
   __shared__ double red[4];
+  if (alpha_from_toi) {
+    const double toi = __longlong_as_double(
+        (long long)__hip_atomic_load(&S.cnt->min_toi, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_AGENT));
+    alpha *= fmin(1.0, toi);
+  }
   const int npt = with_pairs ? min(S.cnt->n_pt, S.cap_pt) : 0;
   const int nee = with_pairs ? min(S.cnt->n_ee, S.cap_ee) : 0;
   const int npg = with_pairs ? min(S.cnt->n_pg, S.cap_pg) : 0;
@@ -1303,10 +1364,10 @@ void launch_ccd(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_ccd, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
 }
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
-                   double* out, hipStream_t st) {
+                   int alpha_from_toi, double* out, hipStream_t st) {
   int mode = mode_with_pairs & 1, with_pairs = (mode_with_pairs >> 1) & 1;
   hipLaunchKernelGGL(k_energy, dim3(ENERGY_BLOCKS), dim3(256), 0, st, S, alpha,
-                     mode, with_pairs);
+                     mode, with_pairs, alpha_from_toi);
   hipLaunchKernelGGL(k_reduce, dim3(1), dim3(256), 0, st, S, ENERGY_BLOCKS, out);
 }
 void launch_update_q(const Scene& S, double alpha, hipStream_t st) {

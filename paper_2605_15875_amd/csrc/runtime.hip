@@ -255,21 +255,38 @@ Counters fresh_counters() {
   return c;
 }
 
-int reset_counters(abd_ctx* ctx) {
-  *ctx->h_cnt = fresh_counters();
-  HIPCHK(hipMemcpyAsync(ctx->S.cnt, ctx->h_cnt, sizeof(Counters),
+/* the counter blocks live in one device array: [0] static phase, [1] swept
+ * phase; ctx->h_cnt mirrors both in pinned memory */
+int reset_counters(abd_ctx* ctx, int which = 0) {
+  ctx->h_cnt[which] = fresh_counters();
+  HIPCHK(hipMemcpyAsync(ctx->S.cnt + which, ctx->h_cnt + which,
+                        sizeof(Counters), hipMemcpyHostToDevice, ctx->st));
+  return ABD_OK;
+}
+
+int reset_both(abd_ctx* ctx) {
+  ctx->h_cnt[0] = fresh_counters();
+  ctx->h_cnt[1] = fresh_counters();
+  HIPCHK(hipMemcpyAsync(ctx->S.cnt, ctx->h_cnt, 2 * sizeof(Counters),
                         hipMemcpyHostToDevice, ctx->st));
   return ABD_OK;
 }
 
-int read_counters(abd_ctx* ctx) {
-  HIPCHK(hipMemcpyAsync(ctx->h_cnt, ctx->S.cnt, sizeof(Counters),
-                        hipMemcpyDeviceToHost, ctx->st));
+int read_counters(abd_ctx* ctx, int which = 0, int n = 1) {
+  HIPCHK(hipMemcpyAsync(ctx->h_cnt + which, ctx->S.cnt + which,
+                        n * sizeof(Counters), hipMemcpyDeviceToHost, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
   resolve_timing(ctx);
-  if (ctx->h_cnt->err)
-    return fail(ctx, ABD_E_DEVICE, "device barrier timed out");
+  for (int i = which; i < which + n; ++i)
+    if (ctx->h_cnt[i].err)
+      return fail(ctx, ABD_E_DEVICE, "device barrier timed out");
   return ABD_OK;
+}
+
+Scene swept_scene(const abd_ctx* ctx) {
+  Scene s = ctx->S;
+  s.cnt = ctx->S.cnt + 1;
+  return s;
 }
 
 double bits_to_double(unsigned long long b) {
@@ -279,9 +296,8 @@ double bits_to_double(unsigned long long b) {
 }
 
 /* ---------------- capacities ---------------- */
-int grow(abd_ctx* ctx, bool* changed) {
+int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
   Scene& S = ctx->S;
-  const Counters& c = *ctx->h_cnt;
   *changed = false;
   auto need = [](int have, int n) { return n > have; };
   int rc;
@@ -336,9 +352,8 @@ int grow(abd_ctx* ctx, bool* changed) {
 }
 
 /* ---------------- phases ---------------- */
-void broad_phase(abd_ctx* ctx, int swept) {
+void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
   StageTimer t(ctx, 1);
-  const Scene& S = ctx->S;
   launch_boxes(S, swept, ctx->st);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
@@ -355,26 +370,78 @@ __global__ void k_clear_slots(Scene S) {
   }
 }
 
+/* static phase on the stream: body terms, broad phase, barrier assembly */
+void launch_static(abd_ctx* ctx) {
+  const Scene& S = ctx->S;
+  {
+    StageTimer t(ctx, 0, (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96));
+    launch_body_terms(S, ctx->st);
+  }
+  broad_phase(ctx, S, 0);
+  {
+    StageTimer t(ctx, 2);
+    launch_filter(S, ctx->st);
+    hipLaunchKernelGGL(k_clear_slots, dim3(512), dim3(256), 0, ctx->st, S);
+    launch_assemble(S, 0, ctx->st);
+  }
+}
+
+/* block-Jacobi PCG and the Newton stop norm on the stream */
+int launch_solve(abd_ctx* ctx) {
+  const Scene& S = ctx->S;
+  {
+    StageTimer t(ctx, 6);
+    HIPCHK(hipMemsetAsync(S.row_cnt, 0, sizeof(int) * (S.B + 1), ctx->st));
+    launch_bsr(S, ctx->st);
+    launch_block_inverse(S, ctx->st);
+    /* the barrier counter and dot accumulators start at zero (the counter
+     * block was reset with the static phase) */
+    HIPCHK(hipMemsetAsync(S.acc, 0, sizeof(double) * 16, ctx->st));
+  }
+  const int grid = std::min(ctx->pcg_grid, std::max(1, (S.B + 15) / 16));
+  StageTimer t(ctx, 3);
+  if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, grid, ctx->st))
+    return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
+  launch_dq_norm(S, ctx->st);
+  return ABD_OK;
+}
+
+void account_pcg_bytes(abd_ctx* ctx) {
+  if (!ctx->timing) return;
+  const Scene& S = ctx->S;
+  /* algorithmic bytes of the PCG launch: per iteration the diagonal and
+   * used off-diagonal blocks once, the block inverses once and seven
+   * length-12B vectors */
+  const double per = (double)(S.B + ctx->h_cnt[0].n_rows_used / 2) * 1152.0 +
+                     (double)S.B * 1152.0 + 7.0 * 12.0 * S.B * 8.0;
+  ctx->t_bytes[3] += per * ctx->h_cnt[0].pcg_iters;
+}
+
+/* swept phase on the stream: broad phase over [q, q + dq], CCD, and the
+ * energy difference at alpha_scale * min(1, TOI) */
+void launch_swept(abd_ctx* ctx, bool ccd, bool energy_at_toi) {
+  const Scene Ssw = swept_scene(ctx);
+  broad_phase(ctx, Ssw, 1);
+  if (ccd) {
+    StageTimer t(ctx, 4);
+    launch_ccd(Ssw, ctx->st);
+  }
+  if (energy_at_toi) {
+    StageTimer t(ctx, 5);
+    launch_energy(Ssw, 1.0, 0 | (1 << 1), 1,
+                  ctx->S.partials + ctx->S.cap_partials - 1, ctx->st);
+  }
+}
+
 /* gradient and Hessian at the current q (static phase), counters read */
 int assemble(abd_ctx* ctx) {
-  const Scene& S = ctx->S;
   for (int attempt = 0; attempt < 8; ++attempt) {
-    int rc = reset_counters(ctx);
+    int rc = reset_counters(ctx, 0);
     if (rc) return rc;
-    {
-      StageTimer t(ctx, 0, (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96));
-      launch_body_terms(S, ctx->st);
-    }
-    broad_phase(ctx, 0);
-    {
-      StageTimer t(ctx, 2);
-      launch_filter(S, ctx->st);
-      hipLaunchKernelGGL(k_clear_slots, dim3(512), dim3(256), 0, ctx->st, S);
-      launch_assemble(S, 0, ctx->st);
-    }
-    if ((rc = read_counters(ctx))) return rc;
+    launch_static(ctx);
+    if ((rc = read_counters(ctx, 0))) return rc;
     bool changed = false;
-    if ((rc = grow(ctx, &changed))) return rc;
+    if ((rc = grow(ctx, ctx->h_cnt[0], &changed))) return rc;
     if (!changed) return ABD_OK;
   }
   return fail(ctx, ABD_E_OOM, "capacity growth did not settle");
@@ -382,34 +449,11 @@ int assemble(abd_ctx* ctx) {
 
 /* PCG on the assembled system; counters read */
 int linear_solve(abd_ctx* ctx, int* iters) {
-  const Scene& S = ctx->S;
-  {
-    StageTimer t(ctx, 6);
-    HIPCHK(hipMemsetAsync(S.row_cnt, 0, sizeof(int) * (S.B + 1), ctx->st));
-    launch_bsr(S, ctx->st);
-    launch_block_inverse(S, ctx->st);
-    /* the barrier counter and dot accumulators start at zero (the
-     * counter block was reset by the assembly) */
-    HIPCHK(hipMemsetAsync(S.acc, 0, sizeof(double) * 16, ctx->st));
-  }
-  int grid = std::min(ctx->pcg_grid, std::max(1, (S.B + 15) / 16));
-  {
-    StageTimer t(ctx, 3);
-    if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, grid, ctx->st))
-      return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
-    launch_dq_norm(S, ctx->st);
-  }
-  int rc = read_counters(ctx);
+  int rc = launch_solve(ctx);
   if (rc) return rc;
-  *iters = ctx->h_cnt->pcg_iters;
-  if (ctx->timing) {
-    /* algorithmic bytes of the PCG launch: per iteration the diagonal and
-     * used off-diagonal blocks once, the block inverses once and seven
-     * length-12B vectors */
-    double per = (double)(S.B + ctx->h_cnt->n_rows_used / 2) * 1152.0 +
-                 (double)S.B * 1152.0 + 7.0 * 12.0 * S.B * 8.0;
-    ctx->t_bytes[3] += per * (*iters);
-  }
+  if ((rc = read_counters(ctx, 0))) return rc;
+  *iters = ctx->h_cnt[0].pcg_iters;
+  account_pcg_bytes(ctx);
   return ABD_OK;
 }
 
@@ -419,28 +463,33 @@ int upload_dq(abd_ctx* ctx, const double* dq) {
   return ABD_OK;
 }
 
-/* swept candidates for the current dq, with capacity growth; counters read */
-int swept_phase(abd_ctx* ctx, bool ccd) {
+/* swept candidates for the current dq, with capacity growth; counters read
+ * (and, if energy_at_toi, the energy difference at the CCD step in
+ * ctx->h_buf[0]) */
+int swept_phase(abd_ctx* ctx, bool ccd, bool energy_at_toi = false) {
   for (int attempt = 0; attempt < 8; ++attempt) {
-    int rc = reset_counters(ctx);
+    int rc = reset_counters(ctx, 1);
     if (rc) return rc;
-    broad_phase(ctx, 1);
-    if (ccd) {
-      StageTimer t(ctx, 4);
-      launch_ccd(ctx->S, ctx->st);
-    }
-    if ((rc = read_counters(ctx))) return rc;
+    launch_swept(ctx, ccd, energy_at_toi);
+    if (energy_at_toi)
+      HIPCHK(hipMemcpyAsync(ctx->h_buf, ctx->S.partials + ctx->S.cap_partials - 1,
+                            sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    if ((rc = read_counters(ctx, 1))) return rc;
     bool changed = false;
-    if ((rc = grow(ctx, &changed))) return rc;
+    if ((rc = grow(ctx, ctx->h_cnt[1], &changed))) return rc;
     if (!changed) return ABD_OK;
   }
   return fail(ctx, ABD_E_OOM, "capacity growth did not settle");
 }
 
-int energy(abd_ctx* ctx, double alpha, int mode, int with_pairs, double* out) {
+/* energy (mode 0: difference at alpha, mode 1: value) over the candidate
+ * list of the given phase */
+int energy(abd_ctx* ctx, int phase, double alpha, int mode, int with_pairs,
+           double* out) {
+  const Scene Sx = phase ? swept_scene(ctx) : ctx->S;
   {
     StageTimer t(ctx, 5);
-    launch_energy(ctx->S, alpha, mode | (with_pairs << 1),
+    launch_energy(Sx, alpha, mode | (with_pairs << 1), 0,
                   ctx->S.partials + ctx->S.cap_partials - 1, ctx->st);
   }
   HIPCHK(hipMemcpyAsync(ctx->h_buf, ctx->S.partials + ctx->S.cap_partials - 1,
@@ -449,6 +498,30 @@ int energy(abd_ctx* ctx, double alpha, int mode, int with_pairs, double* out) {
   resolve_timing(ctx);
   *out = ctx->h_buf[0];
   return ABD_OK;
+}
+
+/* One Newton iteration with a single host synchronisation: static phase,
+ * PCG, swept phase, CCD and the energy difference at the CCD step are
+ * queued back to back; the counters of both phases come back together. */
+int newton_iteration(abd_ctx* ctx) {
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    int rc = reset_both(ctx);
+    if (rc) return rc;
+    launch_static(ctx);
+    if ((rc = launch_solve(ctx))) return rc;
+    launch_swept(ctx, true, true);
+    HIPCHK(hipMemcpyAsync(ctx->h_buf, ctx->S.partials + ctx->S.cap_partials - 1,
+                          sizeof(double), hipMemcpyDeviceToHost, ctx->st));
+    if ((rc = read_counters(ctx, 0, 2))) return rc;
+    bool changed = false;
+    if ((rc = grow(ctx, ctx->h_cnt[0], &changed))) return rc;
+    if (changed) continue;
+    account_pcg_bytes(ctx);
+    if ((rc = grow(ctx, ctx->h_cnt[1], &changed))) return rc;
+    if (changed) return swept_phase(ctx, true, true);
+    return ABD_OK;
+  }
+  return fail(ctx, ABD_E_OOM, "capacity growth did not settle");
 }
 
 int check_ctx(abd_ctx* ctx, bool need_final) {
@@ -737,15 +810,15 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.Ap, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.partials, S.cap_partials))) return rc;
-  if ((rc = dalloc(ctx, &S.cnt, 1))) return rc;
-  if (hipHostMalloc((void**)&ctx->h_cnt, sizeof(Counters)) != hipSuccess ||
+  if ((rc = dalloc(ctx, &S.cnt, 2))) return rc;
+  if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
   ctx->finalized = true;
   /* initial feasibility: every candidate distance > 0 */
   if ((rc = assemble(ctx))) return rc;
-  double md = bits_to_double(ctx->h_cnt->min_dist);
+  double md = bits_to_double(ctx->h_cnt[0].min_dist);
   if (!(md > 0.0)) {
     ctx->finalized = false;
     return fail(ctx, ABD_E_INFEASIBLE, "initial state has a distance <= 0");
@@ -873,33 +946,29 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
   const double hl = ctx->P.dt * ctx->scale;
   int status = ABD_E_NOCONV;
   for (int it = 0; it < ctx->P.max_newton; ++it) {
-    if ((rc = assemble(ctx))) { status = rc; break; }
-    const Counters& c = *ctx->h_cnt;
+    if ((rc = newton_iteration(ctx))) { status = rc; break; }
+    const Counters& c = ctx->h_cnt[0];
     st.n_cand_pt = c.n_pt;
     st.n_cand_ee = c.n_ee;
     st.n_cand_pg = c.n_pg;
     st.n_active = c.n_act;
     st.min_dist = bits_to_double(c.min_dist);
-    int pit = 0;
-    if ((rc = linear_solve(ctx, &pit))) { status = rc; break; }
-    st.pcg_iters_total += pit;
+    st.pcg_iters_total += c.pcg_iters;
     st.newton_iters = it + 1;
-    double eps = bits_to_double(ctx->h_cnt->max_dq) / hl;
+    const double eps = bits_to_double(c.max_dq) / hl;
     st.final_eps_N = eps;
     if (!std::isfinite(eps)) {
       status = fail(ctx, ABD_E_NOCONV, "non-finite Newton direction");
       break;
     }
     if (eps < ctx->P.newton_theta) { status = ABD_OK; break; }
-    if ((rc = swept_phase(ctx, true))) { status = rc; break; }
-    double amax = std::min(1.0, bits_to_double(ctx->h_cnt->min_toi));
-    double alpha = amax, dE;
-    if ((rc = energy(ctx, alpha, 0, 1, &dE))) { status = rc; break; }
+    double alpha = std::min(1.0, bits_to_double(ctx->h_cnt[1].min_toi));
+    double dE = ctx->h_buf[0];
     int nh = 0;
     while (dE > 0.0 && nh < ctx->P.max_ls) {
       alpha *= 0.5;
       ++nh;
-      if ((rc = energy(ctx, alpha, 0, 1, &dE))) break;
+      if ((rc = energy(ctx, 1, alpha, 0, 1, &dE))) break;
     }
     if (rc) { status = rc; break; }
     st.ls_halvings += nh;
@@ -1021,15 +1090,15 @@ int abd_export_candidates(abd_ctx* ctx, int32_t kind, const double* dq,
     if ((rc = swept_phase(ctx, false))) return rc;
   } else {
     for (int attempt = 0; attempt < 8; ++attempt) {
-      if ((rc = reset_counters(ctx))) return rc;
-      broad_phase(ctx, 0);
-      if ((rc = read_counters(ctx))) return rc;
+      if ((rc = reset_counters(ctx, 0))) return rc;
+      broad_phase(ctx, S, 0);
+      if ((rc = read_counters(ctx, 0))) return rc;
       bool changed;
-      if ((rc = grow(ctx, &changed))) return rc;
+      if ((rc = grow(ctx, ctx->h_cnt[0], &changed))) return rc;
       if (!changed) break;
     }
   }
-  const Counters& c = *ctx->h_cnt;
+  const Counters& c = ctx->h_cnt[dq ? 1 : 0];
   int n = kind == ABD_PT ? c.n_pt : kind == ABD_EE ? c.n_ee : c.n_pg;
   *count = n;
   if (!out) return ABD_OK;
@@ -1067,13 +1136,13 @@ int abd_eval(abd_ctx* ctx, const double* q, double* E, double* g,
   HIPCHK(hipMemcpy(save.data(), S.q, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
   if (q) HIPCHK(hipMemcpy(S.q, q, sizeof(double) * 12 * B, hipMemcpyHostToDevice));
   rc = assemble(ctx);
-  if (!rc && E) rc = energy(ctx, 0.0, 1, 1, E);
+  if (!rc && E) rc = energy(ctx, 0, 0.0, 1, 1, E);
   if (!rc) {
-    if (n_active) *n_active = ctx->h_cnt->n_act;
+    if (n_active) *n_active = ctx->h_cnt[0].n_act;
     if (g) HIPCHK(hipMemcpy(g, S.g, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
     if (Hdiag)
       HIPCHK(hipMemcpy(Hdiag, S.Hdiag, sizeof(double) * 144 * B, hipMemcpyDeviceToHost));
-    int nbp = ctx->h_cnt->n_bp;
+    int nbp = ctx->h_cnt[0].n_bp;
     std::vector<int> used(nbp);
     std::vector<int2> bp(nbp);
     if (nbp) {
@@ -1120,7 +1189,7 @@ int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max) {
   if (!dq || !alpha_max) return fail(ctx, ABD_E_INVALID_ARG, "ccd");
   if ((rc = upload_dq(ctx, dq))) return rc;
   if ((rc = swept_phase(ctx, true))) return rc;
-  *alpha_max = std::min(1.0, bits_to_double(ctx->h_cnt->min_toi));
+  *alpha_max = std::min(1.0, bits_to_double(ctx->h_cnt[1].min_toi));
   return ABD_OK;
 }
 
@@ -1131,7 +1200,7 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
   if (!dq || !dE) return fail(ctx, ABD_E_INVALID_ARG, "energy_delta");
   if ((rc = upload_dq(ctx, dq))) return rc;
   if ((rc = swept_phase(ctx, false))) return rc;
-  return energy(ctx, alpha, 0, 1, dE);
+  return energy(ctx, 1, alpha, 0, 1, dE);
 }
 
 int abd_set_timing(abd_ctx* ctx, int32_t on) {
