@@ -58,6 +58,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--quiet", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -66,6 +67,7 @@ def main():
               "build", file=sys.stderr)
         sys.exit(2)
 
+    import numpy as np
     import torch
     from paper_2605_15875_amd import abd, scenes
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -111,6 +113,33 @@ def main():
                     frac=achieved / HBM_PEAK_GBS, traffic=None,
                     launches=d["launches"],
                     avg_launch_ms=d["ms"] / d["launches"])
+    q64, _ = solver.get_state()
+    x64 = solver.vertices()
+    l = float(np.linalg.norm(np.ptp(x64, axis=0)))
+    solver.close()
+    mixed = None
+    if not a.no_mixed:
+        # same workload, same steps and tolerance, FP32 Hessian path
+        ms = abd.Solver(sc, precision=1)
+        for i in range(a.warmup):
+            ms.step()
+        ms.set_timing(True)  # same event overhead as the FP64 run
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mnewton = 0
+        for i in range(a.steps):
+            st = ms.step()
+            mnewton += st["newton_iters"]
+        torch.cuda.synchronize()
+        mel = time.perf_counter() - t1
+        xm = ms.vertices()
+        mixed = dict(newton_iters_per_s=mnewton / mel, newton_iters=mnewton,
+                     ms_per_step=mel * 1e3 / a.steps,
+                     speedup_vs_fp64=elapsed / mel,
+                     final_pos_diff_vs_fp64_over_l=float(
+                         np.abs(xm - x64).max() / l))
+        log(f"mixed: {mnewton} newton iters in {mel*1e3:.1f} ms")
+        ms.close()
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline ...")
@@ -136,10 +165,10 @@ def main():
         "stage_ms": {k: round(v["ms"], 3) for k, v in tm.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
-        "mixed_vs_fp64_speedup": None,
+        "mixed_vs_fp64_speedup": mixed["speedup_vs_fp64"] if mixed else None,
+        "mixed": mixed,
     }
     print(json.dumps(out), flush=True)
-    solver.close()
 
 
 if __name__ == "__main__":

@@ -63,7 +63,12 @@ extern "C" {
 #define ABD_STATIC 1
 
 /* precision of the Newton linear algebra */
-#define ABD_FP64 0
+#define ABD_FP64 0  /* everything FP64 */
+#define ABD_MIXED 1 /* Hessian blocks, their PSD projection, assembly and
+                       the PCG matvec in FP32 (FP32 accumulation); gradient,
+                       distances, CCD, energies, PCG residual and dots FP64:
+                       the FP64 gradient of every Newton iteration refines
+                       the FP32-Hessian steps to the same solution */
 
 /* candidate kinds */
 #define ABD_PT 0 /* point-triangle: (vertex, triangle) */
@@ -87,7 +92,7 @@ typedef struct abd_params {
   int32_t max_newton, max_pcg, max_ls;
   int32_t has_ground;  /* vertex-ground pairs against y = ground_y */
   int32_t mollify_ee;  /* edge-edge mollifier on |ea x eb|^2 */
-  int32_t precision;   /* ABD_FP64 */
+  int32_t precision;   /* ABD_FP64 or ABD_MIXED */
 } abd_params;
 
 typedef struct abd_stats {
@@ -121,9 +126,9 @@ int abd_add_body(abd_ctx* ctx, const double* xbar, int32_t nv,
                  const double* q0, const double* qdot0, int32_t kind,
                  int32_t* body_id);
 
-/* Upload the scene to the device and check that the initial state has
- * every candidate distance > 0.  Errors: INVALID_ARG, INFEASIBLE, OOM,
- * DEVICE. */
+/* Upload the scene to the device and check that the initial state is
+ * feasible: every candidate distance > 0 and no edge of one body crossing a
+ * triangle of another.  Errors: INVALID_ARG, INFEASIBLE, OOM, DEVICE. */
 int abd_finalize(abd_ctx* ctx);
 
 /* sizes[0..3] = bodies, vertices, triangles, edges */

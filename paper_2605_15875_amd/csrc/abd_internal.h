@@ -36,7 +36,25 @@ struct Counters {
   unsigned long long max_dq;    /* bits of a non-negative double */
   unsigned int bar;             /* grid barrier arrivals */
   int n_rows_used;
+  int active; /* problems not done after a pass of the device loop */
   double pcg_rr, pcg_bb;
+};
+
+/* per-problem state of the device-driven Newton loop; a plain context is
+ * one problem, a batch merges several */
+enum { PS_NEWTON = 0, PS_LINESEARCH = 1, PS_DONE = 2 };
+#define LS_TRIALS 8
+struct ProbState {
+  double scale;       /* l: bounding-box diagonal of the dynamic vertices */
+  double alpha_base;  /* first trial step of the current line-search pass */
+  double alpha_acc;   /* accepted step of this pass (0 = none) */
+  double min_alpha, final_eps;
+  double dE[LS_TRIALS];
+  double acc[16];     /* PCG dot ring: [slot][rz, pAp, rr, -] */
+  double bb;          /* |b|^2 of the PCG right-hand side */
+  unsigned long long max_dq, min_toi;
+  int state, status, newton, halvings, ls_count;
+  int pcg_done, pcg_iters, pcg_total;
 };
 
 struct Scene {
@@ -68,8 +86,11 @@ struct Scene {
   int *cand_pg; /* [cap] v */
   int4 *act;    /* active pairs (kind, i, j, slot) */
   int cap_bp, cap_cp, cap_pt, cap_ee, cap_pg, cap_act;
-  /* system */
-  double *g, *Hdiag, *Hoff, *Pinv;
+  /* system: gradient FP64; Hessian blocks, their inverses and the PCG
+   * matvec in FP64 (mixed = 0) or FP32 (mixed = 1) */
+  double *g;
+  void *Hdiag, *Hoff, *Pinv;
+  int mixed;
   int *slot_used;
   int *row_ptr, *row_cnt, *col_slot, *col_body, *col_trans;
   int cap_col;
@@ -79,7 +100,27 @@ struct Scene {
   double *partials; /* [cap_partials] */
   int cap_partials;
   Counters *cnt;
+  /* problems */
+  int NP;
+  int *bprob;     /* [B] problem of each body */
+  ProbState *ps;  /* [NP] */
+  int iter_mode;  /* 0: hooks (every problem); 1: static pass of the device
+                     loop (problems in PS_NEWTON); 2: swept pass (problems
+                     not PS_DONE) */
+  double theta;   /* Newton tolerance */
+  int max_newton, max_ls, max_pcg;
+  double eta;
 };
+
+__device__ __forceinline__ int body_state(const Scene& S, int b) {
+  return S.ps[S.bprob[b]].state;
+}
+/* does the current pass work on body b's problem? */
+__device__ __forceinline__ bool body_in_pass(const Scene& S, int b) {
+  if (S.iter_mode == 0) return true;
+  const int st = S.ps[S.bprob[b]].state;
+  return S.iter_mode == 1 ? st == PS_NEWTON : st != PS_DONE;
+}
 
 /* ------------------------------------------------------------------ */
 /* canonical vertex transform: x_i = p_i + A_i0 xb0 + A_i1 xb1 + A_i2 xb2
@@ -419,60 +460,79 @@ __host__ __device__ constexpr int sidx(int p, int q) {
 /* cyclic Jacobi on a packed symmetric 9x9 held in registers (every     */
 /* index is a compile-time constant after unrolling), then projection   */
 /* to PSD in place: K <- V max(Lambda, 0) V^T.  Rotations in row order, */
-/* stop when the off-diagonal mass is below 1e-30 of the total.         */
+/* stop when the off-diagonal mass is below tol2 of the total (1e-30 in */
+/* FP64, 1e-12 in FP32, i.e. about the square of each precision).      */
 /* ------------------------------------------------------------------ */
-__device__ __forceinline__ void psd9_reg(double* K) {
-  double V[81];
+template <typename T> struct JacobiTol;
+template <> struct JacobiTol<double> {
+  static constexpr double tol2 = 1e-30;
+};
+template <> struct JacobiTol<float> {
+  static constexpr float tol2 = 1e-12f;
+};
+__device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
+__device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
+
+template <typename T>
+__device__ __forceinline__ void psd9_reg(T* K) {
+  T V[81];
 #pragma unroll
-  for (int i = 0; i < 81; ++i) V[i] = (i / 9 == i % 9) ? 1.0 : 0.0;
+  for (int i = 0; i < 81; ++i) V[i] = (i / 9 == i % 9) ? T(1) : T(0);
+  const T tol2 = JacobiTol<T>::tol2;
   for (int sweep = 0; sweep < 60; ++sweep) {
-    double off = 0.0, dia = 0.0;
+    T off = 0, dia = 0;
 #pragma unroll
     for (int p = 0; p < 9; ++p) {
       dia += K[sidx(p, p)] * K[sidx(p, p)];
 #pragma unroll
       for (int q = p + 1; q < 9; ++q) off += K[sidx(p, q)] * K[sidx(p, q)];
     }
-    if (off == 0.0 || off <= 1e-30 * (dia + 2.0 * off)) break;
+    const T tot = dia + T(2) * off;
+    if (off == T(0) || off <= tol2 * tot) break;
+    /* rotations with apq^2 below tol2/36 of the total are skipped: if all
+     * 36 are, the off-diagonal mass is already under the stopping bound */
+    const T skip2 = tol2 * T(1.0 / 36.0) * tot;
 #pragma unroll
     for (int p = 0; p < 8; ++p)
 #pragma unroll
       for (int q = p + 1; q < 9; ++q) {
-        const double apq = K[sidx(p, q)];
-        if (apq != 0.0) {
-          const double app = K[sidx(p, p)], aqq = K[sidx(q, q)];
-          const double theta = (aqq - app) / (2.0 * apq);
-          double t = 1.0 / (fabs(theta) + sqrt(theta * theta + 1.0));
-          t = theta < 0.0 ? -t : t;
-          const double c = 1.0 / sqrt(t * t + 1.0);
-          const double s = t * c;
+        const T apq = K[sidx(p, q)];
+        if (apq * apq > skip2) {
+          const T app = K[sidx(p, p)], aqq = K[sidx(q, q)];
+          /* tan of the rotation angle, t = sgn(a) b / (|a| + hypot(a, b))
+           * with a = aqq - app, b = 2 apq (the smaller root) */
+          const T aa = aqq - app, bb = T(2) * apq;
+          T t = bb / (fabs(aa) + sqrt(aa * aa + bb * bb));
+          t = aa < T(0) ? -t : t;
+          const T c = rsq(t * t + T(1));
+          const T s = t * c;
 #pragma unroll
           for (int r = 0; r < 9; ++r) {
             if (r == p || r == q) continue;
-            const double krp = K[sidx(r, p)], krq = K[sidx(r, q)];
+            const T krp = K[sidx(r, p)], krq = K[sidx(r, q)];
             K[sidx(r, p)] = c * krp - s * krq;
             K[sidx(r, q)] = s * krp + c * krq;
           }
           K[sidx(p, p)] = app - t * apq;
           K[sidx(q, q)] = aqq + t * apq;
-          K[sidx(p, q)] = 0.0;
+          K[sidx(p, q)] = T(0);
 #pragma unroll
           for (int r = 0; r < 9; ++r) {
-            const double vrp = V[9 * r + p], vrq = V[9 * r + q];
+            const T vrp = V[9 * r + p], vrq = V[9 * r + q];
             V[9 * r + p] = c * vrp - s * vrq;
             V[9 * r + q] = s * vrp + c * vrq;
           }
         }
       }
   }
-  double lam[9];
+  T lam[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) lam[k] = fmax(K[sidx(k, k)], 0.0);
+  for (int k = 0; k < 9; ++k) lam[k] = fmax(K[sidx(k, k)], T(0));
 #pragma unroll
   for (int p = 0; p < 9; ++p)
 #pragma unroll
     for (int q = p; q < 9; ++q) {
-      double v = 0.0;
+      T v = 0;
 #pragma unroll
       for (int k = 0; k < 9; ++k) v += V[9 * p + k] * lam[k] * V[9 * q + k];
       K[sidx(p, q)] = v;
@@ -543,6 +603,8 @@ void launch_chunk_pairs(const Scene& S, hipStream_t st);
 void launch_prim_pairs(const Scene& S, int swept, hipStream_t st);
 void launch_pg(const Scene& S, int swept, hipStream_t st);
 void launch_filter(const Scene& S, hipStream_t st);
+void launch_clear_slots(const Scene& S, hipStream_t st);
+void launch_crossings(const Scene& S, hipStream_t st);
 void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st);
 void launch_bsr(const Scene& S, hipStream_t st);
 void launch_block_inverse(const Scene& S, hipStream_t st);
@@ -553,6 +615,11 @@ void launch_dq_norm(const Scene& S, hipStream_t st);
 void launch_ccd(const Scene& S, hipStream_t st);
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st);
+void launch_energy_multi(const Scene& S, hipStream_t st);
+void launch_ctrl(const Scene& S, int which, hipStream_t st);
+void launch_update_multi(const Scene& S, hipStream_t st);
+void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st);
+void launch_reset_pcg(const Scene& S, hipStream_t st);
 void launch_update_q(const Scene& S, double alpha, hipStream_t st);
 void launch_scale(const Scene& S, double* out6, hipStream_t st);
 

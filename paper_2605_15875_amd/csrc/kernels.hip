@@ -12,6 +12,9 @@
  *   CCD step bound                       k_ccd
  *   line search energy                   k_energy, k_reduce
  */
+#include <algorithm>
+#include <cstddef>
+
 #include "abd_internal.h"
 
 namespace abd {
@@ -116,13 +119,15 @@ __global__ void k_scale(Scene S, unsigned long long* out6) {
  * h^2 kappa_A V |A A^T - I|^2 (Hessian projected to PSD), both weighted by
  * 1/kappa_b, and the ADMM penalty rho/2 |q - z + u|^2 of a shared body.
  * Writes g [B][12] and Hdiag [B][144] (static bodies: 0 and identity). */
+template <typename HT>
 __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
   const int b = blockIdx.x * 64 + threadIdx.x;
   if (b >= S.B) return;
-  double* Hd = S.Hdiag + 144 * b;
+  if (!body_in_pass(S, b)) return;
+  HT* Hd = (HT*)S.Hdiag + 144 * b;
   double* g = S.g + 12 * b;
   if (S.kind[b] != 0) {
-    for (int i = 0; i < 144; ++i) Hd[i] = (i % 13 == 0) ? 1.0 : 0.0;
+    for (int i = 0; i < 144; ++i) Hd[i] = (i % 13 == 0) ? HT(1) : HT(0);
     for (int i = 0; i < 12; ++i) g[i] = 0.0;
     return;
   }
@@ -164,7 +169,10 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
       if (l == qq) h += Sm[3 * k + p];
       K[sidx(a, e)] = 4.0 * h;
     }
-  psd9_reg(K);
+  HT Kt[45];
+#pragma unroll
+  for (int i = 0; i < 45; ++i) Kt[i] = (HT)K[i];
+  psd9_reg<HT>(Kt);
   /* gradient */
   double gl[12];
 #pragma unroll
@@ -201,9 +209,9 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
       const int i = r < 3 ? r : (r - 3) / 3, k = r < 3 ? 0 : (r - 3) % 3 + 1;
       const int j = cc < 3 ? cc : (cc - 3) / 3, l = cc < 3 ? 0 : (cc - 3) % 3 + 1;
       double h = (i == j) ? wb * M[4 * k + l] : 0.0;
-      if (r >= 3 && cc >= 3) h += c * K[sidx(r - 3, cc - 3)];
+      if (r >= 3 && cc >= 3) h += c * (double)Kt[sidx(r - 3, cc - 3)];
       if (r == cc) h += rho;
-      Hd[12 * r + cc] = h;
+      Hd[12 * r + cc] = (HT)h;
     }
 }
 
@@ -257,6 +265,8 @@ __global__ void k_body_pairs(Scene S) {
   if ((int)(blockIdx.x * 16 + 15) <= (int)(blockIdx.y * 16)) return;
   if (a >= S.B || b >= S.B || a >= b) return;
   if (S.kind[a] != 0 && S.kind[b] != 0) return;
+  if (S.bprob[a] != S.bprob[b]) return; /* independent problems */
+  if (!body_in_pass(S, a)) return;
   if (!box_overlap(S.body_box + 6 * a, S.body_box + 6 * b, S.dhat)) return;
   int k = atomicAdd(&S.cnt->n_bp, 1);
   if (k < S.cap_bp) S.bp[k] = make_int2(a, b);
@@ -327,49 +337,65 @@ __device__ __forceinline__ void prim_box(const Scene& S, int kind, int id,
   }
 }
 
-/* primitive pairs of every chunk pair, one wavefront per chunk pair: the
- * second chunk's exact boxes are staged in LDS, each lane tests its own
- * primitive of the first chunk against all of them */
+/* primitive pairs of every chunk pair, one wavefront per chunk pair.  The
+ * second chunk's primitives whose exact box meets the first chunk's box are
+ * compacted into LDS (ballot + prefix count); each lane whose own primitive
+ * meets the second chunk's box tests it against the compacted list with
+ * the exact predicate.  Both culls are sound: a primitive box lies inside
+ * its chunk box and the rounded bound hi + dhat is monotone in hi. */
 __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
   __shared__ double qbox[4][ABD_CHUNK][6];
   __shared__ int qid[4][ABD_CHUNK];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int ncp = min(S.cnt->n_cp, S.cap_cp);
   for (int base = blockIdx.x * 4; base < ncp; base += gridDim.x * 4) {
-    int c = base + wave;
-    bool valid = c < ncp;
-    int4 cp = valid ? S.cp[c] : make_int4(0, 0, 0, 0);
-    int P = cp.y, Q = cp.z;
-    int kindP = cp.x == C_PT ? K_VERT : K_EDGE;
-    int kindQ = cp.x == C_PT ? K_TRI : K_EDGE;
-    int nP = valid ? S.ch_count[P] : 0;
-    int nQ = valid ? S.ch_count[Q] : 0;
+    const int c = base + wave;
+    const bool valid = c < ncp;
+    const int4 cp = valid ? S.cp[c] : make_int4(0, 0, 0, 0);
+    const int P = cp.y, Q = cp.z;
+    const int kindP = cp.x == C_PT ? K_VERT : K_EDGE;
+    const int kindQ = cp.x == C_PT ? K_TRI : K_EDGE;
+    const int nP = valid ? S.ch_count[P] : 0;
+    const int nQ = valid ? S.ch_count[Q] : 0;
+    bool keep = false;
+    int id = 0;
+    double qb[6];
     if (lane < nQ) {
-      int id = S.ch_prims[S.ch_start[Q] + lane];
-      qid[wave][lane] = id;
-      prim_box(S, kindQ, id, swept, qbox[wave][lane]);
+      id = S.ch_prims[S.ch_start[Q] + lane];
+      prim_box(S, kindQ, id, swept, qb);
+      keep = box_overlap(qb, S.ch_box + 6 * P, S.dhat);
+    }
+    const unsigned long long m = __ballot(keep);
+    const int nq = __popcll(m);
+    if (keep) {
+      const int pos = __popcll(m & ((1ull << lane) - 1ull));
+      qid[wave][pos] = id;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) qbox[wave][pos][k] = qb[k];
     }
     __syncthreads();
-    if (lane < nP) {
-      int id = S.ch_prims[S.ch_start[P] + lane];
+    if (nq > 0 && lane < nP) {
+      const int pid = S.ch_prims[S.ch_start[P] + lane];
       double box[6];
-      prim_box(S, kindP, id, swept, box);
-      for (int j = 0; j < nQ; ++j) {
-        if (!box_overlap(box, qbox[wave][j], S.dhat)) continue;
-        int other = qid[wave][j];
-        if (cp.x == C_PT) {
-          int k = atomicAdd(&S.cnt->n_pt, 1);
-          if (k < S.cap_pt) {
-            S.cand_pt[3 * k] = id;
-            S.cand_pt[3 * k + 1] = other;
-            S.cand_pt[3 * k + 2] = cp.w;
-          }
-        } else {
-          int k = atomicAdd(&S.cnt->n_ee, 1);
-          if (k < S.cap_ee) {
-            S.cand_ee[3 * k] = min(id, other);
-            S.cand_ee[3 * k + 1] = max(id, other);
-            S.cand_ee[3 * k + 2] = cp.w;
+      prim_box(S, kindP, pid, swept, box);
+      if (box_overlap(box, S.ch_box + 6 * Q, S.dhat)) {
+        for (int j = 0; j < nq; ++j) {
+          if (!box_overlap(box, qbox[wave][j], S.dhat)) continue;
+          const int other = qid[wave][j];
+          if (cp.x == C_PT) {
+            const int k = atomicAdd(&S.cnt->n_pt, 1);
+            if (k < S.cap_pt) {
+              S.cand_pt[3 * k] = pid;
+              S.cand_pt[3 * k + 1] = other;
+              S.cand_pt[3 * k + 2] = cp.w;
+            }
+          } else {
+            const int k = atomicAdd(&S.cnt->n_ee, 1);
+            if (k < S.cap_ee) {
+              S.cand_ee[3 * k] = min(pid, other);
+              S.cand_ee[3 * k + 1] = max(pid, other);
+              S.cand_ee[3 * k + 2] = cp.w;
+            }
           }
         }
       }
@@ -387,6 +413,7 @@ __global__ void k_pg(Scene S, int swept) {
   for (int c = blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64; c < S.NC;
        c += nw) {
     if (S.ch_kind[c] != K_VERT || S.kind[S.ch_body[c]] != 0) continue;
+    if (!body_in_pass(S, S.ch_body[c])) continue;
     if (!(S.ch_box[6 * c + 1] <= top)) continue;
     if (lane >= S.ch_count[c]) continue;
     int v = S.ch_prims[S.ch_start[c] + lane];
@@ -603,12 +630,13 @@ __device__ __forceinline__ void to_frame(const double (*C)[3], const double* G,
     }
 }
 
-/* Barrier gradient g_y and PSD-projected Hessian K (packed, reduced frame)
- * of one PT/EE pair with slot positions x; also returns the distance. */
+/* Barrier gradient g_y (FP64) and the frame-scaled Hessian G H_y G (packed,
+ * reduced frame, not yet projected) of one PT/EE pair with slot positions
+ * x; Gs receives the frame scales |f_r|. */
 __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int ei,
                                                int ej, const double* x,
                                                double w, double* gy,
-                                               double* K) {
+                                               double* K, double* Gs) {
   double D;
   Feat f = classify(kind, x, D);
   const double d = sqrt(D);
@@ -669,7 +697,7 @@ __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int 
     }
   }
   const double i2d = 0.5 / d, i4d3 = 0.25 / (d * d * d);
-  double gd[9], Gs[9];
+  double gd[9];
 #pragma unroll
   for (int p = 0; p < 9; ++p) {
     gd[p] = gD[p] * i2d;
@@ -689,11 +717,6 @@ __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int 
       }
       K[sidx(p, q)] = w * h * Gs[p] * Gs[q];
     }
-  psd9_reg(K);
-#pragma unroll
-  for (int p = 0; p < 9; ++p)
-#pragma unroll
-    for (int q = p; q < 9; ++q) K[sidx(p, q)] /= Gs[p] * Gs[q];
 }
 
 /* One wavefront of 64 active pairs.  Phase 1 (a lane per pair): distance
@@ -701,21 +724,25 @@ __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int 
  * projection, and the frame-to-body maps W.  Phase 2 (all lanes per pair):
  * T = H_y W_Y, then the body-space gradient and 12x12 blocks W_X^T T,
  * accumulated with FP64 atomics into g, Hdiag and Hoff. */
+#define PAIRS_PER_WG 16
+template <typename HT>
 __global__ __launch_bounds__(64) void k_assemble(Scene S) {
-  __shared__ double KL[45 * 64];
+  __shared__ HT KL[45 * 64];
   __shared__ double GW[33 * 64]; /* rows 0..8 g_y, 9..20 W_A, 21..32 W_B */
-  __shared__ double TB[216];
+  __shared__ HT TB[216];
   __shared__ int meta[3 * 64];
   const int lane = threadIdx.x;
   const int nact = min(S.cnt->n_act, S.cap_act);
-  for (int base = blockIdx.x * 64; base < nact; base += gridDim.x * 64) {
+  for (int base = blockIdx.x * PAIRS_PER_WG; base < nact;
+       base += gridDim.x * PAIRS_PER_WG) {
     const int t = base + lane;
     int ba = -1, bb = -1, slot = -1;
-    if (t < nact) {
+    if (lane < PAIRS_PER_WG && t < nact) {
       const int4 a = S.act[t];
       const int kind = a.x;
       slot = a.w;
-      double gy[9], K[45], Wa[12], Wb[12];
+      double gy[9], Wa[12], Wb[12];
+      HT K[45];
 #pragma unroll
       for (int i = 0; i < 12; ++i) Wa[i] = Wb[i] = 0.0;
       if (kind == C_PG) {
@@ -728,9 +755,9 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) gy[i] = 0.0;
 #pragma unroll
-        for (int i = 0; i < 45; ++i) K[i] = 0.0;
+        for (int i = 0; i < 45; ++i) K[i] = HT(0);
         gy[1] = w * b1;
-        K[sidx(1, 1)] = w * b2;
+        K[sidx(1, 1)] = (HT)(w * b2);
         ba = S.vbody[v];
         Wa[0] = 1.0;
         Wa[1] = S.xbar[v]; Wa[2] = S.xbar[S.V + v]; Wa[3] = S.xbar[2 * S.V + v];
@@ -741,7 +768,15 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
 #pragma unroll
         for (int s = 0; s < 4; ++s) vertex_pos(S, vid[s], x + 3 * s);
         const double w = pair_weight(S, vid, 4);
-        pair_frame_derivs(S, kind, a.y, a.z, x, w, gy, K);
+        double Kd[45], Gs[9];
+        pair_frame_derivs(S, kind, a.y, a.z, x, w, gy, Kd, Gs);
+#pragma unroll
+        for (int i = 0; i < 45; ++i) K[i] = (HT)Kd[i];
+        psd9_reg<HT>(K);
+#pragma unroll
+        for (int p = 0; p < 9; ++p)
+#pragma unroll
+          for (int q = p; q < 9; ++q) K[sidx(p, q)] /= (HT)(Gs[p] * Gs[q]);
         /* W_side[r][k] = sum over the side's slots s of f_r[s] xhat_s[k] */
         const int sideB0 = kind == C_PT ? 1 : 2;
         ba = S.vbody[vid[0]];
@@ -777,7 +812,7 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
     meta[64 + lane] = bb;
     meta[128 + lane] = slot;
     __syncthreads();
-    const int npairs = min(64, nact - base);
+    const int npairs = min(PAIRS_PER_WG, nact - base);
     for (int j = 0; j < npairs; ++j) {
       const int A = meta[j], Bq = meta[64 + j], sl = meta[128 + j];
       if (A < 0 && Bq < 0) continue;
@@ -786,10 +821,10 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
         const int Y = e / 108, f = e % 108, ri = f / 12, i2 = (f % 12) / 4,
                   l = f % 4;
         const int wo = Y ? 21 : 9;
-        double v = 0.0;
+        HT v = 0;
 #pragma unroll
         for (int u = 0; u < 3; ++u)
-          v += KL[sidx(ri, 3 * u + i2) * 64 + j] * GW[(wo + 4 * u + l) * 64 + j];
+          v += KL[sidx(ri, 3 * u + i2) * 64 + j] * (HT)GW[(wo + 4 * u + l) * 64 + j];
         TB[e] = v;
       }
       /* gradient */
@@ -811,17 +846,17 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
       /* blocks: (A,A), (B,B), (lo,hi) = W_X^T T_Y */
       for (int blk = 0; blk < 3; ++blk) {
         int X, Y;
-        double* dst;
+        HT* dst;
         if (blk == 0) {
           if (A < 0) continue;
-          X = 0; Y = 0; dst = S.Hdiag + 144 * A;
+          X = 0; Y = 0; dst = (HT*)S.Hdiag + 144 * A;
         } else if (blk == 1) {
           if (Bq < 0) continue;
-          X = 1; Y = 1; dst = S.Hdiag + 144 * Bq;
+          X = 1; Y = 1; dst = (HT*)S.Hdiag + 144 * Bq;
         } else {
           if (A < 0 || Bq < 0) continue;
           if (A < Bq) { X = 0; Y = 1; } else { X = 1; Y = 0; }
-          dst = S.Hoff + 144 * (size_t)sl;
+          dst = (HT*)S.Hoff + 144 * (size_t)sl;
           if (lane == 0) S.slot_used[sl] = 1;
         }
         const int wx = X ? 21 : 9;
@@ -829,10 +864,10 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
           int i, k, i2, l;
           dof_split(e / 12, i, k);
           dof_split(e % 12, i2, l);
-          double v = 0.0;
+          HT v = 0;
 #pragma unroll
           for (int r = 0; r < 3; ++r)
-            v += GW[(wx + 4 * r + k) * 64 + j] *
+            v += (HT)GW[(wx + 4 * r + k) * 64 + j] *
                  TB[Y * 108 + (3 * r + i) * 12 + i2 * 4 + l];
           atomicAdd(dst + e, v);
         }
@@ -905,13 +940,15 @@ __global__ void k_bsr_fill(Scene S) {
 
 /* inverse of every diagonal block by Gauss-Jordan (SPD, no pivoting):
  * 16 bodies per block of 192 threads, one row per thread */
+template <typename HT>
 __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
   __shared__ double M[16][12][25];
   const int lb = threadIdx.x / 12, r = threadIdx.x % 12;
   const int b = blockIdx.x * 16 + lb;
   const bool act = b < S.B;
   for (int c = 0; c < 12; ++c) {
-    M[lb][r][c] = act ? S.Hdiag[144 * b + 12 * r + c] : (r == c ? 1.0 : 0.0);
+    M[lb][r][c] = act ? (double)((const HT*)S.Hdiag)[144 * b + 12 * r + c]
+                      : (r == c ? 1.0 : 0.0);
     M[lb][r][12 + c] = r == c ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -928,65 +965,110 @@ __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
     __syncthreads();
   }
   if (act)
-    for (int c = 0; c < 12; ++c) S.Pinv[144 * b + 12 * r + c] = M[lb][r][12 + c];
+    for (int c = 0; c < 12; ++c)
+      ((HT*)S.Pinv)[144 * b + 12 * r + c] = (HT)M[lb][r][12 + c];
 }
 
-/* grid-wide barrier for the cooperative PCG launch; the spin is bounded so
- * that every wave exits even if a barrier were never completed */
+/* grid-wide barrier for the cooperative PCG launch.  The workgroup barrier
+ * puts every wave's stores in L2; thread 0's agent-scope release add then
+ * makes them visible device-wide, and its acquire loads (before the final
+ * workgroup barrier) order the block's later reads after every arrival.
+ * The spin is bounded so that every wave exits even if a barrier were
+ * never completed (the host then reports a device error). */
 __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned nblocks,
                                           unsigned& gen, int* err) {
   __syncthreads();
   if (threadIdx.x == 0) {
     gen += 1;
-    __threadfence();
-    atomicAdd(bar, 1u);
-    unsigned target = gen * nblocks;
+    __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned target = gen * nblocks;
     long spins = 0;
     while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE,
                              __HIP_MEMORY_SCOPE_AGENT) < target) {
-      __builtin_amdgcn_s_sleep(2);
-      if (++spins > (1L << 26)) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1L << 27)) {
         atomicOr(err, 1);
         break;
       }
     }
-    __threadfence();
   }
   __syncthreads();
 }
 
-__device__ __forceinline__ double block_sum192(double v, double* red) {
-  /* sum over a 192-thread block (3 waves) */
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+
+/* Add per-row values v[0..nv) of one 16-body group into the problem
+ * accumulators dst(p) (bodies of one problem are contiguous, so a group
+ * spans at most 16 problems): LDS atomics per problem, then one global
+ * atomic per problem and value. */
+template <int nv>
+__device__ __forceinline__ void group_add(double (*gs)[4], int gr, int B,
+                                          const int* bprob, int p, bool act,
+                                          const double* v, ProbState* ps,
+                                          const int* off) {
+  const int g0 = gr * 16;
+  const int plo = bprob[g0];
+  const int phi = bprob[min(B, g0 + 16) - 1];
+  if (threadIdx.x < 64)
+    for (int k = 0; k < 4; ++k) gs[threadIdx.x & 15][k] = 0.0;
   __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  if (act)
+#pragma unroll
+    for (int k = 0; k < nv; ++k)
+      if (v[k] != 0.0) atomicAdd(&gs[p - plo][k], v[k]);
   __syncthreads();
-  double s = red[0] + red[1] + red[2];
+  if ((int)threadIdx.x <= phi - plo)
+#pragma unroll
+    for (int k = 0; k < nv; ++k) {
+      double* d = (double*)((char*)(ps + plo + threadIdx.x) + off[k]);
+      atomicAdd(d, gs[threadIdx.x][k]);
+    }
   __syncthreads();
-  return s;
+}
+
+#define PCG_MAX_NP 2048
+__device__ __forceinline__ double ld_acq(const double* p) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
 /* Block-Jacobi preconditioned CG on H dq = -g with zero initial guess,
- * all iterations in one cooperative launch.  Each block owns 16 bodies
- * (192 rows) per pass of a grid-stride loop.  Per iteration: phase A
- * forms p_k = z_k + beta_k p_{k-1} on the fly and the product A p_k; phase
- * B updates dq, r and z = P^-1 r; two grid barriers.  Dots are reduced in
- * FP64 with atomics into a ring of 4 accumulator slots:
- * acc[4*j + 0] = r_j . z_j, + 1 = p_j . A p_j, + 2 = r_j . r_j. */
+ * every problem running its own recurrence, all iterations in one
+ * cooperative launch.  Each block owns 16 bodies (192 rows) per pass of a
+ * grid-stride loop.  Per iteration: phase A forms p_k = z_k + beta_k
+ * p_{k-1} on the fly and the product A p_k; phase B updates dq, r and
+ * z = P^-1 r; two grid barriers.  Dots are reduced in FP64 into each
+ * problem's ring of 4 slots, acc[4*j + 0] = r_j . z_j, + 1 = p_j . A p_j,
+ * + 2 = r_j . r_j.  After each iteration every block reads the same
+ * residuals and marks the same problems converged (|r| <= eta |b|), whose
+ * rows then stay fixed. */
+template <typename HT>
 __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
+  const HT* __restrict__ Hd = (const HT*)S.Hdiag;
+  const HT* __restrict__ Ho = (const HT*)S.Hoff;
+  const HT* __restrict__ Pi = (const HT*)S.Pinv;
   __shared__ double rloc[16][12];
-  __shared__ double red[4];
+  __shared__ double gs[16][4];
+  __shared__ unsigned char pdone[PCG_MAX_NP];
+  __shared__ int any_active;
   const unsigned nblk = gridDim.x;
   unsigned gen = 0;
   const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
   const int ngroups = (S.B + 15) / 16;
-  double* acc = S.acc;
+  const int NP = S.NP;
+  ProbState* ps = S.ps;
+  const int OFF_ACC = (int)offsetof(ProbState, acc);
+  const int OFF_BB = (int)offsetof(ProbState, bb);
+  /* participating problems: every problem for the hooks, the problems in
+   * the Newton state inside the device loop */
+  for (int p = threadIdx.x; p < NP; p += blockDim.x)
+    pdone[p] = (S.iter_mode == 0 || ps[p].state == PS_NEWTON) ? 0 : 1;
+  __syncthreads();
   /* init: x = 0, r = b = -g, z = P^-1 r, p_{-1} = 0 */
-  double prz = 0.0, pbb = 0.0;
   for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
-    int b = gr * 16 + lb;
-    bool act = b < S.B;
-    double rv = act ? -S.g[12 * b + row] : 0.0;
+    const int b = gr * 16 + lb;
+    const int p = b < S.B ? S.bprob[b] : 0;
+    const bool act = b < S.B && !pdone[p];
+    const double rv = act ? -S.g[12 * b + row] : 0.0;
     if (act) {
       S.dq[12 * b + row] = 0.0;
       S.r[12 * b + row] = rv;
@@ -996,107 +1078,152 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
     rloc[lb][row] = rv;
     __syncthreads();
     double z = 0.0;
-    if (act)
-      for (int c = 0; c < 12; ++c) z += S.Pinv[144 * b + 12 * row + c] * rloc[lb][c];
-    if (act) S.zv[12 * b + row] = z;
-    prz += rv * z;
-    pbb += rv * rv;
-    __syncthreads();
-  }
-  double srz = block_sum192(prz, red), sbb = block_sum192(pbb, red);
-  if (threadIdx.x == 0) {
-    atomicAdd(acc + 0, srz);
-    atomicAdd(&S.cnt->pcg_bb, sbb);
+    if (act) {
+      HT zz = 0;
+      for (int c = 0; c < 12; ++c) zz += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+      z = (double)zz;
+      S.zv[12 * b + row] = z;
+    }
+    const double v[2] = {rv * z, rv * rv};
+    const int off[2] = {OFF_ACC + 0, OFF_BB};
+    group_add<2>(gs, gr, S.B, S.bprob, p, act, v, ps, off);
   }
   grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
-  const double bb = S.cnt->pcg_bb;
-  int it = 0;
-  if (bb > 0.0) {
-    const double tol2 = eta * eta * bb;
-    for (it = 0; it < max_it; ++it) {
-      double* pold = (it & 1) ? S.p0 : S.p1;
-      double* pnew = (it & 1) ? S.p1 : S.p0;
-      const double rz = acc[4 * (it & 3) + 0];
-      const double beta = it == 0 ? 0.0 : rz / acc[4 * ((it - 1) & 3) + 0];
-      /* phase A: p = z + beta pold, Ap */
-      double ppap = 0.0;
-      for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
-        int b = gr * 16 + lb;
-        if (b < S.B) {
-          double y = 0.0;
-          const double* H = S.Hdiag + 144 * b + 12 * row;
-          for (int c = 0; c < 12; ++c)
-            y += H[c] * (S.zv[12 * b + c] + beta * pold[12 * b + c]);
-          for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
-            int nb = S.col_body[e];
-            const double* blk = S.Hoff + 144 * (size_t)S.col_slot[e];
-            if (S.col_trans[e]) {
-              for (int c = 0; c < 12; ++c)
-                y += blk[12 * c + row] * (S.zv[12 * nb + c] + beta * pold[12 * nb + c]);
-            } else {
-              for (int c = 0; c < 12; ++c)
-                y += blk[12 * row + c] * (S.zv[12 * nb + c] + beta * pold[12 * nb + c]);
-            }
-          }
-          double pk = S.zv[12 * b + row] + beta * pold[12 * b + row];
-          pnew[12 * b + row] = pk;
-          S.Ap[12 * b + row] = y;
-          ppap += pk * y;
-        }
-      }
-      double s = block_sum192(ppap, red);
-      if (threadIdx.x == 0) atomicAdd(acc + 4 * (it & 3) + 1, s);
-      grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
-      /* phase B */
-      const double alpha = rz / acc[4 * (it & 3) + 1];
-      double prz2 = 0.0, prr = 0.0;
-      if (blockIdx.x == 0 && threadIdx.x < 4) acc[4 * ((it + 2) & 3) + threadIdx.x] = 0.0;
-      for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
-        int b = gr * 16 + lb;
-        bool act = b < S.B;
-        double rv = 0.0;
-        if (act) {
-          int o = 12 * b + row;
-          S.dq[o] += alpha * pnew[o];
-          rv = S.r[o] - alpha * S.Ap[o];
-          S.r[o] = rv;
-        }
-        rloc[lb][row] = rv;
-        __syncthreads();
-        double z = 0.0;
-        if (act) {
-          for (int c = 0; c < 12; ++c) z += S.Pinv[144 * b + 12 * row + c] * rloc[lb][c];
-          S.zv[12 * b + row] = z;
-        }
-        prz2 += rv * z;
-        prr += rv * rv;
-        __syncthreads();
-      }
-      double s1 = block_sum192(prz2, red), s2 = block_sum192(prr, red);
-      if (threadIdx.x == 0) {
-        atomicAdd(acc + 4 * ((it + 1) & 3) + 0, s1);
-        atomicAdd(acc + 4 * ((it + 1) & 3) + 2, s2);
-      }
-      grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
-      double rr = acc[4 * ((it + 1) & 3) + 2];
-      if (S.cnt->err) { ++it; break; }
-      if (rr <= tol2) { ++it; break; }
+  /* problems with a zero right-hand side are done at once */
+  for (int p = threadIdx.x; p < NP; p += blockDim.x)
+    if (!pdone[p] && !(ld_acq(&ps[p].bb) > 0.0)) {
+      pdone[p] = 1;
+      if (blockIdx.x == 0) ps[p].pcg_iters = 0;
     }
+  __syncthreads();
+  int it = 0;
+  for (it = 0; it < max_it; ++it) {
+    double* pold = (it & 1) ? S.p0 : S.p1;
+    double* pnew = (it & 1) ? S.p1 : S.p0;
+    /* phase A: p = z + beta pold, Ap */
+    for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
+      const int b = gr * 16 + lb;
+      const int p = b < S.B ? S.bprob[b] : 0;
+      const bool act = b < S.B && !pdone[p];
+      double pap = 0.0;
+      if (act) {
+        const double* acc = ps[p].acc;
+        const double rz = ld_acq(acc + 4 * (it & 3));
+        const double beta = it == 0 ? 0.0 : rz / ld_acq(acc + 4 * ((it - 1) & 3));
+        /* matvec in the Hessian's precision (FP32 accumulation in the
+         * mixed form); p itself stays FP64 */
+        HT y = 0;
+        const HT* H = Hd + 144 * b + 12 * row;
+        for (int c = 0; c < 12; ++c)
+          y += H[c] * (HT)(S.zv[12 * b + c] + beta * pold[12 * b + c]);
+        for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
+          const int nb = S.col_body[e];
+          const HT* blk = Ho + 144 * (size_t)S.col_slot[e];
+          if (S.col_trans[e]) {
+            for (int c = 0; c < 12; ++c)
+              y += blk[12 * c + row] *
+                   (HT)(S.zv[12 * nb + c] + beta * pold[12 * nb + c]);
+          } else {
+            for (int c = 0; c < 12; ++c)
+              y += blk[12 * row + c] *
+                   (HT)(S.zv[12 * nb + c] + beta * pold[12 * nb + c]);
+          }
+        }
+        const double pk = S.zv[12 * b + row] + beta * pold[12 * b + row];
+        pnew[12 * b + row] = pk;
+        S.Ap[12 * b + row] = (double)y;
+        pap = pk * (double)y;
+      }
+      const double v[1] = {pap};
+      const int off[1] = {OFF_ACC + (int)sizeof(double) * (4 * (it & 3) + 1)};
+      group_add<1>(gs, gr, S.B, S.bprob, p, act, v, ps, off);
+    }
+    grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
+    /* phase B */
+    if (blockIdx.x == 0)
+      for (int t = threadIdx.x; t < 4 * NP; t += blockDim.x)
+        if ((t & 3) != 3) ps[t >> 2].acc[4 * ((it + 2) & 3) + (t & 3)] = 0.0;
+    for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
+      const int b = gr * 16 + lb;
+      const int p = b < S.B ? S.bprob[b] : 0;
+      const bool act = b < S.B && !pdone[p];
+      double rv = 0.0;
+      if (act) {
+        const double* acc = ps[p].acc;
+        const double alpha = ld_acq(acc + 4 * (it & 3)) / ld_acq(acc + 4 * (it & 3) + 1);
+        const int o = 12 * b + row;
+        S.dq[o] += alpha * pnew[o];
+        rv = S.r[o] - alpha * S.Ap[o];
+        S.r[o] = rv;
+      }
+      rloc[lb][row] = rv;
+      __syncthreads();
+      double z = 0.0;
+      if (act) {
+        HT zz = 0;
+        for (int c = 0; c < 12; ++c)
+          zz += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+        z = (double)zz;
+        S.zv[12 * b + row] = z;
+      }
+      const double v[2] = {rv * z, rv * rv};
+      const int off[2] = {OFF_ACC + (int)sizeof(double) * (4 * ((it + 1) & 3) + 0),
+                          OFF_ACC + (int)sizeof(double) * (4 * ((it + 1) & 3) + 2)};
+      group_add<2>(gs, gr, S.B, S.bprob, p, act, v, ps, off);
+    }
+    grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
+    /* the same convergence decision in every block */
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+      if (pdone[p]) continue;
+      const double rr = ld_acq(&ps[p].acc[4 * ((it + 1) & 3) + 2]);
+      if (rr <= eta * eta * ld_acq(&ps[p].bb)) {
+        pdone[p] = 1;
+        if (blockIdx.x == 0) ps[p].pcg_iters = it + 1;
+      } else {
+        any_active = 1;
+      }
+    }
+    __syncthreads();
+    const int more = any_active;
+    __syncthreads();
+    if (S.cnt->err || !more) { ++it; break; }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    S.cnt->pcg_iters = it;
-    S.cnt->pcg_rr = acc[4 * (it & 3) + 2];
+  if (blockIdx.x == 0) {
+    for (int p = threadIdx.x; p < NP; p += blockDim.x)
+      if (!pdone[p]) ps[p].pcg_iters = it;
+    if (threadIdx.x == 0) S.cnt->pcg_iters = it;
   }
 }
 
 /* ================================================================== */
 /* S8 Newton stop                                                      */
 /* ================================================================== */
+/* reduce a value over the wave when every lane belongs to the same
+ * problem, then one atomic per wave; otherwise one atomic per lane */
+__device__ __forceinline__ bool wave_uniform(int p) {
+  return __ballot(p == __shfl(p, 0, 64)) == __ballot(true);
+}
+
 __global__ void k_dq_norm(Scene S) {
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
-  double v = t < 12 * S.B ? fabs(S.dq[t]) : 0.0;
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
-  if ((threadIdx.x & 63) == 0) atomic_max_pos(&S.cnt->max_dq, v);
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const bool act = b < S.B;
+  const int p = act ? S.bprob[b] : -1;
+  double v = 0.0;
+  if (act)
+    for (int i = 0; i < 12; ++i) v = fmax(v, fabs(S.dq[12 * b + i]));
+  const bool uni = wave_uniform(p); /* inactive lanes make it non-uniform */
+  if (uni) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    if ((threadIdx.x & 63) == 0) {
+      atomic_max_pos(&S.ps[p].max_dq, v);
+      atomic_max_pos(&S.cnt->max_dq, v);
+    }
+  } else if (act) {
+    atomic_max_pos(&S.ps[p].max_dq, v);
+    atomic_max_pos(&S.cnt->max_dq, v);
+  }
 }
 
 /* ================================================================== */
@@ -1110,6 +1237,8 @@ __global__ void k_ccd(Scene S) {
   double tmin = 1.0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
        t += gridDim.x * blockDim.x) {
+    double toi = 1.0;
+    int prob;
     if (t < npt + nee) {
       const int* c = t < npt ? S.cand_pt + 3 * t : S.cand_ee + 3 * (t - npt);
       int kind = t < npt ? C_PT : C_EE;
@@ -1122,16 +1251,20 @@ __global__ void k_ccd(Scene S) {
         xform(S.q + 12 * b, b0, b1, b2, x + 3 * k);
         xform(S.dq + 12 * b, b0, b1, b2, dx + 3 * k);
       }
-      tmin = fmin(tmin, accd(kind, x, dx, 1.0));
+      toi = accd(kind, x, dx, 1.0);
+      prob = S.bprob[S.vbody[vid[0]]];
     } else {
       int v = S.cand_pg[t - npt - nee], b = S.vbody[v];
       double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
       double x[3], dx[3];
       xform(S.q + 12 * b, b0, b1, b2, x);
       xform(S.dq + 12 * b, b0, b1, b2, dx);
-      if (dx[1] < 0.0)
-        tmin = fmin(tmin, (1.0 - ACCD_S) * (x[1] - S.ground_y) / (-dx[1]));
+      if (dx[1] < 0.0) toi = (1.0 - ACCD_S) * (x[1] - S.ground_y) / (-dx[1]);
+      prob = S.bprob[b];
     }
+    toi = fmax(fmin(toi, 1.0), 0.0);
+    tmin = fmin(tmin, toi);
+    if (toi < 1.0) atomic_min_pos(&S.ps[prob].min_toi, toi);
   }
   for (int o = 32; o > 0; o >>= 1) tmin = fmin(tmin, __shfl_down(tmin, o, 64));
   if ((threadIdx.x & 63) == 0) atomic_min_pos(&S.cnt->min_toi, fmax(tmin, 0.0));
@@ -1292,6 +1425,290 @@ __global__ void k_update_q(Scene S, double alpha) {
 }
 
 /* ================================================================== */
+/* device-driven Newton loop: line search trials, controllers          */
+/* ================================================================== */
+/* E(q + alpha_k dq) - E(q) for alpha_k = alpha_base 2^-k, k < LS_TRIALS,
+ * per problem, over the bodies and swept candidates of problems that are
+ * not done; one atomic per trial per wave when the wave is uniform. */
+__global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
+  const int npt = min(S.cnt->n_pt, S.cap_pt);
+  const int nee = min(S.cnt->n_ee, S.cap_ee);
+  const int npg = min(S.cnt->n_pg, S.cap_pg);
+  const int tot = S.B + npt + nee + npg;
+  const int nwaves = (tot + 63) / 64;
+  for (int w = blockIdx.x * 4 + threadIdx.x / 64; w < nwaves; w += gridDim.x * 4) {
+    const int t = w * 64 + (threadIdx.x & 63);
+    double e[LS_TRIALS];
+#pragma unroll
+    for (int k = 0; k < LS_TRIALS; ++k) e[k] = 0.0;
+    int prob = -1;
+    if (t < S.B) {
+      if (S.kind[t] == 0 && S.ps[S.bprob[t]].state != PS_DONE) {
+        prob = S.bprob[t];
+        const double a0 = S.ps[prob].alpha_base;
+        double a = a0;
+#pragma unroll
+        for (int k = 0; k < LS_TRIALS; ++k, a *= 0.5) e[k] = body_energy(S, t, a, 0);
+      }
+    } else if (t < tot) {
+      const int u = t - S.B;
+      if (u < npt + nee) {
+        const int* c = u < npt ? S.cand_pt + 3 * u : S.cand_ee + 3 * (u - npt);
+        const int kind = u < npt ? C_PT : C_EE;
+        int vid[4];
+        pair_vertices(S, kind, c[0], c[1], vid);
+        const int pb = S.bprob[S.vbody[vid[0]]];
+        if (S.ps[pb].state != PS_DONE) {
+          prob = pb;
+          double x0[12], x1[12];
+          for (int k = 0; k < 4; ++k) vertex_pos(S, vid[k], x0 + 3 * k);
+          const double E0 = pair_energy_at(S, kind, c[0], c[1], vid, x0);
+          double a = S.ps[prob].alpha_base;
+          for (int k = 0; k < LS_TRIALS; ++k, a *= 0.5) {
+            for (int j = 0; j < 4; ++j) vertex_pos_alpha(S, vid[j], a, x1 + 3 * j);
+            e[k] = pair_energy_at(S, kind, c[0], c[1], vid, x1) - E0;
+          }
+        }
+      } else {
+        const int v = S.cand_pg[u - npt - nee];
+        const int pb = S.bprob[S.vbody[v]];
+        if (S.ps[pb].state != PS_DONE) {
+          prob = pb;
+          double x0[3], x1[3];
+          vertex_pos(S, v, x0);
+          const double w = pair_weight(S, &v, 1);
+          const double E0 = w * barrier_val(x0[1] - S.ground_y, S.dhat);
+          double a = S.ps[prob].alpha_base;
+          for (int k = 0; k < LS_TRIALS; ++k, a *= 0.5) {
+            vertex_pos_alpha(S, v, a, x1);
+            e[k] = w * barrier_val(x1[1] - S.ground_y, S.dhat) - E0;
+          }
+        }
+      }
+    }
+    const bool uni = wave_uniform(prob);
+    if (uni) {
+      if (prob >= 0) {
+#pragma unroll
+        for (int k = 0; k < LS_TRIALS; ++k) {
+          double v = e[k];
+          for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+          if ((threadIdx.x & 63) == 0) atomicAdd(&S.ps[prob].dE[k], v);
+        }
+      }
+    } else if (prob >= 0) {
+#pragma unroll
+      for (int k = 0; k < LS_TRIALS; ++k) atomicAdd(&S.ps[prob].dE[k], e[k]);
+    }
+  }
+}
+
+__device__ __forceinline__ bool static_overflow(const Counters& c, const Scene& S) {
+  return c.n_bp > S.cap_bp || c.n_cp > S.cap_cp || c.n_pt > S.cap_pt ||
+         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg || c.n_act > S.cap_act;
+}
+__device__ __forceinline__ bool swept_overflow(const Counters& c, const Scene& S) {
+  return c.n_bp > S.cap_bp || c.n_cp > S.cap_cp || c.n_pt > S.cap_pt ||
+         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg;
+}
+
+__device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
+                                                const Counters& c0,
+                                                const Counters& c1);
+
+/* One thread per problem.
+ * which 0 (start of a solve): every problem to the Newton state.
+ * which 1 (after the PCG): Newton stop |dq|_inf / (h l) < theta.
+ * which 2 (after CCD): first trial step alpha_max = min(1, TOI), or the
+ *   continuation of a line search.
+ * which 3 (after the trial energies): accept the largest trial step with
+ *   E(q + alpha dq) - E(q) <= 0, else continue halving or stop. */
+__global__ void k_ctrl(Scene S, int which) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= S.NP) return;
+  ProbState& P = S.ps[p];
+  const Counters& c0 = S.cnt[0];
+  const Counters& c1 = S.cnt[1];
+  if (which == 0) {
+    P.state = PS_NEWTON;
+    P.status = -4; /* not converged yet */
+    P.newton = P.halvings = P.ls_count = P.pcg_total = 0;
+    P.min_alpha = 1.0;
+    P.final_eps = 0.0;
+    P.alpha_acc = 0.0;
+    return;
+  }
+  if (which == 1) {
+    if (P.state != PS_NEWTON || static_overflow(c0, S) || c0.err) return;
+    P.newton += 1;
+    P.pcg_total += P.pcg_iters;
+    const double eps =
+        __longlong_as_double((long long)P.max_dq) / (S.dt * P.scale);
+    P.final_eps = eps;
+    if (!isfinite(eps)) {
+      P.state = PS_DONE;
+      P.status = -4;
+    } else if (eps < S.theta) {
+      P.state = PS_DONE;
+      P.status = 0;
+    }
+    return;
+  }
+  if (which == 2) {
+    if (P.state == PS_NEWTON) {
+      const double toi = __longlong_as_double((long long)P.min_toi);
+      P.alpha_base = fmin(1.0, toi);
+      P.ls_count = 0;
+    }
+    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
+    return;
+  }
+  /* which == 3 */
+  ctrl_linesearch(S, P, c0, c1);
+  if (P.state != PS_DONE) atomicAdd(&S.cnt[1].active, 1);
+}
+
+__device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
+                                                const Counters& c0,
+                                                const Counters& c1) {
+  if (P.state == PS_DONE) return;
+  const bool fresh = P.state == PS_NEWTON && P.ls_count == 0;
+  if (fresh && (static_overflow(c0, S) || c0.err)) return; /* pass redone */
+  if (swept_overflow(c1, S) || c1.err) {
+    if (fresh) P.newton -= 1; /* the Newton iteration is redone */
+    return;
+  }
+  /* trial j of this line search is alpha_max 2^-j, j = ls_count + k */
+  int k = 0;
+  while (k < LS_TRIALS && !(P.dE[k] <= 0.0)) ++k;
+  if (k < LS_TRIALS && P.ls_count + k <= S.max_ls) {
+    const double a = P.alpha_base * ldexp(1.0, -k);
+    P.alpha_acc = a;
+    P.halvings += P.ls_count + k;
+    P.ls_count = 0;
+    P.min_alpha = fmin(P.min_alpha, a);
+    P.state = PS_NEWTON;
+    if (P.newton >= S.max_newton) {
+      P.state = PS_DONE;
+      P.status = -4;
+    }
+  } else {
+    P.ls_count += LS_TRIALS;
+    if (P.ls_count > S.max_ls) {
+      P.halvings += S.max_ls;
+      P.state = PS_DONE;
+      P.status = P.final_eps < 10.0 * S.theta ? 0 : -5;
+    } else {
+      P.state = PS_LINESEARCH;
+      P.alpha_base *= ldexp(1.0, -LS_TRIALS);
+    }
+  }
+}
+
+/* q += alpha_acc dq for the bodies of problems that accepted a step */
+__global__ void k_update_multi(Scene S) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 12 * S.B) return;
+  const int b = t / 12;
+  if (S.kind[b] != 0) return;
+  const double a = S.ps[S.bprob[b]].alpha_acc;
+  if (a != 0.0) S.q[t] += a * S.dq[t];
+}
+
+/* fresh PCG accumulators (the hooks' direct linear solve) */
+__global__ void k_reset_pcg(Scene S) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) S.cnt->bar = 0;
+  if (t < S.NP) {
+    ProbState& P = S.ps[t];
+    P.bb = 0.0;
+    P.pcg_iters = 0;
+    for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
+  }
+}
+
+/* start of a pass: fresh counter blocks, per-problem transients, and the
+ * block-row counts of the PCG system */
+__global__ void k_reset_iter(Scene S, Counters fresh) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 2) S.cnt[t] = fresh;
+  if (t < S.NP) {
+    ProbState& P = S.ps[t];
+    P.max_dq = 0;
+    P.min_toi = fresh.min_toi;
+    P.alpha_acc = 0.0;
+    P.bb = 0.0;
+    P.pcg_iters = 0;
+    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
+    for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
+  }
+  for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
+}
+
+/* Interpenetration check for the initial state: counts edge-triangle
+ * crossings between different bodies (segment strictly crossing the
+ * triangle's plane and passing strictly inside its three edges, by signed
+ * volumes), over every body pair and chunk pair whose boxes meet. */
+__device__ __forceinline__ double orient3(const double* a, const double* b,
+                                          const double* c, const double* d) {
+  double u[3], v[3], w[3], n[3];
+  for (int i = 0; i < 3; ++i) {
+    u[i] = b[i] - a[i];
+    v[i] = c[i] - a[i];
+    w[i] = d[i] - a[i];
+  }
+  cross3(u, v, n);
+  return dot3(n, w);
+}
+
+__global__ __launch_bounds__(256) void k_crossings(Scene S) {
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  for (int p = blockIdx.x; p < nbp; p += gridDim.x) {
+    const int2 ab = S.bp[p];
+    for (int dir = 0; dir < 2; ++dir) {
+      const int* ce = S.body_chunk + 6 * (dir ? ab.y : ab.x);
+      const int* ct = S.body_chunk + 6 * (dir ? ab.x : ab.y);
+      const int ne = ce[5] - ce[4], nt = ct[3] - ct[2];
+      for (int t = threadIdx.x; t < ne * nt; t += blockDim.x) {
+        const int E = ce[4] + t / nt, Tc = ct[2] + t % nt;
+        if (!box_overlap(S.ch_box + 6 * E, S.ch_box + 6 * Tc, 0.0)) continue;
+        for (int i = 0; i < S.ch_count[E]; ++i) {
+          const int e = S.ch_prims[S.ch_start[E] + i];
+          double p0[3], p1[3];
+          vertex_pos(S, S.edge[e], p0);
+          vertex_pos(S, S.edge[S.E + e], p1);
+          for (int j = 0; j < S.ch_count[Tc]; ++j) {
+            const int tri = S.ch_prims[S.ch_start[Tc] + j];
+            double a[3], b[3], c[3];
+            vertex_pos(S, S.tri[tri], a);
+            vertex_pos(S, S.tri[S.T + tri], b);
+            vertex_pos(S, S.tri[2 * S.T + tri], c);
+            const double s0 = orient3(a, b, c, p0), s1 = orient3(a, b, c, p1);
+            if (!((s0 > 0 && s1 < 0) || (s0 < 0 && s1 > 0))) continue;
+            const double o1 = orient3(p0, p1, a, b), o2 = orient3(p0, p1, b, c),
+                         o3 = orient3(p0, p1, c, a);
+            if ((o1 > 0 && o2 > 0 && o3 > 0) || (o1 < 0 && o2 < 0 && o3 < 0))
+              atomicAdd(&S.cnt->n_act, 1);
+          }
+        }
+      }
+    }
+  }
+}
+
+/* zero the off-diagonal blocks and used flags of the current body pairs */
+template <typename HT>
+__global__ void k_clear_slots(Scene S) {
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  HT* Ho = (HT*)S.Hoff;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < 144L * nbp;
+       t += (long)gridDim.x * blockDim.x) {
+    Ho[t] = HT(0);
+    if (t % 144 == 0) S.slot_used[t / 144] = 0;
+  }
+}
+
+/* ================================================================== */
 /* host launchers                                                      */
 /* ================================================================== */
 static const int GRID_STRIDE_BLOCKS = 1024;
@@ -1311,7 +1728,10 @@ void launch_scale(const Scene& S, double* out6, hipStream_t st) {
                      st, S, (unsigned long long*)out6);
 }
 void launch_body_terms(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_body_terms, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S);
+  if (S.mixed)
+    hipLaunchKernelGGL(k_body_terms<float>, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S);
+  else
+    hipLaunchKernelGGL(k_body_terms<double>, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S);
 }
 void launch_boxes(const Scene& S, int swept, hipStream_t st) {
   hipLaunchKernelGGL(k_boxes, dim3(cdiv(S.NC + S.B, 256)), dim3(256), 0, st, S, swept);
@@ -1333,8 +1753,36 @@ void launch_filter(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_filter, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
 }
 void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st) {
-  unsigned g = n_act_hint > 0 ? min(4096u, cdiv(n_act_hint, 64)) : 512u;
-  hipLaunchKernelGGL(k_assemble, dim3(g), dim3(64), 0, st, S);
+  unsigned g = n_act_hint > 0 ? min(4096u, cdiv(n_act_hint, PAIRS_PER_WG)) : 2048u;
+  if (S.mixed)
+    hipLaunchKernelGGL(k_assemble<float>, dim3(g), dim3(64), 0, st, S);
+  else
+    hipLaunchKernelGGL(k_assemble<double>, dim3(g), dim3(64), 0, st, S);
+}
+void launch_energy_multi(const Scene& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_energy_multi, dim3(512), dim3(256), 0, st, S);
+}
+void launch_ctrl(const Scene& S, int which, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl, dim3(cdiv(S.NP, 64)), dim3(64), 0, st, S, which);
+}
+void launch_update_multi(const Scene& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_multi, dim3(cdiv(12L * S.B, 256)), dim3(256), 0, st, S);
+}
+void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st) {
+  unsigned g = std::max(cdiv(S.NP, 256), std::min(64u, cdiv(S.B + 1, 256)));
+  hipLaunchKernelGGL(k_reset_iter, dim3(g), dim3(256), 0, st, S, fresh);
+}
+void launch_reset_pcg(const Scene& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_pcg, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);
+}
+void launch_crossings(const Scene& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_crossings, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
+}
+void launch_clear_slots(const Scene& S, hipStream_t st) {
+  if (S.mixed)
+    hipLaunchKernelGGL(k_clear_slots<float>, dim3(512), dim3(256), 0, st, S);
+  else
+    hipLaunchKernelGGL(k_clear_slots<double>, dim3(512), dim3(256), 0, st, S);
 }
 void launch_bsr(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_bsr_count, dim3(256), dim3(256), 0, st, S);
@@ -1342,23 +1790,29 @@ void launch_bsr(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_bsr_fill, dim3(256), dim3(256), 0, st, S);
 }
 void launch_block_inverse(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_block_inverse, dim3(cdiv(S.B, 16)), dim3(192), 0, st, S);
+  if (S.mixed)
+    hipLaunchKernelGGL(k_block_inverse<float>, dim3(cdiv(S.B, 16)), dim3(192), 0, st, S);
+  else
+    hipLaunchKernelGGL(k_block_inverse<double>, dim3(cdiv(S.B, 16)), dim3(192), 0, st, S);
 }
 int pcg_max_grid() {
   int dev = 0, ncu = 0, per = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_pcg, 192, 0);
+  int per32 = 0;
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_pcg<double>, 192, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg<float>, 192, 0);
+  per = std::min(per, per32);
   return ncu * (per > 0 ? per : 1);
 }
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, hipStream_t st) {
   void* args[] = {(void*)&S, (void*)&eta, (void*)&max_it};
-  hipError_t e = hipLaunchCooperativeKernel((const void*)k_pcg, dim3(grid),
-                                            dim3(192), args, 0, st);
+  const void* fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st);
   return e == hipSuccess ? 0 : -1;
 }
 void launch_dq_norm(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_dq_norm, dim3(cdiv(12L * S.B, 256)), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_dq_norm, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S);
 }
 void launch_ccd(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_ccd, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);

@@ -53,6 +53,9 @@ struct abd_ctx {
   abd_params P;
   std::string err;
   hipStream_t st = nullptr;
+  hipStream_t side = nullptr; /* body terms run here, overlapping the
+                                 broad phase (default priority) */
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool finalized = false;
   std::vector<HBody> bodies;
   std::vector<double> xbar; /* [V][3] */
@@ -102,6 +105,21 @@ int dalloc(abd_ctx* ctx, T** p, size_t n) {
   return ABD_OK;
 }
 
+int dalloc_bytes(abd_ctx* ctx, void** p, size_t bytes) {
+  void* q = nullptr;
+  if (hipMalloc(&q, std::max<size_t>(bytes, 8)) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, ABD_E_OOM, "device allocation failed");
+  }
+  ctx->allocs.push_back(q);
+  *p = q;
+  return ABD_OK;
+}
+
+size_t hess_elem(const abd_ctx* ctx) {
+  return ctx->S.mixed ? sizeof(float) : sizeof(double);
+}
+
 template <class T>
 void dfree(abd_ctx* ctx, T* p) {
   if (!p) return;
@@ -134,17 +152,19 @@ struct StageTimer {
   abd_ctx* ctx;
   int stage;
   double bytes;
+  hipStream_t stream;
   hipEvent_t a = nullptr;
-  StageTimer(abd_ctx* c, int s, double b = 0.0) : ctx(c), stage(s), bytes(b) {
+  StageTimer(abd_ctx* c, int s, double b = 0.0, hipStream_t on = nullptr)
+      : ctx(c), stage(s), bytes(b), stream(on ? on : c->st) {
     if (ctx->timing) {
       a = get_event(ctx);
-      (void)hipEventRecord(a, ctx->st);
+      (void)hipEventRecord(a, stream);
     }
   }
   ~StageTimer() {
     if (ctx->timing) {
       hipEvent_t b = get_event(ctx);
-      (void)hipEventRecord(b, ctx->st);
+      (void)hipEventRecord(b, stream);
       ctx->pending.push_back({stage, a, b, bytes});
     }
   }
@@ -307,7 +327,7 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
     dfree(ctx, S.slot_used);
     S.cap_bp = (int)std::min<long>(2L * c.n_bp + 1024, 1L << 30);
     if ((rc = dalloc(ctx, &S.bp, S.cap_bp))) return rc;
-    if ((rc = dalloc(ctx, &S.Hoff, 144L * S.cap_bp))) return rc;
+    if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * hess_elem(ctx)))) return rc;
     if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
     dfree(ctx, S.col_slot);
     dfree(ctx, S.col_body);
@@ -361,42 +381,41 @@ void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
   if (S.has_ground) launch_pg(S, swept, ctx->st);
 }
 
-__global__ void k_clear_slots(Scene S) {
-  int nbp = min(S.cnt->n_bp, S.cap_bp);
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < 144L * nbp;
-       t += (long)gridDim.x * blockDim.x) {
-    S.Hoff[t] = 0.0;
-    if (t % 144 == 0) S.slot_used[t / 144] = 0;
-  }
-}
+void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd);
 
 /* static phase on the stream: body terms, broad phase, barrier assembly */
-void launch_static(abd_ctx* ctx) {
-  const Scene& S = ctx->S;
+void launch_static(abd_ctx* ctx, const Scene& S) {
+  /* body terms (writes g, Hdiag) on the side stream, concurrent with the
+   * broad phase; the assembly (which adds into g, Hdiag) waits for it */
+  (void)hipEventRecord(ctx->ev_fork, ctx->st);
+  (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
   {
-    StageTimer t(ctx, 0, (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96));
-    launch_body_terms(S, ctx->st);
+    StageTimer t(ctx, 0, (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96),
+                 ctx->side);
+    launch_body_terms(S, ctx->side);
   }
+  (void)hipEventRecord(ctx->ev_join, ctx->side);
   broad_phase(ctx, S, 0);
   {
     StageTimer t(ctx, 2);
     launch_filter(S, ctx->st);
-    hipLaunchKernelGGL(k_clear_slots, dim3(512), dim3(256), 0, ctx->st, S);
+    launch_clear_slots(S, ctx->st);
+    (void)hipStreamWaitEvent(ctx->st, ctx->ev_join, 0);
     launch_assemble(S, 0, ctx->st);
   }
 }
 
 /* block-Jacobi PCG and the Newton stop norm on the stream */
-int launch_solve(abd_ctx* ctx) {
-  const Scene& S = ctx->S;
+int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
   {
     StageTimer t(ctx, 6);
-    HIPCHK(hipMemsetAsync(S.row_cnt, 0, sizeof(int) * (S.B + 1), ctx->st));
+    if (!in_loop) {
+      /* the device loop's pass reset already cleared these */
+      HIPCHK(hipMemsetAsync(S.row_cnt, 0, sizeof(int) * (S.B + 1), ctx->st));
+      launch_reset_pcg(S, ctx->st);
+    }
     launch_bsr(S, ctx->st);
     launch_block_inverse(S, ctx->st);
-    /* the barrier counter and dot accumulators start at zero (the counter
-     * block was reset with the static phase) */
-    HIPCHK(hipMemsetAsync(S.acc, 0, sizeof(double) * 16, ctx->st));
   }
   const int grid = std::min(ctx->pcg_grid, std::max(1, (S.B + 15) / 16));
   StageTimer t(ctx, 3);
@@ -412,8 +431,9 @@ void account_pcg_bytes(abd_ctx* ctx) {
   /* algorithmic bytes of the PCG launch: per iteration the diagonal and
    * used off-diagonal blocks once, the block inverses once and seven
    * length-12B vectors */
-  const double per = (double)(S.B + ctx->h_cnt[0].n_rows_used / 2) * 1152.0 +
-                     (double)S.B * 1152.0 + 7.0 * 12.0 * S.B * 8.0;
+  const double blk = 144.0 * (double)hess_elem(ctx);
+  const double per = (double)(S.B + ctx->h_cnt[0].n_rows_used / 2) * blk +
+                     (double)S.B * blk + 7.0 * 12.0 * S.B * 8.0;
   ctx->t_bytes[3] += per * ctx->h_cnt[0].pcg_iters;
 }
 
@@ -421,15 +441,19 @@ void account_pcg_bytes(abd_ctx* ctx) {
  * energy difference at alpha_scale * min(1, TOI) */
 void launch_swept(abd_ctx* ctx, bool ccd, bool energy_at_toi) {
   const Scene Ssw = swept_scene(ctx);
-  broad_phase(ctx, Ssw, 1);
-  if (ccd) {
-    StageTimer t(ctx, 4);
-    launch_ccd(Ssw, ctx->st);
-  }
+  launch_swept_s(ctx, Ssw, ccd);
   if (energy_at_toi) {
     StageTimer t(ctx, 5);
     launch_energy(Ssw, 1.0, 0 | (1 << 1), 1,
                   ctx->S.partials + ctx->S.cap_partials - 1, ctx->st);
+  }
+}
+
+void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd) {
+  broad_phase(ctx, Ssw, 1);
+  if (ccd) {
+    StageTimer t(ctx, 4);
+    launch_ccd(Ssw, ctx->st);
   }
 }
 
@@ -438,7 +462,7 @@ int assemble(abd_ctx* ctx) {
   for (int attempt = 0; attempt < 8; ++attempt) {
     int rc = reset_counters(ctx, 0);
     if (rc) return rc;
-    launch_static(ctx);
+    launch_static(ctx, ctx->S);
     if ((rc = read_counters(ctx, 0))) return rc;
     bool changed = false;
     if ((rc = grow(ctx, ctx->h_cnt[0], &changed))) return rc;
@@ -449,7 +473,7 @@ int assemble(abd_ctx* ctx) {
 
 /* PCG on the assembled system; counters read */
 int linear_solve(abd_ctx* ctx, int* iters) {
-  int rc = launch_solve(ctx);
+  int rc = launch_solve(ctx, ctx->S, false);
   if (rc) return rc;
   if ((rc = read_counters(ctx, 0))) return rc;
   *iters = ctx->h_cnt[0].pcg_iters;
@@ -500,28 +524,52 @@ int energy(abd_ctx* ctx, int phase, double alpha, int mode, int with_pairs,
   return ABD_OK;
 }
 
-/* One Newton iteration with a single host synchronisation: static phase,
- * PCG, swept phase, CCD and the energy difference at the CCD step are
- * queued back to back; the counters of both phases come back together. */
-int newton_iteration(abd_ctx* ctx) {
-  for (int attempt = 0; attempt < 8; ++attempt) {
-    int rc = reset_both(ctx);
-    if (rc) return rc;
-    launch_static(ctx);
-    if ((rc = launch_solve(ctx))) return rc;
-    launch_swept(ctx, true, true);
-    HIPCHK(hipMemcpyAsync(ctx->h_buf, ctx->S.partials + ctx->S.cap_partials - 1,
-                          sizeof(double), hipMemcpyDeviceToHost, ctx->st));
-    if ((rc = read_counters(ctx, 0, 2))) return rc;
-    bool changed = false;
-    if ((rc = grow(ctx, ctx->h_cnt[0], &changed))) return rc;
-    if (changed) continue;
-    account_pcg_bytes(ctx);
-    if ((rc = grow(ctx, ctx->h_cnt[1], &changed))) return rc;
-    if (changed) return swept_phase(ctx, true, true);
-    return ABD_OK;
+/* swept broad phase and CCD on the stream for a given scene */
+void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd);
+
+/* One pass of the device-driven Newton loop, queued without host
+ * synchronisation: every problem in the Newton state assembles, solves
+ * and checks |dq|; every problem not done runs the swept phase, CCD, the
+ * trial energies of its line search and, on acceptance, its update. */
+int run_pass(abd_ctx* ctx) {
+  Scene S1 = ctx->S;
+  S1.iter_mode = 1;
+  Scene S2 = swept_scene(ctx);
+  S2.iter_mode = 2;
+  launch_reset_iter(S1, fresh_counters(), ctx->st);
+  launch_static(ctx, S1);
+  int rc = launch_solve(ctx, S1, true);
+  if (rc) return rc;
+  launch_ctrl(S1, 1, ctx->st);
+  launch_swept_s(ctx, S2, true);
+  launch_ctrl(S1, 2, ctx->st);
+  {
+    StageTimer t(ctx, 5);
+    launch_energy_multi(S2, ctx->st);
   }
-  return fail(ctx, ABD_E_OOM, "capacity growth did not settle");
+  launch_ctrl(S1, 3, ctx->st);
+  launch_update_multi(S1, ctx->st);
+  return ABD_OK;
+}
+
+/* Device loop: passes until every problem is done; one host read per pass
+ * (both counter blocks: overflow and the number of active problems). */
+int device_solve(abd_ctx* ctx) {
+  launch_ctrl(ctx->S, 0, ctx->st);
+  const int max_pass =
+      ctx->P.max_newton * (2 + (ctx->P.max_ls + LS_TRIALS) / LS_TRIALS) + 8;
+  for (int pass = 0; pass < max_pass; ++pass) {
+    int rc = run_pass(ctx);
+    if (rc) return rc;
+    if ((rc = read_counters(ctx, 0, 2))) return rc;
+    bool ch0 = false, ch1 = false;
+    if ((rc = grow(ctx, ctx->h_cnt[0], &ch0))) return rc;
+    if ((rc = grow(ctx, ctx->h_cnt[1], &ch1))) return rc;
+    if (!ch0) account_pcg_bytes(ctx);
+    if (ch0 || ch1) continue;
+    if (ctx->h_cnt[1].active == 0) return ABD_OK;
+  }
+  return fail(ctx, ABD_E_NOCONV, "device loop did not finish");
 }
 
 int check_ctx(abd_ctx* ctx, bool need_final) {
@@ -544,7 +592,8 @@ int abd_create(abd_ctx** out, const abd_params* p) {
   *out = nullptr;
   if (!(p->dt > 0) || !(p->dhat > 0) || !(p->kappa > 0) || !(p->kappa_A >= 0) ||
       p->max_newton < 1 || p->max_pcg < 1 || p->max_ls < 0 ||
-      !(p->newton_theta > 0) || !(p->pcg_eta > 0) || p->precision != ABD_FP64)
+      !(p->newton_theta > 0) || !(p->pcg_eta > 0) ||
+      (p->precision != ABD_FP64 && p->precision != ABD_MIXED))
     return ABD_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -569,6 +618,9 @@ void abd_destroy(abd_ctx* ctx) {
     (void)hipEventDestroy(p.b);
   }
   for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->side) (void)hipStreamDestroy(ctx->side);
   delete ctx;
 }
 
@@ -794,9 +846,10 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.cand_pg, S.cap_pg))) return rc;
   if ((rc = dalloc(ctx, &S.act, S.cap_act))) return rc;
   if ((rc = dalloc(ctx, &S.g, 12L * B))) return rc;
-  if ((rc = dalloc(ctx, &S.Hdiag, 144L * B))) return rc;
-  if ((rc = dalloc(ctx, &S.Pinv, 144L * B))) return rc;
-  if ((rc = dalloc(ctx, &S.Hoff, 144L * S.cap_bp))) return rc;
+  S.mixed = ctx->P.precision == ABD_MIXED;
+  if ((rc = dalloc_bytes(ctx, &S.Hdiag, 144L * B * hess_elem(ctx)))) return rc;
+  if ((rc = dalloc_bytes(ctx, &S.Pinv, 144L * B * hess_elem(ctx)))) return rc;
+  if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * hess_elem(ctx)))) return rc;
   if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
   if ((rc = dalloc(ctx, &S.row_ptr, B + 1))) return rc;
   if ((rc = dalloc(ctx, &S.row_cnt, B + 1))) return rc;
@@ -811,10 +864,26 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.partials, S.cap_partials))) return rc;
   if ((rc = dalloc(ctx, &S.cnt, 2))) return rc;
+  S.NP = 1;
+  S.theta = ctx->P.newton_theta;
+  S.eta = ctx->P.pcg_eta;
+  S.max_newton = ctx->P.max_newton;
+  S.max_ls = ctx->P.max_ls;
+  S.max_pcg = ctx->P.max_pcg;
+  S.iter_mode = 0;
+  {
+    std::vector<int> bp0(B, 0);
+    if ((rc = upload(ctx, &S.bprob, bp0))) return rc;
+    if ((rc = dalloc(ctx, &S.ps, 1))) return rc;
+    HIPCHK(hipMemset(S.ps, 0, sizeof(ProbState)));
+  }
   if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
+  HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
   ctx->finalized = true;
   /* initial feasibility: every candidate distance > 0 */
   if ((rc = assemble(ctx))) return rc;
@@ -822,6 +891,16 @@ int abd_finalize(abd_ctx* ctx) {
   if (!(md > 0.0)) {
     ctx->finalized = false;
     return fail(ctx, ABD_E_INFEASIBLE, "initial state has a distance <= 0");
+  }
+  /* and no edge of one body crosses a triangle of another (the counter
+   * block's active count is reused as the crossing counter) */
+  if ((rc = reset_counters(ctx, 0))) return rc;
+  broad_phase(ctx, S, 0);
+  launch_crossings(S, ctx->st);
+  if ((rc = read_counters(ctx, 0))) return rc;
+  if (ctx->h_cnt[0].n_act > 0) {
+    ctx->finalized = false;
+    return fail(ctx, ABD_E_INFEASIBLE, "initial state has intersecting bodies");
   }
   return ABD_OK;
 }
@@ -918,6 +997,8 @@ int abd_begin_step(abd_ctx* ctx) {
     if (std::isfinite(lo) && std::isfinite(hi)) l2 += (hi - lo) * (hi - lo);
   }
   ctx->scale = l2 > 0 ? std::sqrt(l2) : 1.0;
+  HIPCHK(hipMemcpy(&ctx->S.ps[0].scale, &ctx->scale, sizeof(double),
+                   hipMemcpyHostToDevice));
   return ABD_OK;
 }
 
@@ -930,6 +1011,8 @@ int abd_set_step(abd_ctx* ctx, const double* qt, const double* qtilde,
   HIPCHK(hipMemcpy(ctx->S.qtilde, qtilde, sizeof(double) * 12 * ctx->S.B,
                    hipMemcpyHostToDevice));
   ctx->scale = scale;
+  HIPCHK(hipMemcpy(&ctx->S.ps[0].scale, &ctx->scale, sizeof(double),
+                   hipMemcpyHostToDevice));
   return ABD_OK;
 }
 
@@ -937,54 +1020,30 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
   int rc = check_ctx(ctx, true);
   if (rc) return rc;
   auto t0 = std::chrono::steady_clock::now();
-  const Scene& S = ctx->S;
   abd_stats st;
   std::memset(&st, 0, sizeof(st));
-  st.min_alpha = 1.0;
-  st.min_dist = INFINITY;
   st.scene_scale = ctx->scale;
-  const double hl = ctx->P.dt * ctx->scale;
-  int status = ABD_E_NOCONV;
-  for (int it = 0; it < ctx->P.max_newton; ++it) {
-    if ((rc = newton_iteration(ctx))) { status = rc; break; }
-    const Counters& c = ctx->h_cnt[0];
-    st.n_cand_pt = c.n_pt;
-    st.n_cand_ee = c.n_ee;
-    st.n_cand_pg = c.n_pg;
-    st.n_active = c.n_act;
-    st.min_dist = bits_to_double(c.min_dist);
-    st.pcg_iters_total += c.pcg_iters;
-    st.newton_iters = it + 1;
-    const double eps = bits_to_double(c.max_dq) / hl;
-    st.final_eps_N = eps;
-    if (!std::isfinite(eps)) {
-      status = fail(ctx, ABD_E_NOCONV, "non-finite Newton direction");
-      break;
-    }
-    if (eps < ctx->P.newton_theta) { status = ABD_OK; break; }
-    double alpha = std::min(1.0, bits_to_double(ctx->h_cnt[1].min_toi));
-    double dE = ctx->h_buf[0];
-    int nh = 0;
-    while (dE > 0.0 && nh < ctx->P.max_ls) {
-      alpha *= 0.5;
-      ++nh;
-      if ((rc = energy(ctx, 1, alpha, 0, 1, &dE))) break;
-    }
-    if (rc) { status = rc; break; }
-    st.ls_halvings += nh;
-    if (dE > 0.0) {
-      if (eps < 10.0 * ctx->P.newton_theta) {
-        status = ABD_OK;
-      } else {
-        status = fail(ctx, ABD_E_LINESEARCH, "line search exhausted");
-      }
-      break;
-    }
-    st.min_alpha = std::min(st.min_alpha, alpha);
-    launch_update_q(S, alpha, ctx->st);
+  int status = device_solve(ctx);
+  ProbState P;
+  std::memset(&P, 0, sizeof(P));
+  if (hipMemcpy(&P, ctx->S.ps, sizeof(P), hipMemcpyDeviceToHost) != hipSuccess)
+    status = fail(ctx, ABD_E_DEVICE, "reading the solve state failed");
+  if (status == ABD_OK) {
+    status = P.status;
+    if (status == ABD_E_NOCONV) ctx->err = "Newton did not converge";
+    if (status == ABD_E_LINESEARCH) ctx->err = "line search exhausted";
   }
-  if (status == ABD_E_NOCONV && ctx->err.empty()) ctx->err = "Newton did not converge";
-  (void)hipStreamSynchronize(ctx->st);
+  const Counters& c = ctx->h_cnt[0];
+  st.newton_iters = P.newton;
+  st.pcg_iters_total = P.pcg_total;
+  st.ls_halvings = P.halvings;
+  st.final_eps_N = P.final_eps;
+  st.min_alpha = P.min_alpha;
+  st.n_cand_pt = c.n_pt;
+  st.n_cand_ee = c.n_ee;
+  st.n_cand_pg = c.n_pg;
+  st.n_active = c.n_act;
+  st.min_dist = bits_to_double(c.min_dist);
   st.status = status;
   st.t_solve_ms =
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
@@ -1140,8 +1199,15 @@ int abd_eval(abd_ctx* ctx, const double* q, double* E, double* g,
   if (!rc) {
     if (n_active) *n_active = ctx->h_cnt[0].n_act;
     if (g) HIPCHK(hipMemcpy(g, S.g, sizeof(double) * 12 * B, hipMemcpyDeviceToHost));
-    if (Hdiag)
-      HIPCHK(hipMemcpy(Hdiag, S.Hdiag, sizeof(double) * 144 * B, hipMemcpyDeviceToHost));
+    if (Hdiag) {
+      if (S.mixed) {
+        std::vector<float> h(144L * B);
+        HIPCHK(hipMemcpy(h.data(), S.Hdiag, sizeof(float) * 144 * B, hipMemcpyDeviceToHost));
+        for (size_t i = 0; i < h.size(); ++i) Hdiag[i] = h[i];
+      } else {
+        HIPCHK(hipMemcpy(Hdiag, S.Hdiag, sizeof(double) * 144 * B, hipMemcpyDeviceToHost));
+      }
+    }
     int nbp = ctx->h_cnt[0].n_bp;
     std::vector<int> used(nbp);
     std::vector<int2> bp(nbp);
@@ -1161,8 +1227,15 @@ int abd_eval(abd_ctx* ctx, const double* q, double* E, double* g,
         for (size_t i = 0; i < list.size(); ++i) {
           off_ij[2 * i] = list[i].first.first;
           off_ij[2 * i + 1] = list[i].first.second;
-          HIPCHK(hipMemcpy(Hoff + 144 * i, S.Hoff + 144L * list[i].second,
-                           sizeof(double) * 144, hipMemcpyDeviceToHost));
+          if (S.mixed) {
+            float h[144];
+            HIPCHK(hipMemcpy(h, (float*)S.Hoff + 144L * list[i].second,
+                             sizeof(float) * 144, hipMemcpyDeviceToHost));
+            for (int k = 0; k < 144; ++k) Hoff[144 * i + k] = h[k];
+          } else {
+            HIPCHK(hipMemcpy(Hoff + 144 * i, (double*)S.Hoff + 144L * list[i].second,
+                             sizeof(double) * 144, hipMemcpyDeviceToHost));
+          }
         }
       }
     }

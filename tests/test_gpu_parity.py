@@ -242,6 +242,15 @@ def test_error_paths():
     with pytest.raises(abd.AbdError) as e:
         abd.Solver(overlap)
     assert e.value.code == abd.E_INFEASIBLE
+    # interpenetrating cubes whose closest features are all > 0 apart: the
+    # edge-triangle crossing check rejects them
+    deep = scenes.Scene("deep", scenes.default_params(), [
+        scenes.Body(v, t, 1000.0, scenes.identity_q([0, 2, 0]), np.zeros(12)),
+        scenes.Body(v, t, 1000.0, scenes.identity_q([0.5, 2.3, 0.1]),
+                    np.zeros(12))], 1)
+    with pytest.raises(abd.AbdError) as e:
+        abd.Solver(deep)
+    assert e.value.code == abd.E_INFEASIBLE
     sc = scenes.config(0)
     gpu = abd.Solver(sc)
     with pytest.raises(abd.AbdError) as e:
