@@ -49,6 +49,46 @@ def cpu_baseline(seed, n_steps):
                        f"single thread)")
 
 
+def bench_batch(abd, scenes, torch, n_scenes, steps, warmup):
+    """n_scenes independent 8-cube scenes (different seeds, same
+    parameters): one batched solve per step against one solve per context
+    in turn.  Both advance identical copies of the scenes."""
+    import time as _t
+    scs = [scenes.config(0, seed) for seed in range(n_scenes)]
+    one = [abd.Solver(sc) for sc in scs]
+    many = [abd.Solver(sc) for sc in scs]
+    bt = abd.Batch(many)
+
+    def run(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        it = 0
+        for _ in range(steps):
+            it += fn()
+        torch.cuda.synchronize()
+        return it, _t.perf_counter() - t0
+
+    def seq():
+        return sum(s.step()["newton_iters"] for s in one)
+
+    def bat():
+        return sum(st["newton_iters"] for st in bt.step())
+
+    it_s, t_s = run(seq)
+    it_b, t_b = run(bat)
+    bt.close()
+    for s in one + many:
+        s.close()
+    return dict(workload=f"{n_scenes} independent 8-cube scenes, FP64",
+                steps=steps, batched_newton_iters_per_s=it_b / t_b,
+                sequential_newton_iters_per_s=it_s / t_s,
+                batched_ms_per_step=t_b * 1e3 / steps,
+                sequential_ms_per_step=t_s * 1e3 / steps,
+                speedup=(it_b / t_b) / (it_s / t_s))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -59,6 +99,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--breakdown-steps", type=int, default=3)
+    ap.add_argument("--batch-scenes", type=int, default=64)
+    ap.add_argument("--no-batch", action="store_true")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -85,7 +128,9 @@ def main():
         st = solver.step()
         log(f"warmup {i}: newton={st['newton_iters']} "
             f"pcg={st['pcg_iters_total']} ms={st['t_solve_ms']:.1f}")
-    solver.set_timing(True)
+    # timed region: only the cooperative PCG launch (the one launch outside
+    # the captured pass graphs) carries events, so the solve runs as usual
+    solver.set_timing(abd.TIMING_PCG)
     solver.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -100,21 +145,28 @@ def main():
             f"ms={st['t_solve_ms']:.1f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    tm_timed = solver.timing()
+    x64 = solver.vertices()  # state after warmup + timed steps
+    # stage breakdown from extra instrumented steps (every stage timed,
+    # direct launches instead of graphs); not part of the timed region
+    solver.set_timing(abd.TIMING_ALL)
+    solver.reset_timing()
+    for i in range(a.breakdown_steps):
+        solver.step()
     tm = solver.timing()
-    # dominant kernel family with an algorithmic byte count
-    timed = {k: v for k, v in tm.items() if v["bytes"] > 0 and v["launches"]}
-    dom = max(timed, key=lambda k: timed[k]["ms"]) if timed else None
+    solver.set_timing(abd.TIMING_OFF)
+    dom = max((k for k in tm if tm[k]["launches"]), key=lambda k: tm[k]["ms"])
     roof = None
-    if dom:
-        d = timed[dom]
+    d = tm_timed[dom] if dom == "pcg" else tm[dom]
+    if d["bytes"] > 0 and d["launches"]:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = dict(kernel=dom, bound="hbm", achieved=achieved,
-                    peak=HBM_PEAK_GBS, unit="GB/s",
+        roof = dict(kernel="k_pcg" if dom == "pcg" else dom, bound="hbm",
+                    achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=achieved / HBM_PEAK_GBS, traffic=None,
                     launches=d["launches"],
-                    avg_launch_ms=d["ms"] / d["launches"])
-    q64, _ = solver.get_state()
-    x64 = solver.vertices()
+                    avg_launch_ms=d["ms"] / d["launches"],
+                    measured="timed region" if dom == "pcg"
+                    else "instrumented steps")
     l = float(np.linalg.norm(np.ptp(x64, axis=0)))
     solver.close()
     mixed = None
@@ -123,7 +175,7 @@ def main():
         ms = abd.Solver(sc, precision=1)
         for i in range(a.warmup):
             ms.step()
-        ms.set_timing(True)  # same event overhead as the FP64 run
+        ms.set_timing(abd.TIMING_PCG)  # same event overhead as FP64
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         mnewton = 0
@@ -140,6 +192,10 @@ def main():
                          np.abs(xm - x64).max() / l))
         log(f"mixed: {mnewton} newton iters in {mel*1e3:.1f} ms")
         ms.close()
+    batch = None
+    if not a.no_batch:
+        batch = bench_batch(abd, scenes, torch, a.batch_scenes, 5, 1)
+        log(f"batch: {batch}")
     cpu = None
     if not a.no_cpu_baseline:
         log("cpu baseline ...")
@@ -162,11 +218,13 @@ def main():
                    "seed": a.seed, "precision": "fp64"},
         "newton_iters": newton,
         "pcg_iters": pcg,
-        "stage_ms": {k: round(v["ms"], 3) for k, v in tm.items()},
+        "stage_ms_instrumented": {k: round(v["ms"] / max(a.breakdown_steps, 1),
+                                           3) for k, v in tm.items()},
         "roofline": roof,
         "cpu_baseline": cpu,
         "mixed_vs_fp64_speedup": mixed["speedup_vs_fp64"] if mixed else None,
         "mixed": mixed,
+        "batch": batch,
     }
     print(json.dumps(out), flush=True)
 

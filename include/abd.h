@@ -27,8 +27,9 @@
  *    during the call; every output pointer is a caller-allocated HOST buffer
  *    of the documented size;
  *  - the library owns all device memory (allocated in abd_finalize and
- *    grown on demand); work is issued on the bound stream (default: the
- *    null stream) and every call returns after its results are on the host;
+ *    grown on demand); work is issued on the bound stream (default: a
+ *    stream the library creates) and every call returns after its results
+ *    are on the host;
  *  - arrays are FP64 unless stated, array-of-structures: points [n][3],
  *    body states [n][12], 12x12 blocks [n][144] row-major in the DoF order
  *    [p0 p1 p2 A00 A01 A02 A10 A11 A12 A20 A21 A22];
@@ -167,8 +168,32 @@ int abd_get_qtilde(const abd_ctx* ctx, double* qtilde);
 int abd_set_step(abd_ctx* ctx, const double* qt, const double* qtilde,
                  double scale);
 
-/* Work on a caller stream (a hipStream_t); NULL = null stream. */
+/* Work on a caller stream (a hipStream_t; NULL = the legacy null stream,
+ * on which Newton passes are launched directly instead of replayed from
+ * captured graphs). */
 int abd_set_stream(abd_ctx* ctx, void* hip_stream);
+
+/* ---- batching: many local problems in the same launches ---- */
+typedef struct abd_batch abd_batch;
+
+/* Merge n finalized contexts with identical parameters and pair
+ * replication rule into one device scene (for instance the subdomains of
+ * several workers, or independent small scenes).  Problems never interact:
+ * no candidate pair joins two of them, and each keeps its own PCG
+ * recurrence, Newton stop test (with its own scene scale) and line search,
+ * so a batch solve gives what abd_local_solve would give on each context.
+ * The contexts stay usable and keep their own state.  Errors: INVALID_ARG
+ * (not finalized, parameters differ), OOM, DEVICE. */
+int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out);
+
+/* Solve Eq. 5 for every problem of the batch in one device loop: the
+ * current q, q^t, q-tilde, qdot, scene scale and shared-body data of each
+ * context are gathered in, every Newton pass runs all problems in the same
+ * kernel launches (replayed from captured graphs), and the solutions are
+ * scattered back to the contexts.  out: [n] stats (may be NULL).  Returns
+ * ABD_OK or the first non-OK problem status. */
+int abd_batch_solve(abd_batch* batch, abd_stats* out);
+void abd_batch_destroy(abd_batch* batch);
 
 /* ---- inspection hooks (used for parity; not needed to simulate) ---- */
 
@@ -211,8 +236,14 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
  * 0 body terms, 1 broad phase, 2 barrier assembly, 3 PCG, 4 CCD,
  * 5 line search, 6 other.  abd_get_timing returns the summed milliseconds,
  * the number of timed launches and the algorithmic bytes those launches
- * had to move (sizes as launched).  Timing adds event records; off by
- * default. */
+ * had to move (sizes as launched).  Modes: ABD_TIMING_OFF (default);
+ * ABD_TIMING_ALL times every stage, which replaces the captured graphs by
+ * direct launches; ABD_TIMING_PCG times only the cooperative PCG launch,
+ * which runs outside the graphs, so the solve keeps its normal launch
+ * path.  Other values: INVALID_ARG. */
+#define ABD_TIMING_OFF 0
+#define ABD_TIMING_ALL 1
+#define ABD_TIMING_PCG 2
 int abd_set_timing(abd_ctx* ctx, int32_t on);
 int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms,
                    int64_t* launches, double* bytes);

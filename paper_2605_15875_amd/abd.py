@@ -53,7 +53,11 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_set_step", "abd_set_stream", "abd_get_vertices",
            "abd_export_candidates", "abd_eval", "abd_direction", "abd_ccd",
            "abd_energy_delta", "abd_set_timing", "abd_get_timing",
-           "abd_reset_timing"]
+           "abd_reset_timing", "abd_batch_create", "abd_batch_solve",
+           "abd_batch_destroy"]
+
+
+TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
 
 
 def lib():
@@ -96,6 +100,10 @@ def lib():
         "abd_set_timing": (C.c_int, [vp, C.c_int32]),
         "abd_get_timing": (C.c_int, [vp, C.c_int32, dp, lp, dp]),
         "abd_reset_timing": (C.c_int, [vp]),
+        "abd_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32,
+                                       C.POINTER(vp)]),
+        "abd_batch_solve": (C.c_int, [vp, C.POINTER(Stats)]),
+        "abd_batch_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -331,4 +339,44 @@ class Solver:
             self._check(lib().abd_get_timing(self.h, s, _d(ms), _l(n), _d(by)))
             out[name] = dict(ms=float(ms[0]), launches=int(n[0]),
                              bytes=float(by[0]))
+        return out
+
+
+class Batch:
+    """Several Solver contexts solved together in the same launches."""
+
+    def __init__(self, solvers):
+        self.solvers = list(solvers)
+        arr = (C.c_void_p * len(self.solvers))(*[s.h for s in self.solvers])
+        h = C.c_void_p()
+        rc = lib().abd_batch_create(arr, len(self.solvers), C.byref(h))
+        if rc != OK:
+            raise AbdError(rc, "abd_batch_create: " + self.solvers[0].error())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().abd_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def local_solve(self, check=True):
+        st = (Stats * len(self.solvers))()
+        rc = lib().abd_batch_solve(self.h, st)
+        if check and rc != OK:
+            bad = [i for i in range(len(self.solvers)) if st[i].status != OK]
+            raise AbdError(rc, f"batch solve: problems {bad} failed")
+        return [s.as_dict() for s in st]
+
+    def step(self):
+        for s in self.solvers:
+            s.begin_step()
+        out = self.local_solve()
+        for s in self.solvers:
+            s.end_step()
         return out

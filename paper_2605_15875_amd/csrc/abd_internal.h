@@ -620,6 +620,15 @@ void launch_ctrl(const Scene& S, int which, hipStream_t st);
 void launch_update_multi(const Scene& S, hipStream_t st);
 void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st);
 void launch_reset_pcg(const Scene& S, hipStream_t st);
+/* batch state movement: one descriptor per problem */
+struct ProbCopy {
+  double *q, *qt, *qtilde, *qdot; /* the problem's own context arrays */
+  int nb, off;                     /* bodies, body offset in the batch */
+};
+void launch_gather(const Scene& S, const ProbCopy* pc, const double* scales,
+                   int np, int max_nb, hipStream_t st);
+void launch_scatter(const Scene& S, const ProbCopy* pc, int np, int max_nb,
+                    hipStream_t st);
 void launch_update_q(const Scene& S, double alpha, hipStream_t st);
 void launch_scale(const Scene& S, double* out6, hipStream_t st);
 

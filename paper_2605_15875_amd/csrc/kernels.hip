@@ -1645,6 +1645,25 @@ __global__ void k_reset_iter(Scene S, Counters fresh) {
   for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
 }
 
+/* gather every problem's state into the batch arrays (grid.y = problem) */
+__global__ void k_gather(Scene S, const ProbCopy* pc, const double* scales) {
+  const ProbCopy c = pc[blockIdx.y];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t == 0) S.ps[blockIdx.y].scale = scales[blockIdx.y];
+  if (t >= 12 * c.nb) return;
+  const int o = 12 * c.off + t;
+  S.q[o] = c.q[t];
+  S.qt[o] = c.qt[t];
+  S.qtilde[o] = c.qtilde[t];
+  S.qdot[o] = c.qdot[t];
+}
+__global__ void k_scatter(Scene S, const ProbCopy* pc) {
+  const ProbCopy c = pc[blockIdx.y];
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 12 * c.nb) return;
+  c.q[t] = S.q[12 * c.off + t];
+}
+
 /* Interpenetration check for the initial state: counts edge-triangle
  * crossings between different bodies (segment strictly crossing the
  * triangle's plane and passing strictly inside its three edges, by signed
@@ -1771,6 +1790,16 @@ void launch_update_multi(const Scene& S, hipStream_t st) {
 void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st) {
   unsigned g = std::max(cdiv(S.NP, 256), std::min(64u, cdiv(S.B + 1, 256)));
   hipLaunchKernelGGL(k_reset_iter, dim3(g), dim3(256), 0, st, S, fresh);
+}
+void launch_gather(const Scene& S, const ProbCopy* pc, const double* scales,
+                   int np, int max_nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_gather, dim3(cdiv(12L * max_nb, 256), np), dim3(256), 0,
+                     st, S, pc, scales);
+}
+void launch_scatter(const Scene& S, const ProbCopy* pc, int np, int max_nb,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter, dim3(cdiv(12L * max_nb, 256), np), dim3(256), 0,
+                     st, S, pc);
 }
 void launch_reset_pcg(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_pcg, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);

@@ -63,14 +63,28 @@ struct abd_ctx {
   std::vector<double> erest2;
   int pair_mode = 0;
   double scale = 1.0;
+  /* problems of a merged batch scene (empty: one problem) */
+  std::vector<int> prob_of_body;
+  int np = 1;
+  /* host copy of the shared-body data, and its version */
+  std::vector<int> sh_ids, sh_kappa;
+  std::vector<double> sh_z, sh_u, sh_rho;
+  unsigned sh_version = 0;
   Scene S;
   Counters* h_cnt = nullptr; /* pinned */
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
   std::vector<void*> allocs;
   int pcg_grid = 0;
   int n_shared = 0;
+  /* captured passes of the device loop: [0] before the cooperative PCG
+   * launch, [1] after it; rebuilt whenever buffers or bound data change */
+  hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
+  bool graphs_ok = true; /* capture available on this runtime */
+  bool own_stream = false;
+  bool use_graphs = true;
   /* timing */
-  bool timing = false;
+  int timing = 0;      /* ABD_TIMING_* */
+  bool capturing = false;
   double t_ms[7] = {0}, t_bytes[7] = {0};
   int64_t t_n[7] = {0};
   std::vector<Pending> pending;
@@ -82,6 +96,14 @@ namespace {
 int fail(abd_ctx* c, int code, const std::string& m) {
   if (c) c->err = m;
   return code;
+}
+
+void drop_graphs(abd_ctx* c) {
+  for (auto& g : c->pass_graph)
+    if (g) {
+      (void)hipGraphExecDestroy(g);
+      g = nullptr;
+    }
 }
 
 #define HIPCHK(call)                                                     \
@@ -154,15 +176,21 @@ struct StageTimer {
   double bytes;
   hipStream_t stream;
   hipEvent_t a = nullptr;
+  bool active;
   StageTimer(abd_ctx* c, int s, double b = 0.0, hipStream_t on = nullptr)
       : ctx(c), stage(s), bytes(b), stream(on ? on : c->st) {
-    if (ctx->timing) {
+    /* never inside a capture; the PCG-only mode times the one launch that
+     * is not part of the captured graphs */
+    active = !ctx->capturing &&
+             (ctx->timing == ABD_TIMING_ALL ||
+              (ctx->timing == ABD_TIMING_PCG && stage == 3));
+    if (active) {
       a = get_event(ctx);
       (void)hipEventRecord(a, stream);
     }
   }
   ~StageTimer() {
-    if (ctx->timing) {
+    if (active) {
       hipEvent_t b = get_event(ctx);
       (void)hipEventRecord(b, stream);
       ctx->pending.push_back({stage, a, b, bytes});
@@ -316,8 +344,16 @@ double bits_to_double(unsigned long long b) {
 }
 
 /* ---------------- capacities ---------------- */
+bool over_cap(const Scene& S, const Counters& c) {
+  return c.n_bp > S.cap_bp || c.n_cp > S.cap_cp || c.n_pt > S.cap_pt ||
+         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg || c.n_act > S.cap_act;
+}
+void drop_graphs_if(abd_ctx* ctx, const Counters& c) {
+  if (over_cap(ctx->S, c)) drop_graphs(ctx);
+}
 int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
   Scene& S = ctx->S;
+  drop_graphs_if(ctx, c);
   *changed = false;
   auto need = [](int have, int n) { return n > have; };
   int rc;
@@ -531,15 +567,32 @@ void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd);
  * synchronisation: every problem in the Newton state assembles, solves
  * and checks |dq|; every problem not done runs the swept phase, CCD, the
  * trial energies of its line search and, on acceptance, its update. */
-int run_pass(abd_ctx* ctx) {
+void pass_pre(abd_ctx* ctx) {
+  Scene S1 = ctx->S;
+  S1.iter_mode = 1;
+  launch_reset_iter(S1, fresh_counters(), ctx->st);
+  launch_static(ctx, S1);
+  StageTimer t(ctx, 6);
+  launch_bsr(S1, ctx->st);
+  launch_block_inverse(S1, ctx->st);
+}
+
+int pass_pcg(abd_ctx* ctx) {
+  Scene S1 = ctx->S;
+  S1.iter_mode = 1;
+  const int grid = std::min(ctx->pcg_grid, std::max(1, (S1.B + 15) / 16));
+  StageTimer t(ctx, 3);
+  if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, grid, ctx->st))
+    return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
+  return ABD_OK;
+}
+
+void pass_post(abd_ctx* ctx) {
   Scene S1 = ctx->S;
   S1.iter_mode = 1;
   Scene S2 = swept_scene(ctx);
   S2.iter_mode = 2;
-  launch_reset_iter(S1, fresh_counters(), ctx->st);
-  launch_static(ctx, S1);
-  int rc = launch_solve(ctx, S1, true);
-  if (rc) return rc;
+  launch_dq_norm(S1, ctx->st);
   launch_ctrl(S1, 1, ctx->st);
   launch_swept_s(ctx, S2, true);
   launch_ctrl(S1, 2, ctx->st);
@@ -549,6 +602,65 @@ int run_pass(abd_ctx* ctx) {
   }
   launch_ctrl(S1, 3, ctx->st);
   launch_update_multi(S1, ctx->st);
+}
+
+/* capture one half of a pass into an executable graph */
+bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(ctx->st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  ctx->capturing = true;
+  if (which == 0) pass_pre(ctx);
+  else pass_post(ctx);
+  ctx->capturing = false;
+  hipError_t e = hipStreamEndCapture(ctx->st, &g);
+  if (e != hipSuccess || !g) {
+    (void)hipGetLastError();
+    if (g) (void)hipGraphDestroy(g);
+    return false;
+  }
+  e = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return false;
+  }
+  return true;
+}
+
+/* One pass of the device-driven Newton loop, queued without host
+ * synchronisation: every problem in the Newton state assembles, solves
+ * and checks |dq|; every problem not done runs the swept phase, CCD, the
+ * trial energies of its line search and, on acceptance, its update.  The
+ * parts before and after the cooperative PCG launch are replayed from
+ * captured graphs when possible (not while every stage is timed,
+ * and not on the legacy null stream, which cannot be captured). */
+int run_pass(abd_ctx* ctx) {
+  const bool graphs = ctx->use_graphs && ctx->graphs_ok &&
+                      ctx->timing != ABD_TIMING_ALL &&
+                      ctx->st != nullptr;
+  if (graphs && (!ctx->pass_graph[0] || !ctx->pass_graph[1])) {
+    drop_graphs(ctx);
+    if (!capture(ctx, 0, &ctx->pass_graph[0]) ||
+        !capture(ctx, 1, &ctx->pass_graph[1])) {
+      drop_graphs(ctx);
+      ctx->graphs_ok = false;
+    }
+  }
+  if (graphs && ctx->graphs_ok) {
+    HIPCHK(hipGraphLaunch(ctx->pass_graph[0], ctx->st));
+    int rc = pass_pcg(ctx);
+    if (rc) return rc;
+    HIPCHK(hipGraphLaunch(ctx->pass_graph[1], ctx->st));
+    return ABD_OK;
+  }
+  pass_pre(ctx);
+  int rc = pass_pcg(ctx);
+  if (rc) return rc;
+  pass_post(ctx);
   return ABD_OK;
 }
 
@@ -610,6 +722,8 @@ int abd_create(abd_ctx** out, const abd_params* p) {
 void abd_destroy(abd_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
+  drop_graphs(ctx);
+  if (ctx->own_stream && ctx->st) (void)hipStreamDestroy(ctx->st);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->h_cnt) (void)hipHostFree(ctx->h_cnt);
   if (ctx->h_buf) (void)hipHostFree(ctx->h_buf);
@@ -864,7 +978,7 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.partials, S.cap_partials))) return rc;
   if ((rc = dalloc(ctx, &S.cnt, 2))) return rc;
-  S.NP = 1;
+  S.NP = ctx->np;
   S.theta = ctx->P.newton_theta;
   S.eta = ctx->P.pcg_eta;
   S.max_newton = ctx->P.max_newton;
@@ -873,14 +987,21 @@ int abd_finalize(abd_ctx* ctx) {
   S.iter_mode = 0;
   {
     std::vector<int> bp0(B, 0);
+    if ((int)ctx->prob_of_body.size() == B) bp0 = ctx->prob_of_body;
     if ((rc = upload(ctx, &S.bprob, bp0))) return rc;
-    if ((rc = dalloc(ctx, &S.ps, 1))) return rc;
-    HIPCHK(hipMemset(S.ps, 0, sizeof(ProbState)));
+    if ((rc = dalloc(ctx, &S.ps, S.NP))) return rc;
+    HIPCHK(hipMemset(S.ps, 0, sizeof(ProbState) * S.NP));
   }
   if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
+  if (!ctx->st) {
+    /* a stream of the library's own (default priority): the legacy null
+     * stream cannot be captured into graphs */
+    HIPCHK(hipStreamCreateWithFlags(&ctx->st, hipStreamNonBlocking));
+    ctx->own_stream = true;
+  }
   HIPCHK(hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
   HIPCHK(hipEventCreateWithFlags(&ctx->ev_fork, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&ctx->ev_join, hipEventDisableTiming));
@@ -938,6 +1059,7 @@ int abd_set_shared(abd_ctx* ctx, const int32_t* ids, int32_t n,
   }
   Scene& S = ctx->S;
   if (n > ctx->n_shared) {
+    drop_graphs(ctx); /* z, u, rho move */
     dfree(ctx, S.z);
     dfree(ctx, S.u);
     dfree(ctx, S.rho);
@@ -946,6 +1068,12 @@ int abd_set_shared(abd_ctx* ctx, const int32_t* ids, int32_t n,
     if ((rc = dalloc(ctx, &S.rho, n))) return rc;
     ctx->n_shared = n;
   }
+  ctx->sh_ids.assign(ids, ids + n);
+  ctx->sh_kappa.assign(kappa_b, kappa_b + n);
+  ctx->sh_z.assign(z, z + 12L * n);
+  ctx->sh_u.assign(u, u + 12L * n);
+  ctx->sh_rho.assign(rho, rho + n);
+  ctx->sh_version += 1;
   if (n > 0) {
     HIPCHK(hipMemcpy(S.z, z, sizeof(double) * 12 * n, hipMemcpyHostToDevice));
     HIPCHK(hipMemcpy(S.u, u, sizeof(double) * 12 * n, hipMemcpyHostToDevice));
@@ -962,6 +1090,7 @@ int abd_set_pair_replication(abd_ctx* ctx, int32_t mode) {
     return fail(ctx, ABD_E_INVALID_ARG, "pair replication mode");
   ctx->pair_mode = mode;
   ctx->S.pair_mode = mode;
+  drop_graphs(ctx);
   return ABD_OK;
 }
 
@@ -1108,6 +1237,12 @@ int abd_get_qtilde(const abd_ctx* cctx, double* qtilde) {
 
 int abd_set_stream(abd_ctx* ctx, void* hip_stream) {
   if (!ctx) return ABD_E_INVALID_ARG;
+  drop_graphs(ctx);
+  if (ctx->own_stream && ctx->st) {
+    (void)hipStreamSynchronize(ctx->st);
+    (void)hipStreamDestroy(ctx->st);
+    ctx->own_stream = false;
+  }
   ctx->st = (hipStream_t)hip_stream;
   return ABD_OK;
 }
@@ -1276,9 +1411,156 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
   return energy(ctx, 1, alpha, 0, 1, dE);
 }
 
+}  /* extern "C" */
+
+struct abd_batch {
+  std::vector<abd_ctx*> ctxs;
+  std::vector<int> body_off;
+  std::vector<unsigned> sh_seen;
+  abd_ctx* M = nullptr;
+  ProbCopy* pc = nullptr;  /* device descriptors */
+  double* scales = nullptr; /* device [n] */
+  std::vector<double> h_scales;
+  int max_nb = 0;
+};
+
+extern "C" {
+
+int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out) {
+  if (!ctxs || n < 1 || !out) return ABD_E_INVALID_ARG;
+  *out = nullptr;
+  for (int i = 0; i < n; ++i) {
+    if (!ctxs[i] || !ctxs[i]->finalized) return ABD_E_INVALID_ARG;
+    if (std::memcmp(&ctxs[i]->P, &ctxs[0]->P, sizeof(abd_params)) != 0 ||
+        ctxs[i]->pair_mode != ctxs[0]->pair_mode)
+      return fail(ctxs[i], ABD_E_INVALID_ARG, "batch: parameters differ");
+  }
+  abd_batch* bt = new abd_batch();
+  bt->ctxs.assign(ctxs, ctxs + n);
+  int rc = abd_create(&bt->M, &ctxs[0]->P);
+  if (rc) { delete bt; return rc; }
+  abd_ctx* M = bt->M;
+  M->np = n;
+  M->pair_mode = ctxs[0]->pair_mode;
+  int off = 0;
+  for (int i = 0; i < n; ++i) {
+    abd_ctx* c = ctxs[i];
+    const int B = c->S.B;
+    std::vector<double> q(12L * B), qd(12L * B);
+    if (hipMemcpy(q.data(), c->S.q, sizeof(double) * 12 * B, hipMemcpyDeviceToHost) ||
+        hipMemcpy(qd.data(), c->S.qdot, sizeof(double) * 12 * B, hipMemcpyDeviceToHost)) {
+      abd_batch_destroy(bt);
+      return ABD_E_DEVICE;
+    }
+    bt->body_off.push_back(off);
+    for (int b = 0; b < B; ++b) {
+      const HBody& hb = c->bodies[b];
+      std::vector<int32_t> tl(3L * hb.nt);
+      for (int k = 0; k < 3 * hb.nt; ++k) tl[k] = c->tri[3L * hb.t0 + k] - hb.v0;
+      int32_t id;
+      rc = abd_add_body(M, &c->xbar[3L * hb.v0], hb.nv, tl.data(), hb.nt,
+                        hb.density, &q[12 * b], &qd[12 * b], hb.kind, &id);
+      if (rc) { abd_batch_destroy(bt); return rc; }
+      M->prob_of_body.push_back(i);
+    }
+    off += B;
+    bt->max_nb = std::max(bt->max_nb, B);
+  }
+  if ((rc = abd_finalize(M))) {
+    abd_batch_destroy(bt);
+    return rc;
+  }
+  std::vector<ProbCopy> pc(n);
+  for (int i = 0; i < n; ++i)
+    pc[i] = {ctxs[i]->S.q, ctxs[i]->S.qt, ctxs[i]->S.qtilde, ctxs[i]->S.qdot,
+             ctxs[i]->S.B, bt->body_off[i]};
+  if (hipMalloc(&bt->pc, sizeof(ProbCopy) * n) != hipSuccess ||
+      hipMalloc(&bt->scales, sizeof(double) * n) != hipSuccess ||
+      hipMemcpy(bt->pc, pc.data(), sizeof(ProbCopy) * n, hipMemcpyHostToDevice)) {
+    abd_batch_destroy(bt);
+    return ABD_E_OOM;
+  }
+  bt->sh_seen.assign(n, ~0u);
+  bt->h_scales.assign(n, 1.0);
+  *out = bt;
+  return ABD_OK;
+}
+
+void abd_batch_destroy(abd_batch* bt) {
+  if (!bt) return;
+  if (bt->pc) (void)hipFree(bt->pc);
+  if (bt->scales) (void)hipFree(bt->scales);
+  if (bt->M) abd_destroy(bt->M);
+  delete bt;
+}
+
+int abd_batch_solve(abd_batch* bt, abd_stats* out) {
+  if (!bt) return ABD_E_INVALID_ARG;
+  abd_ctx* M = bt->M;
+  abd_ctx* ctx = M;
+  const int n = (int)bt->ctxs.size();
+  auto t0 = std::chrono::steady_clock::now();
+  /* shared-body data: rebuilt only when a context changed it */
+  bool sh_changed = false;
+  for (int i = 0; i < n; ++i) sh_changed |= bt->sh_seen[i] != bt->ctxs[i]->sh_version;
+  if (sh_changed) {
+    std::vector<int> ids, kb;
+    std::vector<double> z, u, rho;
+    for (int i = 0; i < n; ++i) {
+      const abd_ctx* c = bt->ctxs[i];
+      for (size_t k = 0; k < c->sh_ids.size(); ++k) ids.push_back(c->sh_ids[k] + bt->body_off[i]);
+      kb.insert(kb.end(), c->sh_kappa.begin(), c->sh_kappa.end());
+      z.insert(z.end(), c->sh_z.begin(), c->sh_z.end());
+      u.insert(u.end(), c->sh_u.begin(), c->sh_u.end());
+      rho.insert(rho.end(), c->sh_rho.begin(), c->sh_rho.end());
+      bt->sh_seen[i] = c->sh_version;
+    }
+    int rc = abd_set_shared(M, ids.data(), (int)ids.size(), z.data(), u.data(),
+                            rho.data(), kb.data());
+    if (rc) return rc;
+  }
+  for (int i = 0; i < n; ++i) {
+    (void)hipStreamSynchronize(bt->ctxs[i]->st);
+    bt->h_scales[i] = bt->ctxs[i]->scale;
+  }
+  HIPCHK(hipMemcpyAsync(bt->scales, bt->h_scales.data(), sizeof(double) * n,
+                        hipMemcpyHostToDevice, M->st));
+  launch_gather(M->S, bt->pc, bt->scales, n, bt->max_nb, M->st);
+  int status = device_solve(M);
+  launch_scatter(M->S, bt->pc, n, bt->max_nb, M->st);
+  HIPCHK(hipStreamSynchronize(M->st));
+  std::vector<ProbState> P(n);
+  HIPCHK(hipMemcpy(P.data(), M->S.ps, sizeof(ProbState) * n, hipMemcpyDeviceToHost));
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  int first = status;
+  for (int i = 0; i < n; ++i) {
+    if (out) {
+      abd_stats& st = out[i];
+      std::memset(&st, 0, sizeof(st));
+      st.newton_iters = P[i].newton;
+      st.pcg_iters_total = P[i].pcg_total;
+      st.ls_halvings = P[i].halvings;
+      st.status = status ? status : P[i].status;
+      st.final_eps_N = P[i].final_eps;
+      st.min_alpha = P[i].min_alpha;
+      st.scene_scale = bt->h_scales[i];
+      st.min_dist = bits_to_double(M->h_cnt[0].min_dist);
+      st.t_solve_ms = ms;
+    }
+    if (first == ABD_OK && P[i].status != ABD_OK) {
+      first = P[i].status;
+      bt->ctxs[i]->err = "batch problem did not converge";
+    }
+  }
+  return first;
+}
+
 int abd_set_timing(abd_ctx* ctx, int32_t on) {
   if (!ctx) return ABD_E_INVALID_ARG;
-  ctx->timing = on != 0;
+  if (on != ABD_TIMING_OFF && on != ABD_TIMING_ALL && on != ABD_TIMING_PCG)
+    return fail(ctx, ABD_E_INVALID_ARG, "timing mode");
+  ctx->timing = on;
   return ABD_OK;
 }
 

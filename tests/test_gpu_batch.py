@@ -1,0 +1,112 @@
+"""Batched local solves: several independent problems (scenes of different
+sizes that overlap in space, or several worker shares with their own
+shared-body data) solved in the same kernel launches must give, problem by
+problem, what the oracle gives for each alone (positions within 1e-9 of
+the problem's scene scale, every problem converged), and no contact may
+join two problems."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2605_15875_amd import abd, scenes
+
+pytestmark = pytest.mark.gpu
+
+PARITY = dict(newton_theta=1e-9, pcg_eta=1e-12)
+
+
+def cube_scenes():
+    # same parameters, different sizes and seeds, all around the origin
+    return [scenes.cubes_scene(0, 2, 2, 2, **PARITY),
+            scenes.cubes_scene(1, 3, 1, 2, **PARITY),
+            scenes.cubes_scene(2, 1, 1, 1, **PARITY),
+            scenes.cubes_scene(3, 2, 3, 1, **PARITY)]
+
+
+def test_batch_cubes_match_oracle_per_problem():
+    scs = cube_scenes()
+    refs = [O.Oracle(sc) for sc in scs]
+    gpus = [abd.Solver(sc) for sc in scs]
+    bt = abd.Batch(gpus)
+    for step in range(12):
+        for g, r in zip(gpus, refs):
+            q, qd = r.get_state()
+            g.set_state(q, qd)
+            g.begin_step()
+            r.begin_step()
+        stats = bt.local_solve()
+        for i, (g, r) in enumerate(zip(gpus, refs)):
+            so = r.local_solve()
+            assert stats[i]["status"] == so["status"] == 0
+            l = stats[i]["scene_scale"]
+            err = np.abs(g.vertices() - r.vertices()).max() / l
+            assert err < 1e-9, (step, i, err)
+            g.end_step()
+            r.end_step()
+    bt.close()
+
+
+def test_batch_equals_single_context_solves():
+    scs = cube_scenes()
+    single = [abd.Solver(sc) for sc in scs]
+    batched = [abd.Solver(sc) for sc in scs]
+    bt = abd.Batch(batched)
+    for step in range(10):
+        sb = bt.step()
+        for i, s in enumerate(single):
+            ss = s.step()
+            assert ss["status"] == sb[i]["status"] == 0
+            l = ss["scene_scale"]
+            err = np.abs(s.vertices() - batched[i].vertices()).max() / l
+            # same arithmetic; only the order of floating-point atomics
+            # and reductions may differ
+            assert err < 1e-9, (step, i, err)
+
+
+def test_batch_of_worker_shares_with_shared_data():
+    scs = [scenes.hulls_in_funnel_scene(s, n_bodies=80, n_lo=20, n_hi=50,
+                                        n_shared=12, newton_theta=1e-8,
+                                        pcg_eta=1e-12) for s in (0, 1)]
+    refs = [O.Oracle(sc, dense_max_dof=0) for sc in scs]
+    gpus = [abd.Solver(sc) for sc in scs]
+    for s in gpus + refs:
+        s.set_pair_replication(1)
+    bt = abd.Batch(gpus)
+    for step in range(2):
+        zs = []
+        for sc, g, r in zip(scs, gpus, refs):
+            q, qd = r.get_state()
+            g.set_state(q, qd)
+            g.begin_step()
+            r.begin_step()
+            zs.append(r.qtilde()[sc.shared_ids] + sc.shared_delta)
+        for k in range(2):
+            for sc, g, r, z in zip(scs, gpus, refs, zs):
+                u = sc.shared_u * (1.0 + k)
+                for s in (g, r):
+                    s.set_shared(sc.shared_ids, z, u, sc.shared_rho,
+                                 sc.shared_kappa)
+            stats = bt.local_solve()
+            for i, (g, r) in enumerate(zip(gpus, refs)):
+                so = r.local_solve()
+                assert stats[i]["status"] == so["status"] == 0
+                l = stats[i]["scene_scale"]
+                err = np.abs(g.vertices() - r.vertices()).max() / l
+                assert err < 1e-9, (step, k, i, err)
+                qo, _ = r.get_state()
+                g.set_state(qo)
+        for g, r in zip(gpus, refs):
+            g.end_step()
+            r.end_step()
+    bt.close()
+
+
+def test_batch_rejects_different_parameters():
+    a = abd.Solver(scenes.cubes_scene(0, 1, 1, 1, **PARITY))
+    b = abd.Solver(scenes.cubes_scene(0, 1, 1, 1, newton_theta=1e-7))
+    with pytest.raises(abd.AbdError):
+        abd.Batch([a, b])
+    c = abd.Solver(scenes.cubes_scene(0, 1, 1, 1, **PARITY))
+    c.set_pair_replication(1)
+    with pytest.raises(abd.AbdError):
+        abd.Batch([a, c])
