@@ -102,6 +102,11 @@ def main():
     ap.add_argument("--breakdown-steps", type=int, default=3)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--pcg-variant", type=int, default=None,
+                    help="0: two grid barriers per PCG iteration, "
+                         "1: single-reduction form (default: library's)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library autotuner after warmup")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -124,10 +129,15 @@ def main():
     log(f"scene: {len(sc.bodies)} bodies, {sc.n_vertices} verts, "
         f"{sc.n_triangles} tris")
     solver = abd.Solver(sc)
+    if a.pcg_variant is not None:
+        solver.set_tuning(pcg_variant=a.pcg_variant)
     for i in range(a.warmup):
         st = solver.step()
         log(f"warmup {i}: newton={st['newton_iters']} "
             f"pcg={st['pcg_iters_total']} ms={st['t_solve_ms']:.1f}")
+    if a.autotune:
+        log(f"autotuned: {solver.autotune()}")
+    tuning = solver.tuning()
     # timed region: only the cooperative PCG launch (the one launch outside
     # the captured pass graphs) carries events, so the solve runs as usual
     solver.set_timing(abd.TIMING_PCG)
@@ -155,7 +165,9 @@ def main():
         solver.step()
     tm = solver.timing()
     solver.set_timing(abd.TIMING_OFF)
-    dom = max((k for k in tm if tm[k]["launches"]), key=lambda k: tm[k]["ms"])
+    if not any(v["launches"] for v in tm.values()):
+        tm = tm_timed
+    dom = max(tm, key=lambda k: tm[k]["ms"])
     roof = None
     d = tm_timed[dom] if dom == "pcg" else tm[dom]
     if d["bytes"] > 0 and d["launches"]:
@@ -173,6 +185,7 @@ def main():
     if not a.no_mixed:
         # same workload, same steps and tolerance, FP32 Hessian path
         ms = abd.Solver(sc, precision=1)
+        ms.set_tuning(**tuning)
         for i in range(a.warmup):
             ms.step()
         ms.set_timing(abd.TIMING_PCG)  # same event overhead as FP64
@@ -215,7 +228,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD, "bodies": len(sc.bodies) - 1,
                    "triangles": sc.n_triangles, "vertices": sc.n_vertices,
-                   "seed": a.seed, "precision": "fp64"},
+                   "seed": a.seed, "precision": "fp64", "tuning": tuning},
         "newton_iters": newton,
         "pcg_iters": pcg,
         "stage_ms_instrumented": {k: round(v["ms"] / max(a.breakdown_steps, 1),

@@ -107,6 +107,10 @@ typedef struct abd_stats {
   double scene_scale;      /* l: bounding-box diagonal at step start */
   int64_t n_cand_pt, n_cand_ee, n_cand_pg, n_active; /* last iteration */
   double t_solve_ms;       /* wall time of the call */
+  /* broad-phase sizes of the last pass: body pairs and chunk pairs of the
+   * static phase (at q) and of the swept phase (over q -> q + dq) */
+  int64_t n_body_pairs, n_chunk_pairs, n_body_pairs_swept,
+      n_chunk_pairs_swept;
 } abd_stats;
 
 typedef struct abd_ctx abd_ctx;
@@ -173,6 +177,39 @@ int abd_set_step(abd_ctx* ctx, const double* qt, const double* qtilde,
  * captured graphs). */
 int abd_set_stream(abd_ctx* ctx, void* hip_stream);
 
+/* ---- launch tuning ---- */
+#define ABD_PCG_TWO_BARRIER 0 /* textbook PCG: two grid barriers per iteration */
+#define ABD_PCG_PIPELINED 1   /* single-reduction PCG: one grid barrier */
+typedef struct abd_tuning {
+  int32_t pcg_variant;     /* ABD_PCG_* (default TWO_BARRIER; the pipelined
+                              form carries u, s and t by recurrences, which
+                              can stall short of a very tight tolerance such
+                              as eta = 1e-12 on stiff contact systems) */
+  int32_t pcg_blocks;      /* blocks of the cooperative PCG launch, 16 bodies
+                              each per pass; 0 = one block per 16 bodies up to
+                              the co-resident limit */
+  int32_t grid_blocks;     /* blocks of the grid-stride broad-phase, filter and
+                              CCD kernels (default 1024) */
+  int32_t assemble_blocks; /* blocks of the barrier assembly (default 2048) */
+  int32_t use_graphs;      /* replay Newton passes from captured graphs (1) */
+} abd_tuning;
+
+/* Read or replace the launch settings of a finalized context.  Settings
+ * change launch shapes and the PCG recurrence, not the system solved:
+ * any setting gives a solution within the stated tolerances.
+ * INVALID_ARG for an unknown variant or negative sizes. */
+int abd_get_tuning(abd_ctx* ctx, abd_tuning* out);
+int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t);
+
+/* Autotuner: from the current state, run the next time step's local solve
+ * (prediction, solve) once per candidate setting, each from the same saved
+ * state and timed on the device, restore the state, and keep the fastest
+ * setting that solved the step (returned in out, may be NULL).  The search
+ * is coordinate-wise: PCG form and grid first (the pipelined form only for
+ * pcg_eta >= 1e-6), then the grid-stride grid, then the assembly grid.
+ * Costs about 2 x trials local solves. */
+int abd_autotune(abd_ctx* ctx, abd_tuning* out);
+
 /* ---- batching: many local problems in the same launches ---- */
 typedef struct abd_batch abd_batch;
 
@@ -192,8 +229,85 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out);
  * kernel launches (replayed from captured graphs), and the solutions are
  * scattered back to the contexts.  out: [n] stats (may be NULL).  Returns
  * ABD_OK or the first non-OK problem status. */
-int abd_batch_solve(abd_batch* batch, abd_stats* out);
+int abd_batch_run(abd_batch* batch, abd_stats* out);
+
+/* One-call form: solve the contexts ctxs[0..n) together.  The merged
+ * scene is built on the first call and kept by ctxs[0] for later calls with
+ * the same contexts in the same order (rebuilt when the list or a pair
+ * replication rule changes; released with ctxs[0]).  Same requirements and
+ * results as abd_batch_create + abd_batch_run. */
+int abd_batch_solve(abd_ctx** ctxs, int32_t n, abd_stats* out);
 void abd_batch_destroy(abd_batch* batch);
+
+/* ---- consensus ADMM over the subdomains of a batch ---- */
+/* The problems of a batch are the workers of Sec. 4.1 (subdomains of one
+ * scene, each a context holding its own copies of the shared bodies).  A
+ * consensus object links the replicas of every shared body and runs the
+ * consensus side on the device: the z-update (Eq. 6), the dual update
+ * (Eq. 7), the residuals (Eqs. 9-10), the penalty rule (Eq. 12) with the
+ * mass-aware start (Sec. 4.3) and the merge check and merge of Sec. 4.2.
+ * Replica data moves between the problems through device memory. */
+typedef struct abd_consensus abd_consensus;
+
+typedef struct abd_admm_params {
+  double beta;      /* rho0 = beta * m_b (Sec. 4.3); <= 0: rho0 = rho_fixed */
+  double rho_fixed;
+  double tau, mu;   /* Eq. 12 (2, 5) */
+  double sigma_min, sigma_max; /* rho kept in [sigma_min, sigma_max] * rho0 */
+  double scale;     /* l of Eq. 8; <= 0: the largest problem scene scale */
+  int32_t adapt_rho;   /* apply Eq. 12 between iterations */
+  int32_t merge_check; /* convergence also needs TOI = 1 toward the merge */
+  int32_t max_iters;   /* ADMM iterations per time step (K of Alg. 1) */
+} abd_admm_params;
+
+typedef struct abd_admm_report {
+  int32_t iters;       /* local solves per problem in this time step */
+  int32_t converged;   /* the three tests of Eq. 8 held (and the merge check) */
+  int32_t merge_ok;    /* every problem reached TOI = 1 toward its merge */
+  int32_t newton_iters_total; /* over all problems and iterations */
+  double eps_newton;   /* max over problems of |dq|_inf / (h l_p) */
+  double r_inf, s_inf; /* Eqs. 9-10 divided by h l */
+  double min_toi;      /* smallest merge-check TOI over problems */
+} abd_admm_report;
+
+/* Replica k is body rep_body[k] of problem rep_prob[k] (a dynamic body)
+ * and a copy of shared body rep_group[k] in [0, n_groups); every group
+ * needs a replica, and a problem holds at most one replica per group.
+ * kappa_b of each replica is its group's replica count.  The batch keeps
+ * using these as its shared data (abd_set_shared on its contexts no longer
+ * reaches the batch).  Errors: INVALID_ARG, OOM, DEVICE. */
+int abd_consensus_create(abd_batch* bt, const int32_t* rep_prob,
+                         const int32_t* rep_body, const int32_t* rep_group,
+                         int32_t n_rep, int32_t n_groups,
+                         const abd_admm_params* ap, abd_consensus** out);
+void abd_consensus_destroy(abd_consensus* c);
+
+/* Alg. 1 start of a time step, after abd_begin_step on every context:
+ * z = q-tilde of the replicas, u = 0 (rho keeps its adapted values). */
+int abd_consensus_begin(abd_consensus* c);
+
+/* After a batch local solve: Eqs. 6, 7, 9, 10 on the device, the merge
+ * check if enabled (ACCD of every problem from its q to its merged state),
+ * and the report (may be NULL). */
+int abd_consensus_update(abd_consensus* c, abd_admm_report* rep);
+
+/* Eq. 12 with the residuals of the last update. */
+int abd_consensus_adapt(abd_consensus* c);
+
+/* Sec. 4.2 merge: every replica takes its group's z; written back to the
+ * contexts. */
+int abd_consensus_merge(abd_consensus* c);
+
+/* Copies out z [n_groups*12], u [n_rep*12], rho [n_rep] (any may be NULL). */
+int abd_consensus_get(abd_consensus* c, double* z, double* u, double* rho);
+
+/* One time step of Alg. 1 for every problem: begin_step on each context,
+ * z = q-tilde and u = 0, then up to max_iters rounds of batch local solve
+ * and consensus update (stopping when Eq. 8 and the merge check hold, and
+ * adapting rho between rounds), the merge, and end_step on each context.
+ * Returns ABD_OK, ABD_E_NOCONV (no convergence in max_iters; the replicas
+ * keep their local solutions) or the first failing local solve's status. */
+int abd_admm_step(abd_consensus* c, abd_admm_report* rep);
 
 /* ---- inspection hooks (used for parity; not needed to simulate) ---- */
 

@@ -32,6 +32,36 @@ class Params(C.Structure):
                 ("mollify_ee", C.c_int32), ("precision", C.c_int32)]
 
 
+class Tuning(C.Structure):
+    _fields_ = [("pcg_variant", C.c_int32), ("pcg_blocks", C.c_int32),
+                ("grid_blocks", C.c_int32), ("assemble_blocks", C.c_int32),
+                ("use_graphs", C.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+PCG_TWO_BARRIER, PCG_PIPELINED = 0, 1
+
+
+class AdmmParams(C.Structure):
+    _fields_ = [("beta", C.c_double), ("rho_fixed", C.c_double),
+                ("tau", C.c_double), ("mu", C.c_double),
+                ("sigma_min", C.c_double), ("sigma_max", C.c_double),
+                ("scale", C.c_double), ("adapt_rho", C.c_int32),
+                ("merge_check", C.c_int32), ("max_iters", C.c_int32)]
+
+
+class AdmmReport(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32),
+                ("merge_ok", C.c_int32), ("newton_iters_total", C.c_int32),
+                ("eps_newton", C.c_double), ("r_inf", C.c_double),
+                ("s_inf", C.c_double), ("min_toi", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Stats(C.Structure):
     _fields_ = [("newton_iters", C.c_int32), ("pcg_iters_total", C.c_int32),
                 ("ls_halvings", C.c_int32), ("status", C.c_int32),
@@ -39,7 +69,10 @@ class Stats(C.Structure):
                 ("min_dist", C.c_double), ("scene_scale", C.c_double),
                 ("n_cand_pt", C.c_int64), ("n_cand_ee", C.c_int64),
                 ("n_cand_pg", C.c_int64), ("n_active", C.c_int64),
-                ("t_solve_ms", C.c_double)]
+                ("t_solve_ms", C.c_double),
+                ("n_body_pairs", C.c_int64), ("n_chunk_pairs", C.c_int64),
+                ("n_body_pairs_swept", C.c_int64),
+                ("n_chunk_pairs_swept", C.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -53,8 +86,12 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_set_step", "abd_set_stream", "abd_get_vertices",
            "abd_export_candidates", "abd_eval", "abd_direction", "abd_ccd",
            "abd_energy_delta", "abd_set_timing", "abd_get_timing",
-           "abd_reset_timing", "abd_batch_create", "abd_batch_solve",
-           "abd_batch_destroy"]
+           "abd_reset_timing", "abd_batch_create", "abd_batch_run",
+           "abd_batch_solve", "abd_batch_destroy", "abd_get_tuning", "abd_set_tuning",
+           "abd_autotune", "abd_consensus_create", "abd_consensus_destroy",
+           "abd_consensus_begin", "abd_consensus_update",
+           "abd_consensus_adapt", "abd_consensus_merge", "abd_consensus_get",
+           "abd_admm_step"]
 
 
 TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
@@ -102,8 +139,23 @@ def lib():
         "abd_reset_timing": (C.c_int, [vp]),
         "abd_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32,
                                        C.POINTER(vp)]),
-        "abd_batch_solve": (C.c_int, [vp, C.POINTER(Stats)]),
+        "abd_batch_run": (C.c_int, [vp, C.POINTER(Stats)]),
+        "abd_batch_solve": (C.c_int, [C.POINTER(vp), C.c_int32,
+                                      C.POINTER(Stats)]),
         "abd_batch_destroy": (None, [vp]),
+        "abd_get_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+        "abd_set_tuning": (C.c_int, [vp, C.POINTER(Tuning)]),
+        "abd_autotune": (C.c_int, [vp, C.POINTER(Tuning)]),
+        "abd_consensus_create": (C.c_int, [vp, ip, ip, ip, C.c_int32,
+                                           C.c_int32, C.POINTER(AdmmParams),
+                                           C.POINTER(vp)]),
+        "abd_consensus_destroy": (None, [vp]),
+        "abd_consensus_begin": (C.c_int, [vp]),
+        "abd_consensus_update": (C.c_int, [vp, C.POINTER(AdmmReport)]),
+        "abd_consensus_adapt": (C.c_int, [vp]),
+        "abd_consensus_merge": (C.c_int, [vp]),
+        "abd_consensus_get": (C.c_int, [vp, dp, dp, dp]),
+        "abd_admm_step": (C.c_int, [vp, C.POINTER(AdmmReport)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -323,6 +375,21 @@ class Solver:
                                            _d(e)))
         return float(e[0])
 
+    # ---- launch tuning ----
+    def tuning(self):
+        t = Tuning()
+        self._check(lib().abd_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        t = Tuning(**{**self.tuning(), **kw})
+        self._check(lib().abd_set_tuning(self.h, C.byref(t)))
+
+    def autotune(self):
+        t = Tuning()
+        self._check(lib().abd_autotune(self.h, C.byref(t)))
+        return t.as_dict()
+
     # ---- timing ----
     def set_timing(self, on):
         self._check(lib().abd_set_timing(self.h, int(on)))
@@ -367,7 +434,7 @@ class Batch:
 
     def local_solve(self, check=True):
         st = (Stats * len(self.solvers))()
-        rc = lib().abd_batch_solve(self.h, st)
+        rc = lib().abd_batch_run(self.h, st)
         if check and rc != OK:
             bad = [i for i in range(len(self.solvers)) if st[i].status != OK]
             raise AbdError(rc, f"batch solve: problems {bad} failed")
@@ -380,3 +447,84 @@ class Batch:
         for s in self.solvers:
             s.end_step()
         return out
+
+
+def batch_solve(solvers, check=True):
+    """One-call batched local solve of several Solver contexts (the merged
+    scene is kept by the first context between calls)."""
+    arr = (C.c_void_p * len(solvers))(*[s.h for s in solvers])
+    st = (Stats * len(solvers))()
+    rc = lib().abd_batch_solve(arr, len(solvers), st)
+    if check and rc != OK:
+        raise AbdError(rc, "abd_batch_solve: " + solvers[0].error())
+    return [s.as_dict() for s in st]
+
+
+class Consensus:
+    """Device consensus ADMM over the problems of a Batch (subdomains of one
+    scene); the replica table is a scenes.Split's."""
+
+    def __init__(self, batch, rep_prob, rep_body, rep_group, n_groups,
+                 beta=1.0, rho_fixed=0.0, tau=2.0, mu=5.0, sigma_min=1e-3,
+                 sigma_max=1e3, scale=0.0, adapt_rho=True, merge_check=True,
+                 max_iters=50):
+        self.batch = batch
+        self.rp = np.ascontiguousarray(rep_prob, dtype=np.int32)
+        self.rb = np.ascontiguousarray(rep_body, dtype=np.int32)
+        self.rg = np.ascontiguousarray(rep_group, dtype=np.int32)
+        self.n_rep, self.n_groups = len(self.rp), int(n_groups)
+        self._ap = AdmmParams(beta, rho_fixed, tau, mu, sigma_min, sigma_max,
+                              scale, int(adapt_rho), int(merge_check),
+                              max_iters)
+        h = C.c_void_p()
+        rc = lib().abd_consensus_create(batch.h, _i(self.rp), _i(self.rb),
+                                        _i(self.rg), self.n_rep,
+                                        self.n_groups, C.byref(self._ap),
+                                        C.byref(h))
+        if rc != OK:
+            raise AbdError(rc, "abd_consensus_create: " +
+                           batch.solvers[0].error())
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().abd_consensus_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise AbdError(rc, "consensus call failed")
+
+    def begin(self):
+        self._check(lib().abd_consensus_begin(self.h))
+
+    def update(self):
+        r = AdmmReport()
+        self._check(lib().abd_consensus_update(self.h, C.byref(r)))
+        return r.as_dict()
+
+    def adapt(self):
+        self._check(lib().abd_consensus_adapt(self.h))
+
+    def merge(self):
+        self._check(lib().abd_consensus_merge(self.h))
+
+    def get(self):
+        z = np.zeros((self.n_groups, 12))
+        u = np.zeros((self.n_rep, 12))
+        rho = np.zeros(self.n_rep)
+        self._check(lib().abd_consensus_get(self.h, _d(z), _d(u), _d(rho)))
+        return z, u, rho
+
+    def admm_step(self, check=True):
+        r = AdmmReport()
+        rc = lib().abd_admm_step(self.h, C.byref(r))
+        if check and rc != OK:
+            raise AbdError(rc, "abd_admm_step: " + self.batch.solvers[0].error())
+        return r.as_dict()

@@ -52,6 +52,7 @@ struct ProbState {
   double dE[LS_TRIALS];
   double acc[16];     /* PCG dot ring: [slot][rz, pAp, rr, -] */
   double bb;          /* |b|^2 of the PCG right-hand side */
+  double cg_alpha[2]; /* single-reduction PCG: step of the last iterations */
   unsigned long long max_dq, min_toi;
   int state, status, newton, halvings, ls_count;
   int pcg_done, pcg_iters, pcg_total;
@@ -96,6 +97,11 @@ struct Scene {
   int cap_col;
   /* PCG work */
   double *r, *zv, *p0, *p1, *Ap, *acc; /* acc: [4][4] ring of dots */
+  double *pw; /* single-reduction PCG: [5][12B] w, m0, m1, t0, t1 */
+  /* world positions of the current broad phase, [3][V] each: xw at q,
+   * xw1 at q + dq (swept phase); written by k_positions with the canonical
+   * transform, read by the primitive tests and the distance filter */
+  double *xw, *xw1;
   /* reductions */
   double *partials; /* [cap_partials] */
   int cap_partials;
@@ -107,6 +113,7 @@ struct Scene {
   int iter_mode;  /* 0: hooks (every problem); 1: static pass of the device
                      loop (problems in PS_NEWTON); 2: swept pass (problems
                      not PS_DONE) */
+  int grid_blocks, assemble_blocks; /* launch sizes (tuning) */
   double theta;   /* Newton tolerance */
   int max_newton, max_ls, max_pcg;
   double eta;
@@ -598,6 +605,7 @@ void launch_commit(const Scene& S, hipStream_t st);
 void launch_transform(const Scene& S, double* x, double* dx, hipStream_t st);
 void launch_body_terms(const Scene& S, hipStream_t st);
 void launch_boxes(const Scene& S, int swept, hipStream_t st);
+void launch_positions(const Scene& S, int swept, hipStream_t st);
 void launch_body_pairs(const Scene& S, hipStream_t st);
 void launch_chunk_pairs(const Scene& S, hipStream_t st);
 void launch_prim_pairs(const Scene& S, int swept, hipStream_t st);
@@ -608,7 +616,7 @@ void launch_crossings(const Scene& S, hipStream_t st);
 void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st);
 void launch_bsr(const Scene& S, hipStream_t st);
 void launch_block_inverse(const Scene& S, hipStream_t st);
-int launch_pcg(const Scene& S, double eta, int max_it, int grid,
+int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
                hipStream_t st);
 int pcg_max_grid();
 void launch_dq_norm(const Scene& S, hipStream_t st);
@@ -620,6 +628,26 @@ void launch_ctrl(const Scene& S, int which, hipStream_t st);
 void launch_update_multi(const Scene& S, hipStream_t st);
 void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st);
 void launch_reset_pcg(const Scene& S, hipStream_t st);
+/* consensus over the replicas of shared bodies in a batch scene */
+struct Cons {
+  int n_rep, n_groups;
+  const int* rep_body;  /* [n_rep] body index in the batch scene */
+  const int* rep_group; /* [n_rep] shared body of each replica */
+  const int* grp_ptr;   /* [n_groups + 1] replicas of each group (CSR) */
+  const int* grp_rep;   /* [n_rep] */
+  const double* rho0;   /* [n_rep] initial penalties */
+  double* zc;           /* [n_groups][12] current consensus z */
+  unsigned long long* r_body; /* [n_groups] max over replicas |q - z|_inf */
+  unsigned long long* s_body; /* [n_groups] |z_new - z_old|_inf */
+  unsigned long long* red;    /* [2] r_inf, s_inf (bits of doubles >= 0) */
+  double tau, mu, smin, smax;
+};
+void launch_cons_init(const Scene& S, const Cons& C, hipStream_t st);
+void launch_cons_update(const Scene& S, const Cons& C, hipStream_t st);
+void launch_cons_adapt(const Scene& S, const Cons& C, hipStream_t st);
+void launch_cons_merge(const Scene& S, const Cons& C, hipStream_t st);
+void launch_cons_merge_dq(const Scene& S, const Cons& C, hipStream_t st);
+
 /* batch state movement: one descriptor per problem */
 struct ProbCopy {
   double *q, *qt, *qtilde, *qdot; /* the problem's own context arrays */

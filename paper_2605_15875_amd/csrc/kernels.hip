@@ -258,18 +258,32 @@ __global__ void k_boxes(Scene S, int swept) {
   for (int i = 0; i < 6; ++i) out[i] = box[i];
 }
 
+/* Slot in an append-only list for each lane whose pred holds: one atomic
+ * per wavefront on the list counter, lanes in lane order after it.  Every
+ * lane of the wavefront must make the call. */
+__device__ __forceinline__ int wave_slot(bool pred, int* counter) {
+  const unsigned long long m = __ballot(pred);
+  if (m == 0ull) return -1;
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)m) - 1;
+  int base = 0;
+  if (lane == leader) base = atomicAdd(counter, __popcll(m));
+  base = __shfl(base, leader, 64);
+  return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
+}
+
 /* body pairs (a < b, not both static) whose boxes pass the predicate */
 __global__ void k_body_pairs(Scene S) {
-  int a = blockIdx.y * 16 + threadIdx.y;
-  int b = blockIdx.x * 16 + threadIdx.x;
   if ((int)(blockIdx.x * 16 + 15) <= (int)(blockIdx.y * 16)) return;
-  if (a >= S.B || b >= S.B || a >= b) return;
-  if (S.kind[a] != 0 && S.kind[b] != 0) return;
-  if (S.bprob[a] != S.bprob[b]) return; /* independent problems */
-  if (!body_in_pass(S, a)) return;
-  if (!box_overlap(S.body_box + 6 * a, S.body_box + 6 * b, S.dhat)) return;
-  int k = atomicAdd(&S.cnt->n_bp, 1);
-  if (k < S.cap_bp) S.bp[k] = make_int2(a, b);
+  const int a = blockIdx.y * 16 + threadIdx.y;
+  const int b = blockIdx.x * 16 + threadIdx.x;
+  bool ok = a < S.B && b < S.B && a < b;
+  ok = ok && !(S.kind[a] != 0 && S.kind[b] != 0);
+  ok = ok && S.bprob[a] == S.bprob[b]; /* independent problems */
+  ok = ok && body_in_pass(S, a);
+  ok = ok && box_overlap(S.body_box + 6 * a, S.body_box + 6 * b, S.dhat);
+  const int k = wave_slot(ok, &S.cnt->n_bp);
+  if (ok && k < S.cap_bp) S.bp[k] = make_int2(a, b);
 }
 
 /* chunk pairs of every body pair: vertex chunks x triangle chunks (both
@@ -284,37 +298,57 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
     int nvb = cb[1] - cb[0], ntb = cb[3] - cb[2], neb = cb[5] - cb[4];
     int n1 = nva * ntb, n2 = nvb * nta, n3 = nea * neb;
     int tot = n1 + n2 + n3;
-    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-      int kind, P, Q;
+    for (int t0 = 0; t0 < tot; t0 += blockDim.x) {
+      const int t = t0 + threadIdx.x;
+      int kind = C_EE, P = 0, Q = 0;
       if (t < n1) {
         kind = C_PT; P = ca[0] + t / ntb; Q = cb[2] + t % ntb;
       } else if (t < n1 + n2) {
         int u = t - n1;
         kind = C_PT; P = cb[0] + u / nta; Q = ca[2] + u % nta;
-      } else {
+      } else if (t < tot) {
         int u = t - n1 - n2;
         kind = C_EE; P = ca[4] + u / neb; Q = cb[4] + u % neb;
       }
-      if (!box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat)) continue;
-      int k = atomicAdd(&S.cnt->n_cp, 1);
-      if (k < S.cap_cp) S.cp[k] = make_int4(kind, P, Q, p);
+      const bool ok =
+          t < tot && box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat);
+      const int k = wave_slot(ok, &S.cnt->n_cp);
+      if (ok && k < S.cap_cp) S.cp[k] = make_int4(kind, P, Q, p);
     }
   }
 }
 
-/* exact box of one primitive (static, or swept over the step) */
-__device__ __forceinline__ void vert_box(const Scene& S, int v, int swept,
-                                         double* box) {
+/* world positions for the broad phase: x at q, and x + dx at q + dq for
+ * the swept phase (the same canonical transforms as every other kernel) */
+__global__ void k_positions(Scene S, int swept) {
+  const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= S.V || !body_in_pass(S, S.vbody[v])) return;
   double x[3], x1[3];
   if (swept) {
     vertex_pos_swept(S, v, x, x1);
-    for (int k = 0; k < 3; ++k) {
-      box[k] = fmin(x[k], x1[k]);
-      box[3 + k] = fmax(x[k], x1[k]);
-    }
+#pragma unroll
+    for (int k = 0; k < 3; ++k) S.xw1[k * S.V + v] = x1[k];
   } else {
     vertex_pos(S, v, x);
-    for (int k = 0; k < 3; ++k) box[k] = box[3 + k] = x[k];
+  }
+#pragma unroll
+  for (int k = 0; k < 3; ++k) S.xw[k * S.V + v] = x[k];
+}
+
+/* exact box of one primitive (static, or swept over the step) from the
+ * positions of the current phase */
+__device__ __forceinline__ void vert_box(const Scene& S, int v, int swept,
+                                         double* box) {
+  if (swept) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double a = S.xw[k * S.V + v], b = S.xw1[k * S.V + v];
+      box[k] = fmin(a, b);
+      box[3 + k] = fmax(a, b);
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) box[k] = box[3 + k] = S.xw[k * S.V + v];
   }
 }
 __device__ __forceinline__ void prim_box(const Scene& S, int kind, int id,
@@ -374,29 +408,27 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
       for (int k = 0; k < 6; ++k) qbox[wave][pos][k] = qb[k];
     }
     __syncthreads();
+    bool mine = false;
+    int pid = 0;
+    double box[6];
     if (nq > 0 && lane < nP) {
-      const int pid = S.ch_prims[S.ch_start[P] + lane];
-      double box[6];
+      pid = S.ch_prims[S.ch_start[P] + lane];
       prim_box(S, kindP, pid, swept, box);
-      if (box_overlap(box, S.ch_box + 6 * Q, S.dhat)) {
-        for (int j = 0; j < nq; ++j) {
-          if (!box_overlap(box, qbox[wave][j], S.dhat)) continue;
+      mine = box_overlap(box, S.ch_box + 6 * Q, S.dhat);
+    }
+    if (__ballot(mine) != 0ull) {
+      const bool pt = cp.x == C_PT; /* uniform over the wavefront */
+      int* const counter = pt ? &S.cnt->n_pt : &S.cnt->n_ee;
+      const int cap = pt ? S.cap_pt : S.cap_ee;
+      int* const list = pt ? S.cand_pt : S.cand_ee;
+      for (int j = 0; j < nq; ++j) {
+        const bool ok = mine && box_overlap(box, qbox[wave][j], S.dhat);
+        const int k = wave_slot(ok, counter);
+        if (ok && k < cap) {
           const int other = qid[wave][j];
-          if (cp.x == C_PT) {
-            const int k = atomicAdd(&S.cnt->n_pt, 1);
-            if (k < S.cap_pt) {
-              S.cand_pt[3 * k] = pid;
-              S.cand_pt[3 * k + 1] = other;
-              S.cand_pt[3 * k + 2] = cp.w;
-            }
-          } else {
-            const int k = atomicAdd(&S.cnt->n_ee, 1);
-            if (k < S.cap_ee) {
-              S.cand_ee[3 * k] = min(pid, other);
-              S.cand_ee[3 * k + 1] = max(pid, other);
-              S.cand_ee[3 * k + 2] = cp.w;
-            }
-          }
+          list[3 * k] = pt ? pid : min(pid, other);
+          list[3 * k + 1] = pt ? other : max(pid, other);
+          list[3 * k + 2] = cp.w;
         }
       }
     }
@@ -415,14 +447,16 @@ __global__ void k_pg(Scene S, int swept) {
     if (S.ch_kind[c] != K_VERT || S.kind[S.ch_body[c]] != 0) continue;
     if (!body_in_pass(S, S.ch_body[c])) continue;
     if (!(S.ch_box[6 * c + 1] <= top)) continue;
-    if (lane >= S.ch_count[c]) continue;
-    int v = S.ch_prims[S.ch_start[c] + lane];
-    double box[6];
-    vert_box(S, v, swept, box);
-    if (box[1] <= top) {
-      int k = atomicAdd(&S.cnt->n_pg, 1);
-      if (k < S.cap_pg) S.cand_pg[k] = v;
+    bool ok = false;
+    int v = 0;
+    if (lane < S.ch_count[c]) {
+      v = S.ch_prims[S.ch_start[c] + lane];
+      double box[6];
+      vert_box(S, v, swept, box);
+      ok = box[1] <= top;
     }
+    const int k = wave_slot(ok, &S.cnt->n_pg);
+    if (ok && k < S.cap_pg) S.cand_pg[k] = v;
   }
 }
 
@@ -460,10 +494,12 @@ __global__ void k_filter(Scene S) {
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
   const int tot = npt + nee + npg;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
-       t += gridDim.x * blockDim.x) {
-    int kind, i, j = 0, slot = -1;
-    double d;
+  const int stride = gridDim.x * blockDim.x;
+  double dmin = INFINITY;
+  for (int t0 = blockIdx.x * blockDim.x; t0 < tot; t0 += stride) {
+    const int t = t0 + threadIdx.x;
+    int kind = C_PG, i = 0, j = 0, slot = -1;
+    double d = INFINITY;
     if (t < npt + nee) {
       const int* c = t < npt ? S.cand_pt + 3 * t : S.cand_ee + 3 * (t - npt);
       kind = t < npt ? C_PT : C_EE;
@@ -471,21 +507,21 @@ __global__ void k_filter(Scene S) {
       int vid[4];
       pair_vertices(S, kind, i, j, vid);
       double x[12];
-      for (int k = 0; k < 4; ++k) vertex_pos(S, vid[k], x + 3 * k);
+      for (int k = 0; k < 4; ++k)
+        for (int c = 0; c < 3; ++c) x[3 * k + c] = S.xw[c * S.V + vid[k]];
       d = pair_dist(kind, x);
-    } else {
-      kind = C_PG;
+    } else if (t < tot) {
       i = S.cand_pg[t - npt - nee];
-      double x[3];
-      vertex_pos(S, i, x);
-      d = x[1] - S.ground_y;
+      d = S.xw[S.V + i] - S.ground_y;
     }
-    atomic_min_pos(&S.cnt->min_dist, fmax(d, 0.0));
-    if (d < S.dhat) {
-      int k = atomicAdd(&S.cnt->n_act, 1);
-      if (k < S.cap_act) S.act[k] = make_int4(kind, i, j, slot);
-    }
+    dmin = fmin(dmin, fmax(d, 0.0));
+    const bool ok = t < tot && d < S.dhat;
+    const int k = wave_slot(ok, &S.cnt->n_act);
+    if (ok && k < S.cap_act) S.act[k] = make_int4(kind, i, j, slot);
   }
+  /* smallest distance: reduced over the wavefront, one atomic per wave */
+  for (int o = 32; o > 0; o >>= 1) dmin = fmin(dmin, __shfl_xor(dmin, o, 64));
+  if (__lane_id() == 0 && dmin < INFINITY) atomic_min_pos(&S.cnt->min_dist, dmin);
 }
 
 /* ---- derivatives of the squared-distance features ---- */
@@ -1197,6 +1233,207 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
   }
 }
 
+/* Single-reduction (pipelined) block-Jacobi PCG, the same solve with one
+ * grid barrier per iteration instead of two.  It follows the
+ * Chronopoulos-Gear form of CG, where s = A p and the preconditioned
+ * residual u = P^-1 r are carried by recurrences, so that both inner
+ * products of an iteration, gamma = r.u and delta = w.u with w = A u, come
+ * from the same reduction:
+ *   beta_i = gamma_i / gamma_{i-1},
+ *   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+ *   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s.
+ * The preconditioned vectors are carried too: m = P^-1 w is formed once
+ * per iteration, t = P^-1 s = m + beta t and u_{i+1} = u_i - alpha t_i, so
+ * u_{i+1} of a neighbouring body is an element-wise expression of vectors
+ * written before the last barrier and the product w_{i+1} = A u_{i+1}
+ * needs no second barrier.  u, m and t are double-buffered by iteration
+ * parity; r, s, w, p and x are read only by their own rows. */
+__device__ __forceinline__ double cg_next_u(double u, double m, double tprev,
+                                            double a, double be) {
+  return __fma_rn(-a, __fma_rn(be, tprev, m), u);
+}
+
+template <typename HT>
+__global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
+  const HT* __restrict__ Hd = (const HT*)S.Hdiag;
+  const HT* __restrict__ Ho = (const HT*)S.Hoff;
+  const HT* __restrict__ Pi = (const HT*)S.Pinv;
+  __shared__ double rloc[16][12];
+  __shared__ double gs[16][4];
+  __shared__ unsigned char pdone[PCG_MAX_NP];
+  __shared__ int any_active;
+  const unsigned nblk = gridDim.x;
+  unsigned gen = 0;
+  const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
+  const int ngroups = (S.B + 15) / 16;
+  const int NP = S.NP;
+  const long n12 = 12L * S.B;
+  double* const W = S.pw;
+  double* const Mv[2] = {S.pw + n12, S.pw + 2 * n12};
+  double* const Tv[2] = {S.pw + 3 * n12, S.pw + 4 * n12};
+  double* const Uv[2] = {S.zv, S.p1};
+  double* const P = S.p0;
+  double* const Sv = S.Ap;
+  ProbState* ps = S.ps;
+  const int OFF_ACC = (int)offsetof(ProbState, acc);
+  const int OFF_BB = (int)offsetof(ProbState, bb);
+  for (int p = threadIdx.x; p < NP; p += blockDim.x)
+    pdone[p] = (S.iter_mode == 0 || ps[p].state == PS_NEWTON) ? 0 : 1;
+  __syncthreads();
+  /* phase 0a: x = 0, r = b = -g, u_0 = P^-1 r, p = s = t_{-1} = 0 */
+  for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
+    const int b = gr * 16 + lb;
+    const int p = b < S.B ? S.bprob[b] : 0;
+    const bool act = b < S.B && !pdone[p];
+    const int o = 12 * b + row;
+    const double rv = act ? -S.g[o] : 0.0;
+    rloc[lb][row] = rv;
+    __syncthreads();
+    if (act) {
+      HT zz = 0;
+      for (int c = 0; c < 12; ++c) zz += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+      S.dq[o] = 0.0;
+      S.r[o] = rv;
+      P[o] = 0.0;
+      Sv[o] = 0.0;
+      Tv[1][o] = 0.0;
+      Uv[0][o] = (double)zz;
+    }
+    __syncthreads();
+  }
+  grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
+  /* phase 0b: w_0 = A u_0, m_0 = P^-1 w_0 and the dots of iteration 0 */
+  for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
+    const int b = gr * 16 + lb;
+    const int p = b < S.B ? S.bprob[b] : 0;
+    const bool act = b < S.B && !pdone[p];
+    const int o = 12 * b + row;
+    double y = 0.0, uo = 0.0, rv = 0.0;
+    if (act) {
+      HT acc = 0;
+      const HT* H = Hd + 144 * b + 12 * row;
+      for (int c = 0; c < 12; ++c) acc += H[c] * (HT)Uv[0][12 * b + c];
+      for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
+        const int nb = S.col_body[e];
+        const HT* blk = Ho + 144 * (size_t)S.col_slot[e];
+        const int st = S.col_trans[e] ? 12 : 1, sc = S.col_trans[e] ? 1 : 12;
+        for (int c = 0; c < 12; ++c)
+          acc += blk[sc * row + st * c] * (HT)Uv[0][12 * nb + c];
+      }
+      y = (double)acc;
+      W[o] = y;
+      uo = Uv[0][o];
+      rv = S.r[o];
+    }
+    rloc[lb][row] = y;
+    __syncthreads();
+    if (act) {
+      HT mm = 0;
+      for (int c = 0; c < 12; ++c) mm += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+      Mv[0][o] = (double)mm;
+    }
+    const double v[4] = {rv * uo, y * uo, rv * rv, rv * rv};
+    const int off[4] = {OFF_ACC + 0, OFF_ACC + (int)sizeof(double),
+                        OFF_ACC + 2 * (int)sizeof(double), OFF_BB};
+    group_add<4>(gs, gr, S.B, S.bprob, p, act, v, ps, off);
+  }
+  grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
+  int it = 0;
+  for (it = 0;; ++it) {
+    /* the same decision in every block: converged (|r_it| <= eta |b|, or
+     * a zero right-hand side), out of iterations, or still running */
+    if (threadIdx.x == 0) any_active = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < NP; p += blockDim.x) {
+      if (pdone[p]) continue;
+      const double* acc = ps[p].acc + 4 * (it & 3);
+      const double bb = ld_acq(&ps[p].bb);
+      if (!(bb > 0.0) || ld_acq(acc + 2) <= eta * eta * bb || it >= max_it) {
+        pdone[p] = 1;
+        if (blockIdx.x == 0) ps[p].pcg_iters = it;
+        continue;
+      }
+      any_active = 1;
+      if (blockIdx.x == 0) {
+        const double g = ld_acq(acc), d = ld_acq(acc + 1);
+        double a = g / d;
+        if (it > 0) {
+          const double be = g / ld_acq(ps[p].acc + 4 * ((it - 1) & 3));
+          a = g / (d - be * g / ld_acq(&ps[p].cg_alpha[(it - 1) & 1]));
+        }
+        ps[p].cg_alpha[it & 1] = a;
+        /* the slot of iteration it + 2 is accumulated in the next pass */
+        for (int k = 0; k < 3; ++k) ps[p].acc[4 * ((it + 2) & 3) + k] = 0.0;
+      }
+    }
+    __syncthreads();
+    const int more = any_active;
+    __syncthreads();
+    if (!more || S.cnt->err) break;
+    const int cur = it & 1, nxt = cur ^ 1;
+    for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
+      const int b = gr * 16 + lb;
+      const int p = b < S.B ? S.bprob[b] : 0;
+      const bool act = b < S.B && !pdone[p];
+      const int o = 12 * b + row;
+      double y = 0.0, u1 = 0.0, rv = 0.0;
+      if (act) {
+        const double* acc = ps[p].acc + 4 * (it & 3);
+        const double g = ld_acq(acc), d = ld_acq(acc + 1);
+        double a = g / d, be = 0.0;
+        if (it > 0) {
+          be = g / ld_acq(ps[p].acc + 4 * ((it - 1) & 3));
+          a = g / (d - be * g / ld_acq(&ps[p].cg_alpha[(it - 1) & 1]));
+        }
+        const double uo = Uv[cur][o], mo = Mv[cur][o], tp = Tv[nxt][o];
+        const double pk = __fma_rn(be, P[o], uo);
+        const double sk = __fma_rn(be, Sv[o], W[o]);
+        P[o] = pk;
+        Sv[o] = sk;
+        Tv[cur][o] = __fma_rn(be, tp, mo);
+        S.dq[o] = __fma_rn(a, pk, S.dq[o]);
+        rv = __fma_rn(-a, sk, S.r[o]);
+        S.r[o] = rv;
+        u1 = cg_next_u(uo, mo, tp, a, be);
+        Uv[nxt][o] = u1;
+        /* w_{it+1} = A u_{it+1}, u of every body formed on the fly */
+        HT accv = 0;
+        const HT* H = Hd + 144 * b + 12 * row;
+        for (int c = 0; c < 12; ++c) {
+          const int oc = 12 * b + c;
+          accv += H[c] * (HT)cg_next_u(Uv[cur][oc], Mv[cur][oc], Tv[nxt][oc], a, be);
+        }
+        for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
+          const int nb = S.col_body[e];
+          const HT* blk = Ho + 144 * (size_t)S.col_slot[e];
+          const int st = S.col_trans[e] ? 12 : 1, sc = S.col_trans[e] ? 1 : 12;
+          for (int c = 0; c < 12; ++c) {
+            const int oc = 12 * nb + c;
+            accv += blk[sc * row + st * c] *
+                    (HT)cg_next_u(Uv[cur][oc], Mv[cur][oc], Tv[nxt][oc], a, be);
+          }
+        }
+        y = (double)accv;
+        W[o] = y;
+      }
+      rloc[lb][row] = y;
+      __syncthreads();
+      if (act) {
+        HT mm = 0;
+        for (int c = 0; c < 12; ++c) mm += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+        Mv[nxt][o] = (double)mm;
+      }
+      const double v[3] = {rv * u1, y * u1, rv * rv};
+      const int slot = OFF_ACC + (int)sizeof(double) * 4 * ((it + 1) & 3);
+      const int off[3] = {slot, slot + (int)sizeof(double),
+                          slot + 2 * (int)sizeof(double)};
+      group_add<3>(gs, gr, S.B, S.bprob, p, act, v, ps, off);
+    }
+    grid_sync(&S.cnt->bar, nblk, gen, &S.cnt->err);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) S.cnt->pcg_iters = it;
+}
+
 /* ================================================================== */
 /* S8 Newton stop                                                      */
 /* ================================================================== */
@@ -1645,6 +1882,120 @@ __global__ void k_reset_iter(Scene S, Counters fresh) {
   for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
 }
 
+/* ================================================================== */
+/* consensus step over the replicas of shared bodies                   */
+/* ================================================================== */
+/* Alg. 1 start of a time step: z = q-tilde (the rho-weighted mean over the
+ * replicas, which agree at a step start), u = 0; clears the residual
+ * reductions.  One thread per (group, dof). */
+__global__ void k_cons_init(Scene S, Cons C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < C.n_groups) C.r_body[t] = C.s_body[t] = 0ull;
+  if (t < 2) C.red[t] = 0ull;
+  if (t >= 12 * C.n_groups) return;
+  const int g = t / 12, d = t % 12;
+  double num = 0.0, den = 0.0;
+  for (int j = C.grp_ptr[g]; j < C.grp_ptr[g + 1]; ++j) {
+    const int k = C.grp_rep[j];
+    num += S.rho[k] * S.qtilde[12 * C.rep_body[k] + d];
+    den += S.rho[k];
+  }
+  const double z = num / den;
+  C.zc[12 * g + d] = z;
+  for (int j = C.grp_ptr[g]; j < C.grp_ptr[g + 1]; ++j) {
+    const int k = C.grp_rep[j];
+    S.z[12 * k + d] = z;
+    S.u[12 * k + d] = 0.0;
+  }
+}
+
+/* Eq. 6 (rho-weighted mean of q + u over the replicas), Eq. 7 (u += q - z),
+ * and the residuals of Eqs. 9-10 per body and overall.  The new z becomes
+ * every replica's target for the next local solve.  One thread per
+ * (group, dof). */
+__global__ void k_cons_update(Scene S, Cons C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  double rmax = 0.0, sdev = 0.0;
+  int g = 0;
+  const bool act = t < 12 * C.n_groups;
+  if (act) {
+    g = t / 12;
+    const int d = t % 12;
+    double num = 0.0, den = 0.0;
+    for (int j = C.grp_ptr[g]; j < C.grp_ptr[g + 1]; ++j) {
+      const int k = C.grp_rep[j];
+      num += S.rho[k] * (S.q[12 * C.rep_body[k] + d] + S.u[12 * k + d]);
+      den += S.rho[k];
+    }
+    const double zn = num / den;
+    sdev = fabs(zn - C.zc[12 * g + d]);
+    C.zc[12 * g + d] = zn;
+    for (int j = C.grp_ptr[g]; j < C.grp_ptr[g + 1]; ++j) {
+      const int k = C.grp_rep[j];
+      const double q = S.q[12 * C.rep_body[k] + d];
+      rmax = fmax(rmax, fabs(q - zn));
+      S.u[12 * k + d] += q - zn;
+      S.z[12 * k + d] = zn;
+    }
+    atomic_max_pos(&C.r_body[g], rmax);
+    atomic_max_pos(&C.s_body[g], sdev);
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    rmax = fmax(rmax, __shfl_xor(rmax, o, 64));
+    sdev = fmax(sdev, __shfl_xor(sdev, o, 64));
+  }
+  if (__lane_id() == 0) {
+    atomic_max_pos(&C.red[0], rmax);
+    atomic_max_pos(&C.red[1], sdev);
+  }
+}
+
+/* Eq. 12 per replica from its body's residuals, clamped to
+ * [smin, smax] x rho0; the scaled dual follows as u rho_old / rho_new.
+ * Clears the residual reductions for the next update. */
+__global__ void k_cons_adapt(Scene S, Cons C) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= C.n_rep) return;
+  const int g = C.rep_group[k];
+  const double r = __longlong_as_double((long long)C.r_body[g]);
+  const double sd = __longlong_as_double((long long)C.s_body[g]);
+  const double old = S.rho[k];
+  double nw = old;
+  if (r > C.mu * sd) nw = C.tau * old;
+  else if (sd > C.mu * r) nw = old / C.tau;
+  nw = fmin(fmax(nw, C.smin * C.rho0[k]), C.smax * C.rho0[k]);
+  const double f = old / nw;
+  for (int d = 0; d < 12; ++d) S.u[12 * k + d] *= f;
+  S.rho[k] = nw;
+}
+__global__ void k_cons_clear(Cons C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < C.n_groups) C.r_body[t] = C.s_body[t] = 0ull;
+  if (t < 2) C.red[t] = 0ull;
+}
+
+/* Sec. 4.2: the merged state puts z on every replica */
+__global__ void k_cons_merge(Scene S, Cons C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 12 * C.n_rep) return;
+  const int k = t / 12, d = t % 12;
+  S.q[12 * C.rep_body[k] + d] = C.zc[12 * C.rep_group[k] + d];
+}
+/* step toward the merged state: dq = z - q on replicas, 0 elsewhere; every
+ * problem's CCD minimum starts at 1 */
+__global__ void k_cons_dq_zero(Scene S) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < 12 * S.B) S.dq[t] = 0.0;
+  if (t < S.NP) S.ps[t].min_toi = (unsigned long long)__double_as_longlong(1.0);
+}
+__global__ void k_cons_dq(Scene S, Cons C) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 12 * C.n_rep) return;
+  const int k = t / 12, d = t % 12;
+  const int o = 12 * C.rep_body[k] + d;
+  S.dq[o] = C.zc[12 * C.rep_group[k] + d] - S.q[o];
+}
+
 /* gather every problem's state into the batch arrays (grid.y = problem) */
 __global__ void k_gather(Scene S, const ProbCopy* pc, const double* scales) {
   const ProbCopy c = pc[blockIdx.y];
@@ -1730,7 +2081,6 @@ __global__ void k_clear_slots(Scene S) {
 /* ================================================================== */
 /* host launchers                                                      */
 /* ================================================================== */
-static const int GRID_STRIDE_BLOCKS = 1024;
 static const int ENERGY_BLOCKS = 512;
 
 void launch_predict(const Scene& S, hipStream_t st) {
@@ -1755,24 +2105,28 @@ void launch_body_terms(const Scene& S, hipStream_t st) {
 void launch_boxes(const Scene& S, int swept, hipStream_t st) {
   hipLaunchKernelGGL(k_boxes, dim3(cdiv(S.NC + S.B, 256)), dim3(256), 0, st, S, swept);
 }
+void launch_positions(const Scene& S, int swept, hipStream_t st) {
+  hipLaunchKernelGGL(k_positions, dim3(cdiv(S.V, 256)), dim3(256), 0, st, S, swept);
+}
 void launch_body_pairs(const Scene& S, hipStream_t st) {
   unsigned g = cdiv(S.B, 16);
   hipLaunchKernelGGL(k_body_pairs, dim3(g, g), dim3(16, 16), 0, st, S);
 }
 void launch_chunk_pairs(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_chunk_pairs, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_chunk_pairs, dim3(S.grid_blocks), dim3(256), 0, st, S);
 }
 void launch_prim_pairs(const Scene& S, int swept, hipStream_t st) {
-  hipLaunchKernelGGL(k_prim_pairs, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S, swept);
+  hipLaunchKernelGGL(k_prim_pairs, dim3(S.grid_blocks), dim3(256), 0, st, S, swept);
 }
 void launch_pg(const Scene& S, int swept, hipStream_t st) {
   hipLaunchKernelGGL(k_pg, dim3(min(1024u, cdiv(S.NC, 4))), dim3(256), 0, st, S, swept);
 }
 void launch_filter(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_filter, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_filter, dim3(S.grid_blocks), dim3(256), 0, st, S);
 }
 void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st) {
-  unsigned g = n_act_hint > 0 ? min(4096u, cdiv(n_act_hint, PAIRS_PER_WG)) : 2048u;
+  unsigned g = n_act_hint > 0 ? min(4096u, cdiv(n_act_hint, PAIRS_PER_WG))
+                              : (unsigned)S.assemble_blocks;
   if (S.mixed)
     hipLaunchKernelGGL(k_assemble<float>, dim3(g), dim3(64), 0, st, S);
   else
@@ -1801,11 +2155,34 @@ void launch_scatter(const Scene& S, const ProbCopy* pc, int np, int max_nb,
   hipLaunchKernelGGL(k_scatter, dim3(cdiv(12L * max_nb, 256), np), dim3(256), 0,
                      st, S, pc);
 }
+void launch_cons_init(const Scene& S, const Cons& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_cons_init, dim3(cdiv(12L * C.n_groups + 2, 256)), dim3(256),
+                     0, st, S, C);
+}
+void launch_cons_update(const Scene& S, const Cons& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_cons_clear, dim3(cdiv(C.n_groups + 2, 256)), dim3(256), 0,
+                     st, C);
+  hipLaunchKernelGGL(k_cons_update, dim3(cdiv(12L * C.n_groups, 256)), dim3(256),
+                     0, st, S, C);
+}
+void launch_cons_adapt(const Scene& S, const Cons& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_cons_adapt, dim3(cdiv(C.n_rep, 256)), dim3(256), 0, st, S, C);
+}
+void launch_cons_merge(const Scene& S, const Cons& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_cons_merge, dim3(cdiv(12L * C.n_rep, 256)), dim3(256), 0,
+                     st, S, C);
+}
+void launch_cons_merge_dq(const Scene& S, const Cons& C, hipStream_t st) {
+  hipLaunchKernelGGL(k_cons_dq_zero, dim3(cdiv(12L * S.B + S.NP, 256)), dim3(256),
+                     0, st, S);
+  hipLaunchKernelGGL(k_cons_dq, dim3(cdiv(12L * C.n_rep, 256)), dim3(256), 0, st,
+                     S, C);
+}
 void launch_reset_pcg(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_pcg, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);
 }
 void launch_crossings(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_crossings, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_crossings, dim3(1024), dim3(256), 0, st, S);
 }
 void launch_clear_slots(const Scene& S, hipStream_t st) {
   if (S.mixed)
@@ -1832,11 +2209,20 @@ int pcg_max_grid() {
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)k_pcg<double>, 192, 0);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg<float>, 192, 0);
   per = std::min(per, per32);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg1<double>, 192, 0);
+  per = std::min(per, per32);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg1<float>, 192, 0);
+  per = std::min(per, per32);
   return ncu * (per > 0 ? per : 1);
 }
-int launch_pcg(const Scene& S, double eta, int max_it, int grid, hipStream_t st) {
+int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
+               hipStream_t st) {
   void* args[] = {(void*)&S, (void*)&eta, (void*)&max_it};
-  const void* fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
+  const void* fn;
+  if (variant == 1)
+    fn = S.mixed ? (const void*)k_pcg1<float> : (const void*)k_pcg1<double>;
+  else
+    fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st);
   return e == hipSuccess ? 0 : -1;
 }
@@ -1844,7 +2230,7 @@ void launch_dq_norm(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_dq_norm, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S);
 }
 void launch_ccd(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_ccd, dim3(GRID_STRIDE_BLOCKS), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_ccd, dim3(S.grid_blocks), dim3(256), 0, st, S);
 }
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -51,6 +52,8 @@ struct Pending {
 
 struct abd_ctx {
   abd_params P;
+  uint64_t serial = 0;            /* unique per context in the process */
+  abd_batch* batch_cache = nullptr; /* merged scene of abd_batch_solve */
   std::string err;
   hipStream_t st = nullptr;
   hipStream_t side = nullptr; /* body terms run here, overlapping the
@@ -81,7 +84,7 @@ struct abd_ctx {
   hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
-  bool use_graphs = true;
+  abd_tuning tune = {ABD_PCG_TWO_BARRIER, 0, 1024, 2048, 1};
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -410,6 +413,7 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
 /* ---------------- phases ---------------- */
 void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
   StageTimer t(ctx, 1);
+  launch_positions(S, swept, ctx->st);
   launch_boxes(S, swept, ctx->st);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
@@ -441,6 +445,13 @@ void launch_static(abd_ctx* ctx, const Scene& S) {
   }
 }
 
+/* blocks of the cooperative PCG launch */
+int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
+  const int ng = std::max(1, (S.B + 15) / 16);
+  const int want = ctx->tune.pcg_blocks > 0 ? std::min(ctx->tune.pcg_blocks, ng) : ng;
+  return std::max(1, std::min(ctx->pcg_grid, want));
+}
+
 /* block-Jacobi PCG and the Newton stop norm on the stream */
 int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
   {
@@ -453,9 +464,9 @@ int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
     launch_bsr(S, ctx->st);
     launch_block_inverse(S, ctx->st);
   }
-  const int grid = std::min(ctx->pcg_grid, std::max(1, (S.B + 15) / 16));
   StageTimer t(ctx, 3);
-  if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, grid, ctx->st))
+  if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S),
+                 ctx->tune.pcg_variant, ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
   launch_dq_norm(S, ctx->st);
   return ABD_OK;
@@ -465,11 +476,15 @@ void account_pcg_bytes(abd_ctx* ctx) {
   if (!ctx->timing) return;
   const Scene& S = ctx->S;
   /* algorithmic bytes of the PCG launch: per iteration the diagonal and
-   * used off-diagonal blocks once, the block inverses once and seven
-   * length-12B vectors */
+   * used off-diagonal blocks once, the block inverses once and the
+   * length-12B FP64 vectors read and written once each (two-barrier form:
+   * z, p twice, Ap twice, r twice, dq twice less shared reads = 7 passes;
+   * pipelined form: u, m, t, p, s, w, r, x read and u, m, t, p, s, w, r, x
+   * written = 16 passes) */
   const double blk = 144.0 * (double)hess_elem(ctx);
+  const double vec = ctx->tune.pcg_variant == ABD_PCG_PIPELINED ? 16.0 : 7.0;
   const double per = (double)(S.B + ctx->h_cnt[0].n_rows_used / 2) * blk +
-                     (double)S.B * blk + 7.0 * 12.0 * S.B * 8.0;
+                     (double)S.B * blk + vec * 12.0 * S.B * 8.0;
   ctx->t_bytes[3] += per * ctx->h_cnt[0].pcg_iters;
 }
 
@@ -580,9 +595,9 @@ void pass_pre(abd_ctx* ctx) {
 int pass_pcg(abd_ctx* ctx) {
   Scene S1 = ctx->S;
   S1.iter_mode = 1;
-  const int grid = std::min(ctx->pcg_grid, std::max(1, (S1.B + 15) / 16));
   StageTimer t(ctx, 3);
-  if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, grid, ctx->st))
+  if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S1),
+                 ctx->tune.pcg_variant, ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
   return ABD_OK;
 }
@@ -639,7 +654,7 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
  * captured graphs when possible (not while every stage is timed,
  * and not on the legacy null stream, which cannot be captured). */
 int run_pass(abd_ctx* ctx) {
-  const bool graphs = ctx->use_graphs && ctx->graphs_ok &&
+  const bool graphs = ctx->tune.use_graphs && ctx->graphs_ok &&
                       ctx->timing != ABD_TIMING_ALL &&
                       ctx->st != nullptr;
   if (graphs && (!ctx->pass_graph[0] || !ctx->pass_graph[1])) {
@@ -712,7 +727,9 @@ int abd_create(abd_ctx** out, const abd_params* p) {
     (void)hipGetLastError();
     return ABD_E_DEVICE;
   }
+  static std::atomic<uint64_t> next_serial{1};
   abd_ctx* c = new abd_ctx();
+  c->serial = next_serial.fetch_add(1);
   c->P = *p;
   std::memset(&c->S, 0, sizeof(Scene));
   *out = c;
@@ -722,6 +739,8 @@ int abd_create(abd_ctx** out, const abd_params* p) {
 void abd_destroy(abd_ctx* ctx) {
   if (!ctx) return;
   (void)hipDeviceSynchronize();
+  abd_batch_destroy(ctx->batch_cache);
+  ctx->batch_cache = nullptr;
   drop_graphs(ctx);
   if (ctx->own_stream && ctx->st) (void)hipStreamDestroy(ctx->st);
   for (void* p : ctx->allocs) (void)hipFree(p);
@@ -976,6 +995,11 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.p1, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.Ap, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
+  if ((rc = dalloc(ctx, &S.pw, 5 * 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.xw, 3L * S.V))) return rc;
+  if ((rc = dalloc(ctx, &S.xw1, 3L * S.V))) return rc;
+  S.grid_blocks = ctx->tune.grid_blocks;
+  S.assemble_blocks = ctx->tune.assemble_blocks;
   if ((rc = dalloc(ctx, &S.partials, S.cap_partials))) return rc;
   if ((rc = dalloc(ctx, &S.cnt, 2))) return rc;
   S.NP = ctx->np;
@@ -1172,6 +1196,10 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
   st.n_cand_ee = c.n_ee;
   st.n_cand_pg = c.n_pg;
   st.n_active = c.n_act;
+  st.n_body_pairs = c.n_bp;
+  st.n_chunk_pairs = c.n_cp;
+  st.n_body_pairs_swept = ctx->h_cnt[1].n_bp;
+  st.n_chunk_pairs_swept = ctx->h_cnt[1].n_cp;
   st.min_dist = bits_to_double(c.min_dist);
   st.status = status;
   st.t_solve_ms =
@@ -1415,6 +1443,7 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
 
 struct abd_batch {
   std::vector<abd_ctx*> ctxs;
+  std::vector<uint64_t> key; /* serials and pair rules of the contexts */
   std::vector<int> body_off;
   std::vector<unsigned> sh_seen;
   abd_ctx* M = nullptr;
@@ -1422,7 +1451,32 @@ struct abd_batch {
   double* scales = nullptr; /* device [n] */
   std::vector<double> h_scales;
   int max_nb = 0;
+  bool external_shared = false; /* shared data owned by a consensus object */
 };
+
+/* every context's state and scene scale into the batch scene */
+static int batch_gather(abd_batch* bt) {
+  abd_ctx* ctx = bt->M;
+  const int n = (int)bt->ctxs.size();
+  for (int i = 0; i < n; ++i) {
+    HIPCHK(hipStreamSynchronize(bt->ctxs[i]->st));
+    bt->h_scales[i] = bt->ctxs[i]->scale;
+  }
+  HIPCHK(hipMemcpyAsync(bt->scales, bt->h_scales.data(), sizeof(double) * n,
+                        hipMemcpyHostToDevice, ctx->st));
+  launch_gather(ctx->S, bt->pc, bt->scales, n, bt->max_nb, ctx->st);
+  return ABD_OK;
+}
+
+static std::vector<uint64_t> batch_key(abd_ctx** ctxs, int n) {
+  std::vector<uint64_t> k;
+  for (int i = 0; i < n; ++i) {
+    k.push_back(ctxs[i]->serial);
+    k.push_back((uint64_t)ctxs[i]->pair_mode);
+  }
+  return k;
+}
+
 
 extern "C" {
 
@@ -1466,7 +1520,7 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out) {
     off += B;
     bt->max_nb = std::max(bt->max_nb, B);
   }
-  if ((rc = abd_finalize(M))) {
+  if ((rc = abd_finalize(M)) || (rc = abd_set_tuning(M, &ctxs[0]->tune))) {
     abd_batch_destroy(bt);
     return rc;
   }
@@ -1482,6 +1536,7 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out) {
   }
   bt->sh_seen.assign(n, ~0u);
   bt->h_scales.assign(n, 1.0);
+  bt->key = batch_key(ctxs, n);
   *out = bt;
   return ABD_OK;
 }
@@ -1494,7 +1549,7 @@ void abd_batch_destroy(abd_batch* bt) {
   delete bt;
 }
 
-int abd_batch_solve(abd_batch* bt, abd_stats* out) {
+int abd_batch_run(abd_batch* bt, abd_stats* out) {
   if (!bt) return ABD_E_INVALID_ARG;
   abd_ctx* M = bt->M;
   abd_ctx* ctx = M;
@@ -1503,7 +1558,7 @@ int abd_batch_solve(abd_batch* bt, abd_stats* out) {
   /* shared-body data: rebuilt only when a context changed it */
   bool sh_changed = false;
   for (int i = 0; i < n; ++i) sh_changed |= bt->sh_seen[i] != bt->ctxs[i]->sh_version;
-  if (sh_changed) {
+  if (sh_changed && !bt->external_shared) {
     std::vector<int> ids, kb;
     std::vector<double> z, u, rho;
     for (int i = 0; i < n; ++i) {
@@ -1519,13 +1574,8 @@ int abd_batch_solve(abd_batch* bt, abd_stats* out) {
                             rho.data(), kb.data());
     if (rc) return rc;
   }
-  for (int i = 0; i < n; ++i) {
-    (void)hipStreamSynchronize(bt->ctxs[i]->st);
-    bt->h_scales[i] = bt->ctxs[i]->scale;
-  }
-  HIPCHK(hipMemcpyAsync(bt->scales, bt->h_scales.data(), sizeof(double) * n,
-                        hipMemcpyHostToDevice, M->st));
-  launch_gather(M->S, bt->pc, bt->scales, n, bt->max_nb, M->st);
+  int rc0 = batch_gather(bt);
+  if (rc0) return rc0;
   int status = device_solve(M);
   launch_scatter(M->S, bt->pc, n, bt->max_nb, M->st);
   HIPCHK(hipStreamSynchronize(M->st));
@@ -1554,6 +1604,374 @@ int abd_batch_solve(abd_batch* bt, abd_stats* out) {
     }
   }
   return first;
+}
+
+int abd_batch_solve(abd_ctx** ctxs, int32_t n, abd_stats* out) {
+  if (!ctxs || n < 1) return ABD_E_INVALID_ARG;
+  for (int i = 0; i < n; ++i)
+    if (!ctxs[i]) return ABD_E_INVALID_ARG;
+  abd_ctx* owner = ctxs[0];
+  const std::vector<uint64_t> key = batch_key(ctxs, n);
+  if (!owner->batch_cache || owner->batch_cache->key != key) {
+    abd_batch_destroy(owner->batch_cache);
+    owner->batch_cache = nullptr;
+    int rc = abd_batch_create(ctxs, n, &owner->batch_cache);
+    if (rc) return rc;
+  }
+  return abd_batch_run(owner->batch_cache, out);
+}
+
+}  /* extern "C" */
+
+struct abd_consensus {
+  abd_batch* bt = nullptr;
+  abd_admm_params ap;
+  Cons C;
+  std::vector<void*> allocs;
+  int n_rep = 0, n_groups = 0;
+  double h_red[2] = {0, 0};
+};
+
+static void cons_free(abd_consensus* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+}
+
+template <typename T>
+static int cons_upload(abd_consensus* c, const T** dst, const std::vector<T>& v) {
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(1, v.size())) != hipSuccess)
+    return ABD_E_OOM;
+  c->allocs.push_back(p);
+  if (!v.empty() && hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice))
+    return ABD_E_DEVICE;
+  *dst = (const T*)p;
+  return ABD_OK;
+}
+template <typename T>
+static int cons_alloc(abd_consensus* c, T** dst, size_t n) {
+  void* p = nullptr;
+  if (hipMalloc(&p, sizeof(T) * std::max<size_t>(1, n)) != hipSuccess) return ABD_E_OOM;
+  c->allocs.push_back(p);
+  if (hipMemset(p, 0, sizeof(T) * std::max<size_t>(1, n))) return ABD_E_DEVICE;
+  *dst = (T*)p;
+  return ABD_OK;
+}
+
+extern "C" {
+
+int abd_consensus_create(abd_batch* bt, const int32_t* rep_prob,
+                         const int32_t* rep_body, const int32_t* rep_group,
+                         int32_t n_rep, int32_t n_groups,
+                         const abd_admm_params* ap, abd_consensus** out) {
+  if (!bt || !rep_prob || !rep_body || !rep_group || !ap || !out || n_rep < 1 ||
+      n_groups < 1)
+    return ABD_E_INVALID_ARG;
+  *out = nullptr;
+  abd_ctx* M = bt->M;
+  const int np = (int)bt->ctxs.size();
+  if (!(ap->tau > 1.0) || !(ap->mu >= 1.0) || !(ap->sigma_min > 0.0) ||
+      !(ap->sigma_max >= ap->sigma_min) || ap->max_iters < 1 ||
+      (!(ap->beta > 0.0) && !(ap->rho_fixed > 0.0)))
+    return fail(M, ABD_E_INVALID_ARG, "admm parameters");
+  std::vector<int> cnt(n_groups, 0), ids(n_rep), kb(n_rep);
+  std::vector<double> rho0(n_rep), z(12L * n_rep, 0.0), u(12L * n_rep, 0.0);
+  std::vector<std::pair<int, int>> seen;
+  for (int k = 0; k < n_rep; ++k) {
+    const int p = rep_prob[k], b = rep_body[k], g = rep_group[k];
+    if (p < 0 || p >= np || g < 0 || g >= n_groups || b < 0 || b >= bt->ctxs[p]->S.B ||
+        bt->ctxs[p]->bodies[b].kind != ABD_DYNAMIC)
+      return fail(M, ABD_E_INVALID_ARG, "replica index");
+    seen.push_back({p, g});
+    cnt[g] += 1;
+    ids[k] = bt->body_off[p] + b;
+    const double m = bt->ctxs[p]->bodies[b].Mhat[0];
+    rho0[k] = ap->beta > 0.0 ? ap->beta * m : ap->rho_fixed;
+  }
+  std::sort(seen.begin(), seen.end());
+  if (std::adjacent_find(seen.begin(), seen.end()) != seen.end())
+    return fail(M, ABD_E_INVALID_ARG, "two replicas of one body in a problem");
+  for (int g = 0; g < n_groups; ++g)
+    if (cnt[g] == 0) return fail(M, ABD_E_INVALID_ARG, "a shared body has no replica");
+  for (int k = 0; k < n_rep; ++k) kb[k] = cnt[rep_group[k]];
+  std::vector<int> ptr(n_groups + 1, 0), rep(n_rep), fill(n_groups, 0);
+  for (int g = 0; g < n_groups; ++g) ptr[g + 1] = ptr[g] + cnt[g];
+  for (int k = 0; k < n_rep; ++k) rep[ptr[rep_group[k]] + fill[rep_group[k]]++] = k;
+  int rc = abd_set_shared(M, ids.data(), n_rep, z.data(), u.data(), rho0.data(), kb.data());
+  if (rc) return rc;
+  abd_consensus* c = new abd_consensus();
+  c->bt = bt;
+  c->ap = *ap;
+  c->n_rep = n_rep;
+  c->n_groups = n_groups;
+  Cons& C = c->C;
+  std::memset(&C, 0, sizeof(C));
+  C.n_rep = n_rep;
+  C.n_groups = n_groups;
+  C.tau = ap->tau;
+  C.mu = ap->mu;
+  C.smin = ap->sigma_min;
+  C.smax = ap->sigma_max;
+  std::vector<int> rg(rep_group, rep_group + n_rep);
+  if ((rc = cons_upload(c, &C.rep_body, ids)) || (rc = cons_upload(c, &C.rep_group, rg)) ||
+      (rc = cons_upload(c, &C.grp_ptr, ptr)) || (rc = cons_upload(c, &C.grp_rep, rep)) ||
+      (rc = cons_upload(c, &C.rho0, rho0)) || (rc = cons_alloc(c, &C.zc, 12L * n_groups)) ||
+      (rc = cons_alloc(c, &C.r_body, n_groups)) || (rc = cons_alloc(c, &C.s_body, n_groups)) ||
+      (rc = cons_alloc(c, &C.red, 2))) {
+    cons_free(c);
+    delete c;
+    return fail(M, rc, "consensus allocation");
+  }
+  bt->external_shared = true;
+  *out = c;
+  return ABD_OK;
+}
+
+void abd_consensus_destroy(abd_consensus* c) {
+  if (!c) return;
+  (void)hipDeviceSynchronize();
+  if (c->bt) c->bt->external_shared = false;
+  cons_free(c);
+  delete c;
+}
+
+int abd_consensus_begin(abd_consensus* c) {
+  if (!c) return ABD_E_INVALID_ARG;
+  abd_ctx* ctx = c->bt->M;
+  int rc = batch_gather(c->bt);
+  if (rc) return rc;
+  launch_cons_init(ctx->S, c->C, ctx->st);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return ABD_OK;
+}
+
+static double cons_scale(abd_consensus* c) {
+  if (c->ap.scale > 0.0) return c->ap.scale;
+  double l = 0.0;
+  for (double v : c->bt->h_scales) l = std::max(l, v);
+  return l > 0.0 ? l : 1.0;
+}
+
+int abd_consensus_update(abd_consensus* c, abd_admm_report* rep) {
+  if (!c) return ABD_E_INVALID_ARG;
+  abd_batch* bt = c->bt;
+  abd_ctx* ctx = bt->M;
+  Scene& S = ctx->S;
+  launch_cons_update(S, c->C, ctx->st);
+  HIPCHK(hipMemcpyAsync(c->h_red, c->C.red, 2 * sizeof(double), hipMemcpyDeviceToHost,
+                        ctx->st));
+  const int np = (int)bt->ctxs.size();
+  std::vector<ProbState> P(np);
+  double min_toi = 1.0;
+  if (c->ap.merge_check) {
+    /* ACCD of every problem from its q toward its merged state */
+    launch_cons_merge_dq(S, c->C, ctx->st);
+    int rc = swept_phase(ctx, true);
+    if (rc) return rc;
+  }
+  HIPCHK(hipMemcpyAsync(P.data(), S.ps, sizeof(ProbState) * np, hipMemcpyDeviceToHost,
+                        ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  double eps = 0.0;
+  for (int p = 0; p < np; ++p) {
+    eps = std::max(eps, P[p].final_eps);
+    if (c->ap.merge_check)
+      min_toi = std::min(min_toi, std::min(1.0, bits_to_double(P[p].min_toi)));
+  }
+  const double hl = ctx->P.dt * cons_scale(c);
+  if (rep) {
+    rep->eps_newton = eps;
+    rep->r_inf = c->h_red[0] / hl;
+    rep->s_inf = c->h_red[1] / hl;
+    rep->min_toi = min_toi;
+    rep->merge_ok = min_toi >= 1.0;
+    const double th = ctx->P.newton_theta;
+    rep->converged = eps < th && rep->r_inf < th && rep->s_inf < th &&
+                     (!c->ap.merge_check || rep->merge_ok);
+  }
+  return ABD_OK;
+}
+
+int abd_consensus_adapt(abd_consensus* c) {
+  if (!c) return ABD_E_INVALID_ARG;
+  abd_ctx* ctx = c->bt->M;
+  launch_cons_adapt(ctx->S, c->C, ctx->st);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return ABD_OK;
+}
+
+int abd_consensus_merge(abd_consensus* c) {
+  if (!c) return ABD_E_INVALID_ARG;
+  abd_batch* bt = c->bt;
+  abd_ctx* ctx = bt->M;
+  launch_cons_merge(ctx->S, c->C, ctx->st);
+  launch_scatter(ctx->S, bt->pc, (int)bt->ctxs.size(), bt->max_nb, ctx->st);
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  return ABD_OK;
+}
+
+int abd_consensus_get(abd_consensus* c, double* z, double* u, double* rho) {
+  if (!c) return ABD_E_INVALID_ARG;
+  abd_ctx* ctx = c->bt->M;
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  if (z) HIPCHK(hipMemcpy(z, c->C.zc, sizeof(double) * 12 * c->n_groups, hipMemcpyDeviceToHost));
+  if (u) HIPCHK(hipMemcpy(u, ctx->S.u, sizeof(double) * 12 * c->n_rep, hipMemcpyDeviceToHost));
+  if (rho) HIPCHK(hipMemcpy(rho, ctx->S.rho, sizeof(double) * c->n_rep, hipMemcpyDeviceToHost));
+  return ABD_OK;
+}
+
+int abd_admm_step(abd_consensus* c, abd_admm_report* rep) {
+  if (!c) return ABD_E_INVALID_ARG;
+  abd_batch* bt = c->bt;
+  const int np = (int)bt->ctxs.size();
+  abd_admm_report r;
+  std::memset(&r, 0, sizeof(r));
+  int rc;
+  for (abd_ctx* x : bt->ctxs)
+    if ((rc = abd_begin_step(x))) return rc;
+  if ((rc = abd_consensus_begin(c))) return rc;
+  std::vector<abd_stats> st(np);
+  int status = ABD_E_NOCONV;
+  for (int k = 1; k <= c->ap.max_iters; ++k) {
+    if (k > 1) {
+      if ((rc = abd_consensus_update(c, &r))) return rc;
+      if (r.converged) {
+        status = ABD_OK;
+        break;
+      }
+      if (c->ap.adapt_rho && (rc = abd_consensus_adapt(c))) return rc;
+    }
+    rc = abd_batch_run(bt, st.data());
+    r.iters = k;
+    for (int p = 0; p < np; ++p) r.newton_iters_total += st[p].newton_iters;
+    if (rc) {
+      if (rep) *rep = r;
+      return rc;
+    }
+    if (k == c->ap.max_iters) {
+      if ((rc = abd_consensus_update(c, &r))) return rc;
+      if (r.converged) status = ABD_OK;
+    }
+  }
+  /* merge when the consensus is safe to apply */
+  if (status == ABD_OK || r.merge_ok) {
+    if ((rc = abd_consensus_merge(c))) return rc;
+  }
+  for (abd_ctx* x : bt->ctxs)
+    if ((rc = abd_end_step(x))) return rc;
+  if (rep) *rep = r;
+  if (status != ABD_OK) bt->M->err = "ADMM did not converge within max_iters";
+  return status;
+}
+
+int abd_get_tuning(abd_ctx* ctx, abd_tuning* out) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!out) return fail(ctx, ABD_E_INVALID_ARG, "tuning output");
+  *out = ctx->tune;
+  return ABD_OK;
+}
+
+int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!t || (t->pcg_variant != ABD_PCG_TWO_BARRIER && t->pcg_variant != ABD_PCG_PIPELINED) ||
+      t->pcg_blocks < 0 || t->grid_blocks < 1 || t->assemble_blocks < 1 ||
+      t->grid_blocks > (1 << 20) || t->assemble_blocks > (1 << 20))
+    return fail(ctx, ABD_E_INVALID_ARG, "tuning values");
+  drop_graphs(ctx); /* launch shapes are part of the captured graphs */
+  ctx->tune = *t;
+  ctx->tune.use_graphs = t->use_graphs ? 1 : 0;
+  ctx->S.grid_blocks = t->grid_blocks;
+  ctx->S.assemble_blocks = t->assemble_blocks;
+  return ABD_OK;
+}
+
+int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  Scene& S = ctx->S;
+  const size_t nb = sizeof(double) * 12 * S.B;
+  double *q0 = nullptr, *qd0 = nullptr;
+  if (hipMalloc(&q0, nb) != hipSuccess || hipMalloc(&qd0, nb) != hipSuccess) {
+    if (q0) (void)hipFree(q0);
+    return fail(ctx, ABD_E_OOM, "autotune state copy");
+  }
+  HIPCHK(hipMemcpyAsync(q0, S.q, nb, hipMemcpyDeviceToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(qd0, S.qdot, nb, hipMemcpyDeviceToDevice, ctx->st));
+  const abd_tuning orig = ctx->tune;
+  const int saved_timing = ctx->timing;
+  ctx->timing = ABD_TIMING_OFF;
+  /* one timed solve of the next step from the saved state; the first run
+   * of a setting captures its graphs, so each setting runs twice */
+  auto trial = [&](const abd_tuning& t) -> double {
+    if (abd_set_tuning(ctx, &t) != ABD_OK) return INFINITY;
+    double best = INFINITY;
+    for (int rep = 0; rep < 2; ++rep) {
+      if (hipMemcpyAsync(S.q, q0, nb, hipMemcpyDeviceToDevice, ctx->st) ||
+          hipMemcpyAsync(S.qdot, qd0, nb, hipMemcpyDeviceToDevice, ctx->st))
+        return INFINITY;
+      if (abd_begin_step(ctx) != ABD_OK) return INFINITY;
+      auto t0 = std::chrono::steady_clock::now();
+      int st = device_solve(ctx);
+      ProbState P[1];
+      if (st == ABD_OK &&
+          hipMemcpy(P, S.ps, sizeof(ProbState), hipMemcpyDeviceToHost) != hipSuccess)
+        st = ABD_E_DEVICE;
+      const double ms = std::chrono::duration<double, std::milli>(
+                            std::chrono::steady_clock::now() - t0).count();
+      if (st != ABD_OK || P[0].status != ABD_OK) return INFINITY;
+      if (rep == 1) best = ms;
+    }
+    return best;
+  };
+  abd_tuning best = orig;
+  double best_ms = trial(best);
+  auto consider = [&](abd_tuning t) {
+    const double ms = trial(t);
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = t;
+    }
+  };
+  const int ng = std::max(1, (S.B + 15) / 16);
+  std::vector<std::pair<int, int>> tried = {{orig.pcg_variant, pcg_blocks(ctx, S)}};
+  /* the pipelined form only where its attainable accuracy is not the
+   * binding limit */
+  const int nvar = ctx->P.pcg_eta >= 1e-6 ? 2 : 1;
+  for (int v = 0; v < nvar; ++v)
+    for (int div : {1, 2, 4, 8}) {
+      abd_tuning t = best;
+      t.pcg_variant = v;
+      t.pcg_blocks = std::max(1, (ng + div - 1) / div);
+      const std::pair<int, int> key(v, std::min(t.pcg_blocks, ctx->pcg_grid));
+      if (std::find(tried.begin(), tried.end(), key) != tried.end()) continue;
+      tried.push_back(key);
+      consider(t);
+    }
+  const abd_tuning after_pcg = best;
+  for (int g : {256, 512, 2048, 4096}) {
+    abd_tuning t = after_pcg;
+    t.grid_blocks = g;
+    if (g != orig.grid_blocks) consider(t);
+  }
+  const abd_tuning after_grid = best;
+  for (int g : {512, 1024, 4096}) {
+    abd_tuning t = after_grid;
+    t.assemble_blocks = g;
+    if (g != orig.assemble_blocks) consider(t);
+  }
+  /* restore the state and keep the winner */
+  (void)abd_set_tuning(ctx, &best);
+  ctx->timing = saved_timing;
+  HIPCHK(hipMemcpyAsync(S.q, q0, nb, hipMemcpyDeviceToDevice, ctx->st));
+  HIPCHK(hipMemcpyAsync(S.qdot, qd0, nb, hipMemcpyDeviceToDevice, ctx->st));
+  HIPCHK(hipStreamSynchronize(ctx->st));
+  (void)hipFree(q0);
+  (void)hipFree(qd0);
+  if (!std::isfinite(best_ms)) return fail(ctx, ABD_E_NOCONV, "autotune: no setting solved the step");
+  if (out) *out = best;
+  return ABD_OK;
 }
 
 int abd_set_timing(abd_ctx* ctx, int32_t on) {

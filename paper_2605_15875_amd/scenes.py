@@ -349,6 +349,55 @@ def hulls_in_funnel_scene(seed: int = 0, n_bodies: int = 2500,
     return sc
 
 
+@dataclasses.dataclass
+class Split:
+    """Subdomains of one scene: worker scenes plus the replica table.
+    Replica k is body rep_body[k] of worker rep_prob[k], a copy of shared
+    body rep_group[k]; whole_ids[w][j] is the index in the whole scene of
+    worker w's body j."""
+    workers: List[Scene]
+    rep_prob: np.ndarray
+    rep_body: np.ndarray
+    rep_group: np.ndarray
+    n_groups: int
+    whole_ids: List[np.ndarray]
+
+
+def split_scene(scene: Scene, axis: int = 0, cut: float = 0.0,
+                slab: float = 0.0) -> Split:
+    """Two subdomains cut by the plane x[axis] = cut: worker 0 keeps the
+    dynamic bodies whose centre (q0 translation) lies below cut + slab/2,
+    worker 1 those above cut - slab/2, so bodies inside the slab are kept
+    by both and shared.  Static bodies go to both workers."""
+    keep = [[], []]
+    for i, b in enumerate(scene.bodies):
+        c = b.q0[axis]
+        if b.kind != DYNAMIC or c < cut + 0.5 * slab:
+            keep[0].append(i)
+        if b.kind != DYNAMIC or c > cut - 0.5 * slab:
+            keep[1].append(i)
+    workers, whole = [], []
+    for w in range(2):
+        ids = np.array(keep[w], dtype=np.int64)
+        bodies = [dataclasses.replace(scene.bodies[i]) for i in ids]
+        workers.append(Scene(f"{scene.name}_w{w}", dict(scene.params), bodies,
+                             scene.steps))
+        whole.append(ids)
+    shared = [i for i in keep[0] if i in set(keep[1])
+              and scene.bodies[i].kind == DYNAMIC]
+    group_of = {i: g for g, i in enumerate(shared)}
+    rp, rb, rg = [], [], []
+    for w in range(2):
+        for j, i in enumerate(whole[w]):
+            if i in group_of:
+                rp.append(w)
+                rb.append(j)
+                rg.append(group_of[i])
+    return Split(workers, np.array(rp, dtype=np.int32),
+                 np.array(rb, dtype=np.int32), np.array(rg, dtype=np.int32),
+                 len(shared), whole)
+
+
 def config(idx: int, seed: int = 0, **over) -> Scene:
     """The named workloads: 0 = 8 stacked cubes on the ground (20 steps),
     1 = 1000 icospheres in an open box (50 steps), 2 = one worker's share

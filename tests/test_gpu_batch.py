@@ -110,3 +110,25 @@ def test_batch_rejects_different_parameters():
     c.set_pair_replication(1)
     with pytest.raises(abd.AbdError):
         abd.Batch([a, c])
+
+
+def test_one_call_batch_solve_matches_oracle_and_rebuilds():
+    scs = cube_scenes()[:3]
+    refs = [O.Oracle(sc) for sc in scs]
+    gpus = [abd.Solver(sc) for sc in scs]
+    orders = [[0, 1, 2], [0, 1, 2], [2, 0, 1], [0, 1]]
+    for step, order in enumerate(orders):
+        for i in order:
+            q, qd = refs[i].get_state()
+            gpus[i].set_state(q, qd)
+            gpus[i].begin_step()
+            refs[i].begin_step()
+        stats = abd.batch_solve([gpus[i] for i in order])
+        for k, i in enumerate(order):
+            so = refs[i].local_solve()
+            assert stats[k]["status"] == so["status"] == 0
+            err = (np.abs(gpus[i].vertices() - refs[i].vertices()).max()
+                   / stats[k]["scene_scale"])
+            assert err < 1e-9, (step, i, err)
+            gpus[i].end_step()
+            refs[i].end_step()

@@ -163,9 +163,15 @@ def test_free_fall_closed_form_gpu():
 
 
 def small_spheres(seed=3):
+    # theta 1e-7: at 1e-8 the last Newton steps of this contact-rich scene
+    # sit at the rounding floor of the energy sum, where the line search
+    # halves at random and the order of the device's floating-point
+    # accumulations (which varies run to run) decides how many iterations
+    # are needed
     return scenes.spheres_in_box_scene(
         seed, n_bodies=24, level=1, half=0.25, y_lo=0.09, y_hi=0.45,
-        r_lo=0.05, r_hi=0.08, min_gap=0.0005, vel=0.5, **PARITY_CONTACT)
+        r_lo=0.05, r_hi=0.08, min_gap=0.0005, vel=0.5, newton_theta=1e-7,
+        pcg_eta=1e-12)
 
 
 def test_spheres_in_box_parity():
