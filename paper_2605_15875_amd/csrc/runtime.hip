@@ -253,35 +253,38 @@ struct Leaf {
  * at most ABD_CHUNK per leaf; leaves of static bodies keep splitting while
  * they hold more than one primitive and their box is much larger than the
  * primitives in it (large container walls get boxes of their own). */
+/* Chunks of one body's primitives (one kind) by median splits of the rest
+ * centroids along the longest axis.  A dynamic body's chunk holds up to one
+ * wavefront of primitives.  A static body (walls, containers: few, large,
+ * far-apart primitives) is split further, until each chunk's box is not
+ * much emptier than its primitives: the box volume, every extent padded by
+ * tau, may exceed the sum of the primitives' padded box volumes at most
+ * twice.  Without that, one chunk of a container's faces has the whole
+ * container as its box and meets every body inside. */
 void split_leaves(std::vector<int>& ids, const std::vector<double>& cen,
-                  const std::vector<double>& pbox, bool is_static,
+                  const std::vector<double>& pbox, bool is_static, double tau,
                   std::vector<Leaf>& out) {
   if (ids.empty()) return;
   double lo[3] = {INFINITY, INFINITY, INFINITY},
          hi[3] = {-INFINITY, -INFINITY, -INFINITY};
   double blo[3] = {INFINITY, INFINITY, INFINITY},
          bhi[3] = {-INFINITY, -INFINITY, -INFINITY};
-  double maxd = 0.0;
-  for (int i : ids)
+  double prim_vol = 0.0;
+  for (int i : ids) {
+    double v = 1.0;
     for (int k = 0; k < 3; ++k) {
       lo[k] = std::min(lo[k], cen[3 * i + k]);
       hi[k] = std::max(hi[k], cen[3 * i + k]);
       blo[k] = std::min(blo[k], pbox[6 * i + k]);
       bhi[k] = std::max(bhi[k], pbox[6 * i + 3 + k]);
+      v *= pbox[6 * i + 3 + k] - pbox[6 * i + k] + 2.0 * tau;
     }
-  for (int i : ids) {
-    double d2 = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      double e = pbox[6 * i + 3 + k] - pbox[6 * i + k];
-      d2 += e * e;
-    }
-    maxd = std::max(maxd, std::sqrt(d2));
+    prim_vol += v;
   }
-  double diag = 0.0;
-  for (int k = 0; k < 3; ++k) diag += (bhi[k] - blo[k]) * (bhi[k] - blo[k]);
-  diag = std::sqrt(diag);
-  bool small = (int)ids.size() <= ABD_CHUNK;
-  if (small && (!is_static || ids.size() == 1 || diag <= 2.0 * maxd)) {
+  double box_vol = 1.0;
+  for (int k = 0; k < 3; ++k) box_vol *= bhi[k] - blo[k] + 2.0 * tau;
+  const bool small = (int)ids.size() <= ABD_CHUNK;
+  if (small && (!is_static || ids.size() == 1 || box_vol <= 2.0 * prim_vol)) {
     out.push_back({ids});
     return;
   }
@@ -292,8 +295,8 @@ void split_leaves(std::vector<int>& ids, const std::vector<double>& cen,
   std::nth_element(ids.begin(), ids.begin() + mid, ids.end(),
                    [&](int a, int b) { return cen[3 * a + ax] < cen[3 * b + ax]; });
   std::vector<int> L(ids.begin(), ids.begin() + mid), R(ids.begin() + mid, ids.end());
-  split_leaves(L, cen, pbox, is_static, out);
-  split_leaves(R, cen, pbox, is_static, out);
+  split_leaves(L, cen, pbox, is_static, tau, out);
+  split_leaves(R, cen, pbox, is_static, tau, out);
 }
 
 /* ---------------- counters ---------------- */
@@ -895,7 +898,7 @@ int abd_finalize(abd_ctx* ctx) {
         }
       }
       std::vector<Leaf> leaves;
-      split_leaves(ids, cen, pbox, hb.kind != ABD_DYNAMIC, leaves);
+      split_leaves(ids, cen, pbox, hb.kind != ABD_DYNAMIC, ctx->P.dhat, leaves);
       body_chunk[6 * b + 2 * kind] = (int)ch_body.size();
       for (auto& L : leaves) {
         double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};

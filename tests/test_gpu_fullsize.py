@@ -13,10 +13,12 @@ pytestmark = pytest.mark.gpu
 
 
 def test_fullsize_spheres_parity():
-    # theta 1e-8: at this size the energy decrease of a Newton step of
+    # theta 1e-7: at this size the energy decrease of a Newton step of
     # 1e-9 h l falls below the FP64 rounding of the barrier energy sum, so
-    # the line search could not certify it (on either side)
-    sc = scenes.config(1, newton_theta=1e-8, pcg_eta=1e-12)
+    # the line search cannot certify it (on either side), and near 1e-8 the
+    # iteration count depends on the order of the device's floating-point
+    # accumulations, which varies from run to run
+    sc = scenes.config(1, newton_theta=1e-7, pcg_eta=1e-12)
     gpu = abd.Solver(sc)
     assert gpu.V == 642008 and gpu.T == 1280010
     for _ in range(2):
