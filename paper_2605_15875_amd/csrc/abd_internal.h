@@ -547,10 +547,131 @@ __device__ __forceinline__ void psd9_reg(T* K) {
 }
 
 /* ------------------------------------------------------------------ */
+/* PSD projection of the orthogonality Hessian in closed form           */
+/* ------------------------------------------------------------------ */
+/* f(A) = |A A^T - I|_F^2 depends on A only through its singular values,
+ * f = sum_i (s_i^2 - 1)^2, so with A = U diag(s) V^T its 9x9 Hessian (in
+ * row-major vec(A)) has the eigenvectors of isotropic functions of a 3x3
+ * matrix: U e_i e_i^T V^T (eigenvalue 12 s_i^2 - 4, the separable second
+ * derivative), and for each pair i < j U (e_i e_j^T -/+ e_j e_i^T) V^T / sqrt2
+ * with eigenvalues (f_i +/- f_j) / (s_i +/- s_j), f_i = 4 s_i (s_i^2 - 1),
+ * which reduce to 4(s_i^2 -/+ s_i s_j + s_j^2 - 1).  Clamping the nine
+ * eigenvalues at zero gives the same projection as a numerical eigensolve
+ * of the assembled 9x9 matrix, from a 3x3 eigensolve of A^T A.  Returns
+ * the packed upper triangle (sidx) of the projected Hessian of f. */
+__device__ __forceinline__ void sym3_eig(double* M, double* V) {
+  /* cyclic Jacobi on a symmetric 3x3 (row-major M, overwritten by its
+   * eigenvalues on the diagonal); V gets the eigenvectors as columns */
+#pragma unroll
+  for (int i = 0; i < 9; ++i) V[i] = (i % 4 == 0) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 20; ++sweep) {
+    const double off = M[1] * M[1] + M[2] * M[2] + M[5] * M[5];
+    const double dia = M[0] * M[0] + M[4] * M[4] + M[8] * M[8];
+    if (off == 0.0 || off <= 1e-32 * (dia + off)) break;
+#pragma unroll
+    for (int pq = 0; pq < 3; ++pq) {
+      const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+      const double apq = M[3 * p + q];
+      if (apq == 0.0) continue;
+      const double app = M[3 * p + p], aqq = M[3 * q + q];
+      const double aa = aqq - app, bb = 2.0 * apq;
+      double t = bb / (fabs(aa) + sqrt(aa * aa + bb * bb));
+      t = aa < 0.0 ? -t : t;
+      const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double mrp = M[3 * r + p], mrq = M[3 * r + q];
+        M[3 * r + p] = c * mrp - s * mrq;
+        M[3 * r + q] = s * mrp + c * mrq;
+      }
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double mpr = M[3 * p + r], mqr = M[3 * q + r];
+        M[3 * p + r] = c * mpr - s * mqr;
+        M[3 * q + r] = s * mpr + c * mqr;
+      }
+      M[3 * p + q] = M[3 * q + p] = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r) {
+        const double vrp = V[3 * r + p], vrq = V[3 * r + q];
+        V[3 * r + p] = c * vrp - s * vrq;
+        V[3 * r + q] = s * vrp + c * vrq;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ void orth_hessian_psd(const double* A, double* K) {
+  double AtA[9], V[9];
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      double t = 0.0;
+#pragma unroll
+      for (int n = 0; n < 3; ++n) t += A[3 * n + k] * A[3 * n + m];
+      AtA[3 * k + m] = t;
+    }
+  sym3_eig(AtA, V);
+  double sv[3], U[9];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    sv[i] = sqrt(fmax(AtA[4 * i], 0.0));
+    /* u_i = A v_i / s_i (A is near a rotation, s_i near 1) */
+    const double inv = sv[i] > 0.0 ? 1.0 / sv[i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      double t = 0.0;
+#pragma unroll
+      for (int n = 0; n < 3; ++n) t += A[3 * k + n] * V[3 * n + i];
+      U[3 * k + i] = t * inv;
+    }
+  }
+  double lam[9], vec[9][9];
+  const double r2 = 0.70710678118654752440;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    lam[i] = fmax(12.0 * sv[i] * sv[i] - 4.0, 0.0);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) vec[i][3 * k + l] = U[3 * k + i] * V[3 * l + i];
+  }
+#pragma unroll
+  for (int pr = 0; pr < 3; ++pr) {
+    const int i = pr == 2 ? 1 : 0, j = pr == 0 ? 1 : 2;
+    const double a = sv[i] * sv[i] + sv[j] * sv[j] - 1.0, b = sv[i] * sv[j];
+    lam[3 + pr] = fmax(4.0 * (a - b), 0.0); /* antisymmetric (twist) */
+    lam[6 + pr] = fmax(4.0 * (a + b), 0.0); /* symmetric (flip) */
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int l = 0; l < 3; ++l) {
+        const double x = U[3 * k + i] * V[3 * l + j], y = U[3 * k + j] * V[3 * l + i];
+        vec[3 + pr][3 * k + l] = r2 * (x - y);
+        vec[6 + pr][3 * k + l] = r2 * (x + y);
+      }
+  }
+#pragma unroll
+  for (int a = 0; a < 9; ++a)
+#pragma unroll
+    for (int e = a; e < 9; ++e) {
+      double h = 0.0;
+#pragma unroll
+      for (int m = 0; m < 9; ++m) h += lam[m] * vec[m][a] * vec[m][e];
+      K[sidx(a, e)] = h;
+    }
+}
+
+/* ------------------------------------------------------------------ */
 /* additive CCD on one PT/EE pair along x + t dx                        */
 /* ------------------------------------------------------------------ */
+/* bound (may be null): bits of a TOI another pair of the same problem has
+ * already reached; once t passes it this pair cannot lower the minimum,
+ * so the advance stops there and returns t (a lower bound of its TOI) */
 __device__ inline double accd(int kind, const double* x, const double* dx,
-                              double tmax) {
+                              double tmax,
+                              const unsigned long long* bound = nullptr) {
   double m[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
@@ -580,6 +701,10 @@ __device__ inline double accd(int kind, const double* x, const double* dx,
     if (t > 0.0 && d < gap) return t;
     t = tn;
     if (t > tmax) return tmax;
+    if (bound && (it & 3) == 3 &&
+        t >= __longlong_as_double((long long)__hip_atomic_load(
+                 bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
+      return t;
     tl = 0.9 * d / lp;
   }
   return t;
@@ -628,6 +753,7 @@ void launch_ctrl(const Scene& S, int which, hipStream_t st);
 void launch_update_multi(const Scene& S, hipStream_t st);
 void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st);
 void launch_reset_pcg(const Scene& S, hipStream_t st);
+void launch_reset_toi(const Scene& S, hipStream_t st);
 /* consensus over the replicas of shared bodies in a batch scene */
 struct Cons {
   int n_rep, n_groups;

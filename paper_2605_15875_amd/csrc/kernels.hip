@@ -143,36 +143,24 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
   const double wb = S.wbody[b];
   const double c = wb * S.dt * S.dt * S.kappa_A * S.vol[b];
   const double* A = q + 3;
-  double Sm[9], AtA[9];
+  double Sm[9];
 #pragma unroll
   for (int k = 0; k < 3; ++k)
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      double s = 0.0, t = 0.0;
+      double s = 0.0;
 #pragma unroll
-      for (int n = 0; n < 3; ++n) {
-        s += A[3 * k + n] * A[3 * m + n];
-        t += A[3 * n + k] * A[3 * n + m];
-      }
+      for (int n = 0; n < 3; ++n) s += A[3 * k + n] * A[3 * m + n];
       Sm[3 * k + m] = s - (k == m ? 1.0 : 0.0);
-      AtA[3 * k + m] = t;
     }
-  /* orthogonality Hessian 4[d_kp (A^T A)_ql + A_kq A_pl + S_kp d_lq] */
+  /* projected orthogonality Hessian, in closed form from the singular
+   * values of A (equal to clamping the eigenvalues of the 9x9 Hessian
+   * 4[d_kp (A^T A)_ql + A_kq A_pl + S_kp d_lq]) */
   double K[45];
-#pragma unroll
-  for (int a = 0; a < 9; ++a)
-#pragma unroll
-    for (int e = a; e < 9; ++e) {
-      const int k = a / 3, l = a % 3, p = e / 3, qq = e % 3;
-      double h = A[3 * k + qq] * A[3 * p + l];
-      if (k == p) h += AtA[3 * qq + l];
-      if (l == qq) h += Sm[3 * k + p];
-      K[sidx(a, e)] = 4.0 * h;
-    }
+  orth_hessian_psd(A, K);
   HT Kt[45];
 #pragma unroll
   for (int i = 0; i < 45; ++i) Kt[i] = (HT)K[i];
-  psd9_reg<HT>(Kt);
   /* gradient */
   double gl[12];
 #pragma unroll
@@ -769,11 +757,14 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
   __shared__ int meta[3 * 64];
   const int lane = threadIdx.x;
   const int nact = min(S.cnt->n_act, S.cap_act);
-  for (int base = blockIdx.x * PAIRS_PER_WG; base < nact;
-       base += gridDim.x * PAIRS_PER_WG) {
+  /* pairs per workgroup: as few as the grid allows (each pair's projection
+   * is one lane's serial work, so a few pairs spread over many workgroups
+   * finish soonest), at most PAIRS_PER_WG */
+  const int ppw = max(1, min(PAIRS_PER_WG, (nact + (int)gridDim.x - 1) / (int)gridDim.x));
+  for (int base = blockIdx.x * ppw; base < nact; base += gridDim.x * ppw) {
     const int t = base + lane;
     int ba = -1, bb = -1, slot = -1;
-    if (lane < PAIRS_PER_WG && t < nact) {
+    if (lane < ppw && t < nact) {
       const int4 a = S.act[t];
       const int kind = a.x;
       slot = a.w;
@@ -848,7 +839,7 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
     meta[64 + lane] = bb;
     meta[128 + lane] = slot;
     __syncthreads();
-    const int npairs = min(PAIRS_PER_WG, nact - base);
+    const int npairs = min(ppw, nact - base);
     for (int j = 0; j < npairs; ++j) {
       const int A = meta[j], Bq = meta[64 + j], sl = meta[128 + j];
       if (A < 0 && Bq < 0) continue;
@@ -1488,8 +1479,8 @@ __global__ void k_ccd(Scene S) {
         xform(S.q + 12 * b, b0, b1, b2, x + 3 * k);
         xform(S.dq + 12 * b, b0, b1, b2, dx + 3 * k);
       }
-      toi = accd(kind, x, dx, 1.0);
       prob = S.bprob[S.vbody[vid[0]]];
+      toi = accd(kind, x, dx, 1.0, &S.ps[prob].min_toi);
     } else {
       int v = S.cand_pg[t - npt - nee], b = S.vbody[v];
       double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
@@ -1983,6 +1974,12 @@ __global__ void k_cons_merge(Scene S, Cons C) {
 }
 /* step toward the merged state: dq = z - q on replicas, 0 elsewhere; every
  * problem's CCD minimum starts at 1 */
+/* every problem's CCD minimum starts unset (+inf) */
+__global__ void k_reset_toi(Scene S) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < S.NP)
+    S.ps[t].min_toi = (unsigned long long)__double_as_longlong(INFINITY);
+}
 __global__ void k_cons_dq_zero(Scene S) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t < 12 * S.B) S.dq[t] = 0.0;
@@ -2177,6 +2174,9 @@ void launch_cons_merge_dq(const Scene& S, const Cons& C, hipStream_t st) {
                      0, st, S);
   hipLaunchKernelGGL(k_cons_dq, dim3(cdiv(12L * C.n_rep, 256)), dim3(256), 0, st,
                      S, C);
+}
+void launch_reset_toi(const Scene& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_toi, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);
 }
 void launch_reset_pcg(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_pcg, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);

@@ -75,6 +75,8 @@ struct abd_ctx {
   unsigned sh_version = 0;
   Scene S;
   Counters* h_cnt = nullptr; /* pinned */
+  Counters* h_ring = nullptr; /* pinned [2][2]: counters of passes in flight */
+  hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
   std::vector<void*> allocs;
   int pcg_grid = 0;
@@ -201,17 +203,26 @@ struct StageTimer {
   }
 };
 void resolve_timing(abd_ctx* ctx) {
+  /* events of passes still in flight stay pending */
+  std::vector<Pending> keep;
   for (auto& p : ctx->pending) {
+    if (hipEventQuery(p.b) != hipSuccess) {
+      (void)hipGetLastError();
+      keep.push_back(p);
+      continue;
+    }
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
       ctx->t_ms[p.stage] += ms;
       ctx->t_n[p.stage] += 1;
       ctx->t_bytes[p.stage] += p.bytes;
+    } else {
+      (void)hipGetLastError();
     }
     ctx->ev_pool.push_back(p.a);
     ctx->ev_pool.push_back(p.b);
   }
-  ctx->pending.clear();
+  ctx->pending.swap(keep);
 }
 
 /* ---------------- mass properties (divergence theorem) ---------------- */
@@ -495,6 +506,7 @@ void account_pcg_bytes(abd_ctx* ctx) {
  * energy difference at alpha_scale * min(1, TOI) */
 void launch_swept(abd_ctx* ctx, bool ccd, bool energy_at_toi) {
   const Scene Ssw = swept_scene(ctx);
+  if (ccd) launch_reset_toi(Ssw, ctx->st);
   launch_swept_s(ctx, Ssw, ccd);
   if (energy_at_toi) {
     StageTimer t(ctx, 5);
@@ -682,23 +694,60 @@ int run_pass(abd_ctx* ctx) {
   return ABD_OK;
 }
 
-/* Device loop: passes until every problem is done; one host read per pass
- * (both counter blocks: overflow and the number of active problems). */
+/* Device loop: passes until every problem is done.  The host keeps one
+ * pass queued ahead of the one whose counters it checks (both counter
+ * blocks are copied into a pinned ring slot at the end of every pass), so
+ * the check and the next launch overlap the device's work.  A pass queued
+ * after the last useful one finds every problem done and does nothing; a
+ * pass queued after an overflowing one repeats it, since the controller
+ * keeps the state of a pass whose lists overflowed. */
 int device_solve(abd_ctx* ctx) {
   launch_ctrl(ctx->S, 0, ctx->st);
   const int max_pass =
       ctx->P.max_newton * (2 + (ctx->P.max_ls + LS_TRIALS) / LS_TRIALS) + 8;
-  for (int pass = 0; pass < max_pass; ++pass) {
+  int queued = 0;
+  auto enqueue = [&]() -> int {
     int rc = run_pass(ctx);
     if (rc) return rc;
-    if ((rc = read_counters(ctx, 0, 2))) return rc;
-    bool ch0 = false, ch1 = false;
-    if ((rc = grow(ctx, ctx->h_cnt[0], &ch0))) return rc;
-    if ((rc = grow(ctx, ctx->h_cnt[1], &ch1))) return rc;
-    if (!ch0) account_pcg_bytes(ctx);
-    if (ch0 || ch1) continue;
-    if (ctx->h_cnt[1].active == 0) return ABD_OK;
+    Counters* slot = ctx->h_ring + 2 * (queued & 1);
+    HIPCHK(hipMemcpyAsync(slot, ctx->S.cnt, 2 * sizeof(Counters),
+                          hipMemcpyDeviceToHost, ctx->st));
+    HIPCHK(hipEventRecord(ctx->ring_ev[queued & 1], ctx->st));
+    queued += 1;
+    return ABD_OK;
+  };
+  for (int k = 0; k < max_pass;) {
+    int rc;
+    while (queued < k + 2)
+      if ((rc = enqueue())) return rc;
+    HIPCHK(hipEventSynchronize(ctx->ring_ev[k & 1]));
+    const Counters* c = ctx->h_ring + 2 * (k & 1);
+    ctx->h_cnt[0] = c[0];
+    ctx->h_cnt[1] = c[1];
+    resolve_timing(ctx);
+    if (c[0].err || c[1].err) {
+      HIPCHK(hipStreamSynchronize(ctx->st));
+      return fail(ctx, ABD_E_DEVICE, "device barrier timed out");
+    }
+    if (over_cap(ctx->S, ctx->h_cnt[0]) || over_cap(ctx->S, ctx->h_cnt[1])) {
+      /* drain, grow, and start over from the state the overflowing pass
+       * left unchanged */
+      HIPCHK(hipStreamSynchronize(ctx->st));
+      bool ch0 = false, ch1 = false;
+      if ((rc = grow(ctx, ctx->h_cnt[0], &ch0))) return rc;
+      if ((rc = grow(ctx, ctx->h_cnt[1], &ch1))) return rc;
+      k = queued;
+      continue;
+    }
+    account_pcg_bytes(ctx);
+    if (ctx->h_cnt[1].active == 0) {
+      HIPCHK(hipStreamSynchronize(ctx->st));
+      resolve_timing(ctx);
+      return ABD_OK;
+    }
+    k += 1;
   }
+  HIPCHK(hipStreamSynchronize(ctx->st));
   return fail(ctx, ABD_E_NOCONV, "device loop did not finish");
 }
 
@@ -748,6 +797,9 @@ void abd_destroy(abd_ctx* ctx) {
   if (ctx->own_stream && ctx->st) (void)hipStreamDestroy(ctx->st);
   for (void* p : ctx->allocs) (void)hipFree(p);
   if (ctx->h_cnt) (void)hipHostFree(ctx->h_cnt);
+  if (ctx->h_ring) (void)hipHostFree(ctx->h_ring);
+  for (auto e : ctx->ring_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->h_buf) (void)hipHostFree(ctx->h_buf);
   for (auto& p : ctx->pending) {
     (void)hipEventDestroy(p.a);
@@ -1020,6 +1072,9 @@ int abd_finalize(abd_ctx* ctx) {
     HIPCHK(hipMemset(S.ps, 0, sizeof(ProbState) * S.NP));
   }
   if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_ring, 4 * sizeof(Counters)) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ring_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ring_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
