@@ -180,8 +180,13 @@ int abd_set_stream(abd_ctx* ctx, void* hip_stream);
 /* ---- launch tuning ---- */
 #define ABD_PCG_TWO_BARRIER 0 /* textbook PCG: two grid barriers per iteration */
 #define ABD_PCG_PIPELINED 1   /* single-reduction PCG: one grid barrier */
+#define ABD_PCG_LOCAL 2       /* textbook PCG, blocks wait only for the blocks
+                                 of their own problems; deterministic dot
+                                 products (one block per 16 bodies; scenes
+                                 too large to keep every block resident use
+                                 TWO_BARRIER) */
 typedef struct abd_tuning {
-  int32_t pcg_variant;     /* ABD_PCG_* (default TWO_BARRIER; the pipelined
+  int32_t pcg_variant;     /* ABD_PCG_* (default LOCAL; the pipelined
                               form carries u, s and t by recurrences, which
                               can stall short of a very tight tolerance such
                               as eta = 1e-12 on stiff contact systems) */

@@ -41,7 +41,7 @@ class Tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-PCG_TWO_BARRIER, PCG_PIPELINED = 0, 1
+PCG_TWO_BARRIER, PCG_PIPELINED, PCG_LOCAL = 0, 1, 2
 
 
 class AdmmParams(C.Structure):

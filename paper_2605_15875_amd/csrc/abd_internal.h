@@ -44,6 +44,14 @@ struct Counters {
  * one problem, a batch merges several */
 enum { PS_NEWTON = 0, PS_LINESEARCH = 1, PS_DONE = 2 };
 #define LS_TRIALS 8
+/* per-group record of the problem-local PCG: the group's partial sums of
+ * one phase for each of its (at most 16) problems, published with the
+ * phase number as a flag */
+struct alignas(64) PcgRec {
+  unsigned long long gen;
+  double val[16][3];
+};
+
 struct ProbState {
   double scale;       /* l: bounding-box diagonal of the dynamic vertices */
   double alpha_base;  /* first trial step of the current line-search pass */
@@ -98,6 +106,8 @@ struct Scene {
   /* PCG work */
   double *r, *zv, *p0, *p1, *Ap, *acc; /* acc: [4][4] ring of dots */
   double *pw; /* single-reduction PCG: [5][12B] w, m0, m1, t0, t1 */
+  PcgRec *pcg_rec;         /* [2][groups] problem-local PCG records */
+  int *prob_b0, *prob_b1;  /* [NP] first and last body of each problem */
   /* world positions of the current broad phase, [3][V] each: xw at q,
    * xw1 at q + dq (swept phase); written by k_positions with the canonical
    * transform, read by the primitive tests and the distance filter */

@@ -921,27 +921,37 @@ __global__ void k_bsr_count(Scene S) {
   }
 }
 __global__ void k_bsr_scan(Scene S) {
-  /* single block exclusive scan of row_cnt into row_ptr */
-  __shared__ int part[1024];
+  /* single block (1024 threads) exclusive scan of row_cnt into row_ptr:
+   * per-thread runs, then a wavefront scan and a scan of the 16 wavefront
+   * totals */
+  __shared__ int wsum[16];
   const int n = S.B;
   const int per = (n + blockDim.x - 1) / blockDim.x;
-  int lo = threadIdx.x * per, hi = min(n, lo + per);
+  const int lo = threadIdx.x * per, hi = min(n, lo + per);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int s = 0;
   for (int i = lo; i < hi; ++i) s += S.row_cnt[i];
-  part[threadIdx.x] = s;
+  int x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int acc = 0;
-    for (int i = 0; i < (int)blockDim.x; ++i) {
-      int v = part[i];
-      part[i] = acc;
-      acc += v;
+  if (wave == 0) {
+    int w = lane < 16 ? wsum[lane] : 0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
     }
-    S.row_ptr[n] = acc;
-    S.cnt->n_rows_used = acc;
+    if (lane < 16) wsum[lane] = w;
   }
   __syncthreads();
-  int acc = part[threadIdx.x];
+  int acc = x - s + (wave > 0 ? wsum[wave - 1] : 0);
+  if (threadIdx.x == blockDim.x - 1) {
+    S.row_ptr[n] = acc + s;
+    S.cnt->n_rows_used = acc + s;
+  }
   for (int i = lo; i < hi; ++i) {
     S.row_ptr[i] = acc;
     acc += S.row_cnt[i];
@@ -1010,7 +1020,9 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned nblocks,
     __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned target = gen * nblocks;
     long spins = 0;
-    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE,
+    /* poll without acquire (an acquire load invalidates the L2 on every
+     * poll), then one acquire fence */
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1L << 27)) {
@@ -1018,6 +1030,7 @@ __device__ __forceinline__ void grid_sync(unsigned* bar, unsigned nblocks,
         break;
       }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
 }
@@ -1058,6 +1071,42 @@ __device__ __forceinline__ double ld_acq(const double* p) {
       (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
+/* When every block of the cooperative PCG launch owns exactly one 16-body
+ * group, the group's rows of the system (diagonal blocks, block inverses
+ * and up to PCG_OFF_CACHE off-diagonal blocks) stay in LDS for all
+ * iterations: after each grid barrier only the vectors written by other
+ * blocks have to come from memory. */
+#define PCG_OFF_CACHE 24
+template <typename HT>
+struct PcgCache {
+  HT hd[12 * 192]; /* [c][thread]: row `thread` of its body's diagonal block */
+  HT pi[12 * 192]; /* the same rows of the block inverse */
+  HT off[PCG_OFF_CACHE][144];
+  int e0, n_off;
+};
+template <typename HT>
+__device__ __forceinline__ bool pcg_cache_load(PcgCache<HT>& C, const Scene& S,
+                                               const HT* Hd, const HT* Ho,
+                                               const HT* Pi, int ngroups) {
+  if ((int)gridDim.x < ngroups || (int)blockIdx.x >= ngroups) return false;
+  const int gr = blockIdx.x, lb = threadIdx.x / 12, row = threadIdx.x % 12;
+  const int b = gr * 16 + lb;
+  for (int c = 0; c < 12; ++c) {
+    C.hd[c * 192 + threadIdx.x] = b < S.B ? Hd[144 * b + 12 * row + c] : HT(0);
+    C.pi[c * 192 + threadIdx.x] = b < S.B ? Pi[144 * b + 12 * row + c] : HT(0);
+  }
+  const int e0 = S.row_ptr[gr * 16];
+  const int n = min(S.row_ptr[min(S.B, gr * 16 + 16)] - e0, PCG_OFF_CACHE);
+  for (int i = threadIdx.x; i < n * 144; i += blockDim.x)
+    C.off[i / 144][i % 144] = Ho[144 * (size_t)S.col_slot[e0 + i / 144] + i % 144];
+  if (threadIdx.x == 0) {
+    C.e0 = e0;
+    C.n_off = n;
+  }
+  __syncthreads();
+  return true;
+}
+
 /* Block-Jacobi preconditioned CG on H dq = -g with zero initial guess,
  * every problem running its own recurrence, all iterations in one
  * cooperative launch.  Each block owns 16 bodies (192 rows) per pass of a
@@ -1077,6 +1126,7 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
   __shared__ double gs[16][4];
   __shared__ unsigned char pdone[PCG_MAX_NP];
   __shared__ int any_active;
+  __shared__ PcgCache<HT> cache;
   const unsigned nblk = gridDim.x;
   unsigned gen = 0;
   const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
@@ -1090,6 +1140,7 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
   for (int p = threadIdx.x; p < NP; p += blockDim.x)
     pdone[p] = (S.iter_mode == 0 || ps[p].state == PS_NEWTON) ? 0 : 1;
   __syncthreads();
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
   /* init: x = 0, r = b = -g, z = P^-1 r, p_{-1} = 0 */
   for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
     const int b = gr * 16 + lb;
@@ -1107,7 +1158,9 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
     double z = 0.0;
     if (act) {
       HT zz = 0;
-      for (int c = 0; c < 12; ++c) zz += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+      for (int c = 0; c < 12; ++c)
+        zz += (cached ? cache.pi[c * 192 + threadIdx.x] : Pi[144 * b + 12 * row + c]) *
+              (HT)rloc[lb][c];
       z = (double)zz;
       S.zv[12 * b + row] = z;
     }
@@ -1142,10 +1195,13 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
         HT y = 0;
         const HT* H = Hd + 144 * b + 12 * row;
         for (int c = 0; c < 12; ++c)
-          y += H[c] * (HT)(S.zv[12 * b + c] + beta * pold[12 * b + c]);
+          y += (cached ? cache.hd[c * 192 + threadIdx.x] : H[c]) *
+               (HT)(S.zv[12 * b + c] + beta * pold[12 * b + c]);
         for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
           const int nb = S.col_body[e];
-          const HT* blk = Ho + 144 * (size_t)S.col_slot[e];
+          const HT* blk = (cached && e - cache.e0 < cache.n_off)
+                              ? cache.off[e - cache.e0]
+                              : Ho + 144 * (size_t)S.col_slot[e];
           if (S.col_trans[e]) {
             for (int c = 0; c < 12; ++c)
               y += blk[12 * c + row] *
@@ -1189,7 +1245,8 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
       if (act) {
         HT zz = 0;
         for (int c = 0; c < 12; ++c)
-          zz += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+          zz += (cached ? cache.pi[c * 192 + threadIdx.x] : Pi[144 * b + 12 * row + c]) *
+                (HT)rloc[lb][c];
         z = (double)zz;
         S.zv[12 * b + row] = z;
       }
@@ -1224,6 +1281,276 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
   }
 }
 
+/* Block-Jacobi PCG with problem-local synchronisation (one block per
+ * 16-body group, all blocks co-resident).  The textbook recurrences as
+ * above, but no grid-wide barrier and no global atomics: at the end of each
+ * phase a block writes its per-problem partial sums (summed in a fixed
+ * order) into its group's record and then publishes the phase number with
+ * a release store; before the next phase it waits (acquire) for the
+ * records of the groups that hold its problems, and every block of a
+ * problem sums the same records in the same order, so all of them take the
+ * same step sizes and stop together.  Problems progress independently,
+ * a block leaves when its problems have converged, and the dot products
+ * are deterministic. */
+template <typename HT>
+__device__ __forceinline__ void pcg_publish(PcgRec* rec, int ph, int nloc,
+                                            const double (*part)[3]) {
+  __syncthreads();
+  if ((int)threadIdx.x < 3 * nloc)
+    rec->val[threadIdx.x / 3][threadIdx.x % 3] = part[threadIdx.x / 3][threadIdx.x % 3];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    __hip_atomic_store(&rec->gen, (unsigned long long)(ph + 1), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void pcg_wait(const PcgRec* recs, int glo, int ghi,
+                                         int ph, int* err) {
+  bool polled = false;
+  for (int g = glo + (int)threadIdx.x; g <= ghi; g += blockDim.x) {
+    long spins = 0;
+    polled = true;
+    while (__hip_atomic_load(&recs[g].gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+           (unsigned long long)(ph + 1)) {
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1L << 27)) {
+        atomicOr(err, 1);
+        break;
+      }
+    }
+  }
+  /* one acquire per polling thread after its flags were seen */
+  if (polled) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+}
+
+template <typename HT>
+__global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_it) {
+  const HT* __restrict__ Hd = (const HT*)S.Hdiag;
+  const HT* __restrict__ Ho = (const HT*)S.Hoff;
+  const HT* __restrict__ Pi = (const HT*)S.Pinv;
+  __shared__ double rloc[16][12];
+  __shared__ double vrow[3][192];
+  __shared__ double vbody[3][16];
+  __shared__ double part[16][3];
+  __shared__ double tot[16][3];
+  __shared__ double rz_cur[16], rz_old[16], alpha[16], bbl[16];
+  __shared__ unsigned char ldone[16];
+  __shared__ int s_glo, s_ghi, s_more;
+  __shared__ int e_nb[PCG_OFF_CACHE], e_tr[PCG_OFF_CACHE];
+  __shared__ PcgCache<HT> cache;
+  const int ngroups = (S.B + 15) / 16;
+  const int gr = blockIdx.x;
+  if (gr >= ngroups) return;
+  const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
+  const int g0 = gr * 16, gend = min(S.B, g0 + 16);
+  const int b = g0 + lb;
+  const bool real = b < S.B;
+  const int plo = S.bprob[g0], phi = S.bprob[gend - 1];
+  const int nloc = phi - plo + 1;
+  const int p = real ? S.bprob[b] : phi;
+  const int j = p - plo;
+  ProbState* ps = S.ps;
+  PcgRec* const rec0 = S.pcg_rec;
+  PcgRec* const rec1 = S.pcg_rec + ngroups;
+  if ((int)threadIdx.x < nloc)
+    ldone[threadIdx.x] =
+        (S.iter_mode == 0 || ps[plo + threadIdx.x].state == PS_NEWTON) ? 0 : 1;
+  __syncthreads();
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  if (!cached) __syncthreads();
+  /* the group's block-row structure does not change during the solve */
+  const int e0 = S.row_ptr[g0];
+  for (int i = threadIdx.x; i < PCG_OFF_CACHE && e0 + i < S.row_ptr[gend]; i += blockDim.x) {
+    e_nb[i] = S.col_body[e0 + i];
+    e_tr[i] = S.col_trans[e0 + i];
+  }
+  const int e_lo = real ? S.row_ptr[b] : 0, e_hi = real ? S.row_ptr[b + 1] : 0;
+  __syncthreads();
+  auto hrow = [&](int c) -> HT {
+    return cached ? cache.hd[c * 192 + threadIdx.x] : Hd[144 * b + 12 * row + c];
+  };
+  auto prow = [&](int c) -> HT {
+    return cached ? cache.pi[c * 192 + threadIdx.x] : Pi[144 * b + 12 * row + c];
+  };
+  auto reduce = [&](int nv, const double* v) {
+    for (int k = 0; k < nv; ++k) vrow[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if (row == 0 && lb < 16) {
+      for (int k = 0; k < nv; ++k) {
+        double s = 0.0;
+        for (int c = 0; c < 12; ++c) s += vrow[k][12 * lb + c];
+        vbody[k][lb] = s;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nloc) {
+      const int q = plo + threadIdx.x;
+      const int lo = max(S.prob_b0[q], g0) - g0, hi = min(S.prob_b1[q], gend - 1) - g0;
+      for (int k = 0; k < nv; ++k) {
+        double s = 0.0;
+        for (int c = lo; c <= hi; ++c) s += vbody[k][c];
+        part[threadIdx.x][k] = s;
+      }
+    }
+  };
+  auto totals = [&](const PcgRec* recs, int nv) {
+    for (int q = 0; q < nloc; ++q) {
+      if (ldone[q]) continue;
+      const int pg = plo + q;
+      const int ga = S.prob_b0[pg] / 16, gb = S.prob_b1[pg] / 16;
+      if (threadIdx.x < 64) {
+        double sv[3] = {0.0, 0.0, 0.0};
+        for (int g = ga + (int)threadIdx.x; g <= gb; g += 64) {
+          const int slot = pg - S.bprob[16 * g];
+          for (int k = 0; k < nv; ++k) sv[k] += recs[g].val[slot][k];
+        }
+        for (int o = 32; o > 0; o >>= 1)
+          for (int k = 0; k < nv; ++k) sv[k] += __shfl_xor(sv[k], o, 64);
+        if (threadIdx.x == 0)
+          for (int k = 0; k < nv; ++k) tot[q][k] = sv[k];
+      }
+    }
+    __syncthreads();
+  };
+  auto range = [&]() {
+    if (threadIdx.x == 0) {
+      int lo = -1, hi = -2;
+      for (int q = 0; q < nloc; ++q)
+        if (!ldone[q]) {
+          if (lo < 0) lo = S.prob_b0[plo + q] / 16;
+          hi = S.prob_b1[plo + q] / 16;
+        }
+      s_glo = lo;
+      s_ghi = hi;
+      s_more = lo >= 0;
+    }
+    __syncthreads();
+  };
+  range();
+  if (!s_more) return;
+  int ph = 0;
+  /* own rows of x, r, z, p and A p stay in registers; only z and p, which
+   * the neighbouring rows read, go through memory */
+  double xr = 0.0, rr = 0.0, zr = 0.0, pr = 0.0, apr = 0.0;
+  const int o = 12 * b + row;
+  /* phase 0: x = 0, r = b = -g, z = P^-1 r, p_{-1} = 0 */
+  {
+    const bool act = real && !ldone[j];
+    rr = act ? -S.g[o] : 0.0;
+    rloc[lb][row] = rr;
+    __syncthreads();
+    if (act) {
+      HT zz = 0;
+      for (int c = 0; c < 12; ++c) zz += prow(c) * (HT)rloc[lb][c];
+      zr = (double)zz;
+      S.zv[o] = zr;
+      S.p1[o] = 0.0;
+    }
+    const double v[2] = {rr * zr, rr * rr};
+    reduce(2, v);
+    pcg_publish<HT>(rec0 + gr, ph, nloc, part);
+    pcg_wait(rec0, s_glo, s_ghi, ph, &S.cnt->err);
+    totals(rec0, 2);
+    if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
+      const int q = threadIdx.x, pg = plo + q;
+      rz_cur[q] = tot[q][0];
+      rz_old[q] = 1.0;
+      bbl[q] = tot[q][1];
+      const bool first = S.prob_b0[pg] >= g0; /* this group writes the stats */
+      if (first) ps[pg].bb = bbl[q];
+      if (!(bbl[q] > 0.0)) {
+        ldone[q] = 1;
+        if (first) ps[pg].pcg_iters = 0;
+      }
+    }
+    __syncthreads();
+  }
+  int it = 0;
+  for (it = 0; it < max_it; ++it) {
+    range();
+    if (!s_more || S.cnt->err) break;
+    const double* pold = (it & 1) ? S.p0 : S.p1;
+    double* pnew = (it & 1) ? S.p1 : S.p0;
+    /* phase A: p = z + beta pold and A p */
+    ++ph;
+    {
+      const bool act = real && !ldone[j];
+      const double beta = act && it > 0 ? rz_cur[j] / rz_old[j] : 0.0;
+      if (act) pr = zr + beta * pr;
+      rloc[lb][row] = pr;
+      __syncthreads();
+      double pap = 0.0;
+      if (act) {
+        HT y = 0;
+        for (int c = 0; c < 12; ++c) y += hrow(c) * (HT)rloc[lb][c];
+        for (int e = e_lo; e < e_hi; ++e) {
+          const int le = e - e0;
+          const bool in = le < PCG_OFF_CACHE;
+          const int nb = in ? e_nb[le] : S.col_body[e];
+          const int tr = in ? e_tr[le] : S.col_trans[e];
+          const HT* blk = (cached && le < cache.n_off) ? cache.off[le]
+                                                       : Ho + 144 * (size_t)S.col_slot[e];
+          const int st = tr ? 12 : 1, sc = tr ? 1 : 12;
+          for (int c = 0; c < 12; ++c)
+            y += blk[sc * row + st * c] *
+                 (HT)(S.zv[12 * nb + c] + beta * pold[12 * nb + c]);
+        }
+        pnew[o] = pr;
+        apr = (double)y;
+        pap = pr * apr;
+      }
+      const double v[1] = {pap};
+      reduce(1, v);
+      PcgRec* recs = (ph & 1) ? rec1 : rec0;
+      pcg_publish<HT>(recs + gr, ph, nloc, part);
+      pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err);
+      totals(recs, 1);
+      if ((int)threadIdx.x < nloc && !ldone[threadIdx.x])
+        alpha[threadIdx.x] = rz_cur[threadIdx.x] / tot[threadIdx.x][0];
+      __syncthreads();
+    }
+    /* phase B: x += alpha p, r -= alpha A p, z = P^-1 r */
+    ++ph;
+    {
+      const bool act = real && !ldone[j];
+      if (act) {
+        const double a = alpha[j];
+        xr += a * pr;
+        rr -= a * apr;
+      }
+      rloc[lb][row] = act ? rr : 0.0;
+      __syncthreads();
+      if (act) {
+        HT zz = 0;
+        for (int c = 0; c < 12; ++c) zz += prow(c) * (HT)rloc[lb][c];
+        zr = (double)zz;
+        S.zv[o] = zr;
+      }
+      const double v[2] = {act ? rr * zr : 0.0, act ? rr * rr : 0.0};
+      reduce(2, v);
+      PcgRec* recs = (ph & 1) ? rec1 : rec0;
+      pcg_publish<HT>(recs + gr, ph, nloc, part);
+      pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err);
+      totals(recs, 2);
+      if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
+        const int q = threadIdx.x, pg = plo + q;
+        rz_old[q] = rz_cur[q];
+        rz_cur[q] = tot[q][0];
+        if (tot[q][1] <= eta * eta * bbl[q]) {
+          ldone[q] = 1;
+          if (S.prob_b0[pg] >= g0) ps[pg].pcg_iters = it + 1;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if ((int)threadIdx.x < nloc && !ldone[threadIdx.x] && S.prob_b0[plo + threadIdx.x] >= g0)
+    ps[plo + threadIdx.x].pcg_iters = it;
+  /* the direction of every problem this block took part in */
+  if (real && !(S.iter_mode != 0 && ps[p].state != PS_NEWTON)) S.dq[o] = xr;
+  if (threadIdx.x == 0) atomicMax(&S.cnt->pcg_iters, it);
+}
+
 /* Single-reduction (pipelined) block-Jacobi PCG, the same solve with one
  * grid barrier per iteration instead of two.  It follows the
  * Chronopoulos-Gear form of CG, where s = A p and the preconditioned
@@ -1253,6 +1580,7 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
   __shared__ double gs[16][4];
   __shared__ unsigned char pdone[PCG_MAX_NP];
   __shared__ int any_active;
+  __shared__ PcgCache<HT> cache;
   const unsigned nblk = gridDim.x;
   unsigned gen = 0;
   const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
@@ -1271,6 +1599,17 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
   for (int p = threadIdx.x; p < NP; p += blockDim.x)
     pdone[p] = (S.iter_mode == 0 || ps[p].state == PS_NEWTON) ? 0 : 1;
   __syncthreads();
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  auto hrow = [&](int b, int c) -> HT {
+    return cached ? cache.hd[c * 192 + threadIdx.x] : Hd[144 * b + 12 * row + c];
+  };
+  auto prow = [&](int b, int c) -> HT {
+    return cached ? cache.pi[c * 192 + threadIdx.x] : Pi[144 * b + 12 * row + c];
+  };
+  auto offblk = [&](int e) -> const HT* {
+    return (cached && e - cache.e0 < cache.n_off) ? cache.off[e - cache.e0]
+                                                  : Ho + 144 * (size_t)S.col_slot[e];
+  };
   /* phase 0a: x = 0, r = b = -g, u_0 = P^-1 r, p = s = t_{-1} = 0 */
   for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
     const int b = gr * 16 + lb;
@@ -1282,7 +1621,7 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
     __syncthreads();
     if (act) {
       HT zz = 0;
-      for (int c = 0; c < 12; ++c) zz += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+      for (int c = 0; c < 12; ++c) zz += prow(b, c) * (HT)rloc[lb][c];
       S.dq[o] = 0.0;
       S.r[o] = rv;
       P[o] = 0.0;
@@ -1302,11 +1641,10 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
     double y = 0.0, uo = 0.0, rv = 0.0;
     if (act) {
       HT acc = 0;
-      const HT* H = Hd + 144 * b + 12 * row;
-      for (int c = 0; c < 12; ++c) acc += H[c] * (HT)Uv[0][12 * b + c];
+      for (int c = 0; c < 12; ++c) acc += hrow(b, c) * (HT)Uv[0][12 * b + c];
       for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
         const int nb = S.col_body[e];
-        const HT* blk = Ho + 144 * (size_t)S.col_slot[e];
+        const HT* blk = offblk(e);
         const int st = S.col_trans[e] ? 12 : 1, sc = S.col_trans[e] ? 1 : 12;
         for (int c = 0; c < 12; ++c)
           acc += blk[sc * row + st * c] * (HT)Uv[0][12 * nb + c];
@@ -1320,7 +1658,7 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
     __syncthreads();
     if (act) {
       HT mm = 0;
-      for (int c = 0; c < 12; ++c) mm += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+      for (int c = 0; c < 12; ++c) mm += prow(b, c) * (HT)rloc[lb][c];
       Mv[0][o] = (double)mm;
     }
     const double v[4] = {rv * uo, y * uo, rv * rv, rv * rv};
@@ -1389,14 +1727,13 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
         Uv[nxt][o] = u1;
         /* w_{it+1} = A u_{it+1}, u of every body formed on the fly */
         HT accv = 0;
-        const HT* H = Hd + 144 * b + 12 * row;
         for (int c = 0; c < 12; ++c) {
           const int oc = 12 * b + c;
-          accv += H[c] * (HT)cg_next_u(Uv[cur][oc], Mv[cur][oc], Tv[nxt][oc], a, be);
+          accv += hrow(b, c) * (HT)cg_next_u(Uv[cur][oc], Mv[cur][oc], Tv[nxt][oc], a, be);
         }
         for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
           const int nb = S.col_body[e];
-          const HT* blk = Ho + 144 * (size_t)S.col_slot[e];
+          const HT* blk = offblk(e);
           const int st = S.col_trans[e] ? 12 : 1, sc = S.col_trans[e] ? 1 : 12;
           for (int c = 0; c < 12; ++c) {
             const int oc = 12 * nb + c;
@@ -1411,7 +1748,7 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
       __syncthreads();
       if (act) {
         HT mm = 0;
-        for (int c = 0; c < 12; ++c) mm += Pi[144 * b + 12 * row + c] * (HT)rloc[lb][c];
+        for (int c = 0; c < 12; ++c) mm += prow(b, c) * (HT)rloc[lb][c];
         Mv[nxt][o] = (double)mm;
       }
       const double v[3] = {rv * u1, y * u1, rv * rv};
@@ -1847,6 +2184,8 @@ __global__ void k_update_multi(Scene S) {
 __global__ void k_reset_pcg(Scene S) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) S.cnt->bar = 0;
+  for (int i = t; i < 2 * ((S.B + 15) / 16); i += gridDim.x * blockDim.x)
+    S.pcg_rec[i].gen = 0ull;
   if (t < S.NP) {
     ProbState& P = S.ps[t];
     P.bb = 0.0;
@@ -1871,6 +2210,8 @@ __global__ void k_reset_iter(Scene S, Counters fresh) {
     for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
   }
   for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
+  for (int i = t; i < 2 * ((S.B + 15) / 16); i += gridDim.x * blockDim.x)
+    S.pcg_rec[i].gen = 0ull;
 }
 
 /* ================================================================== */
@@ -2213,6 +2554,10 @@ int pcg_max_grid() {
   per = std::min(per, per32);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg1<float>, 192, 0);
   per = std::min(per, per32);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg_local<double>, 192, 0);
+  per = std::min(per, per32);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg_local<float>, 192, 0);
+  per = std::min(per, per32);
   return ncu * (per > 0 ? per : 1);
 }
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
@@ -2221,6 +2566,8 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
   const void* fn;
   if (variant == 1)
     fn = S.mixed ? (const void*)k_pcg1<float> : (const void*)k_pcg1<double>;
+  else if (variant == 2)
+    fn = S.mixed ? (const void*)k_pcg_local<float> : (const void*)k_pcg_local<double>;
   else
     fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st);

@@ -86,7 +86,7 @@ struct abd_ctx {
   hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
-  abd_tuning tune = {ABD_PCG_TWO_BARRIER, 0, 1024, 2048, 1};
+  abd_tuning tune = {ABD_PCG_LOCAL, 0, 1024, 2048, 1};
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -459,9 +459,18 @@ void launch_static(abd_ctx* ctx, const Scene& S) {
   }
 }
 
+/* PCG form in use: the problem-local form needs one resident block per
+ * 16-body group */
+int pcg_variant(const abd_ctx* ctx, const Scene& S) {
+  const int ng = std::max(1, (S.B + 15) / 16);
+  if (ctx->tune.pcg_variant == ABD_PCG_LOCAL && ng > ctx->pcg_grid)
+    return ABD_PCG_TWO_BARRIER;
+  return ctx->tune.pcg_variant;
+}
 /* blocks of the cooperative PCG launch */
 int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
   const int ng = std::max(1, (S.B + 15) / 16);
+  if (pcg_variant(ctx, S) == ABD_PCG_LOCAL) return ng;
   const int want = ctx->tune.pcg_blocks > 0 ? std::min(ctx->tune.pcg_blocks, ng) : ng;
   return std::max(1, std::min(ctx->pcg_grid, want));
 }
@@ -480,7 +489,7 @@ int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
   }
   StageTimer t(ctx, 3);
   if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S),
-                 ctx->tune.pcg_variant, ctx->st))
+                 pcg_variant(ctx, S), ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
   launch_dq_norm(S, ctx->st);
   return ABD_OK;
@@ -496,7 +505,7 @@ void account_pcg_bytes(abd_ctx* ctx) {
    * pipelined form: u, m, t, p, s, w, r, x read and u, m, t, p, s, w, r, x
    * written = 16 passes) */
   const double blk = 144.0 * (double)hess_elem(ctx);
-  const double vec = ctx->tune.pcg_variant == ABD_PCG_PIPELINED ? 16.0 : 7.0;
+  const double vec = pcg_variant(ctx, S) == ABD_PCG_PIPELINED ? 16.0 : 7.0;
   const double per = (double)(S.B + ctx->h_cnt[0].n_rows_used / 2) * blk +
                      (double)S.B * blk + vec * 12.0 * S.B * 8.0;
   ctx->t_bytes[3] += per * ctx->h_cnt[0].pcg_iters;
@@ -612,7 +621,7 @@ int pass_pcg(abd_ctx* ctx) {
   S1.iter_mode = 1;
   StageTimer t(ctx, 3);
   if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S1),
-                 ctx->tune.pcg_variant, ctx->st))
+                 pcg_variant(ctx, S1), ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
   return ABD_OK;
 }
@@ -1051,6 +1060,18 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.Ap, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.pw, 5 * 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &S.pcg_rec, 2L * ((B + 15) / 16)))) return rc;
+  HIPCHK(hipMemset(S.pcg_rec, 0, sizeof(PcgRec) * 2 * ((B + 15) / 16)));
+  {
+    std::vector<int> b0(ctx->np, B), b1(ctx->np, -1);
+    for (int i = 0; i < B; ++i) {
+      const int p = (int)ctx->prob_of_body.size() == B ? ctx->prob_of_body[i] : 0;
+      b0[p] = std::min(b0[p], i);
+      b1[p] = std::max(b1[p], i);
+    }
+    if ((rc = upload(ctx, &S.prob_b0, b0))) return rc;
+    if ((rc = upload(ctx, &S.prob_b1, b1))) return rc;
+  }
   if ((rc = dalloc(ctx, &S.xw, 3L * S.V))) return rc;
   if ((rc = dalloc(ctx, &S.xw1, 3L * S.V))) return rc;
   S.grid_blocks = ctx->tune.grid_blocks;
@@ -1933,7 +1954,7 @@ int abd_get_tuning(abd_ctx* ctx, abd_tuning* out) {
 int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
   int rc = check_ctx(ctx, true);
   if (rc) return rc;
-  if (!t || (t->pcg_variant != ABD_PCG_TWO_BARRIER && t->pcg_variant != ABD_PCG_PIPELINED) ||
+  if (!t || t->pcg_variant < ABD_PCG_TWO_BARRIER || t->pcg_variant > ABD_PCG_LOCAL ||
       t->pcg_blocks < 0 || t->grid_blocks < 1 || t->assemble_blocks < 1 ||
       t->grid_blocks > (1 << 20) || t->assemble_blocks > (1 << 20))
     return fail(ctx, ABD_E_INVALID_ARG, "tuning values");
@@ -1996,9 +2017,11 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   std::vector<std::pair<int, int>> tried = {{orig.pcg_variant, pcg_blocks(ctx, S)}};
   /* the pipelined form only where its attainable accuracy is not the
    * binding limit */
-  const int nvar = ctx->P.pcg_eta >= 1e-6 ? 2 : 1;
-  for (int v = 0; v < nvar; ++v)
+  std::vector<int> vars = {ABD_PCG_LOCAL, ABD_PCG_TWO_BARRIER};
+  if (ctx->P.pcg_eta >= 1e-6) vars.push_back(ABD_PCG_PIPELINED);
+  for (int v : vars)
     for (int div : {1, 2, 4, 8}) {
+      if (v == ABD_PCG_LOCAL && div > 1) continue; /* one block per group */
       abd_tuning t = best;
       t.pcg_variant = v;
       t.pcg_blocks = std::max(1, (ng + div - 1) / div);

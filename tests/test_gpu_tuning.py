@@ -15,6 +15,7 @@ pytestmark = pytest.mark.gpu
 PARITY = dict(newton_theta=1e-9, pcg_eta=1e-12)
 
 SETTINGS = [
+    dict(pcg_variant=abd.PCG_LOCAL),
     dict(pcg_variant=abd.PCG_TWO_BARRIER),
     dict(pcg_variant=abd.PCG_PIPELINED),
     dict(pcg_variant=abd.PCG_PIPELINED, pcg_blocks=1),
@@ -90,7 +91,8 @@ def test_autotune_keeps_state_and_solves():
     gpu = abd.Solver(sc)
     gpu.set_state(q, qd)
     t = gpu.autotune()
-    assert t["pcg_variant"] in (abd.PCG_TWO_BARRIER, abd.PCG_PIPELINED)
+    assert t["pcg_variant"] in (abd.PCG_TWO_BARRIER, abd.PCG_PIPELINED,
+                                abd.PCG_LOCAL)
     assert gpu.tuning() == t
     q2, qd2 = gpu.get_state()
     np.testing.assert_array_equal(q2, q)
@@ -107,7 +109,7 @@ def test_autotune_keeps_state_and_solves():
 
 def test_tuning_rejects_bad_values():
     gpu = abd.Solver(scenes.cubes_scene(0, 1, 1, 1))
-    for bad in (dict(pcg_variant=5), dict(pcg_blocks=-1), dict(grid_blocks=0),
+    for bad in (dict(pcg_variant=5), dict(pcg_variant=-1), dict(pcg_blocks=-1), dict(grid_blocks=0),
                 dict(assemble_blocks=0)):
         with pytest.raises(abd.AbdError):
             gpu.set_tuning(**bad)
