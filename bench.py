@@ -25,6 +25,20 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 
+# HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this
+# benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each divided
+# by what the same counter reads per byte for a plain device copy of known
+# size (python bench.py --copy-probe).  Valid only for the kernel source it
+# was measured on (sha256 of the kernel file); otherwise traffic is null.
+PMC_TRAFFIC = {
+    "kernel": "k_pcg_local<double>",
+    "fetch_kib": 3343.1,       # FETCH_SIZE per dispatch, 90 dispatches
+    "write_kib": 3660.1,       # WRITE_SIZE per dispatch, 90 dispatches
+    "fetch_per_byte": 131086.6 / 262144.0,  # copy of 256 MiB reads 0.5
+    "write_per_byte": 262144.0 / 262144.0,  # copy of 256 MiB writes 1.0
+    "sha256": "e8abffe4bcb46ac3479ec5ac96c2e879a834a01941c798d97c1f2c03edf960fc",
+}
+
 WORKLOAD = ("1000 icospheres (642 verts, 1280 tris each, r 0.05-0.15) "
             "falling into an open box container, dt 0.01, dhat 1e-3, "
             "kappa 1e5, kappa_A 1e8, FP64, Newton tol 1e-6")
@@ -47,6 +61,33 @@ def cpu_baseline(seed, n_steps):
                 sample=f"first {n_steps} time steps of the workload "
                        f"({iters} Newton iterations, {dt:.1f} s, "
                        f"single thread)")
+
+
+def copy_probe():
+    """A plain device copy of known size, to calibrate the HBM counters."""
+    import torch
+    n = 256 << 20  # bytes per buffer
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
+
+
+def kernel_sha():
+    import hashlib
+    path = os.path.join(ROOT, "paper_2605_15875_amd", "csrc", "kernels.hip")
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def pmc_traffic(kernel):
+    t = PMC_TRAFFIC
+    if not t or t["kernel"] != kernel or t["sha256"] != kernel_sha():
+        return None
+    return (t["fetch_kib"] * 1024.0 / t["fetch_per_byte"] +
+            t["write_kib"] * 1024.0 / t["write_per_byte"])
 
 
 def bench_batch(abd, scenes, torch, n_scenes, steps, warmup):
@@ -96,7 +137,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=6)
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--breakdown-steps", type=int, default=3)
@@ -107,7 +148,13 @@ def main():
                          "1: single-reduction form (default: library's)")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner after warmup")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a device copy of known size (counter "
+                         "calibration) and exit")
     a = ap.parse_args()
+    if a.copy_probe:
+        copy_probe()
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the local solve of one worker runs "
@@ -167,14 +214,22 @@ def main():
     solver.set_timing(abd.TIMING_OFF)
     if not any(v["launches"] for v in tm.values()):
         tm = tm_timed
-    dom = max(tm, key=lambda k: tm[k]["ms"])
+    # the dominant single kernel is the PCG solve (the broad-phase stage
+    # sums several smaller kernels); its launches are timed with events in
+    # the timed region itself
+    dom = "pcg"
     roof = None
-    d = tm_timed[dom] if dom == "pcg" else tm[dom]
+    d = tm_timed[dom]
+    pcg_kernel = {abd.PCG_LOCAL: "k_pcg_local", abd.PCG_TWO_BARRIER: "k_pcg",
+                  abd.PCG_PIPELINED: "k_pcg1"}[tuning["pcg_variant"]] + "<double>"
     if d["bytes"] > 0 and d["launches"]:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        roof = dict(kernel="k_pcg" if dom == "pcg" else dom, bound="hbm",
-                    achieved=achieved, peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=achieved / HBM_PEAK_GBS, traffic=None,
+        kname = pcg_kernel if dom == "pcg" else dom
+        traffic = pmc_traffic(kname)
+        roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS,
+                    unit="GB/s", frac=achieved / HBM_PEAK_GBS,
+                    traffic=traffic, kernel=kname,
+                    bytes_per_launch=d["bytes"] / d["launches"],
                     launches=d["launches"],
                     avg_launch_ms=d["ms"] / d["launches"],
                     measured="timed region" if dom == "pcg"
@@ -191,14 +246,16 @@ def main():
         ms.set_timing(abd.TIMING_PCG)  # same event overhead as FP64
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        mnewton = 0
+        mnewton = fallbacks = 0
         for i in range(a.steps):
             st = ms.step()
             mnewton += st["newton_iters"]
+            fallbacks += st["fp64_fallback"]
         torch.cuda.synchronize()
         mel = time.perf_counter() - t1
         xm = ms.vertices()
         mixed = dict(newton_iters_per_s=mnewton / mel, newton_iters=mnewton,
+                     fp64_fallback_steps=fallbacks,
                      ms_per_step=mel * 1e3 / a.steps,
                      speedup_vs_fp64=elapsed / mel,
                      final_pos_diff_vs_fp64_over_l=float(

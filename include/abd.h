@@ -65,11 +65,14 @@ extern "C" {
 
 /* precision of the Newton linear algebra */
 #define ABD_FP64 0  /* everything FP64 */
-#define ABD_MIXED 1 /* Hessian blocks, their PSD projection, assembly and
-                       the PCG matvec in FP32 (FP32 accumulation); gradient,
+#define ABD_MIXED 1 /* Hessian blocks, assembly and the PCG matvec and
+                       preconditioner in FP32 (FP32 accumulation); gradient,
                        distances, CCD, energies, PCG residual and dots FP64:
                        the FP64 gradient of every Newton iteration refines
-                       the FP32-Hessian steps to the same solution */
+                       the FP32-Hessian steps to the same solution.  A solve
+                       that does not reach the Newton tolerance this way is
+                       repeated from its start with FP64 Hessians
+                       (abd_stats.fp64_fallback) */
 
 /* candidate kinds */
 #define ABD_PT 0 /* point-triangle: (vertex, triangle) */
@@ -111,6 +114,9 @@ typedef struct abd_stats {
    * static phase (at q) and of the swept phase (over q -> q + dq) */
   int64_t n_body_pairs, n_chunk_pairs, n_body_pairs_swept,
       n_chunk_pairs_swept;
+  /* mixed precision: 1 if the FP32-Hessian solve did not reach the Newton
+   * tolerance and the solve was repeated with FP64 Hessians */
+  int32_t fp64_fallback;
 } abd_stats;
 
 typedef struct abd_ctx abd_ctx;

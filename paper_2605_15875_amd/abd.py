@@ -72,7 +72,8 @@ class Stats(C.Structure):
                 ("t_solve_ms", C.c_double),
                 ("n_body_pairs", C.c_int64), ("n_chunk_pairs", C.c_int64),
                 ("n_body_pairs_swept", C.c_int64),
-                ("n_chunk_pairs_swept", C.c_int64)]
+                ("n_chunk_pairs_swept", C.c_int64),
+                ("fp64_fallback", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

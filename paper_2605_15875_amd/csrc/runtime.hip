@@ -76,6 +76,7 @@ struct abd_ctx {
   Scene S;
   Counters* h_cnt = nullptr; /* pinned */
   Counters* h_ring = nullptr; /* pinned [2][2]: counters of passes in flight */
+  double* q_start = nullptr;  /* iterate at solve entry (mixed fallback) */
   hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
   std::vector<void*> allocs;
@@ -146,6 +147,9 @@ int dalloc_bytes(abd_ctx* ctx, void** p, size_t bytes) {
 size_t hess_elem(const abd_ctx* ctx) {
   return ctx->S.mixed ? sizeof(float) : sizeof(double);
 }
+/* Hessian storage is sized for FP64 in both forms, so a mixed context can
+ * repeat a solve in FP64 in the same buffers */
+constexpr size_t HESS_ALLOC = sizeof(double);
 
 template <class T>
 void dfree(abd_ctx* ctx, T* p) {
@@ -380,7 +384,7 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
     dfree(ctx, S.slot_used);
     S.cap_bp = (int)std::min<long>(2L * c.n_bp + 1024, 1L << 30);
     if ((rc = dalloc(ctx, &S.bp, S.cap_bp))) return rc;
-    if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * hess_elem(ctx)))) return rc;
+    if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * HESS_ALLOC))) return rc;
     if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
     dfree(ctx, S.col_slot);
     dfree(ctx, S.col_body);
@@ -760,6 +764,34 @@ int device_solve(abd_ctx* ctx) {
   return fail(ctx, ABD_E_NOCONV, "device loop did not finish");
 }
 
+/* The local solve; a mixed-precision solve whose FP32 Hessian could not
+ * take every problem to the Newton tolerance (NOCONV, LINESEARCH) is
+ * repeated from its start iterate with FP64 Hessians in the same buffers.
+ * *fell_back reports the repeat. */
+int solve_with_fallback(abd_ctx* ctx, bool* fell_back) {
+  Scene& S = ctx->S;
+  *fell_back = false;
+  const size_t nb = sizeof(double) * 12 * S.B;
+  if (S.mixed)
+    HIPCHK(hipMemcpyAsync(ctx->q_start, S.q, nb, hipMemcpyDeviceToDevice, ctx->st));
+  int rc = device_solve(ctx);
+  if (!S.mixed || (rc && rc != ABD_E_NOCONV)) return rc;
+  std::vector<ProbState> P(S.NP);
+  HIPCHK(hipMemcpy(P.data(), S.ps, sizeof(ProbState) * S.NP, hipMemcpyDeviceToHost));
+  bool bad = rc == ABD_E_NOCONV;
+  for (const ProbState& x : P)
+    bad |= x.status == ABD_E_NOCONV || x.status == ABD_E_LINESEARCH;
+  if (!bad) return ABD_OK;
+  HIPCHK(hipMemcpyAsync(S.q, ctx->q_start, nb, hipMemcpyDeviceToDevice, ctx->st));
+  drop_graphs(ctx);
+  S.mixed = 0;
+  rc = device_solve(ctx);
+  drop_graphs(ctx);
+  S.mixed = 1;
+  *fell_back = true;
+  return rc;
+}
+
 int check_ctx(abd_ctx* ctx, bool need_final) {
   if (!ctx) return ABD_E_INVALID_ARG;
   if (need_final && !ctx->finalized)
@@ -1044,9 +1076,9 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.act, S.cap_act))) return rc;
   if ((rc = dalloc(ctx, &S.g, 12L * B))) return rc;
   S.mixed = ctx->P.precision == ABD_MIXED;
-  if ((rc = dalloc_bytes(ctx, &S.Hdiag, 144L * B * hess_elem(ctx)))) return rc;
-  if ((rc = dalloc_bytes(ctx, &S.Pinv, 144L * B * hess_elem(ctx)))) return rc;
-  if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * hess_elem(ctx)))) return rc;
+  if ((rc = dalloc_bytes(ctx, &S.Hdiag, 144L * B * HESS_ALLOC))) return rc;
+  if ((rc = dalloc_bytes(ctx, &S.Pinv, 144L * B * HESS_ALLOC))) return rc;
+  if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * HESS_ALLOC))) return rc;
   if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
   if ((rc = dalloc(ctx, &S.row_ptr, B + 1))) return rc;
   if ((rc = dalloc(ctx, &S.row_cnt, B + 1))) return rc;
@@ -1060,6 +1092,7 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.Ap, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.pw, 5 * 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &ctx->q_start, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.pcg_rec, 2L * ((B + 15) / 16)))) return rc;
   HIPCHK(hipMemset(S.pcg_rec, 0, sizeof(PcgRec) * 2 * ((B + 15) / 16)));
   {
@@ -1255,7 +1288,9 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
   abd_stats st;
   std::memset(&st, 0, sizeof(st));
   st.scene_scale = ctx->scale;
-  int status = device_solve(ctx);
+  bool fell_back = false;
+  int status = solve_with_fallback(ctx, &fell_back);
+  st.fp64_fallback = fell_back ? 1 : 0;
   ProbState P;
   std::memset(&P, 0, sizeof(P));
   if (hipMemcpy(&P, ctx->S.ps, sizeof(P), hipMemcpyDeviceToHost) != hipSuccess)
@@ -1655,7 +1690,8 @@ int abd_batch_run(abd_batch* bt, abd_stats* out) {
   }
   int rc0 = batch_gather(bt);
   if (rc0) return rc0;
-  int status = device_solve(M);
+  bool fell_back = false;
+  int status = solve_with_fallback(M, &fell_back);
   launch_scatter(M->S, bt->pc, n, bt->max_nb, M->st);
   HIPCHK(hipStreamSynchronize(M->st));
   std::vector<ProbState> P(n);
@@ -1676,6 +1712,7 @@ int abd_batch_run(abd_batch* bt, abd_stats* out) {
       st.scene_scale = bt->h_scales[i];
       st.min_dist = bits_to_double(M->h_cnt[0].min_dist);
       st.t_solve_ms = ms;
+      st.fp64_fallback = fell_back ? 1 : 0;
     }
     if (first == ABD_OK && P[i].status != ABD_OK) {
       first = P[i].status;

@@ -74,3 +74,22 @@ def test_mixed_spheres_converge_without_penetration():
         nc, md = ref.penetration(xg)
         assert nc == 0 and md > 0
     gpu.close()
+
+
+def test_mixed_fallback_to_fp64_is_reported():
+    """A mixed solve that cannot reach the tolerance (one Newton iteration
+    allowed) is repeated with FP64 Hessians, which reports the repeat and
+    the final status; a solvable step needs no repeat."""
+    sc = scenes.config(0, newton_theta=1e-6)
+    ok = abd.Solver(sc, precision=1)
+    st = ok.step()
+    assert st["status"] == 0 and st["fp64_fallback"] == 0
+    s1 = abd.Solver(sc, precision=1, max_newton=1)
+    s1.begin_step()
+    st = s1.local_solve(check=False)
+    assert st["fp64_fallback"] == 1
+    assert st["status"] == -4  # NOCONV in FP64 as well
+    # the context keeps working in mixed precision afterwards
+    s2 = abd.Solver(sc, precision=1)
+    for _ in range(3):
+        assert s2.step()["status"] == 0
