@@ -221,7 +221,8 @@ def main():
     roof = None
     d = tm_timed[dom]
     pcg_kernel = {abd.PCG_LOCAL: "k_pcg_local", abd.PCG_TWO_BARRIER: "k_pcg",
-                  abd.PCG_PIPELINED: "k_pcg1"}[tuning["pcg_variant"]] + "<double>"
+                  abd.PCG_PIPELINED: "k_pcg1",
+                  abd.PCG_LOCAL1: "k_pcg_cg1"}[tuning["pcg_variant"]] + "<double>"
     if d["bytes"] > 0 and d["launches"]:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
         kname = pcg_kernel if dom == "pcg" else dom

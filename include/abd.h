@@ -191,8 +191,11 @@ int abd_set_stream(abd_ctx* ctx, void* hip_stream);
                                  products (one block per 16 bodies; scenes
                                  too large to keep every block resident use
                                  TWO_BARRIER) */
+#define ABD_PCG_LOCAL1 3      /* as LOCAL, one exchange per iteration
+                                 (Chronopoulos-Gear recurrences; u and w
+                                 recomputed exactly every iteration) */
 typedef struct abd_tuning {
-  int32_t pcg_variant;     /* ABD_PCG_* (default LOCAL; the pipelined
+  int32_t pcg_variant;     /* ABD_PCG_* (default LOCAL1; the pipelined
                               form carries u, s and t by recurrences, which
                               can stall short of a very tight tolerance such
                               as eta = 1e-12 on stiff contact systems) */

@@ -41,7 +41,7 @@ class Tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-PCG_TWO_BARRIER, PCG_PIPELINED, PCG_LOCAL = 0, 1, 2
+PCG_TWO_BARRIER, PCG_PIPELINED, PCG_LOCAL, PCG_LOCAL1 = 0, 1, 2, 3
 
 
 class AdmmParams(C.Structure):

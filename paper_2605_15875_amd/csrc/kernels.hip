@@ -1551,6 +1551,252 @@ __global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_
   if (threadIdx.x == 0) atomicMax(&S.cnt->pcg_iters, it);
 }
 
+/* Problem-local PCG with one exchange per iteration, in the
+ * Chronopoulos-Gear form: with u = P^-1 r and w = A u, both inner products
+ * gamma = r.u and delta = w.u of an iteration come from one reduction,
+ *   beta_i = gamma_i / gamma_{i-1},
+ *   alpha_i = gamma_i / (delta_i - beta_i gamma_i / alpha_{i-1}),
+ *   p = u + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s,
+ * and u and w are recomputed exactly from the new r every iteration (no
+ * further recurrences).  The product w = A u needs u of the neighbouring
+ * bodies; each block forms them itself, u_nb = P_nb^-1 (r_nb - alpha(w_nb +
+ * beta s_nb)), from the r, w and s the neighbours published in the previous
+ * phase, so one publish-and-wait per iteration carries both the vectors and
+ * the partial sums.  Vectors read by other blocks are double-buffered by
+ * phase; own rows stay in registers. */
+#define PCG_NB_MAX 96
+template <typename HT>
+__global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it) {
+  const HT* __restrict__ Hd = (const HT*)S.Hdiag;
+  const HT* __restrict__ Ho = (const HT*)S.Hoff;
+  const HT* __restrict__ Pi = (const HT*)S.Pinv;
+  __shared__ double rloc[16][12];
+  __shared__ double uloc[16][12];
+  __shared__ double rnb[PCG_NB_MAX][12];
+  __shared__ double unb[PCG_NB_MAX][12];
+  __shared__ double vrow[3][192];
+  __shared__ double vbody[3][16];
+  __shared__ double part[16][3];
+  __shared__ double tot[16][3];
+  __shared__ double gam[16], gam_old[16], alp_old[16], bbl[16], alp[16], bet[16];
+  __shared__ unsigned char ldone[16];
+  __shared__ int s_glo, s_ghi, s_more;
+  __shared__ PcgCache<HT> cache;
+  const int ngroups = (S.B + 15) / 16;
+  const int gr = blockIdx.x;
+  if (gr >= ngroups) return;
+  const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
+  const int g0 = gr * 16, gend = min(S.B, g0 + 16);
+  const int b = g0 + lb;
+  const bool real = b < S.B;
+  const int plo = S.bprob[g0], phi = S.bprob[gend - 1];
+  const int nloc = phi - plo + 1;
+  const int p = real ? S.bprob[b] : phi;
+  const int j = p - plo;
+  ProbState* ps = S.ps;
+  PcgRec* const rec0 = S.pcg_rec;
+  PcgRec* const rec1 = S.pcg_rec + ngroups;
+  const long n12 = 12L * S.B;
+  double* const Rb[2] = {S.pw, S.pw + n12};
+  double* const Wb[2] = {S.pw + 2 * n12, S.pw + 3 * n12};
+  double* const Sb[2] = {S.pw + 4 * n12, S.zv};
+  if ((int)threadIdx.x < nloc)
+    ldone[threadIdx.x] =
+        (S.iter_mode == 0 || ps[plo + threadIdx.x].state == PS_NEWTON) ? 0 : 1;
+  __syncthreads();
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  if (!cached) __syncthreads();
+  const int e0 = S.row_ptr[g0], e_end = S.row_ptr[gend];
+  const int e_lo = real ? S.row_ptr[b] : 0, e_hi = real ? S.row_ptr[b + 1] : 0;
+  auto hrow = [&](int c) -> HT {
+    return cached ? cache.hd[c * 192 + threadIdx.x] : Hd[144 * b + 12 * row + c];
+  };
+  auto prow = [&](int c) -> HT {
+    return cached ? cache.pi[c * 192 + threadIdx.x] : Pi[144 * b + 12 * row + c];
+  };
+  auto reduce = [&](int nv, const double* v) {
+    for (int k = 0; k < nv; ++k) vrow[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if (row == 0 && lb < 16) {
+      for (int k = 0; k < nv; ++k) {
+        double sum = 0.0;
+        for (int c = 0; c < 12; ++c) sum += vrow[k][12 * lb + c];
+        vbody[k][lb] = sum;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < nloc) {
+      const int q = plo + threadIdx.x;
+      const int lo = max(S.prob_b0[q], g0) - g0, hi = min(S.prob_b1[q], gend - 1) - g0;
+      for (int k = 0; k < nv; ++k) {
+        double sum = 0.0;
+        for (int c = lo; c <= hi; ++c) sum += vbody[k][c];
+        part[threadIdx.x][k] = sum;
+      }
+    }
+  };
+  auto totals = [&](const PcgRec* recs) {
+    for (int q = 0; q < nloc; ++q) {
+      if (ldone[q]) continue;
+      const int pg = plo + q;
+      const int ga = S.prob_b0[pg] / 16, gb = S.prob_b1[pg] / 16;
+      if (threadIdx.x < 64) {
+        double sv[3] = {0.0, 0.0, 0.0};
+        for (int g = ga + (int)threadIdx.x; g <= gb; g += 64) {
+          const int slot = pg - S.bprob[16 * g];
+          for (int k = 0; k < 3; ++k) sv[k] += recs[g].val[slot][k];
+        }
+        for (int o = 32; o > 0; o >>= 1)
+          for (int k = 0; k < 3; ++k) sv[k] += __shfl_xor(sv[k], o, 64);
+        if (threadIdx.x == 0)
+          for (int k = 0; k < 3; ++k) tot[q][k] = sv[k];
+      }
+    }
+    __syncthreads();
+  };
+  auto range = [&]() {
+    if (threadIdx.x == 0) {
+      int lo = -1, hi = -2;
+      for (int q = 0; q < nloc; ++q)
+        if (!ldone[q]) {
+          if (lo < 0) lo = S.prob_b0[plo + q] / 16;
+          hi = S.prob_b1[plo + q] / 16;
+        }
+      s_glo = lo;
+      s_ghi = hi;
+      s_more = lo >= 0;
+    }
+    __syncthreads();
+  };
+  /* one phase: from the own new residual rn (registers) and the
+   * neighbours' published vectors, u = P^-1 r for the own body and its
+   * neighbours, w = A u, publish r, w, s and the partial sums */
+  double xr = 0.0, rr = 0.0, pr = 0.0, sr = 0.0, wr = 0.0;
+  const int o = 12 * b + row;
+  auto phase = [&](int ph, bool init) {
+    const int cur = (ph - 1) & 1, nxt = ph & 1; /* buffers read / written */
+    const bool act = real && !ldone[j];
+    /* own body: u = P^-1 r */
+    rloc[lb][row] = act ? rr : 0.0;
+    __syncthreads();
+    double ur = 0.0;
+    if (act) {
+      HT uu = 0;
+      for (int c = 0; c < 12; ++c) uu += prow(c) * (HT)rloc[lb][c];
+      ur = (double)uu;
+    }
+    uloc[lb][row] = ur;
+    HT y = 0;
+    __syncthreads();
+    if (act)
+      for (int c = 0; c < 12; ++c) y += hrow(c) * (HT)uloc[lb][c];
+    /* neighbours, in chunks of PCG_NB_MAX block-row entries of the group */
+    for (int c0 = e0; c0 < e_end; c0 += PCG_NB_MAX) {
+      const int c1 = min(e_end, c0 + PCG_NB_MAX);
+      /* r of each entry's neighbour (alpha, beta of that body's problem) */
+      for (int t = threadIdx.x; t < 12 * (c1 - c0); t += blockDim.x) {
+        const int le = t / 12, c = t % 12, e = c0 + le;
+        const int nb = S.col_body[e];
+        const int q = S.bprob[nb] - plo;
+        double v = 0.0;
+        if (q >= 0 && q < nloc && !ldone[q]) {
+          const int on = 12 * nb + c;
+          v = init ? -S.g[on]
+                   : Rb[cur][on] - alp[q] * (Wb[cur][on] + bet[q] * Sb[(ph) & 1][on]);
+        }
+        rnb[le][c] = v;
+      }
+      __syncthreads();
+      for (int t = threadIdx.x; t < 12 * (c1 - c0); t += blockDim.x) {
+        const int le = t / 12, rw = t % 12, e = c0 + le;
+        const int nb = S.col_body[e];
+        HT uu = 0;
+        const HT* P = Pi + 144 * nb + 12 * rw;
+        for (int c = 0; c < 12; ++c) uu += P[c] * (HT)rnb[le][c];
+        unb[le][rw] = (double)uu;
+      }
+      __syncthreads();
+      if (act)
+        for (int e = max(e_lo, c0); e < min(e_hi, c1); ++e) {
+          const int le = e - c0, lc = e - e0;
+          const HT* blk = (cached && lc < cache.n_off) ? cache.off[lc]
+                                                      : Ho + 144 * (size_t)S.col_slot[e];
+          const int tr = S.col_trans[e];
+          const int st = tr ? 12 : 1, sc = tr ? 1 : 12;
+          for (int c = 0; c < 12; ++c) y += blk[sc * row + st * c] * (HT)unb[le][c];
+        }
+      __syncthreads();
+    }
+    wr = (double)y;
+    if (act) {
+      Rb[nxt][o] = rr;
+      Wb[nxt][o] = wr;
+      Sb[(ph + 1) & 1][o] = sr; /* s of the previous iteration, read next phase */
+    }
+    const double v[3] = {act ? rr * ur : 0.0, act ? wr * ur : 0.0, act ? rr * rr : 0.0};
+    reduce(3, v);
+    PcgRec* recs = (ph & 1) ? rec1 : rec0;
+    pcg_publish<HT>(recs + gr, ph, nloc, part);
+    pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err);
+    totals(recs);
+    return ur;
+  };
+  range();
+  if (!s_more) return;
+  /* phase 0: r = b = -g, x = p = s = 0, u = P^-1 r, w = A u */
+  rr = real && !ldone[j] ? -S.g[o] : 0.0;
+  double ur = phase(0, true);
+  if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
+    const int q = threadIdx.x, pg = plo + q;
+    gam[q] = tot[q][0];
+    bbl[q] = tot[q][2];
+    const bool first = S.prob_b0[pg] >= g0;
+    if (first) ps[pg].bb = bbl[q];
+    if (!(bbl[q] > 0.0)) {
+      ldone[q] = 1;
+      if (first) ps[pg].pcg_iters = 0;
+    } else {
+      alp[q] = gam[q] / tot[q][1];
+      bet[q] = 0.0;
+    }
+  }
+  __syncthreads();
+  int it = 0;
+  for (it = 0; it < max_it; ++it) {
+    range();
+    if (!s_more || S.cnt->err) break;
+    const bool act = real && !ldone[j];
+    if (act) {
+      const double a = alp[j], be = bet[j];
+      pr = ur + be * pr;
+      sr = wr + be * sr;
+      xr += a * pr;
+      rr -= a * sr;
+    }
+    ur = phase(it + 1, false);
+    /* gamma, delta, rho of the new residual: stop, or the next step sizes */
+    if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
+      const int q = threadIdx.x, pg = plo + q;
+      if (tot[q][2] <= eta * eta * bbl[q]) {
+        ldone[q] = 1;
+        if (S.prob_b0[pg] >= g0) ps[pg].pcg_iters = it + 1;
+      } else {
+        gam_old[q] = gam[q];
+        alp_old[q] = alp[q];
+        gam[q] = tot[q][0];
+        const double be = gam[q] / gam_old[q];
+        bet[q] = be;
+        alp[q] = gam[q] / (tot[q][1] - be * gam[q] / alp_old[q]);
+      }
+    }
+    __syncthreads();
+  }
+  if ((int)threadIdx.x < nloc && !ldone[threadIdx.x] && S.prob_b0[plo + threadIdx.x] >= g0)
+    ps[plo + threadIdx.x].pcg_iters = it;
+  if (real && !(S.iter_mode != 0 && ps[p].state != PS_NEWTON)) S.dq[o] = xr;
+  if (threadIdx.x == 0) atomicMax(&S.cnt->pcg_iters, it);
+}
+
 /* Single-reduction (pipelined) block-Jacobi PCG, the same solve with one
  * grid barrier per iteration instead of two.  It follows the
  * Chronopoulos-Gear form of CG, where s = A p and the preconditioned
@@ -2558,6 +2804,8 @@ int pcg_max_grid() {
   per = std::min(per, per32);
   (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg_local<float>, 192, 0);
   per = std::min(per, per32);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per32, (const void*)k_pcg_cg1<double>, 192, 0);
+  per = std::min(per, per32);
   return ncu * (per > 0 ? per : 1);
 }
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
@@ -2568,6 +2816,8 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
     fn = S.mixed ? (const void*)k_pcg1<float> : (const void*)k_pcg1<double>;
   else if (variant == 2)
     fn = S.mixed ? (const void*)k_pcg_local<float> : (const void*)k_pcg_local<double>;
+  else if (variant == 3)
+    fn = S.mixed ? (const void*)k_pcg_cg1<float> : (const void*)k_pcg_cg1<double>;
   else
     fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
   hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st);

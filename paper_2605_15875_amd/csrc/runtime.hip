@@ -87,7 +87,7 @@ struct abd_ctx {
   hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
-  abd_tuning tune = {ABD_PCG_LOCAL, 0, 1024, 2048, 1};
+  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1};
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -467,14 +467,16 @@ void launch_static(abd_ctx* ctx, const Scene& S) {
  * 16-body group */
 int pcg_variant(const abd_ctx* ctx, const Scene& S) {
   const int ng = std::max(1, (S.B + 15) / 16);
-  if (ctx->tune.pcg_variant == ABD_PCG_LOCAL && ng > ctx->pcg_grid)
+  if ((ctx->tune.pcg_variant == ABD_PCG_LOCAL || ctx->tune.pcg_variant == ABD_PCG_LOCAL1) &&
+      ng > ctx->pcg_grid)
     return ABD_PCG_TWO_BARRIER;
   return ctx->tune.pcg_variant;
 }
 /* blocks of the cooperative PCG launch */
 int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
   const int ng = std::max(1, (S.B + 15) / 16);
-  if (pcg_variant(ctx, S) == ABD_PCG_LOCAL) return ng;
+  const int v = pcg_variant(ctx, S);
+  if (v == ABD_PCG_LOCAL || v == ABD_PCG_LOCAL1) return ng;
   const int want = ctx->tune.pcg_blocks > 0 ? std::min(ctx->tune.pcg_blocks, ng) : ng;
   return std::max(1, std::min(ctx->pcg_grid, want));
 }
@@ -1991,7 +1993,7 @@ int abd_get_tuning(abd_ctx* ctx, abd_tuning* out) {
 int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
   int rc = check_ctx(ctx, true);
   if (rc) return rc;
-  if (!t || t->pcg_variant < ABD_PCG_TWO_BARRIER || t->pcg_variant > ABD_PCG_LOCAL ||
+  if (!t || t->pcg_variant < ABD_PCG_TWO_BARRIER || t->pcg_variant > ABD_PCG_LOCAL1 ||
       t->pcg_blocks < 0 || t->grid_blocks < 1 || t->assemble_blocks < 1 ||
       t->grid_blocks > (1 << 20) || t->assemble_blocks > (1 << 20))
     return fail(ctx, ABD_E_INVALID_ARG, "tuning values");
@@ -2054,11 +2056,12 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   std::vector<std::pair<int, int>> tried = {{orig.pcg_variant, pcg_blocks(ctx, S)}};
   /* the pipelined form only where its attainable accuracy is not the
    * binding limit */
-  std::vector<int> vars = {ABD_PCG_LOCAL, ABD_PCG_TWO_BARRIER};
+  std::vector<int> vars = {ABD_PCG_LOCAL, ABD_PCG_LOCAL1, ABD_PCG_TWO_BARRIER};
   if (ctx->P.pcg_eta >= 1e-6) vars.push_back(ABD_PCG_PIPELINED);
   for (int v : vars)
     for (int div : {1, 2, 4, 8}) {
-      if (v == ABD_PCG_LOCAL && div > 1) continue; /* one block per group */
+      if ((v == ABD_PCG_LOCAL || v == ABD_PCG_LOCAL1) && div > 1)
+        continue; /* one block per group */
       abd_tuning t = best;
       t.pcg_variant = v;
       t.pcg_blocks = std::max(1, (ng + div - 1) / div);

@@ -16,6 +16,7 @@ PARITY = dict(newton_theta=1e-9, pcg_eta=1e-12)
 
 SETTINGS = [
     dict(pcg_variant=abd.PCG_LOCAL),
+    dict(pcg_variant=abd.PCG_LOCAL1),
     dict(pcg_variant=abd.PCG_TWO_BARRIER),
     dict(pcg_variant=abd.PCG_PIPELINED),
     dict(pcg_variant=abd.PCG_PIPELINED, pcg_blocks=1),
@@ -92,7 +93,7 @@ def test_autotune_keeps_state_and_solves():
     gpu.set_state(q, qd)
     t = gpu.autotune()
     assert t["pcg_variant"] in (abd.PCG_TWO_BARRIER, abd.PCG_PIPELINED,
-                                abd.PCG_LOCAL)
+                                abd.PCG_LOCAL, abd.PCG_LOCAL1)
     assert gpu.tuning() == t
     q2, qd2 = gpu.get_state()
     np.testing.assert_array_equal(q2, q)
@@ -113,3 +114,25 @@ def test_tuning_rejects_bad_values():
                 dict(assemble_blocks=0)):
         with pytest.raises(abd.AbdError):
             gpu.set_tuning(**bad)
+
+
+@pytest.mark.parametrize("variant", [2, 3])
+def test_local_pcg_forms_on_contact_spheres_match_oracle(variant):
+    """Both problem-local PCG forms at eta 1e-12 on a contact-rich sphere
+    scene: each time step from the oracle's state lands on the oracle's
+    positions."""
+    sc = scenes.spheres_in_box_scene(
+        3, n_bodies=24, level=1, half=0.25, y_lo=0.09, y_hi=0.45,
+        r_lo=0.05, r_hi=0.08, min_gap=0.0005, vel=0.5, newton_theta=1e-7,
+        pcg_eta=1e-12)
+    gpu = abd.Solver(sc)
+    gpu.set_tuning(pcg_variant=variant)
+    ref = O.Oracle(sc)
+    for k in range(10):
+        q, qd = ref.get_state()
+        gpu.set_state(q, qd)
+        sg = gpu.step()
+        so = ref.step()
+        assert sg["status"] == so["status"] == 0
+        err = np.abs(gpu.vertices() - ref.vertices()).max() / sg["scene_scale"]
+        assert err < 1e-9, (variant, k, err)
