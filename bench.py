@@ -146,6 +146,8 @@ def main():
     ap.add_argument("--pcg-variant", type=int, default=None,
                     help="0: two grid barriers per PCG iteration, "
                          "1: single-reduction form (default: library's)")
+    ap.add_argument("--overlap-body", type=int, default=None,
+                    help="1: body terms on a second stream, 0: in line")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner after warmup")
     ap.add_argument("--copy-probe", action="store_true",
@@ -178,6 +180,8 @@ def main():
     solver = abd.Solver(sc)
     if a.pcg_variant is not None:
         solver.set_tuning(pcg_variant=a.pcg_variant)
+    if a.overlap_body is not None:
+        solver.set_tuning(overlap_body=a.overlap_body)
     for i in range(a.warmup):
         st = solver.step()
         log(f"warmup {i}: newton={st['newton_iters']} "

@@ -206,6 +206,8 @@ typedef struct abd_tuning {
                               CCD kernels (default 1024) */
   int32_t assemble_blocks; /* blocks of the barrier assembly (default 2048) */
   int32_t use_graphs;      /* replay Newton passes from captured graphs (1) */
+  int32_t overlap_body;    /* body terms on a second stream, overlapping the
+                              broad phase (1), or in line (0, default) */
 } abd_tuning;
 
 /* Read or replace the launch settings of a finalized context.  Settings

@@ -2078,7 +2078,10 @@ __global__ void k_ccd(Scene S) {
     if (toi < 1.0) atomic_min_pos(&S.ps[prob].min_toi, toi);
   }
   for (int o = 32; o > 0; o >>= 1) tmin = fmin(tmin, __shfl_down(tmin, o, 64));
-  if ((threadIdx.x & 63) == 0) atomic_min_pos(&S.cnt->min_toi, fmax(tmin, 0.0));
+  /* waves without a TOI below 1 leave the minimum alone (its readers take
+   * min(1, .)), which keeps empty waves off the shared counter */
+  if ((threadIdx.x & 63) == 0 && tmin < 1.0)
+    atomic_min_pos(&S.cnt->min_toi, fmax(tmin, 0.0));
 }
 
 /* ================================================================== */

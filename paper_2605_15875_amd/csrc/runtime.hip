@@ -87,7 +87,7 @@ struct abd_ctx {
   hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
-  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1};
+  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1, 0};
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -443,22 +443,27 @@ void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd);
 
 /* static phase on the stream: body terms, broad phase, barrier assembly */
 void launch_static(abd_ctx* ctx, const Scene& S) {
-  /* body terms (writes g, Hdiag) on the side stream, concurrent with the
-   * broad phase; the assembly (which adds into g, Hdiag) waits for it */
-  (void)hipEventRecord(ctx->ev_fork, ctx->st);
-  (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
-  {
-    StageTimer t(ctx, 0, (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96),
-                 ctx->side);
-    launch_body_terms(S, ctx->side);
+  const double body_bytes = (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96);
+  if (ctx->tune.overlap_body) {
+    /* body terms (writes g, Hdiag) on the side stream, concurrent with the
+     * broad phase; the assembly (which adds into g, Hdiag) waits for it */
+    (void)hipEventRecord(ctx->ev_fork, ctx->st);
+    (void)hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0);
+    {
+      StageTimer t(ctx, 0, body_bytes, ctx->side);
+      launch_body_terms(S, ctx->side);
+    }
+    (void)hipEventRecord(ctx->ev_join, ctx->side);
+  } else {
+    StageTimer t(ctx, 0, body_bytes);
+    launch_body_terms(S, ctx->st);
   }
-  (void)hipEventRecord(ctx->ev_join, ctx->side);
   broad_phase(ctx, S, 0);
   {
     StageTimer t(ctx, 2);
     launch_filter(S, ctx->st);
     launch_clear_slots(S, ctx->st);
-    (void)hipStreamWaitEvent(ctx->st, ctx->ev_join, 0);
+    if (ctx->tune.overlap_body) (void)hipStreamWaitEvent(ctx->st, ctx->ev_join, 0);
     launch_assemble(S, 0, ctx->st);
   }
 }
@@ -2000,6 +2005,7 @@ int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
   drop_graphs(ctx); /* launch shapes are part of the captured graphs */
   ctx->tune = *t;
   ctx->tune.use_graphs = t->use_graphs ? 1 : 0;
+  ctx->tune.overlap_body = t->overlap_body ? 1 : 0;
   ctx->S.grid_blocks = t->grid_blocks;
   ctx->S.assemble_blocks = t->assemble_blocks;
   return ABD_OK;
@@ -2081,6 +2087,11 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
     abd_tuning t = after_grid;
     t.assemble_blocks = g;
     if (g != orig.assemble_blocks) consider(t);
+  }
+  {
+    abd_tuning t = best;
+    t.overlap_body = best.overlap_body ? 0 : 1;
+    consider(t);
   }
   /* restore the state and keep the winner */
   (void)abd_set_tuning(ctx, &best);
