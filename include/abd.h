@@ -208,6 +208,10 @@ typedef struct abd_tuning {
   int32_t use_graphs;      /* replay Newton passes from captured graphs (1) */
   int32_t overlap_body;    /* body terms on a second stream, overlapping the
                               broad phase (1), or in line (0, default) */
+  int32_t pcg_coop;        /* 1: cooperative PCG launch; 0 (default): plain
+                              launch when the grid is at most half the
+                              compute units (always resident together),
+                              cooperative otherwise */
 } abd_tuning;
 
 /* Read or replace the launch settings of a finalized context.  Settings

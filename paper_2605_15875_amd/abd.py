@@ -35,7 +35,8 @@ class Params(C.Structure):
 class Tuning(C.Structure):
     _fields_ = [("pcg_variant", C.c_int32), ("pcg_blocks", C.c_int32),
                 ("grid_blocks", C.c_int32), ("assemble_blocks", C.c_int32),
-                ("use_graphs", C.c_int32), ("overlap_body", C.c_int32)]
+                ("use_graphs", C.c_int32), ("overlap_body", C.c_int32),
+                ("pcg_coop", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

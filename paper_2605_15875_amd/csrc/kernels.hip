@@ -2812,7 +2812,7 @@ int pcg_max_grid() {
   return ncu * (per > 0 ? per : 1);
 }
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
-               hipStream_t st) {
+               int coop, hipStream_t st) {
   void* args[] = {(void*)&S, (void*)&eta, (void*)&max_it};
   const void* fn;
   if (variant == 1)
@@ -2823,7 +2823,11 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
     fn = S.mixed ? (const void*)k_pcg_cg1<float> : (const void*)k_pcg_cg1<double>;
   else
     fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
-  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st);
+  /* the blocks wait for each other: a cooperative launch guarantees they
+   * are resident together; a plain launch is used only for grids of at
+   * most half the compute units, which are always resident together */
+  hipError_t e = coop ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st)
+                      : hipLaunchKernel(fn, dim3(grid), dim3(192), args, 0, st);
   return e == hipSuccess ? 0 : -1;
 }
 void launch_dq_norm(const Scene& S, hipStream_t st) {

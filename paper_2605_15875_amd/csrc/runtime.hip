@@ -81,13 +81,14 @@ struct abd_ctx {
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
   std::vector<void*> allocs;
   int pcg_grid = 0;
+  int n_cu = 0;
   int n_shared = 0;
   /* captured passes of the device loop: [0] before the cooperative PCG
    * launch, [1] after it; rebuilt whenever buffers or bound data change */
   hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
-  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1, 0};
+  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1, 0, 0};
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -468,6 +469,13 @@ void launch_static(abd_ctx* ctx, const Scene& S) {
   }
 }
 
+int pcg_blocks(const abd_ctx* ctx, const Scene& S);
+/* cooperative launch unless the tuning allows a plain one and the grid
+ * is at most half the compute units */
+int pcg_coop(const abd_ctx* ctx, const Scene& S) {
+  if (ctx->tune.pcg_coop) return 1;
+  return pcg_blocks(ctx, S) <= ctx->n_cu / 2 ? 0 : 1;
+}
 /* PCG form in use: the problem-local form needs one resident block per
  * 16-body group */
 int pcg_variant(const abd_ctx* ctx, const Scene& S) {
@@ -500,7 +508,7 @@ int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
   }
   StageTimer t(ctx, 3);
   if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S),
-                 pcg_variant(ctx, S), ctx->st))
+                 pcg_variant(ctx, S), pcg_coop(ctx, S), ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
   launch_dq_norm(S, ctx->st);
   return ABD_OK;
@@ -632,7 +640,7 @@ int pass_pcg(abd_ctx* ctx) {
   S1.iter_mode = 1;
   StageTimer t(ctx, 3);
   if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S1),
-                 pcg_variant(ctx, S1), ctx->st))
+                 pcg_variant(ctx, S1), pcg_coop(ctx, S1), ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
   return ABD_OK;
 }
@@ -1139,6 +1147,11 @@ int abd_finalize(abd_ctx* ctx) {
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
+  {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&ctx->n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+  }
   if (!ctx->st) {
     /* a stream of the library's own (default priority): the legacy null
      * stream cannot be captured into graphs */
@@ -2006,6 +2019,7 @@ int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
   ctx->tune = *t;
   ctx->tune.use_graphs = t->use_graphs ? 1 : 0;
   ctx->tune.overlap_body = t->overlap_body ? 1 : 0;
+  ctx->tune.pcg_coop = t->pcg_coop ? 1 : 0;
   ctx->S.grid_blocks = t->grid_blocks;
   ctx->S.assemble_blocks = t->assemble_blocks;
   return ABD_OK;
@@ -2091,6 +2105,11 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   {
     abd_tuning t = best;
     t.overlap_body = best.overlap_body ? 0 : 1;
+    consider(t);
+  }
+  {
+    abd_tuning t = best;
+    t.pcg_coop = best.pcg_coop ? 0 : 1;
     consider(t);
   }
   /* restore the state and keep the winner */

@@ -23,7 +23,8 @@ SETTINGS = [
     dict(pcg_variant=abd.PCG_TWO_BARRIER, pcg_blocks=1),
     dict(grid_blocks=7, assemble_blocks=3),
     dict(use_graphs=0),
-    dict(overlap_body=0),
+    dict(overlap_body=1),
+    dict(pcg_coop=0),
 ]
 
 
