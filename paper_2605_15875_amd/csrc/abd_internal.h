@@ -353,7 +353,7 @@ __device__ __forceinline__ Feat point_seg(const double* x, int p, int e0,
  * first one winning ties.  Codes: PT 0..2 vertex t_k, 3..5 edge k (t0t1,
  * t1t2, t2t0), 6 interior; EE 0..3 (a_i, b_j) -> 2i + j, 4..5 a_i on
  * segment b, 6..7 b_j on segment a, 8 interior. */
-__device__ inline Feat classify(int kind, const double* x, double& Dout) {
+__device__ __forceinline__ Feat classify(int kind, const double* x, double& Dout) {
   Feat best;
   double bestD = INFINITY;
   if (kind == C_PT) {
@@ -679,7 +679,7 @@ __device__ __forceinline__ void orth_hessian_psd(const double* A, double* K) {
 /* bound (may be null): bits of a TOI another pair of the same problem has
  * already reached; once t passes it this pair cannot lower the minimum,
  * so the advance stops there and returns t (a lower bound of its TOI) */
-__device__ inline double accd(int kind, const double* x, const double* dx,
+__device__ __forceinline__ double accd(int kind, const double* x, const double* dx,
                               double tmax,
                               const unsigned long long* bound = nullptr) {
   double m[3];

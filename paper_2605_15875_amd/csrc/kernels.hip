@@ -976,34 +976,45 @@ __global__ void k_bsr_fill(Scene S) {
 }
 
 /* inverse of every diagonal block by Gauss-Jordan (SPD, no pivoting):
- * 16 bodies per block of 192 threads, one row per thread */
+ * twelve lanes per body, one row (with its identity half) per lane, five
+ * bodies per wavefront; the pivot row reaches the other lanes of its body
+ * by cross-lane shuffles, so no barrier is needed */
 template <typename HT>
 __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
-  __shared__ double M[16][12][25];
-  const int lb = threadIdx.x / 12, r = threadIdx.x % 12;
-  const int b = blockIdx.x * 16 + lb;
-  const bool act = b < S.B;
+  const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+  const int slot = lane / 12, r = lane % 12;
+  const int b = (blockIdx.x * 3 + wave) * 5 + slot;
+  const bool act = slot < 5 && b < S.B;
+  const int base = slot < 5 ? lane - r : lane; /* idle lanes read themselves */
+  const HT* Hd = (const HT*)S.Hdiag;
+  double row[24];
+#pragma unroll
   for (int c = 0; c < 12; ++c) {
-    M[lb][r][c] = act ? (double)((const HT*)S.Hdiag)[144 * b + 12 * r + c]
-                      : (r == c ? 1.0 : 0.0);
-    M[lb][r][12 + c] = r == c ? 1.0 : 0.0;
+    row[c] = act ? (double)Hd[144 * b + 12 * r + c] : (r == c ? 1.0 : 0.0);
+    row[12 + c] = r == c ? 1.0 : 0.0;
   }
-  __syncthreads();
+#pragma unroll
   for (int k = 0; k < 12; ++k) {
-    double piv = M[lb][k][k];
-    double f = M[lb][r][k] / piv;
-    double rowk[24];
-    for (int c = 0; c < 24; ++c) rowk[c] = M[lb][k][c];
-    __syncthreads();
-    if (r != k)
-      for (int c = 0; c < 24; ++c) M[lb][r][c] -= f * rowk[c];
-    else
-      for (int c = 0; c < 24; ++c) M[lb][r][c] = rowk[c] / piv;
-    __syncthreads();
+    double pk[24];
+    const int src = slot < 5 ? base + k : lane;
+#pragma unroll
+    for (int c = 0; c < 24; ++c) pk[c] = __shfl(row[c], src, 64);
+    const double piv = pk[k];
+    if (r == k) {
+      const double inv = 1.0 / piv;
+#pragma unroll
+      for (int c = 0; c < 24; ++c) row[c] = pk[c] * inv;
+    } else {
+      const double f = row[k] / piv;
+#pragma unroll
+      for (int c = 0; c < 24; ++c) row[c] -= f * pk[c];
+    }
   }
-  if (act)
-    for (int c = 0; c < 12; ++c)
-      ((HT*)S.Pinv)[144 * b + 12 * r + c] = (HT)M[lb][r][12 + c];
+  if (act) {
+    HT* Pi = (HT*)S.Pinv;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) Pi[144 * b + 12 * r + c] = (HT)row[12 + c];
+  }
 }
 
 /* grid-wide barrier for the cooperative PCG launch.  The workgroup barrier
@@ -2040,7 +2051,7 @@ __global__ void k_dq_norm(Scene S) {
 /* ================================================================== */
 /* S9 CCD                                                              */
 /* ================================================================== */
-__global__ void k_ccd(Scene S) {
+__global__ __launch_bounds__(256) void k_ccd(Scene S) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
@@ -2787,9 +2798,9 @@ void launch_bsr(const Scene& S, hipStream_t st) {
 }
 void launch_block_inverse(const Scene& S, hipStream_t st) {
   if (S.mixed)
-    hipLaunchKernelGGL(k_block_inverse<float>, dim3(cdiv(S.B, 16)), dim3(192), 0, st, S);
+    hipLaunchKernelGGL(k_block_inverse<float>, dim3(cdiv(S.B, 15)), dim3(192), 0, st, S);
   else
-    hipLaunchKernelGGL(k_block_inverse<double>, dim3(cdiv(S.B, 16)), dim3(192), 0, st, S);
+    hipLaunchKernelGGL(k_block_inverse<double>, dim3(cdiv(S.B, 15)), dim3(192), 0, st, S);
 }
 int pcg_max_grid() {
   int dev = 0, ncu = 0, per = 0;
