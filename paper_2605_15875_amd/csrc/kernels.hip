@@ -276,33 +276,71 @@ __global__ void k_body_pairs(Scene S) {
 
 /* chunk pairs of every body pair: vertex chunks x triangle chunks (both
  * directions) and edge chunks x edge chunks */
+/* LDS written and then read by the lanes of one wavefront */
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+/* exclusive prefix of n over the wavefront, and the wavefront's total */
+__device__ __forceinline__ int wave_prefix(int n, int* total) {
+  const int lane = __lane_id();
+  int incl = n;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  *total = __shfl(incl, 63, 64);
+  return incl - n;
+}
+
+__device__ __forceinline__ void chunk_pair_of(const int* ca, const int* cb, int n1,
+                                              int n2, int ntb, int nta, int neb,
+                                              int t, int& kind, int& P, int& Q) {
+  if (t < n1) {
+    kind = C_PT; P = ca[0] + t / ntb; Q = cb[2] + t % ntb;
+  } else if (t < n1 + n2) {
+    const int u = t - n1;
+    kind = C_PT; P = cb[0] + u / nta; Q = ca[2] + u % nta;
+  } else {
+    const int u = t - n1 - n2;
+    kind = C_EE; P = ca[4] + u / neb; Q = cb[4] + u % neb;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
-  int nbp = min(S.cnt->n_bp, S.cap_bp);
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  const int lane = threadIdx.x & 63;
   for (int p = blockIdx.x; p < nbp; p += gridDim.x) {
-    int2 ab = S.bp[p];
+    const int2 ab = S.bp[p];
     const int* ca = S.body_chunk + 6 * ab.x;
     const int* cb = S.body_chunk + 6 * ab.y;
-    int nva = ca[1] - ca[0], nta = ca[3] - ca[2], nea = ca[5] - ca[4];
-    int nvb = cb[1] - cb[0], ntb = cb[3] - cb[2], neb = cb[5] - cb[4];
-    int n1 = nva * ntb, n2 = nvb * nta, n3 = nea * neb;
-    int tot = n1 + n2 + n3;
-    for (int t0 = 0; t0 < tot; t0 += blockDim.x) {
-      const int t = t0 + threadIdx.x;
-      int kind = C_EE, P = 0, Q = 0;
-      if (t < n1) {
-        kind = C_PT; P = ca[0] + t / ntb; Q = cb[2] + t % ntb;
-      } else if (t < n1 + n2) {
-        int u = t - n1;
-        kind = C_PT; P = cb[0] + u / nta; Q = ca[2] + u % nta;
-      } else if (t < tot) {
-        int u = t - n1 - n2;
-        kind = C_EE; P = ca[4] + u / neb; Q = cb[4] + u % neb;
-      }
-      const bool ok =
-          t < tot && box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat);
-      const int k = wave_slot(ok, &S.cnt->n_cp);
-      if (ok && k < S.cap_cp) S.cp[k] = make_int4(kind, P, Q, p);
+    const int nva = ca[1] - ca[0], nta = ca[3] - ca[2], nea = ca[5] - ca[4];
+    const int nvb = cb[1] - cb[0], ntb = cb[3] - cb[2], neb = cb[5] - cb[4];
+    const int n1 = nva * ntb, n2 = nvb * nta, n3 = nea * neb;
+    const int tot = n1 + n2 + n3;
+    /* count this thread's passing tests, one atomic per wavefront, write */
+    int n = 0;
+    for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+      int kind, P, Q;
+      chunk_pair_of(ca, cb, n1, n2, ntb, nta, neb, t, kind, P, Q);
+      n += box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat) ? 1 : 0;
     }
+    int total;
+    const int off = wave_prefix(n, &total);
+    if (total == 0) continue; /* uniform over the wavefront */
+    int base = 0;
+    if (lane == 0) base = atomicAdd(&S.cnt->n_cp, total);
+    int k = __shfl(base, 0, 64) + off;
+    if (n > 0)
+      for (int t = threadIdx.x; t < tot; t += blockDim.x) {
+        int kind, P, Q;
+        chunk_pair_of(ca, cb, n1, n2, ntb, nta, neb, t, kind, P, Q);
+        if (!box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat)) continue;
+        if (k < S.cap_cp) S.cp[k] = make_int4(kind, P, Q, p);
+        ++k;
+      }
   }
 }
 
@@ -370,15 +408,14 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
   __shared__ int qid[4][ABD_CHUNK];
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int ncp = min(S.cnt->n_cp, S.cap_cp);
-  for (int base = blockIdx.x * 4; base < ncp; base += gridDim.x * 4) {
-    const int c = base + wave;
-    const bool valid = c < ncp;
-    const int4 cp = valid ? S.cp[c] : make_int4(0, 0, 0, 0);
+  /* every wavefront works through its own chunk pairs */
+  for (int c = blockIdx.x * 4 + wave; c < ncp; c += gridDim.x * 4) {
+    const int4 cp = S.cp[c];
     const int P = cp.y, Q = cp.z;
     const int kindP = cp.x == C_PT ? K_VERT : K_EDGE;
     const int kindQ = cp.x == C_PT ? K_TRI : K_EDGE;
-    const int nP = valid ? S.ch_count[P] : 0;
-    const int nQ = valid ? S.ch_count[Q] : 0;
+    const int nP = S.ch_count[P];
+    const int nQ = S.ch_count[Q];
     bool keep = false;
     int id = 0;
     double qb[6];
@@ -389,38 +426,49 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
     }
     const unsigned long long m = __ballot(keep);
     const int nq = __popcll(m);
+    if (nq == 0) continue; /* uniform over the wavefront */
     if (keep) {
       const int pos = __popcll(m & ((1ull << lane) - 1ull));
       qid[wave][pos] = id;
 #pragma unroll
       for (int k = 0; k < 6; ++k) qbox[wave][pos][k] = qb[k];
     }
-    __syncthreads();
+    wave_lds_sync();
     bool mine = false;
     int pid = 0;
     double box[6];
-    if (nq > 0 && lane < nP) {
+    if (lane < nP) {
       pid = S.ch_prims[S.ch_start[P] + lane];
       prim_box(S, kindP, pid, swept, box);
       mine = box_overlap(box, S.ch_box + 6 * Q, S.dhat);
     }
-    if (__ballot(mine) != 0ull) {
+    /* count, one atomic per wavefront, then write */
+    int n = 0;
+    if (mine)
+      for (int j = 0; j < nq; ++j) n += box_overlap(box, qbox[wave][j], S.dhat) ? 1 : 0;
+    int total;
+    const int off = wave_prefix(n, &total);
+    if (total > 0) {
       const bool pt = cp.x == C_PT; /* uniform over the wavefront */
       int* const counter = pt ? &S.cnt->n_pt : &S.cnt->n_ee;
       const int cap = pt ? S.cap_pt : S.cap_ee;
       int* const list = pt ? S.cand_pt : S.cand_ee;
-      for (int j = 0; j < nq; ++j) {
-        const bool ok = mine && box_overlap(box, qbox[wave][j], S.dhat);
-        const int k = wave_slot(ok, counter);
-        if (ok && k < cap) {
-          const int other = qid[wave][j];
-          list[3 * k] = pt ? pid : min(pid, other);
-          list[3 * k + 1] = pt ? other : max(pid, other);
-          list[3 * k + 2] = cp.w;
+      int base = 0;
+      if (lane == 0) base = atomicAdd(counter, total);
+      int k = __shfl(base, 0, 64) + off;
+      if (mine)
+        for (int j = 0; j < nq; ++j) {
+          if (!box_overlap(box, qbox[wave][j], S.dhat)) continue;
+          if (k < cap) {
+            const int other = qid[wave][j];
+            list[3 * k] = pt ? pid : min(pid, other);
+            list[3 * k + 1] = pt ? other : max(pid, other);
+            list[3 * k + 2] = cp.w;
+          }
+          ++k;
         }
-      }
     }
-    __syncthreads();
+    wave_lds_sync(); /* qbox is reused by the next chunk pair */
   }
 }
 
