@@ -49,6 +49,7 @@ enum { PS_NEWTON = 0, PS_LINESEARCH = 1, PS_DONE = 2 };
  * phase number as a flag */
 struct alignas(64) PcgRec {
   unsigned long long gen;
+  int plo, pad; /* first problem of the group */
   double val[16][3];
 };
 

@@ -1353,10 +1353,11 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
  * are deterministic. */
 template <typename HT>
 __device__ __forceinline__ void pcg_publish(PcgRec* rec, int ph, int nloc,
-                                            const double (*part)[3]) {
+                                            const double (*part)[3], int plo = 0) {
   __syncthreads();
   if ((int)threadIdx.x < 3 * nloc)
     rec->val[threadIdx.x / 3][threadIdx.x % 3] = part[threadIdx.x / 3][threadIdx.x % 3];
+  if (threadIdx.x == 0) rec->plo = plo;
   __syncthreads();
   if (threadIdx.x == 0)
     __hip_atomic_store(&rec->gen, (unsigned long long)(ph + 1), __ATOMIC_RELEASE,
@@ -1379,6 +1380,39 @@ __device__ __forceinline__ void pcg_wait(const PcgRec* recs, int glo, int ghi,
   }
   /* one acquire per polling thread after its flags were seen */
   if (polled) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  __syncthreads();
+}
+
+/* wait for the records of groups glo..ghi and sum, in a fixed order, the
+ * partial sums of problem pg they carry (the first wavefront polls and
+ * reads, one group per lane) */
+__device__ __forceinline__ void pcg_wait_sum(const PcgRec* recs, int glo, int ghi,
+                                             int ph, int pg, int* err,
+                                             double* out) {
+  if (threadIdx.x < 64) {
+    double sv[3] = {0.0, 0.0, 0.0};
+    for (int g = glo + (int)threadIdx.x; g <= ghi; g += 64) {
+      long spins = 0;
+      while (__hip_atomic_load(&recs[g].gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+             (unsigned long long)(ph + 1)) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1L << 27)) {
+          atomicOr(err, 1);
+          break;
+        }
+      }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      const int slot = pg - recs[g].plo;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sv[k] += recs[g].val[slot][k];
+    }
+    for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sv[k] += __shfl_xor(sv[k], o, 64);
+    if (threadIdx.x == 0)
+#pragma unroll
+      for (int k = 0; k < 3; ++k) out[k] = sv[k];
+  }
   __syncthreads();
 }
 
@@ -1639,7 +1673,9 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   __shared__ double tot[16][3];
   __shared__ double gam[16], gam_old[16], alp_old[16], bbl[16], alp[16], bet[16];
   __shared__ unsigned char ldone[16];
-  __shared__ int s_glo, s_ghi, s_more;
+  __shared__ int s_glo, s_ghi, s_more, s_single;
+  __shared__ int e_nb[PCG_OFF_CACHE], e_q[PCG_OFF_CACHE];
+  __shared__ HT e_pi[PCG_OFF_CACHE][144];
   __shared__ PcgCache<HT> cache;
   const int ngroups = (S.B + 15) / 16;
   const int gr = blockIdx.x;
@@ -1667,6 +1703,17 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   if (!cached) __syncthreads();
   const int e0 = S.row_ptr[g0], e_end = S.row_ptr[gend];
   const int e_lo = real ? S.row_ptr[b] : 0, e_hi = real ? S.row_ptr[b + 1] : 0;
+  /* the neighbours of the first block-row entries: body, problem, inverse */
+  const int n_ec = min(e_end - e0, PCG_OFF_CACHE);
+  for (int i = threadIdx.x; i < n_ec; i += blockDim.x) {
+    const int nb = S.col_body[e0 + i];
+    e_nb[i] = nb;
+    e_q[i] = S.bprob[nb] - plo;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n_ec * 144; i += blockDim.x)
+    e_pi[i / 144][i % 144] = Pi[144 * e_nb[i / 144] + i % 144];
+  __syncthreads();
   auto hrow = [&](int c) -> HT {
     return cached ? cache.hd[c * 192 + threadIdx.x] : Hd[144 * b + 12 * row + c];
   };
@@ -1715,15 +1762,18 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   };
   auto range = [&]() {
     if (threadIdx.x == 0) {
-      int lo = -1, hi = -2;
+      int lo = -1, hi = -2, n = 0, one = -1;
       for (int q = 0; q < nloc; ++q)
         if (!ldone[q]) {
           if (lo < 0) lo = S.prob_b0[plo + q] / 16;
           hi = S.prob_b1[plo + q] / 16;
+          ++n;
+          one = q;
         }
       s_glo = lo;
       s_ghi = hi;
       s_more = lo >= 0;
+      s_single = n == 1 ? one : -1;
     }
     __syncthreads();
   };
@@ -1754,9 +1804,9 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
       const int c1 = min(e_end, c0 + PCG_NB_MAX);
       /* r of each entry's neighbour (alpha, beta of that body's problem) */
       for (int t = threadIdx.x; t < 12 * (c1 - c0); t += blockDim.x) {
-        const int le = t / 12, c = t % 12, e = c0 + le;
-        const int nb = S.col_body[e];
-        const int q = S.bprob[nb] - plo;
+        const int le = t / 12, c = t % 12, e = c0 + le, lc = e - e0;
+        const int nb = lc < n_ec ? e_nb[lc] : S.col_body[e];
+        const int q = lc < n_ec ? e_q[lc] : S.bprob[nb] - plo;
         double v = 0.0;
         if (q >= 0 && q < nloc && !ldone[q]) {
           const int on = 12 * nb + c;
@@ -1767,10 +1817,9 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
       }
       __syncthreads();
       for (int t = threadIdx.x; t < 12 * (c1 - c0); t += blockDim.x) {
-        const int le = t / 12, rw = t % 12, e = c0 + le;
-        const int nb = S.col_body[e];
+        const int le = t / 12, rw = t % 12, e = c0 + le, lc = e - e0;
         HT uu = 0;
-        const HT* P = Pi + 144 * nb + 12 * rw;
+        const HT* P = lc < n_ec ? &e_pi[lc][12 * rw] : Pi + 144 * S.col_body[e] + 12 * rw;
         for (int c = 0; c < 12; ++c) uu += P[c] * (HT)rnb[le][c];
         unb[le][rw] = (double)uu;
       }
@@ -1795,9 +1844,14 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     const double v[3] = {act ? rr * ur : 0.0, act ? wr * ur : 0.0, act ? rr * rr : 0.0};
     reduce(3, v);
     PcgRec* recs = (ph & 1) ? rec1 : rec0;
-    pcg_publish<HT>(recs + gr, ph, nloc, part);
-    pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err);
-    totals(recs);
+    pcg_publish<HT>(recs + gr, ph, nloc, part, plo);
+    if (s_single >= 0) {
+      /* one running problem: wait and sum in one pass over the records */
+      pcg_wait_sum(recs, s_glo, s_ghi, ph, plo + s_single, &S.cnt->err, tot[s_single]);
+    } else {
+      pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err);
+      totals(recs);
+    }
     return ur;
   };
   range();
