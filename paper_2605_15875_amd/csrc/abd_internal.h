@@ -491,6 +491,29 @@ template <> struct JacobiTol<float> {
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 
+/* Rotation parameters of one Jacobi step without the IEEE division and
+ * square-root sequences: hardware reciprocal and reciprocal square root,
+ * each refined by Newton steps (each step squares the relative error, so
+ * two take the ~1e-8 seeds to full double precision).  The rotation only
+ * needs c^2 + s^2 = 1 and t to double precision, not correct rounding. */
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __fma_rn(-x, r, 1.0);
+  r = __fma_rn(r, e, r);
+  e = __fma_rn(-x, r, 1.0);
+  return __fma_rn(r, e, r);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  for (int k = 0; k < 2; ++k) {
+    const double h = 0.5 * x * y;
+    y = __fma_rn(-h, y * y, 1.5 * y) ;
+  }
+  return y;
+}
+__device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq_nr(float x) { return __builtin_amdgcn_rsqf(x); }
+
 template <typename T>
 __device__ __forceinline__ void psd9_reg(T* K) {
   T V[81];
@@ -520,9 +543,10 @@ __device__ __forceinline__ void psd9_reg(T* K) {
           /* tan of the rotation angle, t = sgn(a) b / (|a| + hypot(a, b))
            * with a = aqq - app, b = 2 apq (the smaller root) */
           const T aa = aqq - app, bb = T(2) * apq;
-          T t = bb / (fabs(aa) + sqrt(aa * aa + bb * bb));
+          const T h2 = aa * aa + bb * bb;
+          T t = bb * rcp_nr(fabs(aa) + h2 * rsq_nr(h2));
           t = aa < T(0) ? -t : t;
-          const T c = rsq(t * t + T(1));
+          const T c = rsq_nr(t * t + T(1));
           const T s = t * c;
 #pragma unroll
           for (int r = 0; r < 9; ++r) {

@@ -848,10 +848,13 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
 #pragma unroll
         for (int i = 0; i < 45; ++i) K[i] = (HT)Kd[i];
         psd9_reg<HT>(K);
+        HT ig[9];
+#pragma unroll
+        for (int p = 0; p < 9; ++p) ig[p] = (HT)(1.0 / Gs[p]);
 #pragma unroll
         for (int p = 0; p < 9; ++p)
 #pragma unroll
-          for (int q = p; q < 9; ++q) K[sidx(p, q)] /= (HT)(Gs[p] * Gs[q]);
+          for (int q = p; q < 9; ++q) K[sidx(p, q)] *= ig[p] * ig[q];
         /* W_side[r][k] = sum over the side's slots s of f_r[s] xhat_s[k] */
         const int sideB0 = kind == C_PT ? 1 : 2;
         ba = S.vbody[vid[0]];
