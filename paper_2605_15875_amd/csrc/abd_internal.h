@@ -38,6 +38,10 @@ struct Counters {
   int n_rows_used;
   int active; /* problems not done after a pass of the device loop */
   double pcg_rr, pcg_bb;
+  /* swept block: the pass's lists are complete (no overflow in either
+   * phase), so the next pass may take them as its static lists.  Static
+   * block: this pass took them (the static broad phase is skipped). */
+  int sweep_ok, reuse;
 };
 
 /* per-problem state of the device-driven Newton loop; a plain context is
@@ -789,6 +793,8 @@ void launch_update_multi(const Scene& S, hipStream_t st);
 void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st);
 void launch_reset_pcg(const Scene& S, hipStream_t st);
 void launch_reset_toi(const Scene& S, hipStream_t st);
+void launch_publish_counters(const Scene& S, Counters* ring, unsigned* pass,
+                             hipStream_t st);
 /* consensus over the replicas of shared bodies in a batch scene */
 struct Cons {
   int n_rep, n_groups;

@@ -209,6 +209,7 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S) {
 /* world boxes of every chunk and body (static: at q; swept: over the
  * step q -> q + dq) */
 __global__ void k_boxes(Scene S, int swept) {
+  if (S.cnt->reuse) return;
   int t = blockIdx.x * blockDim.x + threadIdx.x;
   int b;
   const double* rest;
@@ -262,7 +263,7 @@ __device__ __forceinline__ int wave_slot(bool pred, int* counter) {
 
 /* body pairs (a < b, not both static) whose boxes pass the predicate */
 __global__ void k_body_pairs(Scene S) {
-  if ((int)(blockIdx.x * 16 + 15) <= (int)(blockIdx.y * 16)) return;
+  if ((int)(blockIdx.x * 16 + 15) <= (int)(blockIdx.y * 16) || S.cnt->reuse) return;
   const int a = blockIdx.y * 16 + threadIdx.y;
   const int b = blockIdx.x * 16 + threadIdx.x;
   bool ok = a < S.B && b < S.B && a < b;
@@ -310,6 +311,7 @@ __device__ __forceinline__ void chunk_pair_of(const int* ca, const int* cb, int 
 }
 
 __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
+  if (S.cnt->reuse) return;
   const int nbp = min(S.cnt->n_bp, S.cap_bp);
   const int lane = threadIdx.x & 63;
   for (int p = blockIdx.x; p < nbp; p += gridDim.x) {
@@ -406,6 +408,7 @@ __device__ __forceinline__ void prim_box(const Scene& S, int kind, int id,
 __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
   __shared__ double qbox[4][ABD_CHUNK][6];
   __shared__ int qid[4][ABD_CHUNK];
+  if (S.cnt->reuse) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int ncp = min(S.cnt->n_cp, S.cap_cp);
   /* every wavefront works through its own chunk pairs */
@@ -475,6 +478,7 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
 /* vertex-ground candidates: vertex chunks of dynamic bodies whose box
  * reaches the ground band, then each vertex exactly */
 __global__ void k_pg(Scene S, int swept) {
+  if (S.cnt->reuse) return;
   const double top = __dadd_rn(S.ground_y, S.dhat);
   const int lane = threadIdx.x % 64;
   const int nw = gridDim.x * (blockDim.x / 64);
@@ -542,13 +546,17 @@ __global__ void k_filter(Scene S) {
       i = c[0]; j = c[1]; slot = c[2];
       int vid[4];
       pair_vertices(S, kind, i, j, vid);
-      double x[12];
-      for (int k = 0; k < 4; ++k)
-        for (int c = 0; c < 3; ++c) x[3 * k + c] = S.xw[c * S.V + vid[k]];
-      d = pair_dist(kind, x);
+      /* lists taken over from the swept phase also hold pairs of problems
+       * that are not in this pass */
+      if (body_in_pass(S, S.vbody[vid[0]])) {
+        double x[12];
+        for (int k = 0; k < 4; ++k)
+          for (int c = 0; c < 3; ++c) x[3 * k + c] = S.xw[c * S.V + vid[k]];
+        d = pair_dist(kind, x);
+      }
     } else if (t < tot) {
       i = S.cand_pg[t - npt - nee];
-      d = S.xw[S.V + i] - S.ground_y;
+      if (body_in_pass(S, S.vbody[i])) d = S.xw[S.V + i] - S.ground_y;
     }
     dmin = fmin(dmin, fmax(d, 0.0));
     const bool ok = t < tot && d < S.dhat;
@@ -2563,7 +2571,24 @@ __global__ void k_reset_pcg(Scene S) {
  * block-row counts of the PCG system */
 __global__ void k_reset_iter(Scene S, Counters fresh) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t < 2) S.cnt[t] = fresh;
+  if (t == 0) {
+    /* The previous pass's swept lists cover every position q + alpha dq,
+     * alpha in [0, 1], of the bodies it swept: every static candidate of
+     * the accepted (or unchanged) state is among them, so they serve as
+     * this pass's static lists. */
+    const Counters c1 = S.cnt[1];
+    Counters c0 = fresh;
+    if (c1.sweep_ok) {
+      c0.n_bp = c1.n_bp;
+      c0.n_cp = c1.n_cp;
+      c0.n_pt = c1.n_pt;
+      c0.n_ee = c1.n_ee;
+      c0.n_pg = c1.n_pg;
+      c0.reuse = 1;
+    }
+    S.cnt[0] = c0;
+    S.cnt[1] = fresh;
+  }
   if (t < S.NP) {
     ProbState& P = S.ps[t];
     P.max_dq = 0;
@@ -2577,6 +2602,25 @@ __global__ void k_reset_iter(Scene S, Counters fresh) {
   for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
   for (int i = t; i < 2 * ((S.B + 15) / 16); i += gridDim.x * blockDim.x)
     S.pcg_rec[i].gen = 0ull;
+}
+
+/* end of a pass: both counter blocks into the host ring slot of this pass
+ * (slot = pass number mod 2, the pass number kept on the device) */
+__global__ void k_publish_counters(Scene S, Counters* ring, unsigned* pass) {
+  if (threadIdx.x == 0) {
+    const Counters& c0 = S.cnt[0];
+    Counters& c1 = S.cnt[1];
+    c1.sweep_ok = (!static_overflow(c0, S) && !c0.err && !swept_overflow(c1, S) &&
+                   !c1.err) ? 1 : 0;
+  }
+  __syncthreads();
+  const unsigned slot = *pass & 1u;
+  const int n = (int)(2 * sizeof(Counters) / sizeof(unsigned));
+  const unsigned* src = (const unsigned*)S.cnt;
+  unsigned* dst = (unsigned*)(ring + 2 * slot);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) *pass += 1u;
 }
 
 /* ================================================================== */
@@ -2880,6 +2924,10 @@ void launch_cons_merge_dq(const Scene& S, const Cons& C, hipStream_t st) {
                      0, st, S);
   hipLaunchKernelGGL(k_cons_dq, dim3(cdiv(12L * C.n_rep, 256)), dim3(256), 0, st,
                      S, C);
+}
+void launch_publish_counters(const Scene& S, Counters* ring, unsigned* pass,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(k_publish_counters, dim3(1), dim3(64), 0, st, S, ring, pass);
 }
 void launch_reset_toi(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_toi, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);

@@ -76,6 +76,8 @@ struct abd_ctx {
   Scene S;
   Counters* h_cnt = nullptr; /* pinned */
   Counters* h_ring = nullptr; /* pinned [2][2]: counters of passes in flight */
+  Counters* d_ring = nullptr; /* the same memory as the device sees it */
+  unsigned* d_pass = nullptr; /* device pass counter (ring slot parity) */
   double* q_start = nullptr;  /* iterate at solve entry (mixed fallback) */
   hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
@@ -660,6 +662,7 @@ void pass_post(abd_ctx* ctx) {
   }
   launch_ctrl(S1, 3, ctx->st);
   launch_update_multi(S1, ctx->st);
+  launch_publish_counters(S1, ctx->d_ring, ctx->d_pass, ctx->st);
 }
 
 /* capture one half of a pass into an executable graph */
@@ -734,12 +737,13 @@ int device_solve(abd_ctx* ctx) {
   const int max_pass =
       ctx->P.max_newton * (2 + (ctx->P.max_ls + LS_TRIALS) / LS_TRIALS) + 8;
   int queued = 0;
+  /* the pass counter picks each pass's ring slot on the device */
+  HIPCHK(hipMemsetAsync(ctx->d_pass, 0, sizeof(unsigned), ctx->st));
+  /* the first pass runs the full static broad phase */
+  HIPCHK(hipMemsetAsync(&ctx->S.cnt[1].sweep_ok, 0, sizeof(int), ctx->st));
   auto enqueue = [&]() -> int {
-    int rc = run_pass(ctx);
+    int rc = run_pass(ctx); /* ends by writing its counters to the ring */
     if (rc) return rc;
-    Counters* slot = ctx->h_ring + 2 * (queued & 1);
-    HIPCHK(hipMemcpyAsync(slot, ctx->S.cnt, 2 * sizeof(Counters),
-                          hipMemcpyDeviceToHost, ctx->st));
     HIPCHK(hipEventRecord(ctx->ring_ev[queued & 1], ctx->st));
     queued += 1;
     return ABD_OK;
@@ -764,6 +768,8 @@ int device_solve(abd_ctx* ctx) {
       bool ch0 = false, ch1 = false;
       if ((rc = grow(ctx, ctx->h_cnt[0], &ch0))) return rc;
       if ((rc = grow(ctx, ctx->h_cnt[1], &ch1))) return rc;
+      /* grown lists hold nothing to take over */
+      HIPCHK(hipMemsetAsync(&ctx->S.cnt[1].sweep_ok, 0, sizeof(int), ctx->st));
       k = queued;
       continue;
     }
@@ -1107,6 +1113,7 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.Ap, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.pw, 5 * 12L * B))) return rc;
+  if ((rc = dalloc(ctx, &ctx->d_pass, 1))) return rc;
   if ((rc = dalloc(ctx, &ctx->q_start, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.pcg_rec, 2L * ((B + 15) / 16)))) return rc;
   HIPCHK(hipMemset(S.pcg_rec, 0, sizeof(PcgRec) * 2 * ((B + 15) / 16)));
@@ -1142,6 +1149,7 @@ int abd_finalize(abd_ctx* ctx) {
   }
   if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_ring, 4 * sizeof(Counters)) != hipSuccess ||
+      hipHostGetDevicePointer((void**)&ctx->d_ring, ctx->h_ring, 0) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ring_ev[0], hipEventDisableTiming) != hipSuccess ||
       hipEventCreateWithFlags(&ctx->ring_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
