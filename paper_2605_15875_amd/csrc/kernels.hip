@@ -277,6 +277,14 @@ __global__ void k_body_pairs(Scene S) {
 
 /* chunk pairs of every body pair: vertex chunks x triangle chunks (both
  * directions) and edge chunks x edge chunks */
+/* Block barrier for LDS traffic only: waits for the wavefront's own LDS
+ * operations, not for its global stores (a full __syncthreads also waits
+ * for every outstanding global store of the wavefront to be acknowledged).
+ * Global data written before it is not ordered for the other wavefronts. */
+__device__ __forceinline__ void lds_barrier() {
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 /* LDS written and then read by the lanes of one wavefront */
 __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -1375,7 +1383,7 @@ __device__ __forceinline__ void pcg_publish(PcgRec* rec, int ph, int nloc,
                        __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ __forceinline__ void pcg_wait(const PcgRec* recs, int glo, int ghi,
-                                         int ph, int* err) {
+                                         int ph, int* err, int* lerr = nullptr) {
   bool polled = false;
   for (int g = glo + (int)threadIdx.x; g <= ghi; g += blockDim.x) {
     long spins = 0;
@@ -1385,6 +1393,7 @@ __device__ __forceinline__ void pcg_wait(const PcgRec* recs, int glo, int ghi,
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1L << 27)) {
         atomicOr(err, 1);
+        if (lerr) *lerr = 1;
         break;
       }
     }
@@ -1399,7 +1408,7 @@ __device__ __forceinline__ void pcg_wait(const PcgRec* recs, int glo, int ghi,
  * reads, one group per lane) */
 __device__ __forceinline__ void pcg_wait_sum(const PcgRec* recs, int glo, int ghi,
                                              int ph, int pg, int* err,
-                                             double* out) {
+                                             double* out, int* lerr = nullptr) {
   if (threadIdx.x < 64) {
     double sv[3] = {0.0, 0.0, 0.0};
     for (int g = glo + (int)threadIdx.x; g <= ghi; g += 64) {
@@ -1409,13 +1418,22 @@ __device__ __forceinline__ void pcg_wait_sum(const PcgRec* recs, int glo, int gh
         __builtin_amdgcn_s_sleep(1);
         if (++spins > (1L << 27)) {
           atomicOr(err, 1);
+          if (lerr) *lerr = 1;
           break;
         }
       }
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      /* the first slot is read together with the group's first problem,
+       * so a group whose first problem is pg costs one round trip */
       const int slot = pg - recs[g].plo;
+      double v[3];
 #pragma unroll
-      for (int k = 0; k < 3; ++k) sv[k] += recs[g].val[slot][k];
+      for (int k = 0; k < 3; ++k) v[k] = recs[g].val[0][k];
+      if (slot != 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) v[k] = recs[g].val[slot][k];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) sv[k] += v[k];
     }
     for (int o = 32; o > 0; o >>= 1)
 #pragma unroll
@@ -1686,6 +1704,12 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   __shared__ unsigned char ldone[16];
   __shared__ int s_glo, s_ghi, s_more, s_single;
   __shared__ int e_nb[PCG_OFF_CACHE], e_q[PCG_OFF_CACHE];
+  __shared__ unsigned char e_tr[PCG_OFF_CACHE];
+  /* per local problem: its bodies in this group (lo..hi), its groups
+   * (ga..gb), whether this group holds its first body */
+  __shared__ int q_lo[16], q_hi[16], q_ga[16], q_gb[16];
+  __shared__ unsigned char q_first[16];
+  __shared__ int s_err;
   __shared__ HT e_pi[PCG_OFF_CACHE][144];
   __shared__ PcgCache<HT> cache;
   const int ngroups = (S.B + 15) / 16;
@@ -1706,9 +1730,17 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   double* const Rb[2] = {S.pw, S.pw + n12};
   double* const Wb[2] = {S.pw + 2 * n12, S.pw + 3 * n12};
   double* const Sb[2] = {S.pw + 4 * n12, S.zv};
-  if ((int)threadIdx.x < nloc)
-    ldone[threadIdx.x] =
-        (S.iter_mode == 0 || ps[plo + threadIdx.x].state == PS_NEWTON) ? 0 : 1;
+  if ((int)threadIdx.x < nloc) {
+    const int q = threadIdx.x, pg = plo + q;
+    ldone[q] = (S.iter_mode == 0 || ps[pg].state == PS_NEWTON) ? 0 : 1;
+    const int b0 = S.prob_b0[pg], b1 = S.prob_b1[pg];
+    q_lo[q] = max(b0, g0) - g0;
+    q_hi[q] = min(b1, gend - 1) - g0;
+    q_ga[q] = b0 / 16;
+    q_gb[q] = b1 / 16;
+    q_first[q] = b0 >= g0 ? 1 : 0;
+  }
+  if (threadIdx.x == 0) s_err = S.cnt->err;
   __syncthreads();
   const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
   if (!cached) __syncthreads();
@@ -1720,6 +1752,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     const int nb = S.col_body[e0 + i];
     e_nb[i] = nb;
     e_q[i] = S.bprob[nb] - plo;
+    e_tr[i] = (unsigned char)S.col_trans[e0 + i];
   }
   __syncthreads();
   for (int i = threadIdx.x; i < n_ec * 144; i += blockDim.x)
@@ -1733,7 +1766,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   };
   auto reduce = [&](int nv, const double* v) {
     for (int k = 0; k < nv; ++k) vrow[k][threadIdx.x] = v[k];
-    __syncthreads();
+    lds_barrier();
     if (row == 0 && lb < 16) {
       for (int k = 0; k < nv; ++k) {
         double sum = 0.0;
@@ -1741,10 +1774,9 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
         vbody[k][lb] = sum;
       }
     }
-    __syncthreads();
+    lds_barrier();
     if ((int)threadIdx.x < nloc) {
-      const int q = plo + threadIdx.x;
-      const int lo = max(S.prob_b0[q], g0) - g0, hi = min(S.prob_b1[q], gend - 1) - g0;
+      const int lo = q_lo[threadIdx.x], hi = q_hi[threadIdx.x];
       for (int k = 0; k < nv; ++k) {
         double sum = 0.0;
         for (int c = lo; c <= hi; ++c) sum += vbody[k][c];
@@ -1756,11 +1788,11 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     for (int q = 0; q < nloc; ++q) {
       if (ldone[q]) continue;
       const int pg = plo + q;
-      const int ga = S.prob_b0[pg] / 16, gb = S.prob_b1[pg] / 16;
+      const int ga = q_ga[q], gb = q_gb[q];
       if (threadIdx.x < 64) {
         double sv[3] = {0.0, 0.0, 0.0};
         for (int g = ga + (int)threadIdx.x; g <= gb; g += 64) {
-          const int slot = pg - S.bprob[16 * g];
+          const int slot = pg - recs[g].plo;
           for (int k = 0; k < 3; ++k) sv[k] += recs[g].val[slot][k];
         }
         for (int o = 32; o > 0; o >>= 1)
@@ -1769,15 +1801,15 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
           for (int k = 0; k < 3; ++k) tot[q][k] = sv[k];
       }
     }
-    __syncthreads();
+    lds_barrier();
   };
   auto range = [&]() {
     if (threadIdx.x == 0) {
       int lo = -1, hi = -2, n = 0, one = -1;
       for (int q = 0; q < nloc; ++q)
         if (!ldone[q]) {
-          if (lo < 0) lo = S.prob_b0[plo + q] / 16;
-          hi = S.prob_b1[plo + q] / 16;
+          if (lo < 0) lo = q_ga[q];
+          hi = q_gb[q];
           ++n;
           one = q;
         }
@@ -1786,7 +1818,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
       s_more = lo >= 0;
       s_single = n == 1 ? one : -1;
     }
-    __syncthreads();
+    lds_barrier();
   };
   /* one phase: from the own new residual rn (registers) and the
    * neighbours' published vectors, u = P^-1 r for the own body and its
@@ -1796,9 +1828,16 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   auto phase = [&](int ph, bool init) {
     const int cur = (ph - 1) & 1, nxt = ph & 1; /* buffers read / written */
     const bool act = real && !ldone[j];
+    /* r and the previous s go out first: their stores complete while the
+     * block works on, and only the barrier before the publication waits
+     * for them */
+    if (act) {
+      Rb[nxt][o] = rr;
+      Sb[(ph + 1) & 1][o] = sr; /* s of the previous iteration, read next phase */
+    }
     /* own body: u = P^-1 r */
     rloc[lb][row] = act ? rr : 0.0;
-    __syncthreads();
+    lds_barrier();
     double ur = 0.0;
     if (act) {
       HT uu = 0;
@@ -1807,7 +1846,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     }
     uloc[lb][row] = ur;
     HT y = 0;
-    __syncthreads();
+    lds_barrier();
     if (act)
       for (int c = 0; c < 12; ++c) y += hrow(c) * (HT)uloc[lb][c];
     /* neighbours, in chunks of PCG_NB_MAX block-row entries of the group */
@@ -1826,7 +1865,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
         }
         rnb[le][c] = v;
       }
-      __syncthreads();
+      lds_barrier();
       for (int t = threadIdx.x; t < 12 * (c1 - c0); t += blockDim.x) {
         const int le = t / 12, rw = t % 12, e = c0 + le, lc = e - e0;
         HT uu = 0;
@@ -1834,33 +1873,30 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
         for (int c = 0; c < 12; ++c) uu += P[c] * (HT)rnb[le][c];
         unb[le][rw] = (double)uu;
       }
-      __syncthreads();
+      lds_barrier();
       if (act)
         for (int e = max(e_lo, c0); e < min(e_hi, c1); ++e) {
           const int le = e - c0, lc = e - e0;
           const HT* blk = (cached && lc < cache.n_off) ? cache.off[lc]
                                                       : Ho + 144 * (size_t)S.col_slot[e];
-          const int tr = S.col_trans[e];
+          const int tr = lc < n_ec ? e_tr[lc] : S.col_trans[e];
           const int st = tr ? 12 : 1, sc = tr ? 1 : 12;
           for (int c = 0; c < 12; ++c) y += blk[sc * row + st * c] * (HT)unb[le][c];
         }
-      __syncthreads();
+      lds_barrier();
     }
     wr = (double)y;
-    if (act) {
-      Rb[nxt][o] = rr;
-      Wb[nxt][o] = wr;
-      Sb[(ph + 1) & 1][o] = sr; /* s of the previous iteration, read next phase */
-    }
+    if (act) Wb[nxt][o] = wr;
     const double v[3] = {act ? rr * ur : 0.0, act ? wr * ur : 0.0, act ? rr * rr : 0.0};
     reduce(3, v);
     PcgRec* recs = (ph & 1) ? rec1 : rec0;
     pcg_publish<HT>(recs + gr, ph, nloc, part, plo);
     if (s_single >= 0) {
       /* one running problem: wait and sum in one pass over the records */
-      pcg_wait_sum(recs, s_glo, s_ghi, ph, plo + s_single, &S.cnt->err, tot[s_single]);
+      pcg_wait_sum(recs, s_glo, s_ghi, ph, plo + s_single, &S.cnt->err, tot[s_single],
+                   &s_err);
     } else {
-      pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err);
+      pcg_wait(recs, s_glo, s_ghi, ph, &S.cnt->err, &s_err);
       totals(recs);
     }
     return ur;
@@ -1874,7 +1910,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     const int q = threadIdx.x, pg = plo + q;
     gam[q] = tot[q][0];
     bbl[q] = tot[q][2];
-    const bool first = S.prob_b0[pg] >= g0;
+    const bool first = q_first[q];
     if (first) ps[pg].bb = bbl[q];
     if (!(bbl[q] > 0.0)) {
       ldone[q] = 1;
@@ -1884,11 +1920,11 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
       bet[q] = 0.0;
     }
   }
-  __syncthreads();
+  lds_barrier();
   int it = 0;
   for (it = 0; it < max_it; ++it) {
     range();
-    if (!s_more || S.cnt->err) break;
+    if (!s_more || s_err) break;
     const bool act = real && !ldone[j];
     if (act) {
       const double a = alp[j], be = bet[j];
@@ -1903,7 +1939,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
       const int q = threadIdx.x, pg = plo + q;
       if (tot[q][2] <= eta * eta * bbl[q]) {
         ldone[q] = 1;
-        if (S.prob_b0[pg] >= g0) ps[pg].pcg_iters = it + 1;
+        if (q_first[q]) ps[pg].pcg_iters = it + 1;
       } else {
         gam_old[q] = gam[q];
         alp_old[q] = alp[q];
@@ -1913,9 +1949,9 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
         alp[q] = gam[q] / (tot[q][1] - be * gam[q] / alp_old[q]);
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
-  if ((int)threadIdx.x < nloc && !ldone[threadIdx.x] && S.prob_b0[plo + threadIdx.x] >= g0)
+  if ((int)threadIdx.x < nloc && !ldone[threadIdx.x] && q_first[threadIdx.x])
     ps[plo + threadIdx.x].pcg_iters = it;
   if (real && !(S.iter_mode != 0 && ps[p].state != PS_NEWTON)) S.dq[o] = xr;
   if (threadIdx.x == 0) atomicMax(&S.cnt->pcg_iters, it);
