@@ -518,73 +518,6 @@ __device__ __forceinline__ double rsq_nr(double x) {
 __device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rsq_nr(float x) { return __builtin_amdgcn_rsqf(x); }
 
-template <typename T>
-__device__ __forceinline__ void psd9_reg(T* K) {
-  T V[81];
-#pragma unroll
-  for (int i = 0; i < 81; ++i) V[i] = (i / 9 == i % 9) ? T(1) : T(0);
-  const T tol2 = JacobiTol<T>::tol2;
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    T off = 0, dia = 0;
-#pragma unroll
-    for (int p = 0; p < 9; ++p) {
-      dia += K[sidx(p, p)] * K[sidx(p, p)];
-#pragma unroll
-      for (int q = p + 1; q < 9; ++q) off += K[sidx(p, q)] * K[sidx(p, q)];
-    }
-    const T tot = dia + T(2) * off;
-    if (off == T(0) || off <= tol2 * tot) break;
-    /* rotations with apq^2 below tol2/36 of the total are skipped: if all
-     * 36 are, the off-diagonal mass is already under the stopping bound */
-    const T skip2 = tol2 * T(1.0 / 36.0) * tot;
-#pragma unroll
-    for (int p = 0; p < 8; ++p)
-#pragma unroll
-      for (int q = p + 1; q < 9; ++q) {
-        const T apq = K[sidx(p, q)];
-        if (apq * apq > skip2) {
-          const T app = K[sidx(p, p)], aqq = K[sidx(q, q)];
-          /* tan of the rotation angle, t = sgn(a) b / (|a| + hypot(a, b))
-           * with a = aqq - app, b = 2 apq (the smaller root) */
-          const T aa = aqq - app, bb = T(2) * apq;
-          const T h2 = aa * aa + bb * bb;
-          T t = bb * rcp_nr(fabs(aa) + h2 * rsq_nr(h2));
-          t = aa < T(0) ? -t : t;
-          const T c = rsq_nr(t * t + T(1));
-          const T s = t * c;
-#pragma unroll
-          for (int r = 0; r < 9; ++r) {
-            if (r == p || r == q) continue;
-            const T krp = K[sidx(r, p)], krq = K[sidx(r, q)];
-            K[sidx(r, p)] = c * krp - s * krq;
-            K[sidx(r, q)] = s * krp + c * krq;
-          }
-          K[sidx(p, p)] = app - t * apq;
-          K[sidx(q, q)] = aqq + t * apq;
-          K[sidx(p, q)] = T(0);
-#pragma unroll
-          for (int r = 0; r < 9; ++r) {
-            const T vrp = V[9 * r + p], vrq = V[9 * r + q];
-            V[9 * r + p] = c * vrp - s * vrq;
-            V[9 * r + q] = s * vrp + c * vrq;
-          }
-        }
-      }
-  }
-  T lam[9];
-#pragma unroll
-  for (int k = 0; k < 9; ++k) lam[k] = fmax(K[sidx(k, k)], T(0));
-#pragma unroll
-  for (int p = 0; p < 9; ++p)
-#pragma unroll
-    for (int q = p; q < 9; ++q) {
-      T v = 0;
-#pragma unroll
-      for (int k = 0; k < 9; ++k) v += V[9 * p + k] * lam[k] * V[9 * q + k];
-      K[sidx(p, q)] = v;
-    }
-}
-
 /* ------------------------------------------------------------------ */
 /* PSD projection of the orthogonality Hessian in closed form           */
 /* ------------------------------------------------------------------ */

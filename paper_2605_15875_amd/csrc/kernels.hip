@@ -813,12 +813,159 @@ __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int 
  * T = H_y W_Y, then the body-space gradient and 12x12 blocks W_X^T T,
  * accumulated with FP64 atomics into g, Hdiag and Hoff. */
 #define PAIRS_PER_WG 16
+/* PSD projection of a symmetric 9x9 matrix by cyclic Jacobi with the
+ * rotations of a sweep run in parallel: one matrix per group of 16 lanes,
+ * lane r (< 9) holding row r of the matrix and row r of the accumulated
+ * rotation V.  A sweep has nine rounds; round k pairs index a with
+ * (2k - a) mod 9 (the round-robin order, index k rests), so each round's
+ * four rotations touch disjoint rows and columns and commute, and every
+ * pair is visited once per sweep.  Each rotation is the serial step: the
+ * tangent t = sgn(a) b / (|a| + hypot(a, b)) with a = aqq - app, b = 2 apq,
+ * c = 1 / sqrt(1 + t^2), s = t c, columns then rows, and the annihilated
+ * 2x2 block set to (app - t apq, aqq + t apq, 0).  The lane of the lower
+ * index of a pair computes its rotation and shares it through LDS.
+ * Rotations whose apq^2 is below 1/36 of the stopping bound are skipped; a
+ * sweep starts only while the mass of the upper triangle (rounding leaves
+ * the two triangles slightly different) exceeds tol2 of the total.  The
+ * result, V max(D,0) V^T, replaces row r in place. */
+template <typename T>
+struct JacX {
+  T row[9][10]; /* rows of the matrix (of V at the end, max(D,0) in col 9) */
+  T cs[9][6];   /* rotation of the pair led by each index: c s t app aqq apq */
+};
+template <typename T>
+__device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
+  constexpr T tol2 = JacobiTol<T>::tol2;
+  T v[9];
+#pragma unroll
+  for (int m = 0; m < 9; ++m) v[m] = (m == r) ? T(1) : T(0);
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    T fro = 0, offs = 0;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      const T x = on ? k[m] : T(0);
+      fro += x * x;
+      offs += (m > r) ? x * x : T(0);
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+      fro += __shfl_xor(fro, o, 16);
+      offs += __shfl_xor(offs, o, 16);
+    }
+    /* a sweep that skips all 36 rotations leaves the upper triangle under
+     * the bound */
+    const bool done = !on || offs == T(0) || offs <= tol2 * fro;
+    if (__all(done)) break;
+    const T skip2 = tol2 * T(1.0 / 36.0) * fro;
+#pragma unroll
+    for (int kr = 0; kr < 9; ++kr) {
+      const int pr = (2 * kr + 18 - r) % 9; /* partner of row r */
+      if (on) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) X.row[r][m] = k[m];
+      }
+      wave_lds_sync();
+      /* the pair's leading lane: its rotation */
+      if (on && r < pr) {
+        const T app = X.row[r][r], aqq = X.row[pr][pr], apq = X.row[r][pr];
+        T c = T(1), sn = T(0), t = T(0);
+        if (apq * apq > skip2) {
+          const T aa = aqq - app, bb = T(2) * apq;
+          const T h2 = aa * aa + bb * bb;
+          t = bb * rcp_nr(fabs(aa) + h2 * rsq_nr(h2));
+          t = aa < T(0) ? -t : t;
+          c = rsq_nr(t * t + T(1));
+          sn = t * c;
+        }
+        X.cs[r][0] = c; X.cs[r][1] = sn; X.cs[r][2] = t;
+        X.cs[r][3] = app; X.cs[r][4] = aqq; X.cs[r][5] = apq;
+      }
+      wave_lds_sync();
+      T c4[4], s4[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int a = (kr + i + 1) % 9, b = (kr + 8 - i) % 9;
+        const int p = a < b ? a : b;
+        c4[i] = X.cs[p][0];
+        s4[i] = X.cs[p][1];
+      }
+      /* columns: K J and V J (local to the row) */
+      T k1[9], v1[9];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) {
+        const int pm = (2 * kr + 9 - m) % 9;
+        if (pm == m) {
+          k1[m] = k[m];
+          v1[m] = v[m];
+          continue;
+        }
+        /* the pair of column m: m = kr +- (i + 1) mod 9 */
+        const int d = (m + 9 - kr) % 9;
+        const int i = (d <= 4 ? d : 9 - d) - 1;
+        const T sg = m < pm ? -s4[i] : s4[i];
+        k1[m] = c4[i] * k[m] + sg * k[pm];
+        v1[m] = c4[i] * v[m] + sg * v[pm];
+      }
+#pragma unroll
+      for (int m = 0; m < 9; ++m) v[m] = v1[m];
+      if (on) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) X.row[r][m] = k1[m];
+      }
+      wave_lds_sync();
+      /* rows: J^T (K J), with the partner row from LDS */
+      const int lead = r < pr ? r : pr;
+      const T c = X.cs[lead][0], sn = X.cs[lead][1];
+      if (on && pr != r && sn != T(0)) {
+        const T t = X.cs[lead][2], app = X.cs[lead][3], aqq = X.cs[lead][4],
+                apq = X.cs[lead][5];
+        const T sg = r < pr ? -sn : sn;
+#pragma unroll
+        for (int m = 0; m < 9; ++m) k[m] = c * k1[m] + sg * X.row[pr][m];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          if (m == r) k[m] = r < pr ? app - t * apq : aqq + t * apq;
+          if (m == pr) k[m] = T(0);
+        }
+      } else {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) k[m] = k1[m];
+      }
+      wave_lds_sync();
+    }
+  }
+  /* V max(D, 0) V^T, row r */
+  if (on) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) X.row[r][m] = v[m];
+    T lam = T(0);
+#pragma unroll
+    for (int m = 0; m < 9; ++m)
+      if (m == r) lam = k[m];
+    X.row[r][9] = fmax(lam, T(0));
+  }
+  wave_lds_sync();
+  if (on) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) {
+      T acc = 0;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) acc += v[j] * X.row[j][9] * X.row[m][j];
+      k[m] = acc;
+    }
+  }
+  wave_lds_sync();
+}
+
 template <typename HT>
 __global__ __launch_bounds__(64) void k_assemble(Scene S) {
   __shared__ HT KL[45 * 64];
   __shared__ double GW[33 * 64]; /* rows 0..8 g_y, 9..20 W_A, 21..32 W_B */
   __shared__ HT TB[216];
   __shared__ int meta[3 * 64];
+  __shared__ JacX<HT> JX[4];         /* Jacobi exchange, one per lane group */
+  __shared__ HT IG[9 * 64];         /* inverse frame scales of each pair */
+  __shared__ unsigned char proj[64]; /* the pair's 9x9 needs the projection */
   const int lane = threadIdx.x;
   const int nact = min(S.cnt->n_act, S.cap_act);
   /* pairs per workgroup: as few as the grid allows (each pair's projection
@@ -828,6 +975,7 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
   for (int base = blockIdx.x * ppw; base < nact; base += gridDim.x * ppw) {
     const int t = base + lane;
     int ba = -1, bb = -1, slot = -1;
+    proj[lane] = 0;
     if (lane < ppw && t < nact) {
       const int4 a = S.act[t];
       const int kind = a.x;
@@ -863,14 +1011,11 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
         pair_frame_derivs(S, kind, a.y, a.z, x, w, gy, Kd, Gs);
 #pragma unroll
         for (int i = 0; i < 45; ++i) K[i] = (HT)Kd[i];
-        psd9_reg<HT>(K);
-        HT ig[9];
+        /* projected (and scaled back by the inverse frame scales) below,
+         * by the lane groups of the workgroup */
 #pragma unroll
-        for (int p = 0; p < 9; ++p) ig[p] = (HT)(1.0 / Gs[p]);
-#pragma unroll
-        for (int p = 0; p < 9; ++p)
-#pragma unroll
-          for (int q = p; q < 9; ++q) K[sidx(p, q)] *= ig[p] * ig[q];
+        for (int p = 0; p < 9; ++p) IG[p * 64 + lane] = (HT)(1.0 / Gs[p]);
+        proj[lane] = 1;
         /* W_side[r][k] = sum over the side's slots s of f_r[s] xhat_s[k] */
         const int sideB0 = kind == C_PT ? 1 : 2;
         ba = S.vbody[vid[0]];
@@ -907,6 +1052,23 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
     meta[128 + lane] = slot;
     __syncthreads();
     const int npairs = min(ppw, nact - base);
+    /* PSD projection of the PT/EE frame Hessians, four pairs at a time */
+    for (int j0 = 0; j0 < npairs; j0 += 4) {
+      const int j = j0 + lane / 16, r = lane % 16;
+      const bool on = j < npairs && r < 9 && proj[j];
+      HT k[9];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) k[m] = on ? KL[sidx(r, m) * 64 + j] : HT(0);
+      __syncthreads();
+      psd9_par<HT>(JX[lane / 16], r, on, k);
+      if (on) {
+        const HT ir = IG[r * 64 + j];
+#pragma unroll
+        for (int m = 0; m < 9; ++m)
+          if (m >= r) KL[sidx(r, m) * 64 + j] = k[m] * (ir * IG[m * 64 + j]);
+      }
+      __syncthreads();
+    }
     for (int j = 0; j < npairs; ++j) {
       const int A = meta[j], Bq = meta[64 + j], sl = meta[128 + j];
       if (A < 0 && Bq < 0) continue;
