@@ -40,8 +40,14 @@ struct Counters {
   double pcg_rr, pcg_bb;
   /* swept block: the pass's lists are complete (no overflow in either
    * phase), so the next pass may take them as its static lists.  Static
-   * block: this pass took them (the static broad phase is skipped). */
-  int sweep_ok, reuse;
+   * block: this pass took them (the static broad phase is skipped); redo:
+   * a pass launched without the static broad phase found nothing to take
+   * over, so it changes no state (the next pass can take over its swept
+   * lists, which cover the unchanged state). */
+  int sweep_ok, reuse, redo, pad_;
+  /* arrivals of the workgroups of the kernels whose last workgroup runs
+   * the controller or ends the pass */
+  unsigned fin[4];
 };
 
 /* per-problem state of the device-driven Newton loop; a plain context is
@@ -716,18 +722,18 @@ void launch_block_inverse(const Scene& S, hipStream_t st);
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
                int coop, hipStream_t st);
 int pcg_max_grid();
-void launch_dq_norm(const Scene& S, hipStream_t st);
-void launch_ccd(const Scene& S, hipStream_t st);
+void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st);
+void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st);
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st);
 void launch_energy_multi(const Scene& S, hipStream_t st);
-void launch_ctrl(const Scene& S, int which, hipStream_t st);
-void launch_update_multi(const Scene& S, hipStream_t st);
-void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st);
+void launch_ctrl_start(const Scene& S, hipStream_t st);
+void launch_update_multi(const Scene& S, Counters* ring, unsigned* pass,
+                         hipStream_t st);
+void launch_reset_iter(const Scene& S, const Counters& fresh, int expect_reuse,
+                       hipStream_t st);
 void launch_reset_pcg(const Scene& S, hipStream_t st);
 void launch_reset_toi(const Scene& S, hipStream_t st);
-void launch_publish_counters(const Scene& S, Counters* ring, unsigned* pass,
-                             hipStream_t st);
 /* consensus over the replicas of shared bodies in a batch scene */
 struct Cons {
   int n_rep, n_groups;

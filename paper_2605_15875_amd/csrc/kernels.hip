@@ -2339,7 +2339,11 @@ __device__ __forceinline__ bool wave_uniform(int p) {
   return __ballot(p == __shfl(p, 0, 64)) == __ballot(true);
 }
 
-__global__ void k_dq_norm(Scene S) {
+__device__ __forceinline__ void ctrl_newton_check(const Scene& S, ProbState& P,
+                                                  const Counters& c0);
+__device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n);
+/* |dq|_inf per problem; with_ctrl: then the Newton stop test */
+__global__ void k_dq_norm(Scene S, int with_ctrl) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   const bool act = b < S.B;
   const int p = act ? S.bprob[b] : -1;
@@ -2357,16 +2361,24 @@ __global__ void k_dq_norm(Scene S) {
     atomic_max_pos(&S.ps[p].max_dq, v);
     atomic_max_pos(&S.cnt->max_dq, v);
   }
+  if (with_ctrl && last_workgroup(&S.cnt[0].fin[0], gridDim.x))
+    for (int q = threadIdx.x; q < S.NP; q += blockDim.x)
+      ctrl_newton_check(S, S.ps[q], S.cnt[0]);
 }
 
 /* ================================================================== */
 /* S9 CCD                                                              */
 /* ================================================================== */
-__global__ __launch_bounds__(256) void k_ccd(Scene S) {
+__device__ __forceinline__ void ctrl_first_trial(ProbState& P);
+/* with_ctrl: then the first trial step of every problem */
+__global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
   const int tot = npt + nee + npg;
+  /* workgroups with candidates (at least one, to run the controller) */
+  const unsigned nwork = max(1u, min(gridDim.x, (unsigned)((tot + 255) / 256)));
+  if (blockIdx.x >= nwork) return;
   double tmin = 1.0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
        t += gridDim.x * blockDim.x) {
@@ -2404,6 +2416,8 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S) {
    * min(1, .)), which keeps empty waves off the shared counter */
   if ((threadIdx.x & 63) == 0 && tmin < 1.0)
     atomic_min_pos(&S.cnt->min_toi, fmax(tmin, 0.0));
+  if (with_ctrl && last_workgroup(&S.cnt->fin[1], nwork))
+    for (int q = threadIdx.x; q < S.NP; q += blockDim.x) ctrl_first_trial(S.ps[q]);
 }
 
 /* ================================================================== */
@@ -2566,12 +2580,19 @@ __global__ void k_update_q(Scene S, double alpha) {
 /* E(q + alpha_k dq) - E(q) for alpha_k = alpha_base 2^-k, k < LS_TRIALS,
  * per problem, over the bodies and swept candidates of problems that are
  * not done; one atomic per trial per wave when the wave is uniform. */
+__device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n);
+__device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
+                                                const Counters& c0,
+                                                const Counters& c1);
 __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
   const int tot = S.B + npt + nee + npg;
   const int nwaves = (tot + 63) / 64;
+  /* workgroups with elements (at least one, to run the controller) */
+  const unsigned nwork = max(1u, min(gridDim.x, (unsigned)((nwaves + 3) / 4)));
+  if (blockIdx.x >= nwork) return;
   for (int w = blockIdx.x * 4 + threadIdx.x / 64; w < nwaves; w += gridDim.x * 4) {
     const int t = w * 64 + (threadIdx.x & 63);
     double e[LS_TRIALS];
@@ -2637,6 +2658,16 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
       for (int k = 0; k < LS_TRIALS; ++k) atomicAdd(&S.ps[prob].dE[k], e[k]);
     }
   }
+  /* then every problem's line search decision (this scene's counters are
+   * the swept block; the static block precedes it) */
+  if (last_workgroup(&S.cnt->fin[2], nwork)) {
+    const Counters* base = S.cnt - 1;
+    for (int q = threadIdx.x; q < S.NP; q += blockDim.x) {
+      ProbState& P = S.ps[q];
+      ctrl_linesearch(S, P, base[0], base[1]);
+      if (P.state != PS_DONE) atomicAdd(&S.cnt->active, 1);
+    }
+  }
 }
 
 __device__ __forceinline__ bool static_overflow(const Counters& c, const Scene& S) {
@@ -2652,56 +2683,71 @@ __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
                                                 const Counters& c0,
                                                 const Counters& c1);
 
-/* One thread per problem.
- * which 0 (start of a solve): every problem to the Newton state.
- * which 1 (after the PCG): Newton stop |dq|_inf / (h l) < theta.
- * which 2 (after CCD): first trial step alpha_max = min(1, TOI), or the
- *   continuation of a line search.
- * which 3 (after the trial energies): accept the largest trial step with
- *   E(q + alpha dq) - E(q) <= 0, else continue halving or stop. */
-__global__ void k_ctrl(Scene S, int which) {
+/* The controller of the device loop, one problem at a time.  It runs in
+ * the last workgroup of the kernel that produces its input (that
+ * workgroup sees every other one's atomics):
+ *   start of a solve (its own kernel): every problem to the Newton state;
+ *   after the PCG (last workgroup of the |dq| reduction): Newton stop
+ *     |dq|_inf / (h l) < theta;
+ *   after CCD (last workgroup of k_ccd): first trial step
+ *     alpha_max = min(1, TOI), or the continuation of a line search;
+ *   after the trial energies (last workgroup of k_energy_multi): accept the
+ *     largest trial step with E(q + alpha dq) - E(q) <= 0, else continue
+ *     halving or stop. */
+__global__ void k_ctrl_start(Scene S) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= S.NP) return;
   ProbState& P = S.ps[p];
-  const Counters& c0 = S.cnt[0];
-  const Counters& c1 = S.cnt[1];
-  if (which == 0) {
-    P.state = PS_NEWTON;
-    P.status = -4; /* not converged yet */
-    P.newton = P.halvings = P.ls_count = P.pcg_total = 0;
-    P.min_alpha = 1.0;
-    P.final_eps = 0.0;
-    P.alpha_acc = 0.0;
-    return;
+  P.state = PS_NEWTON;
+  P.status = -4; /* not converged yet */
+  P.newton = P.halvings = P.ls_count = P.pcg_total = 0;
+  P.min_alpha = 1.0;
+  P.final_eps = 0.0;
+  P.alpha_acc = 0.0;
+}
+__device__ __forceinline__ void ctrl_newton_check(const Scene& S, ProbState& P,
+                                                  const Counters& c0) {
+  if (P.state != PS_NEWTON || static_overflow(c0, S) || c0.err || c0.redo) return;
+  P.newton += 1;
+  P.pcg_total += P.pcg_iters;
+  const double eps = __longlong_as_double((long long)P.max_dq) / (S.dt * P.scale);
+  P.final_eps = eps;
+  if (!isfinite(eps)) {
+    P.state = PS_DONE;
+    P.status = -4;
+  } else if (eps < S.theta) {
+    P.state = PS_DONE;
+    P.status = 0;
   }
-  if (which == 1) {
-    if (P.state != PS_NEWTON || static_overflow(c0, S) || c0.err) return;
-    P.newton += 1;
-    P.pcg_total += P.pcg_iters;
-    const double eps =
-        __longlong_as_double((long long)P.max_dq) / (S.dt * P.scale);
-    P.final_eps = eps;
-    if (!isfinite(eps)) {
-      P.state = PS_DONE;
-      P.status = -4;
-    } else if (eps < S.theta) {
-      P.state = PS_DONE;
-      P.status = 0;
-    }
-    return;
+}
+__device__ __forceinline__ void ctrl_first_trial(ProbState& P) {
+  if (P.state == PS_NEWTON) {
+    const double toi = __longlong_as_double((long long)P.min_toi);
+    P.alpha_base = fmin(1.0, toi);
+    P.ls_count = 0;
   }
-  if (which == 2) {
-    if (P.state == PS_NEWTON) {
-      const double toi = __longlong_as_double((long long)P.min_toi);
-      P.alpha_base = fmin(1.0, toi);
-      P.ls_count = 0;
-    }
-    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
-    return;
+}
+
+/* whether this workgroup is the last of the grid to arrive at the counter
+ * (which starts the kernel at zero); the last one may read what the others
+ * accumulated with device-scope atomics before arriving.  Only the first n
+ * workgroups of the grid arrive (those with work: the arrivals on one
+ * address are serialised, so idle workgroups leave without one).  The block
+ * barrier waits until every wavefront's atomics have completed, so the
+ * arrival itself needs no release (which would write back the whole L2 in
+ * every workgroup); only the last workgroup acquires. */
+__device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n) {
+  __shared__ int s_last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    s_last = prev + 1 == n ? 1 : 0;
   }
-  /* which == 3 */
-  ctrl_linesearch(S, P, c0, c1);
-  if (P.state != PS_DONE) atomicAdd(&S.cnt[1].active, 1);
+  __syncthreads();
+  if (!s_last) return false;
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return true;
 }
 
 __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
@@ -2709,7 +2755,7 @@ __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
                                                 const Counters& c1) {
   if (P.state == PS_DONE) return;
   const bool fresh = P.state == PS_NEWTON && P.ls_count == 0;
-  if (fresh && (static_overflow(c0, S) || c0.err)) return; /* pass redone */
+  if (fresh && (static_overflow(c0, S) || c0.err || c0.redo)) return; /* pass redone */
   if (swept_overflow(c1, S) || c1.err) {
     if (fresh) P.newton -= 1; /* the Newton iteration is redone */
     return;
@@ -2741,14 +2787,34 @@ __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
   }
 }
 
-/* q += alpha_acc dq for the bodies of problems that accepted a step */
-__global__ void k_update_multi(Scene S) {
+/* q += alpha_acc dq for the bodies of problems that accepted a step; the
+ * last workgroup then ends the pass: whether its lists can be taken over,
+ * and both counter blocks into the host ring slot of this pass (slot =
+ * pass number mod 2, the pass number kept on the device) */
+__global__ void k_update_multi(Scene S, Counters* ring, unsigned* pass) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= 12 * S.B) return;
-  const int b = t / 12;
-  if (S.kind[b] != 0) return;
-  const double a = S.ps[S.bprob[b]].alpha_acc;
-  if (a != 0.0) S.q[t] += a * S.dq[t];
+  if (t < 12 * S.B) {
+    const int b = t / 12;
+    if (S.kind[b] == 0) {
+      const double a = S.ps[S.bprob[b]].alpha_acc;
+      if (a != 0.0) S.q[t] += a * S.dq[t];
+    }
+  }
+  if (!last_workgroup(&S.cnt[0].fin[3], gridDim.x)) return;
+  if (threadIdx.x == 0) {
+    const Counters& c0 = S.cnt[0];
+    Counters& c1 = S.cnt[1];
+    c1.sweep_ok = (!static_overflow(c0, S) && !c0.err && !swept_overflow(c1, S) &&
+                   !c1.err) ? 1 : 0;
+  }
+  __syncthreads();
+  const unsigned slot = *pass & 1u;
+  const int n = (int)(2 * sizeof(Counters) / sizeof(unsigned));
+  const unsigned* src = (const unsigned*)S.cnt;
+  unsigned* dst = (unsigned*)(ring + 2 * slot);
+  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+  __syncthreads();
+  if (threadIdx.x == 0) *pass += 1u;
 }
 
 /* fresh PCG accumulators (the hooks' direct linear solve) */
@@ -2767,7 +2833,7 @@ __global__ void k_reset_pcg(Scene S) {
 
 /* start of a pass: fresh counter blocks, per-problem transients, and the
  * block-row counts of the PCG system */
-__global__ void k_reset_iter(Scene S, Counters fresh) {
+__global__ void k_reset_iter(Scene S, Counters fresh, int expect_reuse) {
   const int t = blockIdx.x * blockDim.x + threadIdx.x;
   if (t == 0) {
     /* The previous pass's swept lists cover every position q + alpha dq,
@@ -2783,6 +2849,8 @@ __global__ void k_reset_iter(Scene S, Counters fresh) {
       c0.n_ee = c1.n_ee;
       c0.n_pg = c1.n_pg;
       c0.reuse = 1;
+    } else if (expect_reuse) {
+      c0.redo = 1;
     }
     S.cnt[0] = c0;
     S.cnt[1] = fresh;
@@ -2800,25 +2868,6 @@ __global__ void k_reset_iter(Scene S, Counters fresh) {
   for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
   for (int i = t; i < 2 * ((S.B + 15) / 16); i += gridDim.x * blockDim.x)
     S.pcg_rec[i].gen = 0ull;
-}
-
-/* end of a pass: both counter blocks into the host ring slot of this pass
- * (slot = pass number mod 2, the pass number kept on the device) */
-__global__ void k_publish_counters(Scene S, Counters* ring, unsigned* pass) {
-  if (threadIdx.x == 0) {
-    const Counters& c0 = S.cnt[0];
-    Counters& c1 = S.cnt[1];
-    c1.sweep_ok = (!static_overflow(c0, S) && !c0.err && !swept_overflow(c1, S) &&
-                   !c1.err) ? 1 : 0;
-  }
-  __syncthreads();
-  const unsigned slot = *pass & 1u;
-  const int n = (int)(2 * sizeof(Counters) / sizeof(unsigned));
-  const unsigned* src = (const unsigned*)S.cnt;
-  unsigned* dst = (unsigned*)(ring + 2 * slot);
-  for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
-  __syncthreads();
-  if (threadIdx.x == 0) *pass += 1u;
 }
 
 /* ================================================================== */
@@ -3080,15 +3129,17 @@ void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st) {
 void launch_energy_multi(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_multi, dim3(512), dim3(256), 0, st, S);
 }
-void launch_ctrl(const Scene& S, int which, hipStream_t st) {
-  hipLaunchKernelGGL(k_ctrl, dim3(cdiv(S.NP, 64)), dim3(64), 0, st, S, which);
+void launch_ctrl_start(const Scene& S, hipStream_t st) {
+  hipLaunchKernelGGL(k_ctrl_start, dim3(cdiv(S.NP, 64)), dim3(64), 0, st, S);
 }
-void launch_update_multi(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_update_multi, dim3(cdiv(12L * S.B, 256)), dim3(256), 0, st, S);
+void launch_update_multi(const Scene& S, Counters* ring, unsigned* pass, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_multi, dim3(cdiv(12L * S.B, 256)), dim3(256), 0, st, S,
+                     ring, pass);
 }
-void launch_reset_iter(const Scene& S, const Counters& fresh, hipStream_t st) {
+void launch_reset_iter(const Scene& S, const Counters& fresh, int expect_reuse,
+                       hipStream_t st) {
   unsigned g = std::max(cdiv(S.NP, 256), std::min(64u, cdiv(S.B + 1, 256)));
-  hipLaunchKernelGGL(k_reset_iter, dim3(g), dim3(256), 0, st, S, fresh);
+  hipLaunchKernelGGL(k_reset_iter, dim3(g), dim3(256), 0, st, S, fresh, expect_reuse);
 }
 void launch_gather(const Scene& S, const ProbCopy* pc, const double* scales,
                    int np, int max_nb, hipStream_t st) {
@@ -3122,10 +3173,6 @@ void launch_cons_merge_dq(const Scene& S, const Cons& C, hipStream_t st) {
                      0, st, S);
   hipLaunchKernelGGL(k_cons_dq, dim3(cdiv(12L * C.n_rep, 256)), dim3(256), 0, st,
                      S, C);
-}
-void launch_publish_counters(const Scene& S, Counters* ring, unsigned* pass,
-                             hipStream_t st) {
-  hipLaunchKernelGGL(k_publish_counters, dim3(1), dim3(64), 0, st, S, ring, pass);
 }
 void launch_reset_toi(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_toi, dim3(cdiv(S.NP, 256)), dim3(256), 0, st, S);
@@ -3192,11 +3239,11 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
                       : hipLaunchKernel(fn, dim3(grid), dim3(192), args, 0, st);
   return e == hipSuccess ? 0 : -1;
 }
-void launch_dq_norm(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_dq_norm, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S);
+void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(k_dq_norm, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S, with_ctrl);
 }
-void launch_ccd(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_ccd, dim3(S.grid_blocks), dim3(256), 0, st, S);
+void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st) {
+  hipLaunchKernelGGL(k_ccd, dim3(S.grid_blocks), dim3(256), 0, st, S, with_ctrl);
 }
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st) {

@@ -87,7 +87,9 @@ struct abd_ctx {
   int n_shared = 0;
   /* captured passes of the device loop: [0] before the cooperative PCG
    * launch, [1] after it; rebuilt whenever buffers or bound data change */
-  hipGraphExec_t pass_graph[2] = {nullptr, nullptr};
+  /* pass halves: [0] before the PCG launch, [1] after it, [2] the first
+   * half without the static broad phase (lists taken over) */
+  hipGraphExec_t pass_graph[3] = {nullptr, nullptr, nullptr};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
   abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1, 0, 0};
@@ -442,10 +444,12 @@ void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
   if (S.has_ground) launch_pg(S, swept, ctx->st);
 }
 
-void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd);
+void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd, bool with_ctrl = false);
 
-/* static phase on the stream: body terms, broad phase, barrier assembly */
-void launch_static(abd_ctx* ctx, const Scene& S) {
+/* static phase on the stream: body terms, broad phase, barrier assembly;
+ * with take_over the candidate lists are the previous pass's swept lists
+ * and only the positions are computed */
+void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false) {
   const double body_bytes = (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96);
   if (ctx->tune.overlap_body) {
     /* body terms (writes g, Hdiag) on the side stream, concurrent with the
@@ -461,7 +465,12 @@ void launch_static(abd_ctx* ctx, const Scene& S) {
     StageTimer t(ctx, 0, body_bytes);
     launch_body_terms(S, ctx->st);
   }
-  broad_phase(ctx, S, 0);
+  if (take_over) {
+    StageTimer t(ctx, 1);
+    launch_positions(S, 0, ctx->st);
+  } else {
+    broad_phase(ctx, S, 0);
+  }
   {
     StageTimer t(ctx, 2);
     launch_filter(S, ctx->st);
@@ -512,7 +521,7 @@ int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
   if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S),
                  pcg_variant(ctx, S), pcg_coop(ctx, S), ctx->st))
     return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
-  launch_dq_norm(S, ctx->st);
+  launch_dq_norm(S, 0, ctx->st);
   return ABD_OK;
 }
 
@@ -545,11 +554,11 @@ void launch_swept(abd_ctx* ctx, bool ccd, bool energy_at_toi) {
   }
 }
 
-void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd) {
+void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd, bool with_ctrl) {
   broad_phase(ctx, Ssw, 1);
   if (ccd) {
     StageTimer t(ctx, 4);
-    launch_ccd(Ssw, ctx->st);
+    launch_ccd(Ssw, with_ctrl ? 1 : 0, ctx->st);
   }
 }
 
@@ -621,17 +630,16 @@ int energy(abd_ctx* ctx, int phase, double alpha, int mode, int with_pairs,
 }
 
 /* swept broad phase and CCD on the stream for a given scene */
-void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd);
 
 /* One pass of the device-driven Newton loop, queued without host
  * synchronisation: every problem in the Newton state assembles, solves
  * and checks |dq|; every problem not done runs the swept phase, CCD, the
  * trial energies of its line search and, on acceptance, its update. */
-void pass_pre(abd_ctx* ctx) {
+void pass_pre(abd_ctx* ctx, bool take_over) {
   Scene S1 = ctx->S;
   S1.iter_mode = 1;
-  launch_reset_iter(S1, fresh_counters(), ctx->st);
-  launch_static(ctx, S1);
+  launch_reset_iter(S1, fresh_counters(), take_over ? 1 : 0, ctx->st);
+  launch_static(ctx, S1, take_over);
   StageTimer t(ctx, 6);
   launch_bsr(S1, ctx->st);
   launch_block_inverse(S1, ctx->st);
@@ -652,17 +660,16 @@ void pass_post(abd_ctx* ctx) {
   S1.iter_mode = 1;
   Scene S2 = swept_scene(ctx);
   S2.iter_mode = 2;
-  launch_dq_norm(S1, ctx->st);
-  launch_ctrl(S1, 1, ctx->st);
-  launch_swept_s(ctx, S2, true);
-  launch_ctrl(S1, 2, ctx->st);
+  /* the controller runs in the last workgroup of the |dq| reduction (stop
+   * test), of CCD (first trial step) and of the trial energies (decision);
+   * the update's last workgroup ends the pass */
+  launch_dq_norm(S1, 1, ctx->st);
+  launch_swept_s(ctx, S2, true, true);
   {
     StageTimer t(ctx, 5);
     launch_energy_multi(S2, ctx->st);
   }
-  launch_ctrl(S1, 3, ctx->st);
-  launch_update_multi(S1, ctx->st);
-  launch_publish_counters(S1, ctx->d_ring, ctx->d_pass, ctx->st);
+  launch_update_multi(S1, ctx->d_ring, ctx->d_pass, ctx->st);
 }
 
 /* capture one half of a pass into an executable graph */
@@ -673,8 +680,8 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
     return false;
   }
   ctx->capturing = true;
-  if (which == 0) pass_pre(ctx);
-  else pass_post(ctx);
+  if (which == 1) pass_post(ctx);
+  else pass_pre(ctx, which == 2);
   ctx->capturing = false;
   hipError_t e = hipStreamEndCapture(ctx->st, &g);
   if (e != hipSuccess || !g) {
@@ -698,27 +705,30 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
  * trial energies of its line search and, on acceptance, its update.  The
  * parts before and after the cooperative PCG launch are replayed from
  * captured graphs when possible (not while every stage is timed,
- * and not on the legacy null stream, which cannot be captured). */
-int run_pass(abd_ctx* ctx) {
+ * and not on the legacy null stream, which cannot be captured).  With
+ * take_over the first half skips the static broad phase and takes over the
+ * previous pass's swept lists (a pass that finds none changes no state). */
+int run_pass(abd_ctx* ctx, bool take_over) {
   const bool graphs = ctx->tune.use_graphs && ctx->graphs_ok &&
                       ctx->timing != ABD_TIMING_ALL &&
                       ctx->st != nullptr;
-  if (graphs && (!ctx->pass_graph[0] || !ctx->pass_graph[1])) {
+  if (graphs && (!ctx->pass_graph[0] || !ctx->pass_graph[1] || !ctx->pass_graph[2])) {
     drop_graphs(ctx);
     if (!capture(ctx, 0, &ctx->pass_graph[0]) ||
-        !capture(ctx, 1, &ctx->pass_graph[1])) {
+        !capture(ctx, 1, &ctx->pass_graph[1]) ||
+        !capture(ctx, 2, &ctx->pass_graph[2])) {
       drop_graphs(ctx);
       ctx->graphs_ok = false;
     }
   }
   if (graphs && ctx->graphs_ok) {
-    HIPCHK(hipGraphLaunch(ctx->pass_graph[0], ctx->st));
+    HIPCHK(hipGraphLaunch(ctx->pass_graph[take_over ? 2 : 0], ctx->st));
     int rc = pass_pcg(ctx);
     if (rc) return rc;
     HIPCHK(hipGraphLaunch(ctx->pass_graph[1], ctx->st));
     return ABD_OK;
   }
-  pass_pre(ctx);
+  pass_pre(ctx, take_over);
   int rc = pass_pcg(ctx);
   if (rc) return rc;
   pass_post(ctx);
@@ -733,7 +743,7 @@ int run_pass(abd_ctx* ctx) {
  * pass queued after an overflowing one repeats it, since the controller
  * keeps the state of a pass whose lists overflowed. */
 int device_solve(abd_ctx* ctx) {
-  launch_ctrl(ctx->S, 0, ctx->st);
+  launch_ctrl_start(ctx->S, ctx->st);
   const int max_pass =
       ctx->P.max_newton * (2 + (ctx->P.max_ls + LS_TRIALS) / LS_TRIALS) + 8;
   int queued = 0;
@@ -741,9 +751,13 @@ int device_solve(abd_ctx* ctx) {
   HIPCHK(hipMemsetAsync(ctx->d_pass, 0, sizeof(unsigned), ctx->st));
   /* the first pass runs the full static broad phase */
   HIPCHK(hipMemsetAsync(&ctx->S.cnt[1].sweep_ok, 0, sizeof(int), ctx->st));
+  /* the first pass of the solve, and the first after the lists grew, run
+   * the static broad phase; the others take over the swept lists */
+  bool full = true;
   auto enqueue = [&]() -> int {
-    int rc = run_pass(ctx); /* ends by writing its counters to the ring */
+    int rc = run_pass(ctx, !full); /* ends by writing its counters to the ring */
     if (rc) return rc;
+    full = false;
     HIPCHK(hipEventRecord(ctx->ring_ev[queued & 1], ctx->st));
     queued += 1;
     return ABD_OK;
@@ -770,6 +784,7 @@ int device_solve(abd_ctx* ctx) {
       if ((rc = grow(ctx, ctx->h_cnt[1], &ch1))) return rc;
       /* grown lists hold nothing to take over */
       HIPCHK(hipMemsetAsync(&ctx->S.cnt[1].sweep_ok, 0, sizeof(int), ctx->st));
+      full = true;
       k = queued;
       continue;
     }
