@@ -1858,8 +1858,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   __shared__ double uloc[16][12];
   __shared__ double rnb[PCG_NB_MAX][12];
   __shared__ double unb[PCG_NB_MAX][12];
-  __shared__ double vrow[3][192];
-  __shared__ double vbody[3][16];
+  __shared__ double wsum[3][16][3];
   __shared__ double part[16][3];
   __shared__ double tot[16][3];
   __shared__ double gam[16], gam_old[16], alp_old[16], bbl[16], alp[16], bet[16];
@@ -1926,24 +1925,46 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   auto prow = [&](int c) -> HT {
     return cached ? cache.pi[c * 192 + threadIdx.x] : Pi[144 * b + 12 * row + c];
   };
-  auto reduce = [&](int nv, const double* v) {
-    for (int k = 0; k < nv; ++k) vrow[k][threadIdx.x] = v[k];
-    lds_barrier();
-    if (row == 0 && lb < 16) {
-      for (int k = 0; k < nv; ++k) {
-        double sum = 0.0;
-        for (int c = 0; c < 12; ++c) sum += vrow[k][12 * lb + c];
-        vbody[k][lb] = sum;
+  /* the group's partial sums per local problem: a problem's rows are one
+   * run of threads, so a segmented tree sum over each wavefront (a lane
+   * adds the lane o above it while that lane is in its run) leaves the
+   * run's sum in its first lane of the wavefront; then the (at most three)
+   * wavefront sums of each problem, in wavefront order */
+  const int seg_lo = real ? 12 * q_lo[j] : threadIdx.x;
+  const int seg_hi = real ? 12 * q_hi[j] + 11 : threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  auto reduce = [&](const double* v) {
+    double x0 = v[0], x1 = v[1], x2 = v[2];
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y0 = __shfl_down(x0, o, 64), y1 = __shfl_down(x1, o, 64),
+                   y2 = __shfl_down(x2, o, 64);
+      if (lane + o < 64 && (int)threadIdx.x + o <= seg_hi) {
+        x0 += y0;
+        x1 += y1;
+        x2 += y2;
       }
+    }
+    if (real && (int)threadIdx.x == max(seg_lo, 64 * wave)) {
+      wsum[wave][j][0] = x0;
+      wsum[wave][j][1] = x1;
+      wsum[wave][j][2] = x2;
     }
     lds_barrier();
     if ((int)threadIdx.x < nloc) {
-      const int lo = q_lo[threadIdx.x], hi = q_hi[threadIdx.x];
-      for (int k = 0; k < nv; ++k) {
-        double sum = 0.0;
-        for (int c = lo; c <= hi; ++c) sum += vbody[k][c];
-        part[threadIdx.x][k] = sum;
-      }
+      const int q = threadIdx.x;
+      const int lo = 12 * q_lo[q], hi = 12 * q_hi[q] + 11;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+      for (int w = 0; w < 3; ++w)
+        if (lo <= 64 * w + 63 && hi >= 64 * w) {
+          s0 += wsum[w][q][0];
+          s1 += wsum[w][q][1];
+          s2 += wsum[w][q][2];
+        }
+      part[q][0] = s0;
+      part[q][1] = s1;
+      part[q][2] = s2;
     }
   };
   auto totals = [&](const PcgRec* recs) {
@@ -2050,7 +2071,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     wr = (double)y;
     if (act) Wb[nxt][o] = wr;
     const double v[3] = {act ? rr * ur : 0.0, act ? wr * ur : 0.0, act ? rr * rr : 0.0};
-    reduce(3, v);
+    reduce(v);
     PcgRec* recs = (ph & 1) ? rec1 : rec0;
     pcg_publish<HT>(recs + gr, ph, nloc, part, plo);
     if (s_single >= 0) {
