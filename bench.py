@@ -29,7 +29,8 @@ HBM_PEAK_GBS = 8000.0
 # benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each divided
 # by what the same counter reads per byte for a plain device copy of known
 # size (python bench.py --copy-probe).  Valid only for the kernel source it
-# was measured on (sha256 of the kernel file); otherwise traffic is null.
+# was measured on (sha256 of the PCG section of the kernel source);
+# otherwise traffic is null.
 PMC_TRAFFIC = {
     "kernel": "k_pcg_local<double>",
     "fetch_kib": 3343.1,       # FETCH_SIZE per dispatch, 90 dispatches
@@ -76,10 +77,15 @@ def copy_probe():
 
 
 def kernel_sha():
+    """sha256 of the PCG section of the kernel source (the block-Jacobi PCG
+    kernels and their helpers), which the traffic figures belong to."""
     import hashlib
     path = os.path.join(ROOT, "paper_2605_15875_amd", "csrc", "kernels.hip")
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    with open(path, "r") as f:
+        src = f.read()
+    a = src.index("/* S7 block-Jacobi PCG")
+    b = src.index("/* Single-reduction (pipelined) block-Jacobi PCG")
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
 def pmc_traffic(kernel):

@@ -2003,6 +2003,25 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
     }
     lds_barrier();
   };
+  /* the same from wavefront 0 after a control step, from a ballot of the
+   * problems still running (lanes below nloc) */
+  auto range_w0 = [&](bool live) {
+    const unsigned long long m = __ballot(live);
+    if (threadIdx.x == 0) {
+      if (m == 0ull) {
+        s_glo = -1;
+        s_ghi = -2;
+        s_more = 0;
+        s_single = -1;
+      } else {
+        const int lo = __ffsll((long long)m) - 1, hi = 63 - __clzll((long long)m);
+        s_glo = q_ga[lo];
+        s_ghi = q_gb[hi];
+        s_more = 1;
+        s_single = __popcll(m) == 1 ? lo : -1;
+      }
+    }
+  };
   /* one phase: from the own new residual rn (registers) and the
    * neighbours' published vectors, u = P^-1 r for the own body and its
    * neighbours, w = A u, publish r, w, s and the partial sums */
@@ -2089,24 +2108,28 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   /* phase 0: r = b = -g, x = p = s = 0, u = P^-1 r, w = A u */
   rr = real && !ldone[j] ? -S.g[o] : 0.0;
   double ur = phase(0, true);
-  if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
-    const int q = threadIdx.x, pg = plo + q;
-    gam[q] = tot[q][0];
-    bbl[q] = tot[q][2];
-    const bool first = q_first[q];
-    if (first) ps[pg].bb = bbl[q];
-    if (!(bbl[q] > 0.0)) {
-      ldone[q] = 1;
-      if (first) ps[pg].pcg_iters = 0;
-    } else {
-      alp[q] = gam[q] / tot[q][1];
-      bet[q] = 0.0;
+  if (threadIdx.x < 64) {
+    bool live = false;
+    if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
+      const int q = threadIdx.x, pg = plo + q;
+      gam[q] = tot[q][0];
+      bbl[q] = tot[q][2];
+      const bool first = q_first[q];
+      if (first) ps[pg].bb = bbl[q];
+      if (!(bbl[q] > 0.0)) {
+        ldone[q] = 1;
+        if (first) ps[pg].pcg_iters = 0;
+      } else {
+        alp[q] = gam[q] / tot[q][1];
+        bet[q] = 0.0;
+        live = true;
+      }
     }
+    range_w0(live);
   }
   lds_barrier();
   int it = 0;
   for (it = 0; it < max_it; ++it) {
-    range();
     if (!s_more || s_err) break;
     const bool act = real && !ldone[j];
     if (act) {
@@ -2117,20 +2140,26 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
       rr -= a * sr;
     }
     ur = phase(it + 1, false);
-    /* gamma, delta, rho of the new residual: stop, or the next step sizes */
-    if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
-      const int q = threadIdx.x, pg = plo + q;
-      if (tot[q][2] <= eta * eta * bbl[q]) {
-        ldone[q] = 1;
-        if (q_first[q]) ps[pg].pcg_iters = it + 1;
-      } else {
-        gam_old[q] = gam[q];
-        alp_old[q] = alp[q];
-        gam[q] = tot[q][0];
-        const double be = gam[q] / gam_old[q];
-        bet[q] = be;
-        alp[q] = gam[q] / (tot[q][1] - be * gam[q] / alp_old[q]);
+    /* gamma, delta, rho of the new residual: stop, or the next step sizes
+     * (wavefront 0, which also finds the groups still running) */
+    if (threadIdx.x < 64) {
+      bool live = false;
+      if ((int)threadIdx.x < nloc && !ldone[threadIdx.x]) {
+        const int q = threadIdx.x, pg = plo + q;
+        if (tot[q][2] <= eta * eta * bbl[q]) {
+          ldone[q] = 1;
+          if (q_first[q]) ps[pg].pcg_iters = it + 1;
+        } else {
+          gam_old[q] = gam[q];
+          alp_old[q] = alp[q];
+          gam[q] = tot[q][0];
+          const double be = gam[q] / gam_old[q];
+          bet[q] = be;
+          alp[q] = gam[q] / (tot[q][1] - be * gam[q] / alp_old[q]);
+          live = true;
+        }
       }
+      range_w0(live);
     }
     lds_barrier();
   }
