@@ -32,12 +32,12 @@ HBM_PEAK_GBS = 8000.0
 # was measured on (sha256 of the PCG section of the kernel source);
 # otherwise traffic is null.
 PMC_TRAFFIC = {
-    "kernel": "k_pcg_local<double>",
-    "fetch_kib": 3343.1,       # FETCH_SIZE per dispatch, 90 dispatches
-    "write_kib": 3660.1,       # WRITE_SIZE per dispatch, 90 dispatches
-    "fetch_per_byte": 131086.6 / 262144.0,  # copy of 256 MiB reads 0.5
+    "kernel": "k_pcg_cg1<double>",
+    "fetch_kib": 2474.2,       # FETCH_SIZE per dispatch, 90 dispatches
+    "write_kib": 5351.0,       # WRITE_SIZE per dispatch, 90 dispatches
+    "fetch_per_byte": 131086.5 / 262144.0,  # copy of 256 MiB reads 0.5
     "write_per_byte": 262144.0 / 262144.0,  # copy of 256 MiB writes 1.0
-    "sha256": "e8abffe4bcb46ac3479ec5ac96c2e879a834a01941c798d97c1f2c03edf960fc",
+    "sha256": "3935e236bc986be5344143bfa681f4e2c83daf0e53a67e9766a73fa378fd675c",
 }
 
 WORKLOAD = ("1000 icospheres (642 verts, 1280 tris each, r 0.05-0.15) "
