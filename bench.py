@@ -250,7 +250,6 @@ def main():
                     measured="timed region" if dom == "pcg"
                     else "instrumented steps")
     l = float(np.linalg.norm(np.ptp(x64, axis=0)))
-    solver.close()
     mixed = None
     if not a.no_mixed:
         # same workload, same steps and tolerance, FP32 Hessian path
@@ -269,14 +268,27 @@ def main():
         torch.cuda.synchronize()
         mel = time.perf_counter() - t1
         xm = ms.vertices()
+        # accuracy: time steps of both precisions from the same states (the
+        # free-running trajectories of a contact pile branch apart once one
+        # solve settles in a different local minimum)
+        one_step = 0.0
+        for i in range(3):
+            q, qd = solver.get_state()
+            ms.set_state(q, qd)
+            solver.step()
+            ms.step()
+            one_step = max(one_step, float(
+                np.abs(ms.vertices() - solver.vertices()).max() / l))
         mixed = dict(newton_iters_per_s=mnewton / mel, newton_iters=mnewton,
                      fp64_fallback_steps=fallbacks,
                      ms_per_step=mel * 1e3 / a.steps,
                      speedup_vs_fp64=elapsed / mel,
-                     final_pos_diff_vs_fp64_over_l=float(
+                     one_step_pos_diff_vs_fp64_over_l=one_step,
+                     free_running_pos_diff_vs_fp64_over_l=float(
                          np.abs(xm - x64).max() / l))
         log(f"mixed: {mnewton} newton iters in {mel*1e3:.1f} ms")
         ms.close()
+    solver.close()
     batch = None
     if not a.no_batch:
         batch = bench_batch(abd, scenes, torch, a.batch_scenes, 5, 1)
