@@ -2639,23 +2639,20 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
   const int tot = S.B + npt + nee + npg;
-  const int nwaves = (tot + 63) / 64;
+  /* one lane per (element, trial): eight elements per wavefront */
+  const int nwaves = (tot + 7) / 8;
   /* workgroups with elements (at least one, to run the controller) */
   const unsigned nwork = max(1u, min(gridDim.x, (unsigned)((nwaves + 3) / 4)));
   if (blockIdx.x >= nwork) return;
+  const int lane = threadIdx.x & 63, k = lane & (LS_TRIALS - 1);
   for (int w = blockIdx.x * 4 + threadIdx.x / 64; w < nwaves; w += gridDim.x * 4) {
-    const int t = w * 64 + (threadIdx.x & 63);
-    double e[LS_TRIALS];
-#pragma unroll
-    for (int k = 0; k < LS_TRIALS; ++k) e[k] = 0.0;
+    const int t = w * 8 + lane / LS_TRIALS;
+    double e = 0.0;
     int prob = -1;
     if (t < S.B) {
       if (S.kind[t] == 0 && S.ps[S.bprob[t]].state != PS_DONE) {
         prob = S.bprob[t];
-        const double a0 = S.ps[prob].alpha_base;
-        double a = a0;
-#pragma unroll
-        for (int k = 0; k < LS_TRIALS; ++k, a *= 0.5) e[k] = body_energy(S, t, a, 0);
+        e = body_energy(S, t, ldexp(S.ps[prob].alpha_base, -k), 0);
       }
     } else if (t < tot) {
       const int u = t - S.B;
@@ -2667,14 +2664,14 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
         const int pb = S.bprob[S.vbody[vid[0]]];
         if (S.ps[pb].state != PS_DONE) {
           prob = pb;
+          const double a = ldexp(S.ps[prob].alpha_base, -k);
           double x0[12], x1[12];
-          for (int k = 0; k < 4; ++k) vertex_pos(S, vid[k], x0 + 3 * k);
-          const double E0 = pair_energy_at(S, kind, c[0], c[1], vid, x0);
-          double a = S.ps[prob].alpha_base;
-          for (int k = 0; k < LS_TRIALS; ++k, a *= 0.5) {
-            for (int j = 0; j < 4; ++j) vertex_pos_alpha(S, vid[j], a, x1 + 3 * j);
-            e[k] = pair_energy_at(S, kind, c[0], c[1], vid, x1) - E0;
+          for (int j = 0; j < 4; ++j) {
+            vertex_pos(S, vid[j], x0 + 3 * j);
+            vertex_pos_alpha(S, vid[j], a, x1 + 3 * j);
           }
+          e = pair_energy_at(S, kind, c[0], c[1], vid, x1) -
+              pair_energy_at(S, kind, c[0], c[1], vid, x0);
         }
       } else {
         const int v = S.cand_pg[u - npt - nee];
@@ -2683,29 +2680,23 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
           prob = pb;
           double x0[3], x1[3];
           vertex_pos(S, v, x0);
-          const double w = pair_weight(S, &v, 1);
-          const double E0 = w * barrier_val(x0[1] - S.ground_y, S.dhat);
-          double a = S.ps[prob].alpha_base;
-          for (int k = 0; k < LS_TRIALS; ++k, a *= 0.5) {
-            vertex_pos_alpha(S, v, a, x1);
-            e[k] = w * barrier_val(x1[1] - S.ground_y, S.dhat) - E0;
-          }
+          vertex_pos_alpha(S, v, ldexp(S.ps[prob].alpha_base, -k), x1);
+          const double wv = pair_weight(S, &v, 1);
+          e = wv * barrier_val(x1[1] - S.ground_y, S.dhat) -
+              wv * barrier_val(x0[1] - S.ground_y, S.dhat);
         }
       }
     }
+    /* per trial: the eight elements of the wavefront summed when they
+     * belong to one problem (lanes k, k + 8, ... hold trial k) */
     const bool uni = wave_uniform(prob);
     if (uni) {
       if (prob >= 0) {
-#pragma unroll
-        for (int k = 0; k < LS_TRIALS; ++k) {
-          double v = e[k];
-          for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-          if ((threadIdx.x & 63) == 0) atomicAdd(&S.ps[prob].dE[k], v);
-        }
+        for (int o = 32; o >= LS_TRIALS; o >>= 1) e += __shfl_down(e, o, 64);
+        if (lane < LS_TRIALS) atomicAdd(&S.ps[prob].dE[k], e);
       }
     } else if (prob >= 0) {
-#pragma unroll
-      for (int k = 0; k < LS_TRIALS; ++k) atomicAdd(&S.ps[prob].dE[k], e[k]);
+      atomicAdd(&S.ps[prob].dE[k], e);
     }
   }
   /* then every problem's line search decision (this scene's counters are
