@@ -318,10 +318,15 @@ __device__ __forceinline__ void chunk_pair_of(const int* ca, const int* cb, int 
   }
 }
 
+/* chunk pairs of one body pair per workgroup pass: every test once, hits
+ * staged in LDS (one global atomic per body pair), more than CP_STAGE
+ * hits of one body pair appended one by one */
+#define CP_STAGE 1024
 __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
+  __shared__ int4 hits[CP_STAGE];
+  __shared__ int s_n, s_base;
   if (S.cnt->reuse) return;
   const int nbp = min(S.cnt->n_bp, S.cap_bp);
-  const int lane = threadIdx.x & 63;
   for (int p = blockIdx.x; p < nbp; p += gridDim.x) {
     const int2 ab = S.bp[p];
     const int* ca = S.body_chunk + 6 * ab.x;
@@ -330,27 +335,29 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
     const int nvb = cb[1] - cb[0], ntb = cb[3] - cb[2], neb = cb[5] - cb[4];
     const int n1 = nva * ntb, n2 = nvb * nta, n3 = nea * neb;
     const int tot = n1 + n2 + n3;
-    /* count this thread's passing tests, one atomic per wavefront, write */
-    int n = 0;
+    if (threadIdx.x == 0) s_n = 0;
+    __syncthreads();
     for (int t = threadIdx.x; t < tot; t += blockDim.x) {
       int kind, P, Q;
       chunk_pair_of(ca, cb, n1, n2, ntb, nta, neb, t, kind, P, Q);
-      n += box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat) ? 1 : 0;
-    }
-    int total;
-    const int off = wave_prefix(n, &total);
-    if (total == 0) continue; /* uniform over the wavefront */
-    int base = 0;
-    if (lane == 0) base = atomicAdd(&S.cnt->n_cp, total);
-    int k = __shfl(base, 0, 64) + off;
-    if (n > 0)
-      for (int t = threadIdx.x; t < tot; t += blockDim.x) {
-        int kind, P, Q;
-        chunk_pair_of(ca, cb, n1, n2, ntb, nta, neb, t, kind, P, Q);
-        if (!box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat)) continue;
-        if (k < S.cap_cp) S.cp[k] = make_int4(kind, P, Q, p);
-        ++k;
+      if (!box_overlap(S.ch_box + 6 * P, S.ch_box + 6 * Q, S.dhat)) continue;
+      const int k = atomicAdd(&s_n, 1);
+      if (k < CP_STAGE) {
+        hits[k] = make_int4(kind, P, Q, p);
+      } else {
+        const int g = atomicAdd(&S.cnt->n_cp, 1);
+        if (g < S.cap_cp) S.cp[g] = make_int4(kind, P, Q, p);
       }
+    }
+    __syncthreads();
+    const int n = min(s_n, CP_STAGE);
+    if (threadIdx.x == 0) s_base = n > 0 ? atomicAdd(&S.cnt->n_cp, n) : 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      const int g = s_base + i;
+      if (g < S.cap_cp) S.cp[g] = hits[i];
+    }
+    __syncthreads(); /* hits and s_n are reused by the next body pair */
   }
 }
 
@@ -427,14 +434,20 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
     const int kindQ = cp.x == C_PT ? K_TRI : K_EDGE;
     const int nP = S.ch_count[P];
     const int nQ = S.ch_count[Q];
-    bool keep = false;
-    int id = 0;
-    double qb[6];
+    /* both sides' primitives are loaded together (independent gathers) */
+    bool keep = false, mine = false;
+    int id = 0, pid = 0;
+    double qb[6], box[6];
     if (lane < nQ) {
       id = S.ch_prims[S.ch_start[Q] + lane];
       prim_box(S, kindQ, id, swept, qb);
-      keep = box_overlap(qb, S.ch_box + 6 * P, S.dhat);
     }
+    if (lane < nP) {
+      pid = S.ch_prims[S.ch_start[P] + lane];
+      prim_box(S, kindP, pid, swept, box);
+    }
+    if (lane < nQ) keep = box_overlap(qb, S.ch_box + 6 * P, S.dhat);
+    if (lane < nP) mine = box_overlap(box, S.ch_box + 6 * Q, S.dhat);
     const unsigned long long m = __ballot(keep);
     const int nq = __popcll(m);
     if (nq == 0) continue; /* uniform over the wavefront */
@@ -445,14 +458,6 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
       for (int k = 0; k < 6; ++k) qbox[wave][pos][k] = qb[k];
     }
     wave_lds_sync();
-    bool mine = false;
-    int pid = 0;
-    double box[6];
-    if (lane < nP) {
-      pid = S.ch_prims[S.ch_start[P] + lane];
-      prim_box(S, kindP, pid, swept, box);
-      mine = box_overlap(box, S.ch_box + 6 * Q, S.dhat);
-    }
     /* count, one atomic per wavefront, then write */
     int n = 0;
     if (mine)
