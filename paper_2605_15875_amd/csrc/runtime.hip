@@ -88,8 +88,15 @@ struct abd_ctx {
   /* captured passes of the device loop: [0] before the cooperative PCG
    * launch, [1] after it; rebuilt whenever buffers or bound data change */
   /* pass halves: [0] before the PCG launch, [1] after it, [2] the first
-   * half without the static broad phase (lists taken over) */
-  hipGraphExec_t pass_graph[3] = {nullptr, nullptr, nullptr};
+   * half without the static broad phase (lists taken over); whole passes
+   * with the PCG launch inside: [3] full, [4] taking over (passes whose PCG
+   * launch is not timed, when that launch can be captured) */
+  hipGraphExec_t pass_graph[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  bool whole_ok = true;
+  /* with ABD_TIMING_PCG, every pcg_sample-th pass of a solve is run in
+   * halves with events around its PCG launch; the others run whole */
+  int pcg_sample = 4;
+  bool pass_timed[2] = {false, false};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
   abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1, 0, 0};
@@ -680,8 +687,22 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
     return false;
   }
   ctx->capturing = true;
-  if (which == 1) pass_post(ctx);
-  else pass_pre(ctx, which == 2);
+  if (which == 1) {
+    pass_post(ctx);
+  } else if (which <= 2) {
+    pass_pre(ctx, which == 2);
+  } else {
+    pass_pre(ctx, which == 4);
+    if (pass_pcg(ctx)) {
+      ctx->capturing = false;
+      hipGraph_t g = nullptr;
+      (void)hipStreamEndCapture(ctx->st, &g);
+      if (g) (void)hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return false;
+    }
+    pass_post(ctx);
+  }
   ctx->capturing = false;
   hipError_t e = hipStreamEndCapture(ctx->st, &g);
   if (e != hipSuccess || !g) {
@@ -708,7 +729,7 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
  * and not on the legacy null stream, which cannot be captured).  With
  * take_over the first half skips the static broad phase and takes over the
  * previous pass's swept lists (a pass that finds none changes no state). */
-int run_pass(abd_ctx* ctx, bool take_over) {
+int run_pass(abd_ctx* ctx, bool take_over, bool timed) {
   const bool graphs = ctx->tune.use_graphs && ctx->graphs_ok &&
                       ctx->timing != ABD_TIMING_ALL &&
                       ctx->st != nullptr;
@@ -719,7 +740,21 @@ int run_pass(abd_ctx* ctx, bool take_over) {
         !capture(ctx, 2, &ctx->pass_graph[2])) {
       drop_graphs(ctx);
       ctx->graphs_ok = false;
+    } else if (ctx->whole_ok &&
+               (!capture(ctx, 3, &ctx->pass_graph[3]) ||
+                !capture(ctx, 4, &ctx->pass_graph[4]))) {
+      /* a PCG launch that cannot be captured (cooperative): halves only */
+      for (int i = 3; i < 5; ++i)
+        if (ctx->pass_graph[i]) {
+          (void)hipGraphExecDestroy(ctx->pass_graph[i]);
+          ctx->pass_graph[i] = nullptr;
+        }
+      ctx->whole_ok = false;
     }
+  }
+  if (graphs && ctx->graphs_ok && !timed && ctx->pass_graph[3] && ctx->pass_graph[4]) {
+    HIPCHK(hipGraphLaunch(ctx->pass_graph[take_over ? 4 : 3], ctx->st));
+    return ABD_OK;
   }
   if (graphs && ctx->graphs_ok) {
     HIPCHK(hipGraphLaunch(ctx->pass_graph[take_over ? 2 : 0], ctx->st));
@@ -755,7 +790,10 @@ int device_solve(abd_ctx* ctx) {
    * the static broad phase; the others take over the swept lists */
   bool full = true;
   auto enqueue = [&]() -> int {
-    int rc = run_pass(ctx, !full); /* ends by writing its counters to the ring */
+    const bool timed = ctx->timing == ABD_TIMING_PCG &&
+                       queued % std::max(1, ctx->pcg_sample) == 0;
+    ctx->pass_timed[queued & 1] = timed || ctx->timing == ABD_TIMING_ALL;
+    int rc = run_pass(ctx, !full, timed); /* ends by writing its counters to the ring */
     if (rc) return rc;
     full = false;
     HIPCHK(hipEventRecord(ctx->ring_ev[queued & 1], ctx->st));
@@ -788,7 +826,7 @@ int device_solve(abd_ctx* ctx) {
       k = queued;
       continue;
     }
-    account_pcg_bytes(ctx);
+    if (ctx->pass_timed[k & 1]) account_pcg_bytes(ctx);
     if (ctx->h_cnt[1].active == 0) {
       HIPCHK(hipStreamSynchronize(ctx->st));
       resolve_timing(ctx);
