@@ -372,9 +372,10 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
  * the number of timed launches and the algorithmic bytes those launches
  * had to move (sizes as launched).  Modes: ABD_TIMING_OFF (default);
  * ABD_TIMING_ALL times every stage, which replaces the captured graphs by
- * direct launches; ABD_TIMING_PCG times only the cooperative PCG launch,
- * which runs outside the graphs, so the solve keeps its normal launch
- * path.  Other values: INVALID_ARG. */
+ * direct launches; ABD_TIMING_PCG times the PCG launch of every fourth
+ * pass of the device loop (those passes run as two captured halves around
+ * it, the others as whole captured passes), so the solve keeps its normal
+ * launch path.  Other values: INVALID_ARG. */
 #define ABD_TIMING_OFF 0
 #define ABD_TIMING_ALL 1
 #define ABD_TIMING_PCG 2
