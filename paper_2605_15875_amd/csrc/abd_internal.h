@@ -708,13 +708,13 @@ void launch_commit(const Scene& S, hipStream_t st);
 void launch_transform(const Scene& S, double* x, double* dx, hipStream_t st);
 void launch_body_terms(const Scene& S, hipStream_t st);
 void launch_boxes(const Scene& S, int swept, hipStream_t st);
-void launch_positions(const Scene& S, int swept, hipStream_t st);
+void launch_positions(const Scene& S, int swept, hipStream_t st,
+                      const Counters* fresh = nullptr, int expect_reuse = 0);
 void launch_body_pairs(const Scene& S, hipStream_t st);
 void launch_chunk_pairs(const Scene& S, hipStream_t st);
 void launch_prim_pairs(const Scene& S, int swept, hipStream_t st);
 void launch_pg(const Scene& S, int swept, hipStream_t st);
 void launch_filter(const Scene& S, hipStream_t st);
-void launch_clear_slots(const Scene& S, hipStream_t st);
 void launch_crossings(const Scene& S, hipStream_t st);
 void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st);
 void launch_bsr(const Scene& S, hipStream_t st);
@@ -730,8 +730,6 @@ void launch_energy_multi(const Scene& S, hipStream_t st);
 void launch_ctrl_start(const Scene& S, hipStream_t st);
 void launch_update_multi(const Scene& S, Counters* ring, unsigned* pass,
                          hipStream_t st);
-void launch_reset_iter(const Scene& S, const Counters& fresh, int expect_reuse,
-                       hipStream_t st);
 void launch_reset_pcg(const Scene& S, hipStream_t st);
 void launch_reset_toi(const Scene& S, hipStream_t st);
 /* consensus over the replicas of shared bodies in a batch scene */

@@ -363,8 +363,51 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
 
 /* world positions for the broad phase: x at q, and x + dx at q + dq for
  * the swept phase (the same canonical transforms as every other kernel) */
-__global__ void k_positions(Scene S, int swept) {
+/* start of a pass of the device loop: fresh counter blocks (the static one
+ * taking over the previous pass's swept lists when they are complete),
+ * per-problem transients, the block-row counts and the PCG records */
+__device__ __forceinline__ void pass_reset(const Scene& S, const Counters& fresh,
+                                           int expect_reuse, int t, int nth) {
+  if (t == 0) {
+    /* The previous pass's swept lists cover every position q + alpha dq,
+     * alpha in [0, 1], of the bodies it swept: every static candidate of
+     * the accepted (or unchanged) state is among them, so they serve as
+     * this pass's static lists. */
+    const Counters c1 = S.cnt[1];
+    Counters c0 = fresh;
+    if (c1.sweep_ok) {
+      c0.n_bp = c1.n_bp;
+      c0.n_cp = c1.n_cp;
+      c0.n_pt = c1.n_pt;
+      c0.n_ee = c1.n_ee;
+      c0.n_pg = c1.n_pg;
+      c0.reuse = 1;
+    } else if (expect_reuse) {
+      c0.redo = 1;
+    }
+    S.cnt[0] = c0;
+    S.cnt[1] = fresh;
+  }
+  for (int q = t; q < S.NP; q += nth) {
+    ProbState& P = S.ps[q];
+    P.max_dq = 0;
+    P.min_toi = fresh.min_toi;
+    P.alpha_acc = 0.0;
+    P.bb = 0.0;
+    P.pcg_iters = 0;
+    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
+    for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
+  }
+  for (int i = t; i <= S.B; i += nth) S.row_cnt[i] = 0;
+  for (int i = t; i < 2 * ((S.B + 15) / 16); i += nth)
+    S.pcg_rec[i].gen = 0ull;
+}
+
+/* reset_mode (first launch of a device-loop pass): 1 the pass reset,
+ * 2 the same for a pass that expects to take its lists over */
+__global__ void k_positions(Scene S, int swept, Counters fresh, int reset_mode) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (reset_mode) pass_reset(S, fresh, reset_mode == 2, v, gridDim.x * blockDim.x);
   if (v >= S.V || !body_in_pass(S, S.vbody[v])) return;
   double x[3], x1[3];
   if (swept) {
@@ -542,7 +585,8 @@ __device__ __forceinline__ double pair_weight(const Scene& S, const int* vid,
   return 0.5 * w;
 }
 
-__global__ void k_filter(Scene S) {
+/* hoff_words: 8-byte words per off-diagonal block (144 FP64, 72 FP32) */
+__global__ void k_filter(Scene S, int hoff_words) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
@@ -579,6 +623,15 @@ __global__ void k_filter(Scene S) {
   /* smallest distance: reduced over the wavefront, one atomic per wave */
   for (int o = 32; o > 0; o >>= 1) dmin = fmin(dmin, __shfl_xor(dmin, o, 64));
   if (__lane_id() == 0 && dmin < INFINITY) atomic_min_pos(&S.cnt->min_dist, dmin);
+  /* the same launch clears the off-diagonal blocks and used flags of the
+   * current body pairs, which the assembly then adds into */
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  unsigned long long* Ho = (unsigned long long*)S.Hoff;
+  const long nw = (long)hoff_words * nbp;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nw; t += stride)
+    Ho[t] = 0ull;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < nbp; t += stride)
+    S.slot_used[t] = 0;
 }
 
 /* ---- derivatives of the squared-distance features ---- */
@@ -1190,6 +1243,70 @@ __global__ void k_bsr_scan(Scene S) {
     S.row_ptr[i] = acc;
     acc += S.row_cnt[i];
     S.row_cnt[i] = 0; /* reused as fill cursor */
+  }
+}
+/* the three steps in one workgroup when the block-row counts fit in LDS:
+ * counts by LDS atomics, the same scan, then the counts become the fill
+ * cursors */
+#define BSR_LDS_ROWS 12288
+__global__ __launch_bounds__(1024) void k_bsr_small(Scene S) {
+  __shared__ int cnt[BSR_LDS_ROWS + 1];
+  __shared__ int wsum[16];
+  const int n = S.B;
+  for (int i = threadIdx.x; i <= n; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
+    if (!S.slot_used[p]) continue;
+    const int2 ab = S.bp[p];
+    atomicAdd(&cnt[ab.x], 1);
+    atomicAdd(&cnt[ab.y], 1);
+  }
+  __syncthreads();
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per, hi = min(n, lo + per);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += cnt[i];
+  int x = s;
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[wave] = x;
+  __syncthreads();
+  if (wave == 0) {
+    int w = lane < 16 ? wsum[lane] : 0;
+    for (int o = 1; o < 16; o <<= 1) {
+      const int y = __shfl_up(w, o, 64);
+      if (lane >= o) w += y;
+    }
+    if (lane < 16) wsum[lane] = w;
+  }
+  __syncthreads();
+  int acc = x - s + (wave > 0 ? wsum[wave - 1] : 0);
+  if (threadIdx.x == blockDim.x - 1) {
+    S.row_ptr[n] = acc + s;
+    S.cnt->n_rows_used = acc + s;
+  }
+  for (int i = lo; i < hi; ++i) {
+    const int c = cnt[i];
+    S.row_ptr[i] = acc;
+    cnt[i] = acc;
+    acc += c;
+  }
+  __syncthreads();
+  for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
+    if (!S.slot_used[p]) continue;
+    const int2 ab = S.bp[p];
+    int k = atomicAdd(&cnt[ab.x], 1);
+    if (k < S.cap_col) {
+      S.col_slot[k] = p; S.col_body[k] = ab.y; S.col_trans[k] = 0;
+    }
+    k = atomicAdd(&cnt[ab.y], 1);
+    if (k < S.cap_col) {
+      S.col_slot[k] = p; S.col_body[k] = ab.x; S.col_trans[k] = 1;
+    }
   }
 }
 __global__ void k_bsr_fill(Scene S) {
@@ -2879,42 +2996,6 @@ __global__ void k_reset_pcg(Scene S) {
 
 /* start of a pass: fresh counter blocks, per-problem transients, and the
  * block-row counts of the PCG system */
-__global__ void k_reset_iter(Scene S, Counters fresh, int expect_reuse) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t == 0) {
-    /* The previous pass's swept lists cover every position q + alpha dq,
-     * alpha in [0, 1], of the bodies it swept: every static candidate of
-     * the accepted (or unchanged) state is among them, so they serve as
-     * this pass's static lists. */
-    const Counters c1 = S.cnt[1];
-    Counters c0 = fresh;
-    if (c1.sweep_ok) {
-      c0.n_bp = c1.n_bp;
-      c0.n_cp = c1.n_cp;
-      c0.n_pt = c1.n_pt;
-      c0.n_ee = c1.n_ee;
-      c0.n_pg = c1.n_pg;
-      c0.reuse = 1;
-    } else if (expect_reuse) {
-      c0.redo = 1;
-    }
-    S.cnt[0] = c0;
-    S.cnt[1] = fresh;
-  }
-  if (t < S.NP) {
-    ProbState& P = S.ps[t];
-    P.max_dq = 0;
-    P.min_toi = fresh.min_toi;
-    P.alpha_acc = 0.0;
-    P.bb = 0.0;
-    P.pcg_iters = 0;
-    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
-    for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
-  }
-  for (int i = t; i <= S.B; i += gridDim.x * blockDim.x) S.row_cnt[i] = 0;
-  for (int i = t; i < 2 * ((S.B + 15) / 16); i += gridDim.x * blockDim.x)
-    S.pcg_rec[i].gen = 0ull;
-}
 
 /* ================================================================== */
 /* consensus step over the replicas of shared bodies                   */
@@ -3106,17 +3187,6 @@ __global__ __launch_bounds__(256) void k_crossings(Scene S) {
   }
 }
 
-/* zero the off-diagonal blocks and used flags of the current body pairs */
-template <typename HT>
-__global__ void k_clear_slots(Scene S) {
-  const int nbp = min(S.cnt->n_bp, S.cap_bp);
-  HT* Ho = (HT*)S.Hoff;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < 144L * nbp;
-       t += (long)gridDim.x * blockDim.x) {
-    Ho[t] = HT(0);
-    if (t % 144 == 0) S.slot_used[t / 144] = 0;
-  }
-}
 
 /* ================================================================== */
 /* host launchers                                                      */
@@ -3145,8 +3215,12 @@ void launch_body_terms(const Scene& S, hipStream_t st) {
 void launch_boxes(const Scene& S, int swept, hipStream_t st) {
   hipLaunchKernelGGL(k_boxes, dim3(cdiv(S.NC + S.B, 256)), dim3(256), 0, st, S, swept);
 }
-void launch_positions(const Scene& S, int swept, hipStream_t st) {
-  hipLaunchKernelGGL(k_positions, dim3(cdiv(S.V, 256)), dim3(256), 0, st, S, swept);
+void launch_positions(const Scene& S, int swept, hipStream_t st,
+                      const Counters* fresh, int expect_reuse) {
+  const Counters f = fresh ? *fresh : Counters{};
+  const int mode = fresh ? (expect_reuse ? 2 : 1) : 0;
+  hipLaunchKernelGGL(k_positions, dim3(cdiv(S.V, 256)), dim3(256), 0, st, S, swept, f,
+                     mode);
 }
 void launch_body_pairs(const Scene& S, hipStream_t st) {
   unsigned g = cdiv(S.B, 16);
@@ -3162,7 +3236,8 @@ void launch_pg(const Scene& S, int swept, hipStream_t st) {
   hipLaunchKernelGGL(k_pg, dim3(min(1024u, cdiv(S.NC, 4))), dim3(256), 0, st, S, swept);
 }
 void launch_filter(const Scene& S, hipStream_t st) {
-  hipLaunchKernelGGL(k_filter, dim3(S.grid_blocks), dim3(256), 0, st, S);
+  hipLaunchKernelGGL(k_filter, dim3(S.grid_blocks), dim3(256), 0, st, S,
+                     S.mixed ? 72 : 144);
 }
 void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st) {
   unsigned g = n_act_hint > 0 ? min(4096u, cdiv(n_act_hint, PAIRS_PER_WG))
@@ -3181,11 +3256,6 @@ void launch_ctrl_start(const Scene& S, hipStream_t st) {
 void launch_update_multi(const Scene& S, Counters* ring, unsigned* pass, hipStream_t st) {
   hipLaunchKernelGGL(k_update_multi, dim3(cdiv(12L * S.B, 256)), dim3(256), 0, st, S,
                      ring, pass);
-}
-void launch_reset_iter(const Scene& S, const Counters& fresh, int expect_reuse,
-                       hipStream_t st) {
-  unsigned g = std::max(cdiv(S.NP, 256), std::min(64u, cdiv(S.B + 1, 256)));
-  hipLaunchKernelGGL(k_reset_iter, dim3(g), dim3(256), 0, st, S, fresh, expect_reuse);
 }
 void launch_gather(const Scene& S, const ProbCopy* pc, const double* scales,
                    int np, int max_nb, hipStream_t st) {
@@ -3229,13 +3299,11 @@ void launch_reset_pcg(const Scene& S, hipStream_t st) {
 void launch_crossings(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_crossings, dim3(1024), dim3(256), 0, st, S);
 }
-void launch_clear_slots(const Scene& S, hipStream_t st) {
-  if (S.mixed)
-    hipLaunchKernelGGL(k_clear_slots<float>, dim3(512), dim3(256), 0, st, S);
-  else
-    hipLaunchKernelGGL(k_clear_slots<double>, dim3(512), dim3(256), 0, st, S);
-}
 void launch_bsr(const Scene& S, hipStream_t st) {
+  if (S.B <= BSR_LDS_ROWS) {
+    hipLaunchKernelGGL(k_bsr_small, dim3(1), dim3(1024), 0, st, S);
+    return;
+  }
   hipLaunchKernelGGL(k_bsr_count, dim3(256), dim3(256), 0, st, S);
   hipLaunchKernelGGL(k_bsr_scan, dim3(1), dim3(1024), 0, st, S);
   hipLaunchKernelGGL(k_bsr_fill, dim3(256), dim3(256), 0, st, S);

@@ -441,9 +441,10 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
 }
 
 /* ---------------- phases ---------------- */
-void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
+void broad_phase(abd_ctx* ctx, const Scene& S, int swept,
+                 const Counters* fresh = nullptr) {
   StageTimer t(ctx, 1);
-  launch_positions(S, swept, ctx->st);
+  launch_positions(S, swept, ctx->st, fresh, 0);
   launch_boxes(S, swept, ctx->st);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
@@ -456,7 +457,8 @@ void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd, bool with_ctrl = f
 /* static phase on the stream: body terms, broad phase, barrier assembly;
  * with take_over the candidate lists are the previous pass's swept lists
  * and only the positions are computed */
-void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false) {
+void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
+                   const Counters* fresh = nullptr) {
   const double body_bytes = (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96);
   if (ctx->tune.overlap_body) {
     /* body terms (writes g, Hdiag) on the side stream, concurrent with the
@@ -474,14 +476,13 @@ void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false) {
   }
   if (take_over) {
     StageTimer t(ctx, 1);
-    launch_positions(S, 0, ctx->st);
+    launch_positions(S, 0, ctx->st, fresh, 1);
   } else {
-    broad_phase(ctx, S, 0);
+    broad_phase(ctx, S, 0, fresh);
   }
   {
     StageTimer t(ctx, 2);
     launch_filter(S, ctx->st);
-    launch_clear_slots(S, ctx->st);
     if (ctx->tune.overlap_body) (void)hipStreamWaitEvent(ctx->st, ctx->ev_join, 0);
     launch_assemble(S, 0, ctx->st);
   }
@@ -645,8 +646,9 @@ int energy(abd_ctx* ctx, int phase, double alpha, int mode, int with_pairs,
 void pass_pre(abd_ctx* ctx, bool take_over) {
   Scene S1 = ctx->S;
   S1.iter_mode = 1;
-  launch_reset_iter(S1, fresh_counters(), take_over ? 1 : 0, ctx->st);
-  launch_static(ctx, S1, take_over);
+  /* the pass reset runs in the first positions launch */
+  const Counters fresh = fresh_counters();
+  launch_static(ctx, S1, take_over, &fresh);
   StageTimer t(ctx, 6);
   launch_bsr(S1, ctx->st);
   launch_block_inverse(S1, ctx->st);
