@@ -463,9 +463,12 @@ __device__ __forceinline__ void prim_box(const Scene& S, int kind, int id,
  * meets the second chunk's box tests it against the compacted list with
  * the exact predicate.  Both culls are sound: a primitive box lies inside
  * its chunk box and the rounded bound hi + dhat is monotone in hi. */
+#define PP_STAGE 256
 __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
   __shared__ double qbox[4][ABD_CHUNK][6];
   __shared__ int qid[4][ABD_CHUNK];
+  __shared__ int2 hits[4][PP_STAGE];
+  __shared__ int hcount[4];
   if (S.cnt->reuse) return;
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
   const int ncp = min(S.cnt->n_cp, S.cap_cp);
@@ -501,33 +504,48 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
       for (int k = 0; k < 6; ++k) qbox[wave][pos][k] = qb[k];
     }
     wave_lds_sync();
-    /* count, one atomic per wavefront, then write */
-    int n = 0;
+    /* every test once: hits staged in LDS and appended with one global
+     * atomic per chunk pair (beyond PP_STAGE hits, one by one) */
+    const bool pt = cp.x == C_PT; /* uniform over the wavefront */
+    int* const counter = pt ? &S.cnt->n_pt : &S.cnt->n_ee;
+    const int cap = pt ? S.cap_pt : S.cap_ee;
+    int* const list = pt ? S.cand_pt : S.cand_ee;
+    if (lane == 0) hcount[wave] = 0;
+    wave_lds_sync();
     if (mine)
-      for (int j = 0; j < nq; ++j) n += box_overlap(box, qbox[wave][j], S.dhat) ? 1 : 0;
-    int total;
-    const int off = wave_prefix(n, &total);
-    if (total > 0) {
-      const bool pt = cp.x == C_PT; /* uniform over the wavefront */
-      int* const counter = pt ? &S.cnt->n_pt : &S.cnt->n_ee;
-      const int cap = pt ? S.cap_pt : S.cap_ee;
-      int* const list = pt ? S.cand_pt : S.cand_ee;
-      int base = 0;
-      if (lane == 0) base = atomicAdd(counter, total);
-      int k = __shfl(base, 0, 64) + off;
-      if (mine)
-        for (int j = 0; j < nq; ++j) {
-          if (!box_overlap(box, qbox[wave][j], S.dhat)) continue;
+      for (int j = 0; j < nq; ++j) {
+        if (!box_overlap(box, qbox[wave][j], S.dhat)) continue;
+        const int other = qid[wave][j];
+        const int a0 = pt ? pid : min(pid, other), a1 = pt ? other : max(pid, other);
+        const int h = atomicAdd(&hcount[wave], 1);
+        if (h < PP_STAGE) {
+          hits[wave][h] = make_int2(a0, a1);
+        } else {
+          const int k = atomicAdd(counter, 1);
           if (k < cap) {
-            const int other = qid[wave][j];
-            list[3 * k] = pt ? pid : min(pid, other);
-            list[3 * k + 1] = pt ? other : max(pid, other);
+            list[3 * k] = a0;
+            list[3 * k + 1] = a1;
             list[3 * k + 2] = cp.w;
           }
-          ++k;
         }
+      }
+    wave_lds_sync();
+    const int nh = min(hcount[wave], PP_STAGE);
+    if (nh > 0) {
+      int base = 0;
+      if (lane == 0) base = atomicAdd(counter, nh);
+      base = __shfl(base, 0, 64);
+      for (int i = lane; i < nh; i += 64) {
+        const int k = base + i;
+        if (k < cap) {
+          const int2 hh = hits[wave][i];
+          list[3 * k] = hh.x;
+          list[3 * k + 1] = hh.y;
+          list[3 * k + 2] = cp.w;
+        }
+      }
     }
-    wave_lds_sync(); /* qbox is reused by the next chunk pair */
+    wave_lds_sync(); /* qbox, hits are reused by the next chunk pair */
   }
 }
 
