@@ -706,7 +706,11 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* a,
 void launch_predict(const Scene& S, hipStream_t st);
 void launch_commit(const Scene& S, hipStream_t st);
 void launch_transform(const Scene& S, double* x, double* dx, hipStream_t st);
-void launch_body_terms(const Scene& S, hipStream_t st);
+void launch_body_terms(const Scene& S, hipStream_t st, const Counters* fresh = nullptr,
+                       int expect_reuse = 0);
+/* the pass reset of the device loop alone */
+void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
+                       hipStream_t st);
 void launch_boxes(const Scene& S, int swept, hipStream_t st);
 void launch_positions(const Scene& S, int swept, hipStream_t st,
                       const Counters* fresh = nullptr, int expect_reuse = 0);

@@ -115,13 +115,56 @@ __global__ void k_scale(Scene S, unsigned long long* out6) {
 /* ================================================================== */
 /* S3 + S6: body terms                                                 */
 /* ================================================================== */
+/* start of a pass of the device loop: fresh counter blocks (the static one
+ * taking over the previous pass's swept lists when they are complete),
+ * per-problem transients, the block-row counts and the PCG records */
+__device__ __forceinline__ void pass_reset(const Scene& S, const Counters& fresh,
+                                           int expect_reuse, int t, int nth) {
+  if (t == 0) {
+    /* The previous pass's swept lists cover every position q + alpha dq,
+     * alpha in [0, 1], of the bodies it swept: every static candidate of
+     * the accepted (or unchanged) state is among them, so they serve as
+     * this pass's static lists. */
+    const Counters c1 = S.cnt[1];
+    Counters c0 = fresh;
+    if (c1.sweep_ok) {
+      c0.n_bp = c1.n_bp;
+      c0.n_cp = c1.n_cp;
+      c0.n_pt = c1.n_pt;
+      c0.n_ee = c1.n_ee;
+      c0.n_pg = c1.n_pg;
+      c0.reuse = 1;
+    } else if (expect_reuse) {
+      c0.redo = 1;
+    }
+    S.cnt[0] = c0;
+    S.cnt[1] = fresh;
+  }
+  for (int q = t; q < S.NP; q += nth) {
+    ProbState& P = S.ps[q];
+    P.max_dq = 0;
+    P.min_toi = fresh.min_toi;
+    P.alpha_acc = 0.0;
+    P.bb = 0.0;
+    P.pcg_iters = 0;
+    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
+    for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
+  }
+  for (int i = t; i <= S.B; i += nth) S.row_cnt[i] = 0;
+  for (int i = t; i < 2 * ((S.B + 15) / 16); i += nth)
+    S.pcg_rec[i].gen = 0ull;
+}
+
 /* Per dynamic body: inertia 1/2 (q - qt)^T M (q - qt), orthogonality
  * h^2 kappa_A V |A A^T - I|^2 (Hessian projected to PSD), both weighted by
  * 1/kappa_b, and the ADMM penalty rho/2 |q - z + u|^2 of a shared body.
  * Writes g [B][12] and Hdiag [B][144] (static bodies: 0 and identity). */
 template <typename HT>
-__global__ __launch_bounds__(64) void k_body_terms(Scene S) {
+__global__ __launch_bounds__(64) void k_body_terms(Scene S, Counters fresh, int reset_mode) {
   const int b = blockIdx.x * 64 + threadIdx.x;
+  /* reset_mode (first launch of a device-loop pass): 1 the pass reset,
+   * 2 the same for a pass that expects to take its lists over */
+  if (reset_mode) pass_reset(S, fresh, reset_mode == 2, b, gridDim.x * 64);
   if (b >= S.B) return;
   if (!body_in_pass(S, b)) return;
   HT* Hd = (HT*)S.Hdiag + 144 * b;
@@ -363,52 +406,11 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
 
 /* world positions for the broad phase: x at q, and x + dx at q + dq for
  * the swept phase (the same canonical transforms as every other kernel) */
-/* start of a pass of the device loop: fresh counter blocks (the static one
- * taking over the previous pass's swept lists when they are complete),
- * per-problem transients, the block-row counts and the PCG records */
-__device__ __forceinline__ void pass_reset(const Scene& S, const Counters& fresh,
-                                           int expect_reuse, int t, int nth) {
-  if (t == 0) {
-    /* The previous pass's swept lists cover every position q + alpha dq,
-     * alpha in [0, 1], of the bodies it swept: every static candidate of
-     * the accepted (or unchanged) state is among them, so they serve as
-     * this pass's static lists. */
-    const Counters c1 = S.cnt[1];
-    Counters c0 = fresh;
-    if (c1.sweep_ok) {
-      c0.n_bp = c1.n_bp;
-      c0.n_cp = c1.n_cp;
-      c0.n_pt = c1.n_pt;
-      c0.n_ee = c1.n_ee;
-      c0.n_pg = c1.n_pg;
-      c0.reuse = 1;
-    } else if (expect_reuse) {
-      c0.redo = 1;
-    }
-    S.cnt[0] = c0;
-    S.cnt[1] = fresh;
-  }
-  for (int q = t; q < S.NP; q += nth) {
-    ProbState& P = S.ps[q];
-    P.max_dq = 0;
-    P.min_toi = fresh.min_toi;
-    P.alpha_acc = 0.0;
-    P.bb = 0.0;
-    P.pcg_iters = 0;
-    for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
-    for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
-  }
-  for (int i = t; i <= S.B; i += nth) S.row_cnt[i] = 0;
-  for (int i = t; i < 2 * ((S.B + 15) / 16); i += nth)
-    S.pcg_rec[i].gen = 0ull;
-}
-
-/* reset_mode (first launch of a device-loop pass): 1 the pass reset,
- * 2 the same for a pass that expects to take its lists over */
+/* reset_mode as for the body terms; swept < 0: the reset only */
 __global__ void k_positions(Scene S, int swept, Counters fresh, int reset_mode) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (reset_mode) pass_reset(S, fresh, reset_mode == 2, v, gridDim.x * blockDim.x);
-  if (v >= S.V || !body_in_pass(S, S.vbody[v])) return;
+  if (swept < 0 || v >= S.V || !body_in_pass(S, S.vbody[v])) return;
   double x[3], x1[3];
   if (swept) {
     vertex_pos_swept(S, v, x, x1);
@@ -625,13 +627,16 @@ __global__ void k_filter(Scene S, int hoff_words) {
        * that are not in this pass */
       if (body_in_pass(S, S.vbody[vid[0]])) {
         double x[12];
-        for (int k = 0; k < 4; ++k)
-          for (int c = 0; c < 3; ++c) x[3 * k + c] = S.xw[c * S.V + vid[k]];
+        for (int k = 0; k < 4; ++k) vertex_pos(S, vid[k], x + 3 * k);
         d = pair_dist(kind, x);
       }
     } else if (t < tot) {
       i = S.cand_pg[t - npt - nee];
-      if (body_in_pass(S, S.vbody[i])) d = S.xw[S.V + i] - S.ground_y;
+      if (body_in_pass(S, S.vbody[i])) {
+        double xv[3];
+        vertex_pos(S, i, xv);
+        d = xv[1] - S.ground_y;
+      }
     }
     dmin = fmin(dmin, fmax(d, 0.0));
     const bool ok = t < tot && d < S.dhat;
@@ -3224,11 +3229,20 @@ void launch_scale(const Scene& S, double* out6, hipStream_t st) {
   hipLaunchKernelGGL(k_scale, dim3(min(1024u, cdiv(S.V, 256))), dim3(256), 0,
                      st, S, (unsigned long long*)out6);
 }
-void launch_body_terms(const Scene& S, hipStream_t st) {
+void launch_body_terms(const Scene& S, hipStream_t st, const Counters* fresh,
+                       int expect_reuse) {
+  const Counters f = fresh ? *fresh : Counters{};
+  const int mode = fresh ? (expect_reuse ? 2 : 1) : 0;
   if (S.mixed)
-    hipLaunchKernelGGL(k_body_terms<float>, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S);
+    hipLaunchKernelGGL(k_body_terms<float>, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S, f, mode);
   else
-    hipLaunchKernelGGL(k_body_terms<double>, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S);
+    hipLaunchKernelGGL(k_body_terms<double>, dim3(cdiv(S.B, 64)), dim3(64), 0, st, S, f, mode);
+}
+void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
+                       hipStream_t st) {
+  const long n = std::max<long>(std::max<long>(S.B + 1, S.NP), 2L * ((S.B + 15) / 16));
+  hipLaunchKernelGGL(k_positions, dim3(cdiv(n, 256)), dim3(256), 0, st, S, -1, fresh,
+                     expect_reuse ? 2 : 1);
 }
 void launch_boxes(const Scene& S, int swept, hipStream_t st) {
   hipLaunchKernelGGL(k_boxes, dim3(cdiv(S.NC + S.B, 256)), dim3(256), 0, st, S, swept);

@@ -441,10 +441,9 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
 }
 
 /* ---------------- phases ---------------- */
-void broad_phase(abd_ctx* ctx, const Scene& S, int swept,
-                 const Counters* fresh = nullptr) {
+void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
   StageTimer t(ctx, 1);
-  launch_positions(S, swept, ctx->st, fresh, 0);
+  launch_positions(S, swept, ctx->st);
   launch_boxes(S, swept, ctx->st);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
@@ -456,11 +455,13 @@ void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd, bool with_ctrl = f
 
 /* static phase on the stream: body terms, broad phase, barrier assembly;
  * with take_over the candidate lists are the previous pass's swept lists
- * and only the positions are computed */
+ * (the filter computes the positions it needs).  fresh: the device-loop
+ * pass reset, run by the first kernel on the stream */
 void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
                    const Counters* fresh = nullptr) {
   const double body_bytes = (double)S.B * (96 * 3 + 128 + 8 + 1152 + 96);
   if (ctx->tune.overlap_body) {
+    if (fresh) launch_pass_reset(S, *fresh, take_over ? 1 : 0, ctx->st);
     /* body terms (writes g, Hdiag) on the side stream, concurrent with the
      * broad phase; the assembly (which adds into g, Hdiag) waits for it */
     (void)hipEventRecord(ctx->ev_fork, ctx->st);
@@ -472,14 +473,9 @@ void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
     (void)hipEventRecord(ctx->ev_join, ctx->side);
   } else {
     StageTimer t(ctx, 0, body_bytes);
-    launch_body_terms(S, ctx->st);
+    launch_body_terms(S, ctx->st, fresh, take_over ? 1 : 0);
   }
-  if (take_over) {
-    StageTimer t(ctx, 1);
-    launch_positions(S, 0, ctx->st, fresh, 1);
-  } else {
-    broad_phase(ctx, S, 0, fresh);
-  }
+  if (!take_over) broad_phase(ctx, S, 0);
   {
     StageTimer t(ctx, 2);
     launch_filter(S, ctx->st);
@@ -646,7 +642,7 @@ int energy(abd_ctx* ctx, int phase, double alpha, int mode, int with_pairs,
 void pass_pre(abd_ctx* ctx, bool take_over) {
   Scene S1 = ctx->S;
   S1.iter_mode = 1;
-  /* the pass reset runs in the first positions launch */
+  /* the pass reset runs in the first kernel of the static phase */
   const Counters fresh = fresh_counters();
   launch_static(ctx, S1, take_over, &fresh);
   StageTimer t(ctx, 6);
