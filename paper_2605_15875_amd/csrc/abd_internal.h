@@ -485,11 +485,9 @@ __host__ __device__ constexpr int sidx(int p, int q) {
 }
 
 /* ------------------------------------------------------------------ */
-/* cyclic Jacobi on a packed symmetric 9x9 held in registers (every     */
-/* index is a compile-time constant after unrolling), then projection   */
-/* to PSD in place: K <- V max(Lambda, 0) V^T.  Rotations in row order, */
-/* stop when the off-diagonal mass is below tol2 of the total (1e-30 in */
-/* FP64, 1e-12 in FP32, i.e. about the square of each precision).      */
+/* stopping bound of the Jacobi eigensolver of the PSD projections: the */
+/* off-diagonal mass below tol2 of the total (1e-30 in FP64, 1e-12 in   */
+/* FP32, i.e. about the square of each precision)                       */
 /* ------------------------------------------------------------------ */
 template <typename T> struct JacobiTol;
 template <> struct JacobiTol<double> {
@@ -711,7 +709,6 @@ void launch_body_terms(const Scene& S, hipStream_t st, const Counters* fresh = n
 /* the pass reset of the device loop alone */
 void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
                        hipStream_t st);
-void launch_boxes(const Scene& S, int swept, hipStream_t st);
 void launch_positions(const Scene& S, int swept, hipStream_t st,
                       const Counters* fresh = nullptr, int expect_reuse = 0);
 void launch_body_pairs(const Scene& S, hipStream_t st);

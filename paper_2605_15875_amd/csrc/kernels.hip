@@ -251,9 +251,7 @@ __global__ __launch_bounds__(64) void k_body_terms(Scene S, Counters fresh, int 
 /* ================================================================== */
 /* world boxes of every chunk and body (static: at q; swept: over the
  * step q -> q + dq) */
-__global__ void k_boxes(Scene S, int swept) {
-  if (S.cnt->reuse) return;
-  int t = blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void chunk_or_body_box(const Scene& S, int swept, int t) {
   int b;
   const double* rest;
   double* out;
@@ -406,11 +404,18 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
 
 /* world positions for the broad phase: x at q, and x + dx at q + dq for
  * the swept phase (the same canonical transforms as every other kernel) */
-/* reset_mode as for the body terms; swept < 0: the reset only */
+/* reset_mode as for the body terms; swept < 0: the reset only.  Threads
+ * past the vertices compute the chunk and body boxes of the phase (from
+ * the rest boxes, independent of the positions) */
 __global__ void k_positions(Scene S, int swept, Counters fresh, int reset_mode) {
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (reset_mode) pass_reset(S, fresh, reset_mode == 2, v, gridDim.x * blockDim.x);
-  if (swept < 0 || v >= S.V || !body_in_pass(S, S.vbody[v])) return;
+  if (swept < 0) return;
+  if (v >= S.V) {
+    if (!S.cnt->reuse) chunk_or_body_box(S, swept, v - S.V);
+    return;
+  }
+  if (!body_in_pass(S, S.vbody[v])) return;
   double x[3], x1[3];
   if (swept) {
     vertex_pos_swept(S, v, x, x1);
@@ -3244,15 +3249,12 @@ void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
   hipLaunchKernelGGL(k_positions, dim3(cdiv(n, 256)), dim3(256), 0, st, S, -1, fresh,
                      expect_reuse ? 2 : 1);
 }
-void launch_boxes(const Scene& S, int swept, hipStream_t st) {
-  hipLaunchKernelGGL(k_boxes, dim3(cdiv(S.NC + S.B, 256)), dim3(256), 0, st, S, swept);
-}
 void launch_positions(const Scene& S, int swept, hipStream_t st,
                       const Counters* fresh, int expect_reuse) {
   const Counters f = fresh ? *fresh : Counters{};
   const int mode = fresh ? (expect_reuse ? 2 : 1) : 0;
-  hipLaunchKernelGGL(k_positions, dim3(cdiv(S.V, 256)), dim3(256), 0, st, S, swept, f,
-                     mode);
+  hipLaunchKernelGGL(k_positions, dim3(cdiv((long)S.V + S.NC + S.B, 256)), dim3(256), 0,
+                     st, S, swept, f, mode);
 }
 void launch_body_pairs(const Scene& S, hipStream_t st) {
   unsigned g = cdiv(S.B, 16);

@@ -444,7 +444,6 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
 void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
   StageTimer t(ctx, 1);
   launch_positions(S, swept, ctx->st);
-  launch_boxes(S, swept, ctx->st);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
   launch_prim_pairs(S, swept, ctx->st);
