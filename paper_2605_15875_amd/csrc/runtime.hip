@@ -96,6 +96,7 @@ struct abd_ctx {
   /* with ABD_TIMING_PCG, every pcg_sample-th pass of a solve is run in
    * halves with events around its PCG launch; the others run whole */
   int pcg_sample = 4;
+  unsigned long long pass_seq = 0; /* passes launched by this context */
   bool pass_timed[2] = {false, false};
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
@@ -787,8 +788,10 @@ int device_solve(abd_ctx* ctx) {
    * the static broad phase; the others take over the swept lists */
   bool full = true;
   auto enqueue = [&]() -> int {
+    /* the sample runs over all passes of the context, so it does not
+     * favour the first passes of a solve */
     const bool timed = ctx->timing == ABD_TIMING_PCG &&
-                       queued % std::max(1, ctx->pcg_sample) == 0;
+                       ctx->pass_seq++ % std::max(1, ctx->pcg_sample) == 0;
     ctx->pass_timed[queued & 1] = timed || ctx->timing == ABD_TIMING_ALL;
     int rc = run_pass(ctx, !full, timed); /* ends by writing its counters to the ring */
     if (rc) return rc;

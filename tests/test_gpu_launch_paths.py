@@ -53,7 +53,7 @@ def test_launch_paths_match_oracle(name, mode):
     elif mode["timing"] == abd.TIMING_PCG:
         # a sample of the passes: at least one PCG launch per solve, fewer
         # than one per Newton iteration, and bytes for exactly those
-        assert 8 <= tm["pcg"]["launches"] < newton
+        assert 2 <= tm["pcg"]["launches"] < newton
         assert tm["pcg"]["ms"] > 0.0 and tm["pcg"]["bytes"] > 0.0
         assert all(v["launches"] == 0 for s, v in tm.items() if s != "pcg")
     else:
