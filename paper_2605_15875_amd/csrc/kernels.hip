@@ -925,6 +925,13 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
   T v[9];
 #pragma unroll
   for (int m = 0; m < 9; ++m) v[m] = (m == r) ? T(1) : T(0);
+  /* the matrix lives in LDS between rounds (row r also in lane r's
+   * registers during a round) */
+  if (on) {
+#pragma unroll
+    for (int m = 0; m < 9; ++m) X.row[r][m] = k[m];
+  }
+  wave_lds_sync();
   for (int sweep = 0; sweep < 60; ++sweep) {
     T fro = 0, offs = 0;
 #pragma unroll
@@ -946,11 +953,6 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
 #pragma unroll
     for (int kr = 0; kr < 9; ++kr) {
       const int pr = (2 * kr + 18 - r) % 9; /* partner of row r */
-      if (on) {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) X.row[r][m] = k[m];
-      }
-      wave_lds_sync();
       /* the pair's leading lane: its rotation */
       if (on && r < pr) {
         const T app = X.row[r][r], aqq = X.row[pr][pr], apq = X.row[r][pr];
@@ -999,35 +1001,39 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
         for (int m = 0; m < 9; ++m) X.row[r][m] = k1[m];
       }
       wave_lds_sync();
-      /* rows: J^T (K J), with the partner row from LDS */
+      /* rows: J^T (K J), with the partner row from LDS; the annihilated
+       * 2x2 block is then written into the row in LDS */
       const int lead = r < pr ? r : pr;
       const T c = X.cs[lead][0], sn = X.cs[lead][1];
-      if (on && pr != r && sn != T(0)) {
-        const T t = X.cs[lead][2], app = X.cs[lead][3], aqq = X.cs[lead][4],
-                apq = X.cs[lead][5];
+      const bool rot = on && pr != r && sn != T(0);
+      if (rot) {
         const T sg = r < pr ? -sn : sn;
 #pragma unroll
         for (int m = 0; m < 9; ++m) k[m] = c * k1[m] + sg * X.row[pr][m];
-#pragma unroll
-        for (int m = 0; m < 9; ++m) {
-          if (m == r) k[m] = r < pr ? app - t * apq : aqq + t * apq;
-          if (m == pr) k[m] = T(0);
-        }
-      } else {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) k[m] = k1[m];
       }
       wave_lds_sync();
+      if (rot) {
+        const T t = X.cs[lead][2], app = X.cs[lead][3], aqq = X.cs[lead][4],
+                apq = X.cs[lead][5];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) X.row[r][m] = k[m];
+        X.row[r][r] = r < pr ? app - t * apq : aqq + t * apq;
+        X.row[r][pr] = T(0);
+      }
+      wave_lds_sync();
+      if (on) {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) k[m] = X.row[r][m];
+      }
     }
   }
   /* V max(D, 0) V^T, row r */
+  T lam = T(0);
+  if (on) lam = X.row[r][r];
+  wave_lds_sync();
   if (on) {
 #pragma unroll
     for (int m = 0; m < 9; ++m) X.row[r][m] = v[m];
-    T lam = T(0);
-#pragma unroll
-    for (int m = 0; m < 9; ++m)
-      if (m == r) lam = k[m];
     X.row[r][9] = fmax(lam, T(0));
   }
   wave_lds_sync();
