@@ -199,10 +199,9 @@ def main():
     if a.autotune:
         log(f"autotuned: {solver.autotune()}")
     tuning = solver.tuning()
-    # timed region: every fourth pass runs in two captured halves around an
-    # event-bracketed PCG launch (the others run as whole captured passes),
-    # so the PCG kernel's launch duration is measured on a sample of the
-    # timed region's own launches
+    # timed region: the PCG launch of every fourth pass is bracketed by
+    # events, so the PCG kernel's launch duration is measured on a sample of
+    # the timed region's own launches
     solver.set_timing(abd.TIMING_PCG)
     solver.reset_timing()
     torch.cuda.synchronize()

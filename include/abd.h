@@ -205,7 +205,8 @@ typedef struct abd_tuning {
   int32_t grid_blocks;     /* blocks of the grid-stride broad-phase, filter and
                               CCD kernels (default 1024) */
   int32_t assemble_blocks; /* blocks of the barrier assembly (default 2048) */
-  int32_t use_graphs;      /* replay Newton passes from captured graphs (1) */
+  int32_t use_graphs;      /* replay Newton passes from captured graphs (1)
+                              or launch their kernels directly (0, default) */
   int32_t overlap_body;    /* body terms on a second stream, overlapping the
                               broad phase (1), or in line (0, default) */
   int32_t pcg_coop;        /* 1: cooperative PCG launch; 0 (default): plain

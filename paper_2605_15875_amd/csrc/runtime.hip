@@ -98,9 +98,15 @@ struct abd_ctx {
   int pcg_sample = 4;
   unsigned long long pass_seq = 0; /* passes launched by this context */
   bool pass_timed[2] = {false, false};
+  /* whether the next PCG launch is timed with ABD_TIMING_PCG (the device
+   * loop clears it for passes outside the sample) */
+  bool pcg_timed_now = true;
   bool graphs_ok = true; /* capture available on this runtime */
   bool own_stream = false;
-  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 1, 0, 0};
+  /* direct launches by default: on the benchmark scene a replayed graph
+   * per pass costs more at each graph boundary than the pass's kernel
+   * launches do (the host queues passes ahead either way) */
+  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 0, 0, 0};
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -205,7 +211,7 @@ struct StageTimer {
      * is not part of the captured graphs */
     active = !ctx->capturing &&
              (ctx->timing == ABD_TIMING_ALL ||
-              (ctx->timing == ABD_TIMING_PCG && stage == 3));
+              (ctx->timing == ABD_TIMING_PCG && stage == 3 && ctx->pcg_timed_now));
     if (active) {
       a = get_event(ctx);
       (void)hipEventRecord(a, stream);
@@ -728,6 +734,7 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
  * take_over the first half skips the static broad phase and takes over the
  * previous pass's swept lists (a pass that finds none changes no state). */
 int run_pass(abd_ctx* ctx, bool take_over, bool timed) {
+  ctx->pcg_timed_now = timed;
   const bool graphs = ctx->tune.use_graphs && ctx->graphs_ok &&
                       ctx->timing != ABD_TIMING_ALL &&
                       ctx->st != nullptr;
@@ -776,6 +783,11 @@ int run_pass(abd_ctx* ctx, bool take_over, bool timed) {
  * pass queued after an overflowing one repeats it, since the controller
  * keeps the state of a pass whose lists overflowed. */
 int device_solve(abd_ctx* ctx) {
+  /* PCG launches outside the device loop are timed as before */
+  struct TimedAgain {
+    abd_ctx* c;
+    ~TimedAgain() { c->pcg_timed_now = true; }
+  } timed_again{ctx};
   launch_ctrl_start(ctx->S, ctx->st);
   const int max_pass =
       ctx->P.max_newton * (2 + (ctx->P.max_ls + LS_TRIALS) / LS_TRIALS) + 8;
@@ -2171,6 +2183,11 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   {
     abd_tuning t = best;
     t.pcg_coop = best.pcg_coop ? 0 : 1;
+    consider(t);
+  }
+  {
+    abd_tuning t = best;
+    t.use_graphs = best.use_graphs ? 0 : 1;
     consider(t);
   }
   /* restore the state and keep the winner */

@@ -1,7 +1,8 @@
 """The device loop's launch paths give the same solve: whole passes replayed
 from one captured graph (no timing), passes in two captured halves around
 an event-timed PCG launch (every fourth pass with PCG timing), direct
-launches (every stage timed) and no graphs at all.  From the oracle's state
+launches with every stage timed, and direct launches (the default) with
+and without PCG timing.  From the oracle's state
 each time step lands on the oracle's positions, and the timed modes report
 what they timed.  Graph replays are repeated across several solves with
 host work in between, so a replay that kept stale state would show."""
@@ -14,10 +15,11 @@ from paper_2605_15875_amd import abd, scenes
 pytestmark = pytest.mark.gpu
 
 MODES = [
-    ("whole graphs", dict(timing=abd.TIMING_OFF)),
-    ("sampled PCG timing", dict(timing=abd.TIMING_PCG)),
+    ("whole graphs", dict(timing=abd.TIMING_OFF, use_graphs=1)),
+    ("graphs, sampled PCG timing", dict(timing=abd.TIMING_PCG, use_graphs=1)),
     ("every stage timed", dict(timing=abd.TIMING_ALL)),
-    ("no graphs", dict(timing=abd.TIMING_OFF, use_graphs=0)),
+    ("direct launches", dict(timing=abd.TIMING_OFF, use_graphs=0)),
+    ("direct, sampled PCG timing", dict(timing=abd.TIMING_PCG, use_graphs=0)),
 ]
 
 

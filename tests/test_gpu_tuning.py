@@ -23,6 +23,7 @@ SETTINGS = [
     dict(pcg_variant=abd.PCG_TWO_BARRIER, pcg_blocks=1),
     dict(grid_blocks=7, assemble_blocks=3),
     dict(use_graphs=0),
+    dict(use_graphs=1),
     dict(overlap_body=1),
     dict(pcg_coop=0),
 ]
