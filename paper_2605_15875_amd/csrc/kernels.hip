@@ -900,45 +900,50 @@ __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int 
  * accumulated with FP64 atomics into g, Hdiag and Hoff. */
 #define PAIRS_PER_WG 16
 /* PSD projection of a symmetric 9x9 matrix by cyclic Jacobi with the
- * rotations of a sweep run in parallel: one matrix per group of 16 lanes,
- * lane r (< 9) holding row r of the matrix and row r of the accumulated
- * rotation V.  A sweep has nine rounds; round k pairs index a with
- * (2k - a) mod 9 (the round-robin order, index k rests), so each round's
- * four rotations touch disjoint rows and columns and commute, and every
- * pair is visited once per sweep.  Each rotation is the serial step: the
- * tangent t = sgn(a) b / (|a| + hypot(a, b)) with a = aqq - app, b = 2 apq,
+ * rotations of a sweep run in parallel: one matrix per group of 32 lanes,
+ * lane r (< 9) holding row r of the matrix and lane 16 + r row r of the
+ * accumulated rotation V, so that one column update serves both.  A sweep
+ * has nine rounds; round k pairs index a with (2k - a) mod 9 (the
+ * round-robin order, index k rests), so each round's four rotations touch
+ * disjoint rows and columns and commute, and every pair is visited once
+ * per sweep.  Each rotation is the serial step: the tangent
+ * t = sgn(a) b / (|a| + hypot(a, b)) with a = aqq - app, b = 2 apq,
  * c = 1 / sqrt(1 + t^2), s = t c, columns then rows, and the annihilated
  * 2x2 block set to (app - t apq, aqq + t apq, 0).  The lane of the lower
  * index of a pair computes its rotation and shares it through LDS.
  * Rotations whose apq^2 is below 1/36 of the stopping bound are skipped; a
  * sweep starts only while the mass of the upper triangle (rounding leaves
  * the two triangles slightly different) exceeds tol2 of the total.  The
- * result, V max(D,0) V^T, replaces row r in place. */
+ * result, V max(D,0) V^T, replaces row r in place (matrix lanes). */
 template <typename T>
 struct JacX {
-  T row[9][10]; /* rows of the matrix (of V at the end, max(D,0) in col 9) */
+  T row[9][10]; /* rows of the matrix between rounds */
+  T vrow[9][9]; /* rows of V at the end */
+  T lam[9];     /* max(D, 0) */
   T cs[9][6];   /* rotation of the pair led by each index: c s t app aqq apq */
 };
 template <typename T>
-__device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
+__device__ __forceinline__ void psd9_par(JacX<T>& X, int g, bool on, T* k) {
   constexpr T tol2 = JacobiTol<T>::tol2;
-  T v[9];
+  const bool is_k = g < 16;
+  const int r = is_k ? g : g - 16;
+  const bool kon = on && is_k && r < 9; /* a row of the matrix */
+  const bool von = on && !is_k && r < 9; /* a row of V */
+  T x[9];
 #pragma unroll
-  for (int m = 0; m < 9; ++m) v[m] = (m == r) ? T(1) : T(0);
-  /* the matrix lives in LDS between rounds (row r also in lane r's
-   * registers during a round) */
-  if (on) {
+  for (int m = 0; m < 9; ++m) x[m] = kon ? k[m] : ((m == r) ? T(1) : T(0));
+  if (kon) {
 #pragma unroll
-    for (int m = 0; m < 9; ++m) X.row[r][m] = k[m];
+    for (int m = 0; m < 9; ++m) X.row[r][m] = x[m];
   }
   wave_lds_sync();
   for (int sweep = 0; sweep < 60; ++sweep) {
     T fro = 0, offs = 0;
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
-      const T x = on ? k[m] : T(0);
-      fro += x * x;
-      offs += (m > r) ? x * x : T(0);
+      const T v = kon ? x[m] : T(0);
+      fro += v * v;
+      offs += (m > r) ? v * v : T(0);
     }
 #pragma unroll
     for (int o = 8; o > 0; o >>= 1) {
@@ -946,15 +951,15 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
       offs += __shfl_xor(offs, o, 16);
     }
     /* a sweep that skips all 36 rotations leaves the upper triangle under
-     * the bound */
-    const bool done = !on || offs == T(0) || offs <= tol2 * fro;
+     * the bound (the V lanes only follow) */
+    const bool done = !kon || offs == T(0) || offs <= tol2 * fro;
     if (__all(done)) break;
     const T skip2 = tol2 * T(1.0 / 36.0) * fro;
 #pragma unroll
     for (int kr = 0; kr < 9; ++kr) {
       const int pr = (2 * kr + 18 - r) % 9; /* partner of row r */
       /* the pair's leading lane: its rotation */
-      if (on && r < pr) {
+      if (kon && r < pr) {
         const T app = X.row[r][r], aqq = X.row[pr][pr], apq = X.row[r][pr];
         T c = T(1), sn = T(0), t = T(0);
         if (apq * apq > skip2) {
@@ -977,72 +982,68 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int r, bool on, T* k) {
         c4[i] = X.cs[p][0];
         s4[i] = X.cs[p][1];
       }
-      /* columns: K J and V J (local to the row) */
-      T k1[9], v1[9];
+      /* columns: K J on the matrix lanes, V J on the V lanes */
+      T x1[9];
 #pragma unroll
       for (int m = 0; m < 9; ++m) {
         const int pm = (2 * kr + 9 - m) % 9;
         if (pm == m) {
-          k1[m] = k[m];
-          v1[m] = v[m];
+          x1[m] = x[m];
           continue;
         }
         /* the pair of column m: m = kr +- (i + 1) mod 9 */
         const int d = (m + 9 - kr) % 9;
         const int i = (d <= 4 ? d : 9 - d) - 1;
         const T sg = m < pm ? -s4[i] : s4[i];
-        k1[m] = c4[i] * k[m] + sg * k[pm];
-        v1[m] = c4[i] * v[m] + sg * v[pm];
+        x1[m] = c4[i] * x[m] + sg * x[pm];
       }
+      if (kon) {
 #pragma unroll
-      for (int m = 0; m < 9; ++m) v[m] = v1[m];
-      if (on) {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) X.row[r][m] = k1[m];
+        for (int m = 0; m < 9; ++m) X.row[r][m] = x1[m];
       }
       wave_lds_sync();
-      /* rows: J^T (K J), with the partner row from LDS; the annihilated
-       * 2x2 block is then written into the row in LDS */
+      /* rows of the matrix: J^T (K J), with the partner row from LDS; the
+       * annihilated 2x2 block is then written into the row in LDS */
       const int lead = r < pr ? r : pr;
       const T c = X.cs[lead][0], sn = X.cs[lead][1];
-      const bool rot = on && pr != r && sn != T(0);
+      const bool rot = kon && pr != r && sn != T(0);
       if (rot) {
         const T sg = r < pr ? -sn : sn;
 #pragma unroll
-        for (int m = 0; m < 9; ++m) k[m] = c * k1[m] + sg * X.row[pr][m];
+        for (int m = 0; m < 9; ++m) x[m] = c * x1[m] + sg * X.row[pr][m];
       }
       wave_lds_sync();
       if (rot) {
         const T t = X.cs[lead][2], app = X.cs[lead][3], aqq = X.cs[lead][4],
                 apq = X.cs[lead][5];
 #pragma unroll
-        for (int m = 0; m < 9; ++m) X.row[r][m] = k[m];
+        for (int m = 0; m < 9; ++m) X.row[r][m] = x[m];
         X.row[r][r] = r < pr ? app - t * apq : aqq + t * apq;
         X.row[r][pr] = T(0);
       }
       wave_lds_sync();
-      if (on) {
+      if (kon) {
 #pragma unroll
-        for (int m = 0; m < 9; ++m) k[m] = X.row[r][m];
+        for (int m = 0; m < 9; ++m) x[m] = X.row[r][m];
+      } else {
+#pragma unroll
+        for (int m = 0; m < 9; ++m) x[m] = x1[m];
       }
     }
   }
   /* V max(D, 0) V^T, row r */
-  T lam = T(0);
-  if (on) lam = X.row[r][r];
-  wave_lds_sync();
-  if (on) {
+  if (kon) X.lam[r] = fmax(X.row[r][r], T(0));
+  if (von) {
 #pragma unroll
-    for (int m = 0; m < 9; ++m) X.row[r][m] = v[m];
-    X.row[r][9] = fmax(lam, T(0));
+    for (int m = 0; m < 9; ++m) X.vrow[r][m] = x[m];
   }
   wave_lds_sync();
-  if (on) {
+  if (kon) {
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
       T acc = 0;
 #pragma unroll
-      for (int j = 0; j < 9; ++j) acc += v[j] * X.row[j][9] * X.row[m][j];
+      for (int j = 0; j < 9; ++j) acc += X.vrow[r][j] * X.lam[j] * X.vrow[m][j];
       k[m] = acc;
     }
   }
@@ -1055,7 +1056,7 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
   __shared__ double GW[33 * 64]; /* rows 0..8 g_y, 9..20 W_A, 21..32 W_B */
   __shared__ HT TB[216];
   __shared__ int meta[3 * 64];
-  __shared__ JacX<HT> JX[4];         /* Jacobi exchange, one per lane group */
+  __shared__ JacX<HT> JX[2];         /* Jacobi exchange, one per lane group */
   __shared__ HT IG[9 * 64];         /* inverse frame scales of each pair */
   __shared__ unsigned char proj[64]; /* the pair's 9x9 needs the projection */
   const int lane = threadIdx.x;
@@ -1144,16 +1145,17 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
     meta[128 + lane] = slot;
     __syncthreads();
     const int npairs = min(ppw, nact - base);
-    /* PSD projection of the PT/EE frame Hessians, four pairs at a time */
-    for (int j0 = 0; j0 < npairs; j0 += 4) {
-      const int j = j0 + lane / 16, r = lane % 16;
-      const bool on = j < npairs && r < 9 && proj[j];
+    /* PSD projection of the PT/EE frame Hessians, two pairs at a time */
+    for (int j0 = 0; j0 < npairs; j0 += 2) {
+      const int j = j0 + lane / 32, g = lane % 32, r = g;
+      const bool on = j < npairs && proj[j];
+      const bool kon = on && g < 9; /* the lanes holding the matrix rows */
       HT k[9];
 #pragma unroll
-      for (int m = 0; m < 9; ++m) k[m] = on ? KL[sidx(r, m) * 64 + j] : HT(0);
+      for (int m = 0; m < 9; ++m) k[m] = kon ? KL[sidx(r, m) * 64 + j] : HT(0);
       __syncthreads();
-      psd9_par<HT>(JX[lane / 16], r, on, k);
-      if (on) {
+      psd9_par<HT>(JX[lane / 32], g, on, k);
+      if (kon) {
         const HT ir = IG[r * 64 + j];
 #pragma unroll
         for (int m = 0; m < 9; ++m)
