@@ -2007,6 +2007,25 @@ __global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_
  * the partial sums.  Vectors read by other blocks are double-buffered by
  * phase; own rows stay in registers. */
 #define PCG_NB_MAX 96
+/* sum over the wavefront by DPP moves of the two halves of a double: row
+ * shifts by 1, 2, 4, 8 (an inclusive scan within each row of 16 lanes),
+ * then the last lane of row 0 into rows 1 and 3 and the last lane of row 1
+ * into rows 2 and 3; lane 63 ends with the total.  Lanes a shift reads
+ * from outside the row contribute zero. */
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_move(double x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ void wave_sum_dpp(double& x) {
+  x += dpp_move<0x111, 0xF>(x); /* row_shr:1 */
+  x += dpp_move<0x112, 0xF>(x); /* row_shr:2 */
+  x += dpp_move<0x114, 0xF>(x); /* row_shr:4 */
+  x += dpp_move<0x118, 0xF>(x); /* row_shr:8 */
+  x += dpp_move<0x142, 0xA>(x); /* row_bcast:15 into rows 1, 3 */
+  x += dpp_move<0x143, 0xC>(x); /* row_bcast:31 into rows 2, 3 */
+}
 template <typename HT>
 __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it) {
   const HT* __restrict__ Hd = (const HT*)S.Hdiag;
@@ -2093,6 +2112,24 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   auto reduce = [&](const double* v) {
     double x0 = v[0], x1 = v[1], x2 = v[2];
+    if (nloc == 1) {
+      /* one problem in the group: plain wavefront sums by DPP (the total
+       * lands in lane 63), then the three wavefronts' in order */
+      wave_sum_dpp(x0);
+      wave_sum_dpp(x1);
+      wave_sum_dpp(x2);
+      if (lane == 63) {
+        wsum[wave][0][0] = x0;
+        wsum[wave][0][1] = x1;
+        wsum[wave][0][2] = x2;
+      }
+      lds_barrier();
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) part[0][c] = wsum[0][0][c] + wsum[1][0][c] + wsum[2][0][c];
+      }
+      return;
+    }
 #pragma unroll
     for (int o = 1; o < 64; o <<= 1) {
       const double y0 = __shfl_down(x0, o, 64), y1 = __shfl_down(x1, o, 64),
