@@ -33,11 +33,11 @@ HBM_PEAK_GBS = 8000.0
 # otherwise traffic is null.
 PMC_TRAFFIC = {
     "kernel": "k_pcg_cg1<double>",
-    "fetch_kib": 2490.4,       # FETCH_SIZE per dispatch, 90 dispatches
-    "write_kib": 5350.8,       # WRITE_SIZE per dispatch, 90 dispatches
+    "fetch_kib": 2473.1,       # FETCH_SIZE per dispatch, 90 dispatches
+    "write_kib": 5346.0,       # WRITE_SIZE per dispatch, 90 dispatches
     "fetch_per_byte": 131086.5 / 262144.0,  # copy of 256 MiB reads 0.5
     "write_per_byte": 262144.0 / 262144.0,  # copy of 256 MiB writes 1.0
-    "sha256": "8c714d69eb9c220a53f90719a7a7f6ca0713d7cfc0b2206e2fb9c67aec4217a6",
+    "sha256": "6eaa85fabf0744a19da079fdfb0d3f500eee447519f4a32017c3fef0a441c2bb",
 }
 
 WORKLOAD = ("1000 icospheres (642 verts, 1280 tris each, r 0.05-0.15) "
