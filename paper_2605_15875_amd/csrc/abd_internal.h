@@ -710,7 +710,8 @@ void launch_body_terms(const Scene& S, hipStream_t st, const Counters* fresh = n
 void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
                        hipStream_t st);
 void launch_positions(const Scene& S, int swept, hipStream_t st,
-                      const Counters* fresh = nullptr, int expect_reuse = 0);
+                      const Counters* fresh = nullptr, int expect_reuse = 0,
+                      int stop_test = 0);
 void launch_body_pairs(const Scene& S, hipStream_t st);
 void launch_chunk_pairs(const Scene& S, hipStream_t st);
 void launch_prim_pairs(const Scene& S, int swept, hipStream_t st);

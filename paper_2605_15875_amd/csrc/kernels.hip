@@ -404,10 +404,20 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
 
 /* world positions for the broad phase: x at q, and x + dx at q + dq for
  * the swept phase (the same canonical transforms as every other kernel) */
+__device__ void newton_stop_test(const Scene& S, Counters* c0, int blk, int nblk);
 /* reset_mode as for the body terms; swept < 0: the reset only.  Threads
  * past the vertices compute the chunk and body boxes of the phase (from
- * the rest boxes, independent of the positions) */
-__global__ void k_positions(Scene S, int swept, Counters fresh, int reset_mode) {
+ * the rest boxes, independent of the positions).  With stop_test, the
+ * workgroups from nmain on run the Newton stop test of the device loop
+ * (|dq|_inf per problem, then the controller in the last of them); the
+ * swept positions of a problem that stops here are not used. */
+__global__ void k_positions(Scene S, int swept, Counters fresh, int reset_mode,
+                            int stop_test, int nmain) {
+  if (stop_test && (int)blockIdx.x >= nmain) {
+    /* this scene's counters are the swept block; the static one precedes */
+    newton_stop_test(S, S.cnt - 1, blockIdx.x - nmain, gridDim.x - nmain);
+    return;
+  }
   const int v = blockIdx.x * blockDim.x + threadIdx.x;
   if (reset_mode) pass_reset(S, fresh, reset_mode == 2, v, gridDim.x * blockDim.x);
   if (swept < 0) return;
@@ -2587,6 +2597,31 @@ __device__ __forceinline__ bool wave_uniform(int p) {
 __device__ __forceinline__ void ctrl_newton_check(const Scene& S, ProbState& P,
                                                   const Counters& c0);
 __device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n);
+/* |dq|_inf per problem over workgroup blk of nblk (256 bodies each) into
+ * the counter block c0, then the Newton stop test in the last of them */
+__device__ void newton_stop_test(const Scene& S, Counters* c0, int blk, int nblk) {
+  const int b = blk * blockDim.x + threadIdx.x;
+  const bool act = b < S.B;
+  const int p = act ? S.bprob[b] : -1;
+  double v = 0.0;
+  if (act)
+    for (int i = 0; i < 12; ++i) v = fmax(v, fabs(S.dq[12 * b + i]));
+  const bool uni = wave_uniform(p); /* inactive lanes make it non-uniform */
+  if (uni) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_down(v, o, 64));
+    if ((threadIdx.x & 63) == 0) {
+      atomic_max_pos(&S.ps[p].max_dq, v);
+      atomic_max_pos(&c0->max_dq, v);
+    }
+  } else if (act) {
+    atomic_max_pos(&S.ps[p].max_dq, v);
+    atomic_max_pos(&c0->max_dq, v);
+  }
+  if (last_workgroup(&c0->fin[0], (unsigned)nblk))
+    for (int q = threadIdx.x; q < S.NP; q += blockDim.x)
+      ctrl_newton_check(S, S.ps[q], *c0);
+}
+
 /* |dq|_inf per problem; with_ctrl: then the Newton stop test */
 __global__ void k_dq_norm(Scene S, int with_ctrl) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
@@ -3292,14 +3327,16 @@ void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
                        hipStream_t st) {
   const long n = std::max<long>(std::max<long>(S.B + 1, S.NP), 2L * ((S.B + 15) / 16));
   hipLaunchKernelGGL(k_positions, dim3(cdiv(n, 256)), dim3(256), 0, st, S, -1, fresh,
-                     expect_reuse ? 2 : 1);
+                     expect_reuse ? 2 : 1, 0, 0);
 }
 void launch_positions(const Scene& S, int swept, hipStream_t st,
-                      const Counters* fresh, int expect_reuse) {
+                      const Counters* fresh, int expect_reuse, int stop_test) {
   const Counters f = fresh ? *fresh : Counters{};
   const int mode = fresh ? (expect_reuse ? 2 : 1) : 0;
-  hipLaunchKernelGGL(k_positions, dim3(cdiv((long)S.V + S.NC + S.B, 256)), dim3(256), 0,
-                     st, S, swept, f, mode);
+  const unsigned nmain = cdiv((long)S.V + S.NC + S.B, 256);
+  const unsigned g = nmain + (stop_test ? cdiv(S.B, 256) : 0u);
+  hipLaunchKernelGGL(k_positions, dim3(g), dim3(256), 0, st, S, swept, f, mode, stop_test,
+                     (int)nmain);
 }
 void launch_body_pairs(const Scene& S, hipStream_t st) {
   unsigned g = cdiv(S.B, 16);

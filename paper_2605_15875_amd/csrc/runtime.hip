@@ -448,9 +448,9 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
 }
 
 /* ---------------- phases ---------------- */
-void broad_phase(abd_ctx* ctx, const Scene& S, int swept) {
+void broad_phase(abd_ctx* ctx, const Scene& S, int swept, int stop_test = 0) {
   StageTimer t(ctx, 1);
-  launch_positions(S, swept, ctx->st);
+  launch_positions(S, swept, ctx->st, nullptr, 0, stop_test);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
   launch_prim_pairs(S, swept, ctx->st);
@@ -565,7 +565,8 @@ void launch_swept(abd_ctx* ctx, bool ccd, bool energy_at_toi) {
 }
 
 void launch_swept_s(abd_ctx* ctx, const Scene& Ssw, bool ccd, bool with_ctrl) {
-  broad_phase(ctx, Ssw, 1);
+  /* with the controller: the Newton stop test rides on the positions launch */
+  broad_phase(ctx, Ssw, 1, with_ctrl ? 1 : 0);
   if (ccd) {
     StageTimer t(ctx, 4);
     launch_ccd(Ssw, with_ctrl ? 1 : 0, ctx->st);
@@ -672,9 +673,9 @@ void pass_post(abd_ctx* ctx) {
   Scene S2 = swept_scene(ctx);
   S2.iter_mode = 2;
   /* the controller runs in the last workgroup of the |dq| reduction (stop
-   * test), of CCD (first trial step) and of the trial energies (decision);
-   * the update's last workgroup ends the pass */
-  launch_dq_norm(S1, 1, ctx->st);
+   * test, part of the swept positions launch), of CCD (first trial step)
+   * and of the trial energies (decision); the update's last workgroup ends
+   * the pass */
   launch_swept_s(ctx, S2, true, true);
   {
     StageTimer t(ctx, 5);
