@@ -4,13 +4,17 @@
  *   prediction of Eq. 1 and commit      k_predict, k_commit
  *   body terms (inertia, orthogonality,  k_body_terms
  *   ADMM penalty of Eq. 5)
- *   broad phase                          k_boxes, k_body_pairs,
+ *   broad phase                          k_positions (positions, chunk and
+ *                                        body boxes), k_body_pairs,
  *                                        k_chunk_pairs, k_prim_pairs, k_pg
  *   barrier (narrow phase + assembly)    k_filter, k_assemble
- *   block-Jacobi PCG                     k_bsr_*, k_block_inverse, k_pcg
- *   Newton stop                          k_dq_norm
+ *   block-Jacobi PCG                     k_bsr_*, k_block_inverse, k_pcg_cg1
+ *                                        (k_pcg_local, k_pcg, k_pcg1)
+ *   Newton stop                          k_positions (swept, stop-test
+ *                                        workgroups), k_dq_norm
  *   CCD step bound                       k_ccd
- *   line search energy                   k_energy, k_reduce
+ *   line search energy                   k_energy_multi, k_energy, k_reduce
+ *   device loop                          k_ctrl_start, k_update_multi
  */
 #include <algorithm>
 #include <cstddef>
