@@ -1214,19 +1214,10 @@ int abd_finalize(abd_ctx* ctx) {
     HIPCHK(hipMemset(S.ps, 0, sizeof(ProbState) * S.NP));
   }
   if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
-      /* the ring is coherent host memory: the device's stores reach it
-       * without a cache writeback, so the events that mark the passes need
-       * no system-scope fence (which would write back and invalidate the
-       * caches between passes) */
-      hipHostMalloc((void**)&ctx->h_ring, 4 * sizeof(Counters), hipHostMallocCoherent) !=
-          hipSuccess ||
+      hipHostMalloc((void**)&ctx->h_ring, 4 * sizeof(Counters)) != hipSuccess ||
       hipHostGetDevicePointer((void**)&ctx->d_ring, ctx->h_ring, 0) != hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ring_ev[0],
-                              hipEventDisableTiming | hipEventDisableSystemFence) !=
-          hipSuccess ||
-      hipEventCreateWithFlags(&ctx->ring_ev[1],
-                              hipEventDisableTiming | hipEventDisableSystemFence) !=
-          hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ring_ev[0], hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&ctx->ring_ev[1], hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
