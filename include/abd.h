@@ -97,6 +97,11 @@ typedef struct abd_params {
   int32_t has_ground;  /* vertex-ground pairs against y = ground_y */
   int32_t mollify_ee;  /* edge-edge mollifier on |ea x eb|^2 */
   int32_t precision;   /* ABD_FP64 or ABD_MIXED */
+  int64_t list_capacity; /* initial capacity of each pair and candidate list;
+                            0: the default (64K entries, body pairs at least
+                            4 per body).  Lists grow on overflow either way:
+                            a small value exercises that growth, a large one
+                            avoids it on scenes known to be contact-rich */
 } abd_params;
 
 typedef struct abd_stats {

@@ -29,7 +29,8 @@ class Params(C.Structure):
                 ("pcg_eta", C.c_double), ("ground_y", C.c_double),
                 ("max_newton", C.c_int32), ("max_pcg", C.c_int32),
                 ("max_ls", C.c_int32), ("has_ground", C.c_int32),
-                ("mollify_ee", C.c_int32), ("precision", C.c_int32)]
+                ("mollify_ee", C.c_int32), ("precision", C.c_int32),
+                ("list_capacity", C.c_int64)]
 
 
 class Tuning(C.Structure):
@@ -197,6 +198,7 @@ def make_params(p: dict) -> Params:
     o.has_ground = int(p.get("has_ground", 0))
     o.mollify_ee = int(p.get("mollify_ee", 1))
     o.precision = int(p.get("precision", 0))
+    o.list_capacity = int(p.get("list_capacity", 0))
     return o
 
 

@@ -900,7 +900,7 @@ int abd_create(abd_ctx** out, const abd_params* p) {
   if (!(p->dt > 0) || !(p->dhat > 0) || !(p->kappa > 0) || !(p->kappa_A >= 0) ||
       p->max_newton < 1 || p->max_pcg < 1 || p->max_ls < 0 ||
       !(p->newton_theta > 0) || !(p->pcg_eta > 0) ||
-      (p->precision != ABD_FP64 && p->precision != ABD_MIXED))
+      (p->precision != ABD_FP64 && p->precision != ABD_MIXED) || p->list_capacity < 0)
     return ABD_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1153,6 +1153,10 @@ int abd_finalize(abd_ctx* ctx) {
   S.cap_bp = std::max(4 * B, 4096);
   S.cap_cp = 1 << 16;
   S.cap_pt = S.cap_ee = S.cap_pg = S.cap_act = 1 << 16;
+  if (ctx->P.list_capacity > 0) {
+    const int c = (int)std::min<int64_t>(ctx->P.list_capacity, 1 << 29);
+    S.cap_bp = S.cap_cp = S.cap_pt = S.cap_ee = S.cap_pg = S.cap_act = c;
+  }
   S.cap_col = 2 * S.cap_bp;
   S.cap_partials = 1024;
   if ((rc = dalloc(ctx, &S.bp, S.cap_bp))) return rc;
