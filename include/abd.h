@@ -188,6 +188,28 @@ int abd_set_step(abd_ctx* ctx, const double* qt, const double* qtilde,
  * captured graphs). */
 int abd_set_stream(abd_ctx* ctx, void* hip_stream);
 
+/* Caller-owned device memory for the context's buffers (the caller's
+ * allocator, e.g. PyTorch's, owns the memory; the library sub-allocates).
+ * dev_ptr: device memory of the current device, bytes >= 256; it must stay
+ * valid and untouched by the caller until abd_destroy.  Bind once, after
+ * abd_create and before abd_finalize: from then on every buffer of the
+ * context (scene data, state, lists, Hessian blocks, PCG vectors, test-hook
+ * and autotune temporaries) is taken from it, 256-byte aligned, as a stack;
+ * lists grown during a solve take fresh space above the lists they replace,
+ * whose space comes back only once nothing above it is live.  Pinned host
+ * counters, events and graphs, and the objects of abd_batch_* and
+ * abd_consensus_*, are allocated by the library as before.  When the
+ * workspace runs out the call that needed memory fails with ABD_E_OOM and
+ * abd_last_error names the size asked for; the context keeps its state.
+ * Errors: INVALID_ARG (NULL context or pointer, bytes < 256, pointer not
+ * device memory of the current device, context finalized or already
+ * bound). */
+int abd_bind_workspace(abd_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* info[3]: usable workspace bytes (0 when none is bound), bytes in use
+ * (top of the stack), and the most ever in use. */
+int abd_workspace_info(const abd_ctx* ctx, int64_t* info);
+
 /* ---- launch tuning ---- */
 #define ABD_PCG_TWO_BARRIER 0 /* textbook PCG: two grid barriers per iteration */
 #define ABD_PCG_PIPELINED 1   /* single-reduction PCG: one grid barrier */

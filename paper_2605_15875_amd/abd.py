@@ -94,7 +94,7 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_autotune", "abd_consensus_create", "abd_consensus_destroy",
            "abd_consensus_begin", "abd_consensus_update",
            "abd_consensus_adapt", "abd_consensus_merge", "abd_consensus_get",
-           "abd_admm_step"]
+           "abd_admm_step", "abd_bind_workspace", "abd_workspace_info"]
 
 
 TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
@@ -130,6 +130,8 @@ def lib():
         "abd_get_qtilde": (C.c_int, [vp, dp]),
         "abd_set_step": (C.c_int, [vp, dp, dp, C.c_double]),
         "abd_set_stream": (C.c_int, [vp, vp]),
+        "abd_bind_workspace": (C.c_int, [vp, vp, C.c_size_t]),
+        "abd_workspace_info": (C.c_int, [vp, lp]),
         "abd_get_vertices": (C.c_int, [vp, dp, dp, dp, dp]),
         "abd_export_candidates": (C.c_int, [vp, C.c_int32, dp, ip, C.c_int64,
                                             lp]),
@@ -211,7 +213,10 @@ class AbdError(RuntimeError):
 class Solver:
     """One libabd context holding a scenes.Scene on the current device."""
 
-    def __init__(self, scene, finalize=True, **param_over):
+    def __init__(self, scene, finalize=True, workspace=None, **param_over):
+        """workspace: optional device memory for every buffer of the
+        context, a CUDA tensor (kept alive by the Solver) or a
+        (device pointer, bytes) pair."""
         L = lib()
         p = dict(scene.params)
         p.update(param_over)
@@ -223,6 +228,15 @@ class Solver:
             raise AbdError(rc, "abd_create failed")
         self.h = h
         self.scene = scene
+        self._ws = workspace
+        if workspace is not None:
+            if isinstance(workspace, tuple):
+                ptr, nbytes = workspace
+            else:
+                ptr = workspace.data_ptr()
+                nbytes = workspace.numel() * workspace.element_size()
+            self._check(L.abd_bind_workspace(h, C.c_void_p(int(ptr)),
+                                             int(nbytes)))
         bid = np.zeros(1, dtype=np.int32)
         for b in scene.bodies:
             xb = _f64(b.xbar)
@@ -241,12 +255,20 @@ class Solver:
         if getattr(self, "h", None):
             lib().abd_destroy(self.h)
             self.h = None
+        self._ws = None
 
     def __del__(self):
         try:
             self.close()
         except Exception:
             pass
+
+    def workspace_info(self):
+        """(usable bytes, bytes in use, most bytes ever in use) of the bound
+        workspace; zeros when none is bound."""
+        info = np.zeros(3, dtype=np.int64)
+        self._check(lib().abd_workspace_info(self.h, _l(info)))
+        return tuple(int(v) for v in info)
 
     def error(self):
         return lib().abd_last_error(self.h).decode()

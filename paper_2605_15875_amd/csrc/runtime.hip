@@ -81,7 +81,17 @@ struct abd_ctx {
   double* q_start = nullptr;  /* iterate at solve entry (mixed fallback) */
   hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
-  std::vector<void*> allocs;
+  std::vector<void*> allocs; /* device memory of our own (hipMalloc) */
+  /* caller workspace: blocks are handed out 256-byte aligned from its
+   * bottom, as a stack; a released block's bytes are taken back once every
+   * block above it has been released too */
+  struct WsBlock {
+    size_t off, bytes;
+    bool live;
+  };
+  char* ws_base = nullptr;
+  size_t ws_size = 0, ws_top = 0, ws_peak = 0;
+  std::vector<WsBlock> ws_blocks;
   int pcg_grid = 0;
   int n_cu = 0;
   int n_shared = 0;
@@ -139,27 +149,40 @@ void drop_graphs(abd_ctx* c) {
                   std::string(#call) + ": " + hipGetErrorString(e_));    \
   } while (0)
 
-template <class T>
-int dalloc(abd_ctx* ctx, T** p, size_t n) {
-  size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+/* Device memory for a context buffer: from the bound workspace if there is
+ * one, else from hipMalloc (kept in ctx->allocs, freed at destroy). */
+int dalloc_bytes(abd_ctx* ctx, void** p, size_t bytes) {
+  bytes = std::max<size_t>(bytes, 8);
+  if (ctx->ws_base) {
+    const size_t off = (ctx->ws_top + 255) & ~size_t(255);
+    if (off > ctx->ws_size || bytes > ctx->ws_size - off)
+      return fail(ctx, ABD_E_OOM,
+                  "workspace exhausted: " + std::to_string(bytes) +
+                      " bytes asked for at offset " + std::to_string(off) +
+                      " of a " + std::to_string(ctx->ws_size) +
+                      "-byte workspace");
+    ctx->ws_blocks.push_back({off, bytes, true});
+    ctx->ws_top = off + bytes;
+    ctx->ws_peak = std::max(ctx->ws_peak, ctx->ws_top);
+    *p = ctx->ws_base + off;
+    return ABD_OK;
+  }
   void* q = nullptr;
   if (hipMalloc(&q, bytes) != hipSuccess) {
     (void)hipGetLastError();
     return fail(ctx, ABD_E_OOM, "device allocation failed");
   }
   ctx->allocs.push_back(q);
-  *p = (T*)q;
+  *p = q;
   return ABD_OK;
 }
 
-int dalloc_bytes(abd_ctx* ctx, void** p, size_t bytes) {
+template <class T>
+int dalloc(abd_ctx* ctx, T** p, size_t n) {
   void* q = nullptr;
-  if (hipMalloc(&q, std::max<size_t>(bytes, 8)) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(ctx, ABD_E_OOM, "device allocation failed");
-  }
-  ctx->allocs.push_back(q);
-  *p = q;
+  int rc = dalloc_bytes(ctx, &q, std::max<size_t>(n, 1) * sizeof(T));
+  if (rc) return rc;
+  *p = (T*)q;
   return ABD_OK;
 }
 
@@ -173,6 +196,18 @@ constexpr size_t HESS_ALLOC = sizeof(double);
 template <class T>
 void dfree(abd_ctx* ctx, T* p) {
   if (!p) return;
+  const char* c = (const char*)p;
+  if (ctx->ws_base && c >= ctx->ws_base && c < ctx->ws_base + ctx->ws_size) {
+    const size_t off = size_t(c - ctx->ws_base);
+    for (auto& b : ctx->ws_blocks)
+      if (b.off == off) b.live = false;
+    while (!ctx->ws_blocks.empty() && !ctx->ws_blocks.back().live)
+      ctx->ws_blocks.pop_back();
+    ctx->ws_top = ctx->ws_blocks.empty()
+                      ? 0
+                      : ctx->ws_blocks.back().off + ctx->ws_blocks.back().bytes;
+    return;
+  }
   auto it = std::find(ctx->allocs.begin(), ctx->allocs.end(), (void*)p);
   if (it != ctx->allocs.end()) ctx->allocs.erase(it);
   (void)hipFree(p);
@@ -1475,6 +1510,40 @@ int abd_get_qtilde(const abd_ctx* cctx, double* qtilde) {
   return ABD_OK;
 }
 
+int abd_bind_workspace(abd_ctx* ctx, void* dev_ptr, size_t bytes) {
+  if (!ctx) return ABD_E_INVALID_ARG;
+  if (ctx->finalized || ctx->ws_base)
+    return fail(ctx, ABD_E_INVALID_ARG,
+                "a workspace is bound once, before abd_finalize");
+  if (!dev_ptr || bytes < 256)
+    return fail(ctx, ABD_E_INVALID_ARG, "workspace pointer or size invalid");
+  hipPointerAttribute_t at;
+  int dev = -1;
+  if (hipPointerGetAttributes(&at, dev_ptr) != hipSuccess ||
+      hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(ctx, ABD_E_INVALID_ARG, "workspace is not device memory");
+  }
+  if (at.type != hipMemoryTypeDevice || at.device != dev)
+    return fail(ctx, ABD_E_INVALID_ARG,
+                "workspace is not device memory of the current device");
+  char* b = (char*)dev_ptr;
+  const size_t pad = (256 - (uintptr_t)b % 256) % 256;
+  ctx->ws_base = b + pad;
+  ctx->ws_size = bytes - pad;
+  ctx->ws_top = ctx->ws_peak = 0;
+  ctx->ws_blocks.clear();
+  return ABD_OK;
+}
+
+int abd_workspace_info(const abd_ctx* ctx, int64_t* info) {
+  if (!ctx || !info) return ABD_E_INVALID_ARG;
+  info[0] = (int64_t)ctx->ws_size;
+  info[1] = (int64_t)ctx->ws_top;
+  info[2] = (int64_t)ctx->ws_peak;
+  return ABD_OK;
+}
+
 int abd_set_stream(abd_ctx* ctx, void* hip_stream) {
   if (!ctx) return ABD_E_INVALID_ARG;
   drop_graphs(ctx);
@@ -2109,9 +2178,9 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   Scene& S = ctx->S;
   const size_t nb = sizeof(double) * 12 * S.B;
   double *q0 = nullptr, *qd0 = nullptr;
-  if (hipMalloc(&q0, nb) != hipSuccess || hipMalloc(&qd0, nb) != hipSuccess) {
-    if (q0) (void)hipFree(q0);
-    return fail(ctx, ABD_E_OOM, "autotune state copy");
+  if (dalloc(ctx, &q0, 12L * S.B) || dalloc(ctx, &qd0, 12L * S.B)) {
+    dfree(ctx, q0);
+    return fail(ctx, ABD_E_OOM, "autotune state copy: " + ctx->err);
   }
   HIPCHK(hipMemcpyAsync(q0, S.q, nb, hipMemcpyDeviceToDevice, ctx->st));
   HIPCHK(hipMemcpyAsync(qd0, S.qdot, nb, hipMemcpyDeviceToDevice, ctx->st));
@@ -2201,8 +2270,8 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   HIPCHK(hipMemcpyAsync(S.q, q0, nb, hipMemcpyDeviceToDevice, ctx->st));
   HIPCHK(hipMemcpyAsync(S.qdot, qd0, nb, hipMemcpyDeviceToDevice, ctx->st));
   HIPCHK(hipStreamSynchronize(ctx->st));
-  (void)hipFree(q0);
-  (void)hipFree(qd0);
+  dfree(ctx, qd0);
+  dfree(ctx, q0);
   if (!std::isfinite(best_ms)) return fail(ctx, ABD_E_NOCONV, "autotune: no setting solved the step");
   if (out) *out = best;
   return ABD_OK;
