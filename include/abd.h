@@ -27,7 +27,8 @@
  *    during the call; every output pointer is a caller-allocated HOST buffer
  *    of the documented size;
  *  - the library owns all device memory (allocated in abd_finalize and
- *    grown on demand); work is issued on the bound stream (default: a
+ *    grown on demand), unless the caller binds a workspace of its own
+ *    (abd_bind_workspace); work is issued on the bound stream (default: a
  *    stream the library creates) and every call returns after its results
  *    are on the host;
  *  - arrays are FP64 unless stated, array-of-structures: points [n][3],
@@ -387,8 +388,15 @@ int abd_eval(abd_ctx* ctx, const double* q, double* E, double* g,
 int abd_direction(abd_ctx* ctx, double* dq, int32_t* pcg_iters);
 
 /* alpha_max = min(1, min over swept candidates of the additive-CCD
- * time of impact) for the step dq [B][12] from the current q. */
-int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max);
+ * time of impact) for the step dq [B][12] from the current q (the CCD
+ * filter of the line search, Sec. 3 and Alg. 1).  toi (may be NULL): each
+ * swept candidate's own time of impact in [0, 1] (1: no impact along the
+ * step), in the order abd_export_candidates(kind, dq) lists the pairs: PT,
+ * then EE, then PG, each sorted; cap is its capacity (CAPACITY when the
+ * candidates do not fit) and *count (may be NULL) receives their number.
+ * alpha_max equals min(1, min of toi). */
+int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max, double* toi,
+            int64_t cap, int64_t* count);
 
 /* E(q + alpha dq) - E(q) at the current q, summed term by term. */
 int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,

@@ -137,7 +137,7 @@ def lib():
                                             lp]),
         "abd_eval": (C.c_int, [vp, dp, dp, dp, dp, C.c_int64, lp, ip, dp, lp]),
         "abd_direction": (C.c_int, [vp, dp, ip]),
-        "abd_ccd": (C.c_int, [vp, dp, dp]),
+        "abd_ccd": (C.c_int, [vp, dp, dp, dp, C.c_int64, lp]),
         "abd_energy_delta": (C.c_int, [vp, dp, C.c_double, dp]),
         "abd_set_timing": (C.c_int, [vp, C.c_int32]),
         "abd_get_timing": (C.c_int, [vp, C.c_int32, dp, lp, dp]),
@@ -388,11 +388,20 @@ class Solver:
         self._check(lib().abd_direction(self.h, _d(dq), _i(it)))
         return dq, int(it[0])
 
-    def ccd(self, dq):
+    def ccd(self, dq, per_pair=False):
+        """alpha_max of the step dq; with per_pair, also each swept
+        candidate's TOI (PT, EE, PG pairs in the order of candidates())."""
         dd = _f64(dq, (-1, 12))
         a = np.zeros(1)
-        self._check(lib().abd_ccd(self.h, _d(dd), _d(a)))
-        return float(a[0])
+        n = np.zeros(1, dtype=np.int64)
+        if not per_pair:
+            self._check(lib().abd_ccd(self.h, _d(dd), _d(a), None, 0, None))
+            return float(a[0])
+        self._check(lib().abd_ccd(self.h, _d(dd), _d(a), None, 0, _l(n)))
+        toi = np.zeros(max(1, int(n[0])))
+        self._check(lib().abd_ccd(self.h, _d(dd), _d(a), _d(toi), len(toi),
+                                  _l(n)))
+        return float(a[0]), toi[:int(n[0])]
 
     def energy_delta(self, dq, alpha):
         dd = _f64(dq, (-1, 12))

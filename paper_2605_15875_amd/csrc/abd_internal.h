@@ -726,6 +726,8 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
 int pcg_max_grid();
 void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st);
 void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st);
+/* each candidate's TOI into toi[n] (n = the list's PT + EE + PG count) */
+void launch_ccd_pairs(const Scene& S, double* toi, int64_t n, hipStream_t st);
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st);
 void launch_energy_multi(const Scene& S, hipStream_t st);

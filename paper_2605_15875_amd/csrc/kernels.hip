@@ -12,7 +12,7 @@
  *                                        (k_pcg_local, k_pcg, k_pcg1)
  *   Newton stop                          k_positions (swept, stop-test
  *                                        workgroups), k_dq_norm
- *   CCD step bound                       k_ccd
+ *   CCD step bound                       k_ccd (k_ccd_pairs: each pair's TOI)
  *   line search energy                   k_energy_multi, k_energy, k_reduce
  *   device loop                          k_ctrl_start, k_update_multi
  */
@@ -2655,6 +2655,40 @@ __global__ void k_dq_norm(Scene S, int with_ctrl) {
 /* ================================================================== */
 __device__ __forceinline__ void ctrl_first_trial(ProbState& P);
 /* with_ctrl: then the first trial step of every problem */
+/* TOI of candidate t of the list (PT, then EE, then PG), clamped to
+ * [0, 1]; *prob receives its problem.  With use_bound the advance of a PT
+ * or EE pair stops once it passes the smallest TOI its problem has reached
+ * (a lower bound of the pair's TOI that cannot lower the minimum). */
+__device__ __forceinline__ double candidate_toi(const Scene& S, int t, int npt,
+                                                int nee, bool use_bound,
+                                                int* prob) {
+  double toi = 1.0;
+  if (t < npt + nee) {
+    const int* c = t < npt ? S.cand_pt + 3 * t : S.cand_ee + 3 * (t - npt);
+    int kind = t < npt ? C_PT : C_EE;
+    int vid[4];
+    pair_vertices(S, kind, c[0], c[1], vid);
+    double x[12], dx[12];
+    for (int k = 0; k < 4; ++k) {
+      int v = vid[k], b = S.vbody[v];
+      double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
+      xform(S.q + 12 * b, b0, b1, b2, x + 3 * k);
+      xform(S.dq + 12 * b, b0, b1, b2, dx + 3 * k);
+    }
+    *prob = S.bprob[S.vbody[vid[0]]];
+    toi = accd(kind, x, dx, 1.0, use_bound ? &S.ps[*prob].min_toi : nullptr);
+  } else {
+    int v = S.cand_pg[t - npt - nee], b = S.vbody[v];
+    double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
+    double x[3], dx[3];
+    xform(S.q + 12 * b, b0, b1, b2, x);
+    xform(S.dq + 12 * b, b0, b1, b2, dx);
+    if (dx[1] < 0.0) toi = (1.0 - ACCD_S) * (x[1] - S.ground_y) / (-dx[1]);
+    *prob = S.bprob[b];
+  }
+  return fmax(fmin(toi, 1.0), 0.0);
+}
+
 __global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
@@ -2666,32 +2700,8 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
   double tmin = 1.0;
   for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
        t += gridDim.x * blockDim.x) {
-    double toi = 1.0;
     int prob;
-    if (t < npt + nee) {
-      const int* c = t < npt ? S.cand_pt + 3 * t : S.cand_ee + 3 * (t - npt);
-      int kind = t < npt ? C_PT : C_EE;
-      int vid[4];
-      pair_vertices(S, kind, c[0], c[1], vid);
-      double x[12], dx[12];
-      for (int k = 0; k < 4; ++k) {
-        int v = vid[k], b = S.vbody[v];
-        double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
-        xform(S.q + 12 * b, b0, b1, b2, x + 3 * k);
-        xform(S.dq + 12 * b, b0, b1, b2, dx + 3 * k);
-      }
-      prob = S.bprob[S.vbody[vid[0]]];
-      toi = accd(kind, x, dx, 1.0, &S.ps[prob].min_toi);
-    } else {
-      int v = S.cand_pg[t - npt - nee], b = S.vbody[v];
-      double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
-      double x[3], dx[3];
-      xform(S.q + 12 * b, b0, b1, b2, x);
-      xform(S.dq + 12 * b, b0, b1, b2, dx);
-      if (dx[1] < 0.0) toi = (1.0 - ACCD_S) * (x[1] - S.ground_y) / (-dx[1]);
-      prob = S.bprob[b];
-    }
-    toi = fmax(fmin(toi, 1.0), 0.0);
+    const double toi = candidate_toi(S, t, npt, nee, true, &prob);
     tmin = fmin(tmin, toi);
     if (toi < 1.0) atomic_min_pos(&S.ps[prob].min_toi, toi);
   }
@@ -2702,6 +2712,20 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
     atomic_min_pos(&S.cnt->min_toi, fmax(tmin, 0.0));
   if (with_ctrl && last_workgroup(&S.cnt->fin[1], nwork))
     for (int q = threadIdx.x; q < S.NP; q += blockDim.x) ctrl_first_trial(S.ps[q]);
+}
+
+/* every candidate's own TOI, without the early stop (a test hook):
+ * toi[t] for the t-th candidate of the list */
+__global__ __launch_bounds__(256) void k_ccd_pairs(Scene S, double* toi) {
+  const int npt = min(S.cnt->n_pt, S.cap_pt);
+  const int nee = min(S.cnt->n_ee, S.cap_ee);
+  const int npg = min(S.cnt->n_pg, S.cap_pg);
+  const int tot = npt + nee + npg;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
+       t += gridDim.x * blockDim.x) {
+    int prob;
+    toi[t] = candidate_toi(S, t, npt, nee, false, &prob);
+  }
 }
 
 /* ================================================================== */
@@ -3478,6 +3502,10 @@ void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st) {
 }
 void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st) {
   hipLaunchKernelGGL(k_ccd, dim3(S.grid_blocks), dim3(256), 0, st, S, with_ctrl);
+}
+void launch_ccd_pairs(const Scene& S, double* toi, int64_t n, hipStream_t st) {
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_ccd_pairs, dim3(blocks), dim3(256), 0, st, S, toi);
 }
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st) {

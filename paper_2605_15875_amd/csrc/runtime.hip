@@ -1700,13 +1700,49 @@ int abd_direction(abd_ctx* ctx, double* dq, int32_t* pcg_iters) {
   return ABD_OK;
 }
 
-int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max) {
+int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max, double* toi,
+            int64_t cap, int64_t* count) {
   int rc = check_ctx(ctx, true);
   if (rc) return rc;
-  if (!dq || !alpha_max) return fail(ctx, ABD_E_INVALID_ARG, "ccd");
+  if (!dq || !alpha_max || cap < 0) return fail(ctx, ABD_E_INVALID_ARG, "ccd");
   if ((rc = upload_dq(ctx, dq))) return rc;
   if ((rc = swept_phase(ctx, true))) return rc;
   *alpha_max = std::min(1.0, bits_to_double(ctx->h_cnt[1].min_toi));
+  const Scene& S = ctx->S;
+  const Counters& c = ctx->h_cnt[1];
+  const int64_t npt = std::min(c.n_pt, S.cap_pt), nee = std::min(c.n_ee, S.cap_ee),
+                npg = std::min(c.n_pg, S.cap_pg), n = npt + nee + npg;
+  if (count) *count = n;
+  if (!toi) return ABD_OK;
+  if (n > cap) return fail(ctx, ABD_E_CAPACITY, "TOI buffer too small");
+  if (n == 0) return ABD_OK;
+  double* d_toi = nullptr;
+  if ((rc = dalloc(ctx, &d_toi, n))) return rc;
+  launch_ccd_pairs(swept_scene(ctx), d_toi, n, ctx->st);
+  std::vector<double> t(n);
+  std::vector<int> pt(3 * npt), ee(3 * nee), pg(npg);
+  hipError_t e = hipStreamSynchronize(ctx->st);
+  if (e == hipSuccess) e = hipMemcpy(t.data(), d_toi, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && npt)
+    e = hipMemcpy(pt.data(), S.cand_pt, sizeof(int) * 3 * npt, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && nee)
+    e = hipMemcpy(ee.data(), S.cand_ee, sizeof(int) * 3 * nee, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && npg)
+    e = hipMemcpy(pg.data(), S.cand_pg, sizeof(int) * npg, hipMemcpyDeviceToHost);
+  dfree(ctx, d_toi);
+  if (e != hipSuccess) return fail(ctx, ABD_E_DEVICE, std::string("ccd: ") + hipGetErrorString(e));
+  /* the candidates' order of abd_export_candidates: PT pairs sorted, then
+   * EE pairs sorted, then PG vertices sorted */
+  int64_t o = 0;
+  auto emit = [&](int64_t first, int64_t m, auto key) {
+    std::vector<int64_t> idx(m);
+    for (int64_t i = 0; i < m; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+    for (int64_t i = 0; i < m; ++i) toi[o++] = t[first + idx[i]];
+  };
+  emit(0, npt, [&](int64_t i) { return std::make_pair(pt[3 * i], pt[3 * i + 1]); });
+  emit(npt, nee, [&](int64_t i) { return std::make_pair(ee[3 * i], ee[3 * i + 1]); });
+  emit(npt + nee, npg, [&](int64_t i) { return std::make_pair(pg[i], 0); });
   return ABD_OK;
 }
 

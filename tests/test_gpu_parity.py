@@ -109,6 +109,46 @@ def test_direction_ccd_energy_parity(cubes_contact, cubes_gpu):
             assert dg == pytest.approx(do, rel=1e-7, abs=1e-14)
 
 
+def test_per_pair_toi_parity(cubes_contact, cubes_gpu):
+    """Each swept candidate's own time of impact against the oracle's
+    additive CCD of that pair (positions and step from the oracle's vertex
+    map), in the exported candidate order, and alpha_max as their
+    minimum."""
+    sc, ref, states = cubes_contact
+    offs = np.cumsum([0] + [len(b.xbar) for b in sc.bodies[:-1]])
+    tris = np.concatenate([b.tris + o for b, o in zip(sc.bodies, offs)])
+    edges = ref.edges()
+    s = 0.1                      # additive-CCD gap fraction of both sides
+    impacts = 0
+    for k in (9, 13, 15):
+        q, qd = states[k]
+        set_both(cubes_gpu, ref, q, qd)
+        dq, _ = ref.direction(q)
+        for scale in (1.0, 4.0):       # a longer step reaches more contacts
+            d = scale * dq
+            a, toi = cubes_gpu.ccd(d, per_pair=True)
+            pt, ee, pg = (cubes_gpu.candidates(kd, d)
+                          for kd in (O.PT, O.EE, O.PG))
+            assert len(toi) == len(pt) + len(ee) + len(pg) > 0
+            x, dx = ref.vertices(q), ref.vertices(d)   # dx = J d (linear)
+            want = []
+            for kd, pairs in ((O.PT, pt), (O.EE, ee)):
+                for i, j in pairs:
+                    vid = ([i, *tris[j]] if kd == O.PT
+                           else [*edges[i], *edges[j]])
+                    want.append(O.accd(kd, x[vid].ravel(), dx[vid].ravel(),
+                                       s))
+            for v in pg:
+                dy = dx[v, 1]
+                want.append((1 - s) * (x[v, 1] - sc.params["ground_y"]) / -dy
+                            if dy < 0 else 1.0)
+            want = np.clip(np.array(want), 0.0, 1.0)
+            np.testing.assert_allclose(toi, want, rtol=1e-9, atol=1e-15)
+            assert a == min(1.0, float(toi.min()))
+            impacts += int((toi < 1.0).sum())
+    assert impacts > 0
+
+
 def test_step_parity_from_shared_state(cubes_contact, cubes_gpu):
     """Each time step of the 8-cube run from the oracle's start state:
     positions within 1e-9 of the scene scale, same Newton iteration
