@@ -420,6 +420,31 @@ int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms,
                    int64_t* launches, double* bytes);
 int abd_reset_timing(abd_ctx* ctx);
 
+/* ---- load balancing of the plane between two workers (Sec. 5.2) ----
+ * A discrete-time PD controller on the workers' smoothed frame times moves
+ * the plane p_12 + s n_12 that separates worker 1 from worker 2 (n_12 from
+ * 1 to 2): Eq. 13, T = (eta - 1) / (eta + 1) with eta = tau_1 / tau_2 (0
+ * when balanced, > 0 when worker 1 is slower), and Eq. 14, the shift
+ * dp = k_p T + k_d (T - T_prev), applied by the caller as p_12 += dp n_12.
+ * The times are smoothed as tau = (1 - smooth) tau + smooth t, starting
+ * from the first frame's times; the first frame has no derivative term.
+ * As printed, a controller that shrinks the slower worker's side has
+ * negative gains in this orientation.  Host-only: no device is used. */
+typedef struct abd_balance {
+  double k_p, k_d;  /* gains, in plane-shift length per unit imbalance */
+  double smooth;    /* weight of the newest frame time, in (0, 1] */
+  double tau[2];    /* state: smoothed times of workers 1 and 2 */
+  double T_prev;    /* state: imbalance of the previous frame */
+  int32_t frames;   /* state: frames seen; 0 starts the controller afresh */
+  int32_t pad_;
+} abd_balance;
+
+/* One frame: the compute times t1, t2 > 0 of workers 1 and 2 update the
+ * state of *b and *dp receives the plane shift of Eq. 14.  Errors:
+ * INVALID_ARG (NULL pointer, a time not finite and positive, smooth outside
+ * (0, 1], a gain not finite); the state is then left as it was. */
+int abd_balance_update(abd_balance* b, double t1, double t2, double* dp);
+
 #ifdef __cplusplus
 }
 #endif

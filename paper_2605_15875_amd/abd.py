@@ -81,6 +81,13 @@ class Stats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BalanceState(C.Structure):
+    _fields_ = [("k_p", C.c_double), ("k_d", C.c_double),
+                ("smooth", C.c_double), ("tau", C.c_double * 2),
+                ("T_prev", C.c_double), ("frames", C.c_int32),
+                ("pad_", C.c_int32)]
+
+
 _lib = None
 EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_finalize", "abd_sizes", "abd_set_shared",
@@ -94,7 +101,8 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_autotune", "abd_consensus_create", "abd_consensus_destroy",
            "abd_consensus_begin", "abd_consensus_update",
            "abd_consensus_adapt", "abd_consensus_merge", "abd_consensus_get",
-           "abd_admm_step", "abd_bind_workspace", "abd_workspace_info"]
+           "abd_admm_step", "abd_bind_workspace", "abd_workspace_info",
+           "abd_balance_update"]
 
 
 TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
@@ -132,6 +140,8 @@ def lib():
         "abd_set_stream": (C.c_int, [vp, vp]),
         "abd_bind_workspace": (C.c_int, [vp, vp, C.c_size_t]),
         "abd_workspace_info": (C.c_int, [vp, lp]),
+        "abd_balance_update": (C.c_int, [C.POINTER(BalanceState), C.c_double,
+                                         C.c_double, dp]),
         "abd_get_vertices": (C.c_int, [vp, dp, dp, dp, dp]),
         "abd_export_candidates": (C.c_int, [vp, C.c_int32, dp, ip, C.c_int64,
                                             lp]),
@@ -563,3 +573,20 @@ class Consensus:
         if check and rc != OK:
             raise AbdError(rc, "abd_admm_step: " + self.batch.solvers[0].error())
         return r.as_dict()
+
+
+class Balance:
+    """PD controller of the plane between two workers (libabd host code):
+    update(t1, t2) takes the frame times of workers 1 and 2 and returns the
+    shift of the plane along its normal (from worker 1 to worker 2)."""
+
+    def __init__(self, k_p, k_d, smooth=1.0):
+        self.st = BalanceState(k_p=k_p, k_d=k_d, smooth=smooth)
+
+    def update(self, t1, t2):
+        dp = C.c_double()
+        rc = lib().abd_balance_update(C.byref(self.st), float(t1), float(t2),
+                                      C.byref(dp))
+        if rc != OK:
+            raise AbdError(rc, "abd_balance_update: bad gains or times")
+        return dp.value

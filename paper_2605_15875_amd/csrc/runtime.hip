@@ -1544,6 +1544,27 @@ int abd_workspace_info(const abd_ctx* ctx, int64_t* info) {
   return ABD_OK;
 }
 
+int abd_balance_update(abd_balance* b, double t1, double t2, double* dp) {
+  if (!b || !dp || !std::isfinite(t1) || !std::isfinite(t2) || !(t1 > 0.0) ||
+      !(t2 > 0.0) || !(b->smooth > 0.0 && b->smooth <= 1.0) ||
+      !std::isfinite(b->k_p) || !std::isfinite(b->k_d))
+    return ABD_E_INVALID_ARG;
+  if (b->frames <= 0) {
+    b->tau[0] = t1;
+    b->tau[1] = t2;
+  } else {
+    b->tau[0] = (1.0 - b->smooth) * b->tau[0] + b->smooth * t1;
+    b->tau[1] = (1.0 - b->smooth) * b->tau[1] + b->smooth * t2;
+  }
+  const double eta = b->tau[0] / b->tau[1];
+  const double T = (eta - 1.0) / (eta + 1.0); /* Eq. 13 */
+  const double Tp = b->frames <= 0 ? T : b->T_prev;
+  *dp = b->k_p * T + b->k_d * (T - Tp); /* Eq. 14 */
+  b->T_prev = T;
+  b->frames = b->frames <= 0 ? 1 : b->frames + 1;
+  return ABD_OK;
+}
+
 int abd_set_stream(abd_ctx* ctx, void* hip_stream) {
   if (!ctx) return ABD_E_INVALID_ARG;
   drop_graphs(ctx);
