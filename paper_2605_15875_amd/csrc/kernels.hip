@@ -2887,7 +2887,10 @@ __global__ void k_update_q(Scene S, double alpha) {
 /* ================================================================== */
 /* E(q + alpha_k dq) - E(q) for alpha_k = alpha_base 2^-k, k < LS_TRIALS,
  * per problem, over the bodies and swept candidates of problems that are
- * not done; one atomic per trial per wave when the wave is uniform. */
+ * not done.  A wave whose elements belong to one problem sums them per
+ * trial and keeps running sums across its grid-stride iterations; the
+ * workgroup then adds its waves' sums with one atomic per trial and
+ * problem (a wave straddling problems adds its lanes directly). */
 __device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n);
 __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
                                                 const Counters& c0,
@@ -2903,6 +2906,9 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
   const unsigned nwork = max(1u, min(gridDim.x, (unsigned)((nwaves + 3) / 4)));
   if (blockIdx.x >= nwork) return;
   const int lane = threadIdx.x & 63, k = lane & (LS_TRIALS - 1);
+  /* lanes k < LS_TRIALS: running sum of trial k for problem accp */
+  double acc = 0.0;
+  int accp = -1;
   for (int w = blockIdx.x * 4 + threadIdx.x / 64; w < nwaves; w += gridDim.x * 4) {
     const int t = w * 8 + lane / LS_TRIALS;
     double e = 0.0;
@@ -2951,11 +2957,41 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
     if (uni) {
       if (prob >= 0) {
         for (int o = 32; o >= LS_TRIALS; o >>= 1) e += __shfl_down(e, o, 64);
-        if (lane < LS_TRIALS) atomicAdd(&S.ps[prob].dE[k], e);
+        if (lane < LS_TRIALS) {
+          if (accp != prob) {
+            if (accp >= 0) atomicAdd(&S.ps[accp].dE[k], acc);
+            acc = 0.0;
+            accp = prob;
+          }
+          acc += e;
+        }
       }
     } else if (prob >= 0) {
       atomicAdd(&S.ps[prob].dE[k], e);
     }
+  }
+  /* the four waves' running sums: lanes 0..LS_TRIALS-1 of a wave share
+   * accp, so lane 0 publishes it */
+  __shared__ double s_acc[4][LS_TRIALS];
+  __shared__ int s_accp[4];
+  const int wv = threadIdx.x >> 6;
+  if (lane < LS_TRIALS) s_acc[wv][lane] = acc;
+  if (lane == 0) s_accp[wv] = accp;
+  __syncthreads();
+  if (threadIdx.x < LS_TRIALS) {
+    int p = -1;
+    double sum = 0.0;
+    for (int i = 0; i < 4; ++i) {
+      const int pi = s_accp[i];
+      if (pi < 0) continue;
+      if (pi != p) {
+        if (p >= 0) atomicAdd(&S.ps[p].dE[threadIdx.x], sum);
+        p = pi;
+        sum = 0.0;
+      }
+      sum += s_acc[i][threadIdx.x];
+    }
+    if (p >= 0) atomicAdd(&S.ps[p].dE[threadIdx.x], sum);
   }
   /* then every problem's line search decision (this scene's counters are
    * the swept block; the static block precedes it) */
