@@ -2698,12 +2698,27 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
   const unsigned nwork = max(1u, min(gridDim.x, (unsigned)((tot + 255) / 256)));
   if (blockIdx.x >= nwork) return;
   double tmin = 1.0;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
-       t += gridDim.x * blockDim.x) {
-    int prob;
-    const double toi = candidate_toi(S, t, npt, nee, true, &prob);
+  const int lane = threadIdx.x & 63;
+  /* whole workgroups step through the list together, so every lane of a
+   * wavefront takes part in the reductions below */
+  for (int base = blockIdx.x * blockDim.x; base < tot; base += gridDim.x * blockDim.x) {
+    const int t = base + threadIdx.x;
+    int prob = -1;
+    double toi = 1.0;
+    if (t < tot) toi = candidate_toi(S, t, npt, nee, true, &prob);
     tmin = fmin(tmin, toi);
-    if (toi < 1.0) atomic_min_pos(&S.ps[prob].min_toi, toi);
+    /* the wavefront's smallest TOI below 1 of its first such lane's problem
+     * with one atomic; lanes of other problems add theirs directly */
+    const int p = toi < 1.0 ? prob : -1;
+    const unsigned long long m = __ballot(p >= 0);
+    if (m) {
+      const int first = __ffsll((unsigned long long)m) - 1;
+      const int p0 = __shfl(p, first, 64);
+      double v = p == p0 ? toi : 1.0;
+      for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+      if (lane == first) atomic_min_pos(&S.ps[p0].min_toi, v);
+      if (p >= 0 && p != p0) atomic_min_pos(&S.ps[p].min_toi, toi);
+    }
   }
   for (int o = 32; o > 0; o >>= 1) tmin = fmin(tmin, __shfl_down(tmin, o, 64));
   /* waves without a TOI below 1 leave the minimum alone (its readers take
