@@ -154,8 +154,6 @@ def main():
                          "1: single-reduction form (default: library's)")
     ap.add_argument("--overlap-body", type=int, default=None,
                     help="1: body terms on a second stream, 0: in line")
-    ap.add_argument("--pcg-coop", type=int, default=None,
-                    help="1: cooperative PCG launch, 0: plain launch")
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner after warmup")
     ap.add_argument("--copy-probe", action="store_true",
@@ -190,8 +188,6 @@ def main():
         solver.set_tuning(pcg_variant=a.pcg_variant)
     if a.overlap_body is not None:
         solver.set_tuning(overlap_body=a.overlap_body)
-    if a.pcg_coop is not None:
-        solver.set_tuning(pcg_coop=a.pcg_coop)
     for i in range(a.warmup):
         st = solver.step()
         log(f"warmup {i}: newton={st['newton_iters']} "

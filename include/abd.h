@@ -227,7 +227,7 @@ typedef struct abd_tuning {
                               form carries u, s and t by recurrences, which
                               can stall short of a very tight tolerance such
                               as eta = 1e-12 on stiff contact systems) */
-  int32_t pcg_blocks;      /* blocks of the cooperative PCG launch, 16 bodies
+  int32_t pcg_blocks;      /* blocks of the persistent PCG launch, 16 bodies
                               each per pass; 0 = one block per 16 bodies up to
                               the co-resident limit */
   int32_t grid_blocks;     /* blocks of the grid-stride broad-phase, filter and
@@ -237,10 +237,12 @@ typedef struct abd_tuning {
                               or launch their kernels directly (0, default) */
   int32_t overlap_body;    /* body terms on a second stream, overlapping the
                               broad phase (1), or in line (0, default) */
-  int32_t pcg_coop;        /* 1: cooperative PCG launch; 0 (default): plain
-                              launch when the grid is at most half the
-                              compute units (always resident together),
-                              cooperative otherwise */
+  int32_t pcg_coop;        /* reserved, must be 0 (INVALID_ARG otherwise):
+                              the PCG is always a plain launch whose grid
+                              is at most what the device holds resident
+                              at once; its waits are bounded and end in
+                              DEVICE should the blocks not be resident
+                              together (another process filling the GPU) */
 } abd_tuning;
 
 /* Read or replace the launch settings of a finalized context.  Settings

@@ -1155,6 +1155,156 @@ double accd(int kind, const double* x, const double* dx, double s,
   return t;
 }
 
+/* ------------------------------------------------------------------ */
+/* exact time of impact along the linear trajectory                     */
+/* ------------------------------------------------------------------ */
+/* Affine bodies move every vertex on a straight line over a Newton step,
+ * x(t) = x + t dx.  Two primitives touch at the first t where their
+ * distance is zero, and a zero distance needs the four points to be
+ * coplanar, i.e. a root of the signed volume
+ *     PT: f(t) = ((t1 - t0) x (t2 - t0)) . (p - t0)
+ *     EE: f(t) = ((a1 - a0) x (b1 - b0)) . (b0 - a0),
+ * a cubic in t.  The real roots in [0, tmax] are isolated on the monotone
+ * pieces between the roots of f'(t) (a quadratic), bracketed by the sign of
+ * f evaluated directly from the moved points, and bisected down to adjacent
+ * doubles; a critical point where f nearly vanishes (a tangential touch) is
+ * a root candidate too.  The earliest candidate at which the primitives'
+ * distance is zero up to rounding (within 1e-12 of the coordinates'
+ * magnitude) is the contact; the lower end of its bracket is returned.  A
+ * pair whose signed volume vanishes identically (motion inside a common
+ * plane) is resolved by dense sampling of the distance instead.  Returns
+ * tmax when the primitives do not touch in [0, tmax]. */
+struct Moving {
+  const double* x;
+  const double* dx;
+  int kind;
+  void at(double t, double* y) const {
+    for (int i = 0; i < 12; ++i) y[i] = x[i] + t * dx[i];
+  }
+  /* (u, v, w) of the signed volume (u x v) . w for point set y */
+  void uvw(const double* y, double* u, double* v, double* w) const {
+    if (kind == ORC_PT) {
+      sub3(y + 6, y + 3, u);
+      sub3(y + 9, y + 3, v);
+      sub3(y + 0, y + 3, w);
+    } else {
+      sub3(y + 3, y + 0, u);
+      sub3(y + 9, y + 6, v);
+      sub3(y + 6, y + 0, w);
+    }
+  }
+  double volume(double t) const {
+    double y[12], u[3], v[3], w[3], n[3];
+    at(t, y);
+    uvw(y, u, v, w);
+    cross3(u, v, n);
+    return dot3(n, w);
+  }
+  double distance(double t) const {
+    double y[12];
+    at(t, y);
+    return pair_distance(kind, y);
+  }
+};
+
+/* bisect a sign change of f on [lo, hi] down to adjacent doubles; returns
+ * the lower end (f(lo) has the sign of the start or is zero) */
+double bisect_root(const Moving& m, double lo, double hi, double flo) {
+  if (flo == 0.0) return lo;
+  for (int it = 0; it < 2000; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    const double fm = m.volume(mid);
+    if (fm == 0.0) return mid;
+    if ((fm > 0.0) == (flo > 0.0)) {
+      lo = mid;
+      flo = fm;
+    } else {
+      hi = mid;
+    }
+  }
+  return lo;
+}
+
+double exact_toi(int kind, const double* x, const double* dx, double tmax) {
+  Moving m{x, dx, kind};
+  double mag = 0.0;
+  for (int i = 0; i < 12; ++i) mag = std::max(mag, std::fabs(x[i]) + std::fabs(dx[i]));
+  const double tol_d = 1e-12 * mag;
+  if (m.distance(0.0) <= tol_d) return 0.0;
+  /* cubic coefficients of f(t) = (u x v) . w with u = u0 + t du, ... */
+  double y0[12], u0[3], v0[3], w0[3], du[3], dv[3], dw[3];
+  m.at(0.0, y0);
+  m.uvw(y0, u0, v0, w0);
+  m.uvw(dx, du, dv, dw); /* the same differences of the displacements */
+  double n00[3], n01[3], n10[3], n11[3];
+  cross3(u0, v0, n00);
+  cross3(u0, dv, n01);
+  cross3(du, v0, n10);
+  cross3(du, dv, n11);
+  const double c1 = dot3(n00, dw) + dot3(n01, w0) + dot3(n10, w0);
+  const double c2 = dot3(n01, dw) + dot3(n10, dw) + dot3(n11, w0);
+  const double c3 = dot3(n11, dw);
+  const double c0 = dot3(n00, w0);
+  const double vol_scale = mag * mag * mag;
+  const double tol_f = 1e-13 * vol_scale;
+  if (std::fabs(c0) <= tol_f && std::fabs(c1) <= tol_f && std::fabs(c2) <= tol_f &&
+      std::fabs(c3) <= tol_f) {
+    /* coplanar throughout: first sampled zero distance */
+    const int N = 20000;
+    double prev = 0.0;
+    for (int i = 1; i <= N; ++i) {
+      const double t = tmax * i / N;
+      if (m.distance(t) <= tol_d) return prev;
+      prev = t;
+    }
+    return tmax;
+  }
+  /* split points: roots of f'(t) = c1 + 2 c2 t + 3 c3 t^2 inside (0, tmax) */
+  std::vector<double> cuts = {0.0};
+  {
+    const double A = 3.0 * c3, Bq = 2.0 * c2, Cq = c1;
+    std::vector<double> r;
+    if (std::fabs(A) > 1e-300) {
+      const double disc = Bq * Bq - 4.0 * A * Cq;
+      if (disc >= 0.0) {
+        const double sq = std::sqrt(disc);
+        /* numerically stable pair of roots */
+        const double qq = -0.5 * (Bq + (Bq >= 0.0 ? sq : -sq));
+        if (qq != 0.0) {
+          r.push_back(qq / A);
+          r.push_back(Cq / qq);
+        } else {
+          r.push_back(0.0);
+        }
+      }
+    } else if (std::fabs(Bq) > 1e-300) {
+      r.push_back(-Cq / Bq);
+    }
+    std::sort(r.begin(), r.end());
+    for (double t : r)
+      if (t > 0.0 && t < tmax) cuts.push_back(t);
+  }
+  cuts.push_back(tmax);
+  /* root candidates in increasing order */
+  std::vector<double> cand;
+  for (size_t k = 0; k + 1 < cuts.size(); ++k) {
+    const double a = cuts[k], b = cuts[k + 1];
+    const double fa = m.volume(a), fb = m.volume(b);
+    if (k > 0 && std::fabs(fa) <= tol_f) cand.push_back(a); /* touch at a cut */
+    if (fa == 0.0)
+      cand.push_back(a);
+    else if (fb == 0.0)
+      cand.push_back(b);
+    else if ((fa > 0.0) != (fb > 0.0))
+      cand.push_back(bisect_root(m, a, b, fa));
+  }
+  std::sort(cand.begin(), cand.end());
+  for (double t : cand)
+    if (t >= 0.0 && t <= tmax && m.distance(t) <= tol_d) return t;
+  return tmax;
+}
+
 double ccd_alpha(orc_scene* s, const std::vector<double>& x,
                  const std::vector<double>& dx, const Cands& C) {
   double amax = 1.0;
@@ -1834,6 +1984,11 @@ void orc_eig(int32_t n, const double* H, double* w, double* V) {
 double orc_accd(int32_t kind, const double* x12, const double* dx12,
                 double s, double tmax) {
   return accd(kind, x12, dx12, s, tmax);
+}
+
+double orc_exact_toi(int32_t kind, const double* x12, const double* dx12,
+                     double tmax) {
+  return exact_toi(kind, x12, dx12, tmax);
 }
 
 }  // extern "C"

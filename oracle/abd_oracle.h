@@ -129,6 +129,12 @@ void orc_eig(int32_t n, const double* H, double* w, double* V);
 /* additive CCD: returns the TOI in (0, tmax], tmax if no hit */
 double orc_accd(int32_t kind, const double* x12, const double* dx12,
                 double s, double tmax);
+/* exact first time of impact of a PT or EE pair moving as x + t dx: the
+ * earliest root of the coplanarity cubic in [0, tmax] at which the
+ * primitives' distance vanishes (lower end of its bisection bracket);
+ * tmax when they do not touch */
+double orc_exact_toi(int32_t kind, const double* x12, const double* dx12,
+                     double tmax);
 
 #ifdef __cplusplus
 }

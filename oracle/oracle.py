@@ -95,6 +95,7 @@ def lib():
             "orc_eig": (None, [C.c_int32, dp, dp, dp]),
             "orc_accd": (C.c_double, [C.c_int32, dp, dp, C.c_double,
                                       C.c_double]),
+            "orc_exact_toi": (C.c_double, [C.c_int32, dp, dp, C.c_double]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -405,3 +406,10 @@ def accd(kind, x12, dx12, s=0.1, tmax=1.0):
     x = _f64(x12, (12,))
     d = _f64(dx12, (12,))
     return float(lib().orc_accd(kind, _d(x), _d(d), float(s), float(tmax)))
+
+
+def exact_toi(kind, x12, dx12, tmax=1.0):
+    """Exact first time of impact of a PT or EE pair (tmax: none)."""
+    x = _f64(x12, (12,))
+    d = _f64(dx12, (12,))
+    return float(lib().orc_exact_toi(kind, _d(x), _d(d), float(tmax)))

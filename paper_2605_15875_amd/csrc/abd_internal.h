@@ -722,7 +722,7 @@ void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st);
 void launch_bsr(const Scene& S, hipStream_t st);
 void launch_block_inverse(const Scene& S, hipStream_t st);
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
-               int coop, hipStream_t st);
+               hipStream_t st);
 int pcg_max_grid();
 void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st);
 void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st);

@@ -1418,7 +1418,7 @@ __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
   }
 }
 
-/* grid-wide barrier for the cooperative PCG launch.  The workgroup barrier
+/* grid-wide barrier for the persistent PCG launch.  The workgroup barrier
  * puts every wave's stores in L2; thread 0's agent-scope release add then
  * makes them visible device-wide, and its acquire loads (before the final
  * workgroup barrier) order the block's later reads after every arrival.
@@ -1483,7 +1483,7 @@ __device__ __forceinline__ double ld_acq(const double* p) {
       (const unsigned long long*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
 }
 
-/* When every block of the cooperative PCG launch owns exactly one 16-body
+/* When every block of the persistent PCG launch owns exactly one 16-body
  * group, the group's rows of the system (diagonal blocks, block inverses
  * and up to PCG_OFF_CACHE off-diagonal blocks) stay in LDS for all
  * iterations: after each grid barrier only the vectors written by other
@@ -1521,7 +1521,7 @@ __device__ __forceinline__ bool pcg_cache_load(PcgCache<HT>& C, const Scene& S,
 
 /* Block-Jacobi preconditioned CG on H dq = -g with zero initial guess,
  * every problem running its own recurrence, all iterations in one
- * cooperative launch.  Each block owns 16 bodies (192 rows) per pass of a
+ * persistent launch.  Each block owns 16 bodies (192 rows) per pass of a
  * grid-stride loop.  Per iteration: phase A forms p_k = z_k + beta_k
  * p_{k-1} on the fly and the product A p_k; phase B updates dq, r and
  * z = P^-1 r; two grid barriers.  Dots are reduced in FP64 into each
@@ -3080,17 +3080,22 @@ __device__ __forceinline__ void ctrl_first_trial(ProbState& P) {
 
 /* whether this workgroup is the last of the grid to arrive at the counter
  * (which starts the kernel at zero); the last one may read what the others
- * accumulated with device-scope atomics before arriving.  Only the first n
- * workgroups of the grid arrive (those with work: the arrivals on one
- * address are serialised, so idle workgroups leave without one).  The block
- * barrier waits until every wavefront's atomics have completed, so the
- * arrival itself needs no release (which would write back the whole L2 in
- * every workgroup); only the last workgroup acquires. */
+ * accumulated with device-scope atomics (and stored) before arriving.  Only
+ * the first n workgroups of the grid arrive (those with work: the arrivals
+ * on one address are serialised, so idle workgroups leave without one).
+ * The workgroup barrier by itself does not wait for outstanding vector
+ * memory operations (a workgroup-scope release waits only for LDS here),
+ * so every wavefront first waits until its own atomics and stores have
+ * been acknowledged (vmcnt = 0), and thread 0 then arrives with an
+ * agent-scope release (one L2 write-back per workgroup, for plain stores);
+ * only the last workgroup acquires. */
 __device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n) {
   __shared__ int s_last;
+  /* s_waitcnt vmcnt(0), expcnt and lgkmcnt left at their maxima */
+  __builtin_amdgcn_s_waitcnt(0x0F70);
   __syncthreads();
   if (threadIdx.x == 0) {
-    const unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED,
+    const unsigned prev = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE,
                                                  __HIP_MEMORY_SCOPE_AGENT);
     s_last = prev + 1 == n ? 1 : 0;
   }
@@ -3530,7 +3535,7 @@ int pcg_max_grid() {
   return ncu * (per > 0 ? per : 1);
 }
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
-               int coop, hipStream_t st) {
+               hipStream_t st) {
   void* args[] = {(void*)&S, (void*)&eta, (void*)&max_it};
   const void* fn;
   if (variant == 1)
@@ -3541,11 +3546,11 @@ int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
     fn = S.mixed ? (const void*)k_pcg_cg1<float> : (const void*)k_pcg_cg1<double>;
   else
     fn = S.mixed ? (const void*)k_pcg<float> : (const void*)k_pcg<double>;
-  /* the blocks wait for each other: a cooperative launch guarantees they
-   * are resident together; a plain launch is used only for grids of at
-   * most half the compute units, which are always resident together */
-  hipError_t e = coop ? hipLaunchCooperativeKernel(fn, dim3(grid), dim3(192), args, 0, st)
-                      : hipLaunchKernel(fn, dim3(grid), dim3(192), args, 0, st);
+  /* the blocks wait for each other, so the grid never exceeds what the
+   * device holds resident at once (pcg_max_grid); every wait is bounded
+   * and reports a device error instead of hanging should blocks of the
+   * grid not be resident together */
+  hipError_t e = hipLaunchKernel(fn, dim3(grid), dim3(192), args, 0, st);
   return e == hipSuccess ? 0 : -1;
 }
 void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st) {

@@ -95,8 +95,6 @@ struct abd_ctx {
   int pcg_grid = 0;
   int n_cu = 0;
   int n_shared = 0;
-  /* captured passes of the device loop: [0] before the cooperative PCG
-   * launch, [1] after it; rebuilt whenever buffers or bound data change */
   /* pass halves: [0] before the PCG launch, [1] after it, [2] the first
    * half without the static broad phase (lists taken over); whole passes
    * with the PCG launch inside: [3] full, [4] taking over (passes whose PCG
@@ -525,13 +523,6 @@ void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
   }
 }
 
-int pcg_blocks(const abd_ctx* ctx, const Scene& S);
-/* cooperative launch unless the tuning allows a plain one and the grid
- * is at most half the compute units */
-int pcg_coop(const abd_ctx* ctx, const Scene& S) {
-  if (ctx->tune.pcg_coop) return 1;
-  return pcg_blocks(ctx, S) <= ctx->n_cu / 2 ? 0 : 1;
-}
 /* PCG form in use: the problem-local form needs one resident block per
  * 16-body group */
 int pcg_variant(const abd_ctx* ctx, const Scene& S) {
@@ -541,7 +532,7 @@ int pcg_variant(const abd_ctx* ctx, const Scene& S) {
     return ABD_PCG_TWO_BARRIER;
   return ctx->tune.pcg_variant;
 }
-/* blocks of the cooperative PCG launch */
+/* blocks of the persistent PCG launch (at most the resident capacity) */
 int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
   const int ng = std::max(1, (S.B + 15) / 16);
   const int v = pcg_variant(ctx, S);
@@ -564,8 +555,8 @@ int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
   }
   StageTimer t(ctx, 3);
   if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S),
-                 pcg_variant(ctx, S), pcg_coop(ctx, S), ctx->st))
-    return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
+                 pcg_variant(ctx, S), ctx->st))
+    return fail(ctx, ABD_E_DEVICE, "PCG launch failed");
   launch_dq_norm(S, 0, ctx->st);
   return ABD_OK;
 }
@@ -697,8 +688,8 @@ int pass_pcg(abd_ctx* ctx) {
   S1.iter_mode = 1;
   StageTimer t(ctx, 3);
   if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S1),
-                 pcg_variant(ctx, S1), pcg_coop(ctx, S1), ctx->st))
-    return fail(ctx, ABD_E_DEVICE, "cooperative PCG launch failed");
+                 pcg_variant(ctx, S1), ctx->st))
+    return fail(ctx, ABD_E_DEVICE, "PCG launch failed");
   return ABD_OK;
 }
 
@@ -764,7 +755,7 @@ bool capture(abd_ctx* ctx, int which, hipGraphExec_t* out) {
  * synchronisation: every problem in the Newton state assembles, solves
  * and checks |dq|; every problem not done runs the swept phase, CCD, the
  * trial energies of its line search and, on acceptance, its update.  The
- * parts before and after the cooperative PCG launch are replayed from
+ * parts before and after the PCG launch are replayed from
  * captured graphs when possible (not while every stage is timed,
  * and not on the legacy null stream, which cannot be captured).  With
  * take_over the first half skips the static broad phase and takes over the
@@ -784,7 +775,7 @@ int run_pass(abd_ctx* ctx, bool take_over, bool timed) {
     } else if (ctx->whole_ok &&
                (!capture(ctx, 3, &ctx->pass_graph[3]) ||
                 !capture(ctx, 4, &ctx->pass_graph[4]))) {
-      /* a PCG launch that cannot be captured (cooperative): halves only */
+      /* a PCG launch that cannot be captured: halves only */
       for (int i = 3; i < 5; ++i)
         if (ctx->pass_graph[i]) {
           (void)hipGraphExecDestroy(ctx->pass_graph[i]);
@@ -1721,6 +1712,44 @@ int abd_direction(abd_ctx* ctx, double* dq, int32_t* pcg_iters) {
   return ABD_OK;
 }
 
+}  /* extern "C" */
+
+namespace {
+/* every swept candidate's own TOI into toi (host, n entries) in the order
+ * of abd_export_candidates (PT pairs sorted, then EE pairs sorted, then PG
+ * vertices sorted), staged through d_toi (device, n entries) */
+int toi_in_export_order(abd_ctx* ctx, double* d_toi, int64_t npt, int64_t nee,
+                        int64_t npg, double* toi) {
+  const Scene& S = ctx->S;
+  const int64_t n = npt + nee + npg;
+  launch_ccd_pairs(swept_scene(ctx), d_toi, n, ctx->st);
+  std::vector<double> t(n);
+  std::vector<int> pt(3 * npt), ee(3 * nee), pg(npg);
+  hipError_t e = hipStreamSynchronize(ctx->st);
+  if (e == hipSuccess) e = hipMemcpy(t.data(), d_toi, sizeof(double) * n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && npt)
+    e = hipMemcpy(pt.data(), S.cand_pt, sizeof(int) * 3 * npt, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && nee)
+    e = hipMemcpy(ee.data(), S.cand_ee, sizeof(int) * 3 * nee, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && npg)
+    e = hipMemcpy(pg.data(), S.cand_pg, sizeof(int) * npg, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return fail(ctx, ABD_E_DEVICE, std::string("ccd: ") + hipGetErrorString(e));
+  int64_t o = 0;
+  auto emit = [&](int64_t first, int64_t m, auto key) {
+    std::vector<int64_t> idx(m);
+    for (int64_t i = 0; i < m; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
+    for (int64_t i = 0; i < m; ++i) toi[o++] = t[first + idx[i]];
+  };
+  emit(0, npt, [&](int64_t i) { return std::make_pair(pt[3 * i], pt[3 * i + 1]); });
+  emit(npt, nee, [&](int64_t i) { return std::make_pair(ee[3 * i], ee[3 * i + 1]); });
+  emit(npt + nee, npg, [&](int64_t i) { return std::make_pair(pg[i], 0); });
+  return ABD_OK;
+}
+}  // namespace
+
+extern "C" {
+
 int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max, double* toi,
             int64_t cap, int64_t* count) {
   int rc = check_ctx(ctx, true);
@@ -1739,32 +1768,9 @@ int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max, double* toi,
   if (n == 0) return ABD_OK;
   double* d_toi = nullptr;
   if ((rc = dalloc(ctx, &d_toi, n))) return rc;
-  launch_ccd_pairs(swept_scene(ctx), d_toi, n, ctx->st);
-  std::vector<double> t(n);
-  std::vector<int> pt(3 * npt), ee(3 * nee), pg(npg);
-  hipError_t e = hipStreamSynchronize(ctx->st);
-  if (e == hipSuccess) e = hipMemcpy(t.data(), d_toi, sizeof(double) * n, hipMemcpyDeviceToHost);
-  if (e == hipSuccess && npt)
-    e = hipMemcpy(pt.data(), S.cand_pt, sizeof(int) * 3 * npt, hipMemcpyDeviceToHost);
-  if (e == hipSuccess && nee)
-    e = hipMemcpy(ee.data(), S.cand_ee, sizeof(int) * 3 * nee, hipMemcpyDeviceToHost);
-  if (e == hipSuccess && npg)
-    e = hipMemcpy(pg.data(), S.cand_pg, sizeof(int) * npg, hipMemcpyDeviceToHost);
+  rc = toi_in_export_order(ctx, d_toi, npt, nee, npg, toi);
   dfree(ctx, d_toi);
-  if (e != hipSuccess) return fail(ctx, ABD_E_DEVICE, std::string("ccd: ") + hipGetErrorString(e));
-  /* the candidates' order of abd_export_candidates: PT pairs sorted, then
-   * EE pairs sorted, then PG vertices sorted */
-  int64_t o = 0;
-  auto emit = [&](int64_t first, int64_t m, auto key) {
-    std::vector<int64_t> idx(m);
-    for (int64_t i = 0; i < m; ++i) idx[i] = i;
-    std::sort(idx.begin(), idx.end(), [&](int64_t a, int64_t b) { return key(a) < key(b); });
-    for (int64_t i = 0; i < m; ++i) toi[o++] = t[first + idx[i]];
-  };
-  emit(0, npt, [&](int64_t i) { return std::make_pair(pt[3 * i], pt[3 * i + 1]); });
-  emit(npt, nee, [&](int64_t i) { return std::make_pair(ee[3 * i], ee[3 * i + 1]); });
-  emit(npt + nee, npg, [&](int64_t i) { return std::make_pair(pg[i], 0); });
-  return ABD_OK;
+  return rc;
 }
 
 int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
@@ -2219,11 +2225,13 @@ int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
       t->pcg_blocks < 0 || t->grid_blocks < 1 || t->assemble_blocks < 1 ||
       t->grid_blocks > (1 << 20) || t->assemble_blocks > (1 << 20))
     return fail(ctx, ABD_E_INVALID_ARG, "tuning values");
+  if (t->pcg_coop != 0)
+    return fail(ctx, ABD_E_INVALID_ARG,
+                "pcg_coop is reserved and must be 0: the PCG launch is always a plain launch");
   drop_graphs(ctx); /* launch shapes are part of the captured graphs */
   ctx->tune = *t;
   ctx->tune.use_graphs = t->use_graphs ? 1 : 0;
   ctx->tune.overlap_body = t->overlap_body ? 1 : 0;
-  ctx->tune.pcg_coop = t->pcg_coop ? 1 : 0;
   ctx->S.grid_blocks = t->grid_blocks;
   ctx->S.assemble_blocks = t->assemble_blocks;
   return ABD_OK;
@@ -2309,11 +2317,6 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
   {
     abd_tuning t = best;
     t.overlap_body = best.overlap_body ? 0 : 1;
-    consider(t);
-  }
-  {
-    abd_tuning t = best;
-    t.pcg_coop = best.pcg_coop ? 0 : 1;
     consider(t);
   }
   {

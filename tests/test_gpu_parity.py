@@ -131,19 +131,24 @@ def test_per_pair_toi_parity(cubes_contact, cubes_gpu):
                           for kd in (O.PT, O.EE, O.PG))
             assert len(toi) == len(pt) + len(ee) + len(pg) > 0
             x, dx = ref.vertices(q), ref.vertices(d)   # dx = J d (linear)
-            want = []
+            want, exact = [], []
             for kd, pairs in ((O.PT, pt), (O.EE, ee)):
                 for i, j in pairs:
                     vid = ([i, *tris[j]] if kd == O.PT
                            else [*edges[i], *edges[j]])
                     want.append(O.accd(kd, x[vid].ravel(), dx[vid].ravel(),
                                        s))
+                    exact.append(O.exact_toi(kd, x[vid].ravel(),
+                                             dx[vid].ravel()))
             for v in pg:
                 dy = dx[v, 1]
-                want.append((1 - s) * (x[v, 1] - sc.params["ground_y"]) / -dy
-                            if dy < 0 else 1.0)
+                y0 = x[v, 1] - sc.params["ground_y"]
+                want.append((1 - s) * y0 / -dy if dy < 0 else 1.0)
+                exact.append(min(1.0, y0 / -dy) if dy < 0 else 1.0)
             want = np.clip(np.array(want), 0.0, 1.0)
             np.testing.assert_allclose(toi, want, rtol=1e-9, atol=1e-15)
+            # the CCD contract: never beyond the exact first contact
+            assert np.all(toi <= np.array(exact)), "TOI above exact contact"
             assert a == min(1.0, float(toi.min()))
             impacts += int((toi < 1.0).sum())
     assert impacts > 0
@@ -314,3 +319,49 @@ def test_error_paths():
     q, _ = gpu.get_state()
     assert np.all(np.isfinite(q))
     gpu.close()
+
+
+def test_spheres_toi_never_above_exact_contact():
+    """Sphere scene (PT/EE between curved meshes and against the static
+    box): every swept pair's GPU time of impact stays at or below the
+    oracle's exact first contact time of that pair, for the Newton step and
+    for steps stretched until many pairs would collide."""
+    sc = small_spheres()
+    gpu = abd.Solver(sc)
+    ref = O.Oracle(sc)
+    offs = np.cumsum([0] + [len(b.xbar) for b in sc.bodies[:-1]])
+    tris = np.concatenate([b.tris + o for b, o in zip(sc.bodies, offs)])
+    edges = ref.edges()
+    impacts = 0
+    for k in range(10):
+        q, qd = ref.get_state()
+        if k in (4, 7, 9):
+            set_both(gpu, ref, q, qd)
+            dq, _ = ref.direction(q)
+            for scale in (1.0, 8.0, 40.0):
+                d = scale * dq
+                a, toi = gpu.ccd(d, per_pair=True)
+                pt, ee, pg = (gpu.candidates(kd, d) for kd in (O.PT, O.EE, O.PG))
+                x, dx = ref.vertices(q), ref.vertices(d)
+                exact = []
+                for kd, pairs in ((O.PT, pt), (O.EE, ee)):
+                    for i, j in pairs:
+                        vid = ([i, *tris[j]] if kd == O.PT
+                               else [*edges[i], *edges[j]])
+                        exact.append(O.exact_toi(kd, x[vid].ravel(),
+                                                 dx[vid].ravel()))
+                assert len(pg) == 0
+                exact = np.array(exact)
+                assert len(toi) == len(exact)
+                assert np.all(toi <= exact), (k, scale)
+                assert a <= exact.min(initial=1.0)
+                impacts += int((exact < 1.0).sum())
+        ref.step()
+    assert impacts > 0
+    gpu.close()
+
+
+def test_cooperative_launch_setting_is_rejected(cubes_gpu):
+    with pytest.raises(abd.AbdError) as e:
+        cubes_gpu.set_tuning(pcg_coop=1)
+    assert e.value.code == abd.E_INVALID_ARG
