@@ -10,9 +10,22 @@ time step (prediction, the full local Newton solve, commit); W steps run
 untimed first, then K steps are timed.  value = Newton iterations per
 second over the timed steps, inputs resident on the device throughout.
 
-The JSON line carries the roofline of the dominant kernel (measured live
-with HIP events on the library's stream) and the CPU oracle timed on a
-bounded sample of the same workload.
+Also on the line:
+  roofline      the dominant kernel (the PCG launch), its launch duration
+                measured with HIP events on the library's stream inside the
+                timed region;
+  roofline_s5   the barrier stage (distance filter and assembly) against
+                both the HBM and the FP64 roofline, from extra steps with
+                every stage timed;
+  run50         all 50 steps of the workload from its initial state, FP64
+                and mixed precision, each step checked for penetration on
+                the device; mixed_vs_fp64_speedup is the ratio of their
+                wall times;
+  vs_oracle     per-step position errors of the FP64 and mixed GPU steps
+                against the CPU oracle's steps from the same states (the
+                first timed steps);
+  cpu_baseline  the oracle (single thread) on those same time steps, and
+                cpu_baseline_omp its OpenMP build on all host cores.
 """
 import argparse
 import json
@@ -24,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFS = 78.6
 
 # HBM traffic of the dominant kernel from two rocprofv3 --pmc runs of this
 # benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each divided
@@ -40,28 +54,31 @@ PMC_TRAFFIC = {
     "sha256": "6eaa85fabf0744a19da079fdfb0d3f500eee447519f4a32017c3fef0a441c2bb",
 }
 
+METRIC = ("local Newton iters/s at ~1M tris; mixed vs FP64 speedup at 1e-6 "
+          "residual")
 WORKLOAD = ("1000 icospheres (642 verts, 1280 tris each, r 0.05-0.15) "
             "falling into an open box container, dt 0.01, dhat 1e-3, "
             "kappa 1e5, kappa_A 1e8, FP64, Newton tol 1e-6")
 
 
-def cpu_baseline(seed, n_steps):
-    """Oracle on the first n_steps time steps of the same scene."""
-    from oracle import oracle as O
-    from paper_2605_15875_amd import scenes
-    sc = scenes.config(1, seed)
-    orc = O.Oracle(sc)
-    iters = 0
-    t0 = time.perf_counter()
-    for _ in range(n_steps):
-        st = orc.step()
-        iters += st["newton_iters"]
-    dt = time.perf_counter() - t0
-    return dict(value=iters / dt, unit="newton_iters/s", cores=1,
-                kind="oracle",
-                sample=f"first {n_steps} time steps of the workload "
-                       f"({iters} Newton iterations, {dt:.1f} s, "
-                       f"single thread)")
+def host_cores():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def step(solver):
+    """One time step; a solve that ends without convergence (NOCONV) keeps
+    its last iterate, which is penetration free like every iterate, and the
+    step is counted as such instead of stopping the benchmark."""
+    solver.begin_step()
+    st = solver.local_solve(check=False)
+    if st["status"] not in (0, -4):
+        raise RuntimeError(f"local solve failed: status {st['status']}: "
+                           f"{solver.error()}")
+    solver.end_step()
+    return st
 
 
 def copy_probe():
@@ -96,11 +113,93 @@ def pmc_traffic(kernel):
             t["write_kib"] * 1024.0 / t["write_per_byte"])
 
 
+def run_all_steps(abd, sc, n, precision, tuning, log):
+    """All n steps from the initial state: wall time of the steps alone,
+    every state checked for penetration on the device between steps."""
+    s = abd.Solver(sc, precision=precision)
+    s.set_tuning(**tuning)
+    t = 0.0
+    newton = n32 = switched = noconv = 0
+    worst_newton = 0
+    min_dist = float("inf")
+    crossings = 0
+    for k in range(n):
+        t0 = time.perf_counter()
+        st = step(s)
+        t += time.perf_counter() - t0
+        newton += st["newton_iters"]
+        n32 += st["newton_fp32"]
+        switched += st["fp64_fallback"]
+        noconv += st["status"] == -4
+        worst_newton = max(worst_newton, st["newton_iters"])
+        nc, md = s.check_penetration()
+        crossings += nc
+        min_dist = min(min_dist, md)
+    x = s.vertices()
+    s.close()
+    log(f"run{n} precision={precision}: {newton} newton in {t*1e3:.1f} ms, "
+        f"switched={switched} noconv={noconv} min_dist={min_dist:.3g}")
+    out = dict(steps=n, wall_ms=t * 1e3, newton_iters=newton,
+               newton_iters_per_s=newton / t, max_newton_per_step=worst_newton,
+               noconv_steps=noconv, penetration_free=bool(
+                   crossings == 0 and min_dist > 0),
+               edge_triangle_crossings=crossings, min_distance=min_dist)
+    if precision:
+        out.update(newton_fp32=n32, fp64_switch_steps=switched)
+    return out, x
+
+
+def versus_oracle(abd, O, sc, q0, qd0, n, gpu64, gpumx, log):
+    """The oracle (single thread, then its OpenMP build) on n time steps
+    from the state (q0, qd0); the FP64 and mixed GPU contexts step from the
+    oracle's state before each of its steps, and their positions are
+    compared with the oracle's after it."""
+    import numpy as np
+    ref = O.Oracle(sc)
+    ref.set_state(q0, qd0)
+    err64 = []
+    errmx = []
+    t_orc = 0.0
+    it_orc = 0
+    for k in range(n):
+        q, qd = ref.get_state()
+        for g in (gpu64, gpumx):
+            g.set_state(q, qd)
+        s64 = step(gpu64)
+        smx = step(gpumx)
+        t0 = time.perf_counter()
+        sr = ref.step()
+        t_orc += time.perf_counter() - t0
+        it_orc += sr["newton_iters"]
+        xr = ref.vertices()
+        l = sr["scene_scale"]
+        err64.append(float(np.abs(gpu64.vertices() - xr).max() / l))
+        errmx.append(float(np.abs(gpumx.vertices() - xr).max() / l))
+        log(f"oracle step {k}: newton={sr['newton_iters']} (gpu fp64 "
+            f"{s64['newton_iters']}, mixed {smx['newton_iters']}) "
+            f"err/l fp64={err64[-1]:.2e} mixed={errmx[-1]:.2e}")
+    q_end, _ = ref.get_state()
+    # the OpenMP build on the same steps (same results, several threads)
+    omp = O.Oracle(sc, omp=True)
+    omp.set_state(q0, qd0)
+    t_omp = 0.0
+    it_omp = 0
+    for k in range(n):
+        t0 = time.perf_counter()
+        it_omp += omp.step()["newton_iters"]
+        t_omp += time.perf_counter() - t0
+    q_omp, _ = omp.get_state()
+    same = bool(np.array_equal(q_end, q_omp))
+    return (dict(steps=n, pos_err_over_l_fp64=err64,
+                 pos_err_over_l_mixed=errmx, max_fp64=max(err64),
+                 max_mixed=max(errmx)),
+            dict(t=t_orc, it=it_orc), dict(t=t_omp, it=it_omp, same=same))
+
+
 def bench_batch(abd, scenes, torch, n_scenes, steps, warmup):
     """n_scenes independent 8-cube scenes (different seeds, same
     parameters): one batched solve per step against one solve per context
     in turn.  Both advance identical copies of the scenes."""
-    import time as _t
     scs = [scenes.config(0, seed) for seed in range(n_scenes)]
     one = [abd.Solver(sc) for sc in scs]
     many = [abd.Solver(sc) for sc in scs]
@@ -110,12 +209,12 @@ def bench_batch(abd, scenes, torch, n_scenes, steps, warmup):
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
-        t0 = _t.perf_counter()
+        t0 = time.perf_counter()
         it = 0
         for _ in range(steps):
             it += fn()
         torch.cuda.synchronize()
-        return it, _t.perf_counter() - t0
+        return it, time.perf_counter() - t0
 
     def seq():
         return sum(s.step()["newton_iters"] for s in one)
@@ -140,20 +239,19 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=6)
+    ap.add_argument("--cpu-steps", type=int, default=2,
+                    help="time steps of the oracle comparison and CPU "
+                         "baseline (the first timed steps)")
     ap.add_argument("--quiet", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-run50", action="store_true")
+    ap.add_argument("--run-steps", type=int, default=50)
     ap.add_argument("--breakdown-steps", type=int, default=3)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--pcg-variant", type=int, default=None,
-                    help="0: two grid barriers per PCG iteration, "
-                         "1: single-reduction form (default: library's)")
-    ap.add_argument("--overlap-body", type=int, default=None,
-                    help="1: body terms on a second stream, 0: in line")
+    ap.add_argument("--pcg-variant", type=int, default=None)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner after warmup")
     ap.add_argument("--copy-probe", action="store_true",
@@ -170,7 +268,6 @@ def main():
               "build", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
     from paper_2605_15875_amd import abd, scenes
     assert torch.cuda.is_available(), "bench needs a GPU"
@@ -186,15 +283,14 @@ def main():
     solver = abd.Solver(sc)
     if a.pcg_variant is not None:
         solver.set_tuning(pcg_variant=a.pcg_variant)
-    if a.overlap_body is not None:
-        solver.set_tuning(overlap_body=a.overlap_body)
     for i in range(a.warmup):
-        st = solver.step()
+        st = step(solver)
         log(f"warmup {i}: newton={st['newton_iters']} "
             f"pcg={st['pcg_iters_total']} ms={st['t_solve_ms']:.1f}")
     if a.autotune:
         log(f"autotuned: {solver.autotune()}")
     tuning = solver.tuning()
+    q_first, qd_first = solver.get_state()  # state at the first timed step
     # timed region: the PCG launch of every fourth pass is bracketed by
     # events, so the PCG kernel's launch duration is measured on a sample of
     # the timed region's own launches
@@ -202,100 +298,105 @@ def main():
     solver.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    newton = pcg = 0
+    newton = pcg = noconv = 0
+    per_step = []
     for i in range(a.steps):
-        st = solver.step()
+        ts = time.perf_counter()
+        st = step(solver)
+        per_step.append((st["newton_iters"], time.perf_counter() - ts))
         newton += st["newton_iters"]
         pcg += st["pcg_iters_total"]
+        noconv += st["status"] == -4
         log(f"step {i}: newton={st['newton_iters']} pcg={st['pcg_iters_total']}"
             f" active={st['n_active']} cand={st['n_cand_pt']}+"
             f"{st['n_cand_ee']} alpha_min={st['min_alpha']:.3g} "
-            f"ms={st['t_solve_ms']:.1f}")
+            f"status={st['status']} ms={st['t_solve_ms']:.1f}")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     tm_timed = solver.timing()
-    x64 = solver.vertices()  # state after warmup + timed steps
-    # stage breakdown from extra instrumented steps (every stage timed,
-    # direct launches instead of graphs); not part of the timed region
+    # stage breakdown from extra instrumented steps (every stage timed);
+    # not part of the timed region
     solver.set_timing(abd.TIMING_ALL)
     solver.reset_timing()
     for i in range(a.breakdown_steps):
-        solver.step()
+        step(solver)
     tm = solver.timing()
     solver.set_timing(abd.TIMING_OFF)
     if not any(v["launches"] for v in tm.values()):
         tm = tm_timed
-    # the dominant single kernel is the PCG solve (the broad-phase stage
-    # sums several smaller kernels); its launches are timed with events in
-    # the timed region itself
-    dom = "pcg"
-    roof = None
-    d = tm_timed[dom]
     pcg_kernel = {abd.PCG_LOCAL: "k_pcg_local", abd.PCG_TWO_BARRIER: "k_pcg",
                   abd.PCG_PIPELINED: "k_pcg1",
                   abd.PCG_LOCAL1: "k_pcg_cg1"}[tuning["pcg_variant"]] + "<double>"
+    roof = None
+    d = tm_timed["pcg"]
     if d["bytes"] > 0 and d["launches"]:
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-        kname = pcg_kernel if dom == "pcg" else dom
-        traffic = pmc_traffic(kname)
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=traffic, kernel=kname,
+                    traffic=pmc_traffic(pcg_kernel), kernel=pcg_kernel,
                     bytes_per_launch=d["bytes"] / d["launches"],
                     launches=d["launches"],
                     avg_launch_ms=d["ms"] / d["launches"],
-                    measured="timed region" if dom == "pcg"
-                    else "instrumented steps")
-    l = float(np.linalg.norm(np.ptp(x64, axis=0)))
-    mixed = None
-    if not a.no_mixed:
-        # same workload, same steps and tolerance, FP32 Hessian path
-        ms = abd.Solver(sc, precision=1)
-        ms.set_tuning(**tuning)
-        for i in range(a.warmup):
-            ms.step()
-        ms.set_timing(abd.TIMING_PCG)  # same event overhead as FP64
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        mnewton = fallbacks = 0
-        for i in range(a.steps):
-            st = ms.step()
-            mnewton += st["newton_iters"]
-            fallbacks += st["fp64_fallback"]
-        torch.cuda.synchronize()
-        mel = time.perf_counter() - t1
-        xm = ms.vertices()
-        # accuracy: time steps of both precisions from the same states (the
-        # free-running trajectories of a contact pile branch apart once one
-        # solve settles in a different local minimum)
-        one_step = 0.0
-        for i in range(3):
-            q, qd = solver.get_state()
-            ms.set_state(q, qd)
-            solver.step()
-            ms.step()
-            one_step = max(one_step, float(
-                np.abs(ms.vertices() - solver.vertices()).max() / l))
-        mixed = dict(newton_iters_per_s=mnewton / mel, newton_iters=mnewton,
-                     fp64_fallback_steps=fallbacks,
-                     ms_per_step=mel * 1e3 / a.steps,
-                     speedup_vs_fp64=elapsed / mel,
-                     one_step_pos_diff_vs_fp64_over_l=one_step,
-                     free_running_pos_diff_vs_fp64_over_l=float(
-                         np.abs(xm - x64).max() / l))
-        log(f"mixed: {mnewton} newton iters in {mel*1e3:.1f} ms")
-        ms.close()
+                    measured="timed region")
+    roof5 = None
+    d5 = tm["barrier"]
+    if d5["launches"] and d5["ms"] > 0:
+        gbs = d5["bytes"] / (d5["ms"] * 1e-3) / 1e9
+        tfs = d5["flops"] / (d5["ms"] * 1e-3) / 1e12
+        fh, ff = gbs / HBM_PEAK_GBS, tfs / FP64_PEAK_TFS
+        roof5 = dict(bound="fp64" if ff > fh else "hbm",
+                     kernels="k_filter + k_assemble<double>",
+                     achieved_GBs=gbs, peak_GBs=HBM_PEAK_GBS, frac_hbm=fh,
+                     achieved_TFs=tfs, peak_TFs=FP64_PEAK_TFS, frac_fp64=ff,
+                     bytes_per_pass=d5["bytes"] / d5["launches"],
+                     flops_per_pass=d5["flops"] / d5["launches"],
+                     avg_ms_per_pass=d5["ms"] / d5["launches"],
+                     passes=d5["launches"], traffic=None,
+                     measured=f"{a.breakdown_steps} steps after the timed "
+                              "region, every stage timed")
     solver.close()
+
+    run50 = None
+    mixed_speedup = None
+    if not a.no_run50:
+        r64, _ = run_all_steps(abd, sc, a.run_steps, 0, tuning, log)
+        rmx, _ = run_all_steps(abd, sc, a.run_steps, 1, tuning, log)
+        mixed_speedup = r64["wall_ms"] / rmx["wall_ms"]
+        run50 = dict(workload=f"all {a.run_steps} steps from the initial "
+                              "state", fp64=r64, mixed=rmx,
+                     mixed_vs_fp64_wall_speedup=mixed_speedup)
+
+    vs_oracle = cpu = cpu_omp = None
+    if not a.no_cpu_baseline and a.cpu_steps > 0:
+        from oracle import oracle as O
+        log("oracle on the first timed steps ...")
+        g64 = abd.Solver(sc)
+        gmx = abd.Solver(sc, precision=1)
+        for g in (g64, gmx):
+            g.set_tuning(**tuning)
+        vs_oracle, orc, omp = versus_oracle(abd, O, sc, q_first, qd_first,
+                                            a.cpu_steps, g64, gmx, log)
+        g64.close()
+        gmx.close()
+        n = a.cpu_steps
+        gpu_it = sum(p[0] for p in per_step[:n])
+        gpu_t = sum(p[1] for p in per_step[:n])
+        sample = (f"time steps {a.warmup}-{a.warmup + n - 1} of the workload "
+                  f"(the first {n} timed steps) from the GPU's state at the "
+                  f"first timed step: {orc['it']} Newton iterations")
+        cpu = dict(value=orc["it"] / orc["t"], unit="newton_iters/s", cores=1,
+                   kind="oracle", sample=sample + f", {orc['t']:.1f} s",
+                   gpu_same_steps_newton_iters_per_s=gpu_it / gpu_t)
+        cpu_omp = dict(value=omp["it"] / omp["t"], unit="newton_iters/s",
+                       cores=host_cores(), kind="oracle (OpenMP build)",
+                       sample=sample + f", {omp['t']:.1f} s",
+                       bit_identical_to_single_thread=omp["same"])
     batch = None
     if not a.no_batch:
         batch = bench_batch(abd, scenes, torch, a.batch_scenes, 5, 1)
         log(f"batch: {batch}")
-    cpu = None
-    if not a.no_cpu_baseline:
-        log("cpu baseline ...")
-        cpu = cpu_baseline(a.seed, a.cpu_steps)
     out = {
-        "metric": "local Newton iters/s at ~1M tris",
+        "metric": METRIC,
         "value": newton / elapsed,
         "unit": "newton_iters/s",
         "n_gpus": 1,
@@ -312,12 +413,17 @@ def main():
                    "seed": a.seed, "precision": "fp64", "tuning": tuning},
         "newton_iters": newton,
         "pcg_iters": pcg,
+        "noconv_steps": noconv,
         "stage_ms_instrumented": {k: round(v["ms"] / max(a.breakdown_steps, 1),
                                            3) for k, v in tm.items()},
         "roofline": roof,
+        "roofline_s5": roof5,
         "cpu_baseline": cpu,
-        "mixed_vs_fp64_speedup": mixed["speedup_vs_fp64"] if mixed else None,
-        "mixed": mixed,
+        "cpu_baseline_omp": cpu_omp,
+        "host_cores": host_cores(),
+        "mixed_vs_fp64_speedup": mixed_speedup,
+        "run50": run50,
+        "vs_oracle": vs_oracle,
         "batch": batch,
     }
     print(json.dumps(out), flush=True)

@@ -71,9 +71,11 @@ extern "C" {
                        distances, CCD, energies, PCG residual and dots FP64:
                        the FP64 gradient of every Newton iteration refines
                        the FP32-Hessian steps to the same solution.  A solve
-                       that does not reach the Newton tolerance this way is
-                       repeated from its start with FP64 Hessians
-                       (abd_stats.fp64_fallback) */
+                       in which a problem stops making progress this way
+                       (eps_N not halving for 16 Newton iterations, or
+                       mixed_switch iterations spent) continues from its
+                       current iterate with FP64 Hessians
+                       (abd_stats.fp64_fallback, newton_fp32) */
 
 /* candidate kinds */
 #define ABD_PT 0 /* point-triangle: (vertex, triangle) */
@@ -103,6 +105,11 @@ typedef struct abd_params {
                             4 per body).  Lists grow on overflow either way:
                             a small value exercises that growth, a large one
                             avoids it on scenes known to be contact-rich */
+  int32_t mixed_switch;  /* ABD_MIXED: Newton iterations after which a solve
+                            continues with FP64 Hessians in any case (0: a
+                            third of max_newton); a stall (eps_N not halving
+                            for 16 iterations) switches earlier */
+  int32_t pad_;
 } abd_params;
 
 typedef struct abd_stats {
@@ -120,9 +127,12 @@ typedef struct abd_stats {
    * static phase (at q) and of the swept phase (over q -> q + dq) */
   int64_t n_body_pairs, n_chunk_pairs, n_body_pairs_swept,
       n_chunk_pairs_swept;
-  /* mixed precision: 1 if the FP32-Hessian solve did not reach the Newton
-   * tolerance and the solve was repeated with FP64 Hessians */
+  /* mixed precision: 1 if a problem stopped making progress with FP32
+   * Hessians and the solve continued from its current iterate with FP64
+   * Hessians (no work is repeated); newton_fp32 of the newton_iters were
+   * taken with FP32 Hessians */
   int32_t fp64_fallback;
+  int32_t newton_fp32;
 } abd_stats;
 
 typedef struct abd_ctx abd_ctx;
@@ -400,6 +410,13 @@ int abd_direction(abd_ctx* ctx, double* dq, int32_t* pcg_iters);
 int abd_ccd(abd_ctx* ctx, const double* dq, double* alpha_max, double* toi,
             int64_t cap, int64_t* count);
 
+/* Penetration check of the current state: *min_dist receives the smallest
+ * distance over the candidate pairs at q (pairs whose d-hat inflated boxes
+ * meet; +inf when there are none) and *n_cross the number of edges of one
+ * body crossing a triangle of another (strictly, by signed volumes).  The
+ * state is penetration free iff *n_cross == 0 and *min_dist > 0. */
+int abd_check_penetration(abd_ctx* ctx, int64_t* n_cross, double* min_dist);
+
 /* E(q + alpha dq) - E(q) at the current q, summed term by term. */
 int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
                      double* dE);
@@ -421,6 +438,17 @@ int abd_set_timing(abd_ctx* ctx, int32_t on);
 int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms,
                    int64_t* launches, double* bytes);
 int abd_reset_timing(abd_ctx* ctx);
+/* Algorithmic FP64 flops of the timed launches of a stage (ABD_TIMING_ALL;
+ * counted for the barrier stage 2 only, 0 for the others).  With the bytes
+ * of abd_get_timing this places stage 2 against both the HBM and the FP64
+ * roofline.  Per pass: about 100 flops per candidate distance and 22,300
+ * per active point-triangle or edge-edge pair (distance derivatives, 9x9
+ * PSD projection, mapping to three body blocks).  The stage's bytes count
+ * each access once with no cache reuse: candidate entries and their four
+ * vertices' rest positions and body ids, active-pair entries, three 12x12
+ * blocks and two 12-gradients read and written per active pair, and the
+ * off-diagonal block cleared per body pair. */
+int abd_get_timing_flops(abd_ctx* ctx, int32_t stage, double* flops);
 
 /* ---- load balancing of the plane between two workers (Sec. 5.2) ----
  * A discrete-time PD controller on the workers' smoothed frame times moves

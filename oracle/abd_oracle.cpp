@@ -742,6 +742,7 @@ void positions(const orc_scene* s, const double* q /*B*12*/,
                std::vector<double>& x) {
   size_t V = s->vbody.size();
   x.resize(V * 3);
+#pragma omp parallel for schedule(static)
   for (size_t v = 0; v < V; ++v)
     vertex_pos(q + 12 * s->vbody[v], &s->xbar[3 * v], &x[3 * v]);
 }
@@ -773,15 +774,18 @@ void candidates(const orc_scene* s, const std::vector<double>& x,
     for (size_t i = 0; i < 3 * V; ++i) x1[i] = x[i] + dx[i];
   }
   std::vector<Box> vb(V), tb(T), eb(E);
+#pragma omp parallel for schedule(static)
   for (size_t v = 0; v < V; ++v) {
     box_empty(vb[v]);
     box_add(vb[v], &x[3 * v]);
     if (dx) box_add(vb[v], &x1[3 * v]);
   }
+#pragma omp parallel for schedule(static)
   for (size_t t = 0; t < T; ++t) {
     box_empty(tb[t]);
     for (int k = 0; k < 3; ++k) box_merge(tb[t], vb[s->tri[3 * t + k]]);
   }
+#pragma omp parallel for schedule(static)
   for (size_t e = 0; e < E; ++e) {
     box_empty(eb[e]);
     for (int k = 0; k < 2; ++k) box_merge(eb[e], vb[s->edge[2 * e + k]]);
@@ -796,8 +800,14 @@ void candidates(const orc_scene* s, const std::vector<double>& x,
   C.pt.clear();
   C.ee.clear();
   C.pg.clear();
-  std::vector<int> L1, L2;
-  for (size_t a = 0; a < nb; ++a)
+  /* body pairs (a, b > a): the pairs found for each a are collected on
+   * their own and joined in the order of a; the lists are sorted below, so
+   * the result does not depend on how the loop over a is split */
+  std::vector<Cands> per_a(nb);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (size_t a = 0; a < nb; ++a) {
+    Cands& Ca = per_a[a];
+    std::vector<int> L1, L2;
     for (size_t b = a + 1; b < nb; ++b) {
       const orc_body& A = s->B[a];
       const orc_body& Bb = s->B[b];
@@ -816,7 +826,7 @@ void candidates(const orc_scene* s, const std::vector<double>& x,
           if (overlap(tb[Q.t0 + t], boxP, dh)) L2.push_back(Q.t0 + t);
         for (int v : L1)
           for (int t : L2)
-            if (overlap(vb[v], tb[t], dh)) C.pt.push_back({v, t});
+            if (overlap(vb[v], tb[t], dh)) Ca.pt.push_back({v, t});
       }
       L1.clear();
       L2.clear();
@@ -827,8 +837,13 @@ void candidates(const orc_scene* s, const std::vector<double>& x,
       for (int e : L1)
         for (int f : L2)
           if (overlap(eb[e], eb[f], dh))
-            C.ee.push_back({std::min(e, f), std::max(e, f)});
+            Ca.ee.push_back({std::min(e, f), std::max(e, f)});
     }
+  }
+  for (const Cands& Ca : per_a) {
+    C.pt.insert(C.pt.end(), Ca.pt.begin(), Ca.pt.end());
+    C.ee.insert(C.ee.end(), Ca.ee.begin(), Ca.ee.end());
+  }
   if (s->P.has_ground) {
     double top = s->P.ground_y + dh;
     for (size_t v = 0; v < V; ++v)
@@ -963,24 +978,41 @@ void pair_terms(const orc_scene* s, const std::vector<double>& x,
                 const Cands& C, System& S) {
   const double w0 = s->P.dt * s->P.dt * s->P.kappa;
   const double dh = s->P.dhat;
-  double x12[12], g12[12], H144[144], E, d;
-  int vid[4], dtype;
-  for (int kind = 0; kind < 2; ++kind) {
-    const auto& L = kind == ORC_PT ? C.pt : C.ee;
-    for (const auto& pr : L) {
-      pair_slots(s, kind, pr.first, pr.second, vid);
-      for (int k = 0; k < 4; ++k)
-        for (int i = 0; i < 3; ++i) x12[3 * k + i] = x[3 * vid[k] + i];
-      double w = w0 / pair_kappa_c(s, vid, 4);
-      double ex = kind == ORC_EE ? pair_eps_x(s, pr.first, pr.second) : 0.0;
-      int act = pair_energy(kind, x12, ex, dh, w, true, s->project, &E, g12,
-                            H144, &d, &dtype);
-      S.min_dist = std::min(S.min_dist, d);
-      if (!act) continue;
-      S.n_active++;
-      S.E += E;
-      jmap(s, vid, 4, g12, H144, 12, S);
-    }
+  /* each PT/EE pair's energy, gradient and projected Hessian is computed
+   * on its own (in parallel in the OpenMP build), then the pairs are added
+   * to the system one after another in list order */
+  const size_t npt = C.pt.size(), n = npt + C.ee.size();
+  struct PairOut {
+    int act;
+    double E, d, g12[12], H144[144];
+  };
+  std::vector<PairOut> out(n);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (size_t c = 0; c < n; ++c) {
+    const int kind = c < npt ? ORC_PT : ORC_EE;
+    const auto& pr = c < npt ? C.pt[c] : C.ee[c - npt];
+    int vid[4], dtype;
+    double x12[12];
+    pair_slots(s, kind, pr.first, pr.second, vid);
+    for (int k = 0; k < 4; ++k)
+      for (int i = 0; i < 3; ++i) x12[3 * k + i] = x[3 * vid[k] + i];
+    double w = w0 / pair_kappa_c(s, vid, 4);
+    double ex = kind == ORC_EE ? pair_eps_x(s, pr.first, pr.second) : 0.0;
+    PairOut& o = out[c];
+    o.act = pair_energy(kind, x12, ex, dh, w, true, s->project, &o.E, o.g12,
+                        o.H144, &o.d, &dtype);
+  }
+  for (size_t c = 0; c < n; ++c) {
+    const int kind = c < npt ? ORC_PT : ORC_EE;
+    const auto& pr = c < npt ? C.pt[c] : C.ee[c - npt];
+    const PairOut& o = out[c];
+    S.min_dist = std::min(S.min_dist, o.d);
+    if (!o.act) continue;
+    int vid[4];
+    pair_slots(s, kind, pr.first, pr.second, vid);
+    S.n_active++;
+    S.E += o.E;
+    jmap(s, vid, 4, o.g12, o.H144, 12, S);
   }
   for (int v : C.pg) {
     double dist = x[3 * v + 1] - s->P.ground_y;
@@ -1308,19 +1340,21 @@ double exact_toi(int kind, const double* x, const double* dx, double tmax) {
 double ccd_alpha(orc_scene* s, const std::vector<double>& x,
                  const std::vector<double>& dx, const Cands& C) {
   double amax = 1.0;
-  double x12[12], d12[12];
-  int vid[4];
-  for (int kind = 0; kind < 2; ++kind) {
-    const auto& L = kind == ORC_PT ? C.pt : C.ee;
-    for (const auto& pr : L) {
-      pair_slots(s, kind, pr.first, pr.second, vid);
-      for (int k = 0; k < 4; ++k)
-        for (int i = 0; i < 3; ++i) {
-          x12[3 * k + i] = x[3 * vid[k] + i];
-          d12[3 * k + i] = dx[3 * vid[k] + i];
-        }
-      amax = std::min(amax, accd(kind, x12, d12, ACCD_S, 1.0));
-    }
+  /* a minimum: the same in any order of the pairs */
+  const long npt = (long)C.pt.size(), n = npt + (long)C.ee.size();
+#pragma omp parallel for schedule(dynamic, 16) reduction(min : amax)
+  for (long c = 0; c < n; ++c) {
+    const int kind = c < npt ? ORC_PT : ORC_EE;
+    const auto& pr = c < npt ? C.pt[c] : C.ee[c - npt];
+    double x12[12], d12[12];
+    int vid[4];
+    pair_slots(s, kind, pr.first, pr.second, vid);
+    for (int k = 0; k < 4; ++k)
+      for (int i = 0; i < 3; ++i) {
+        x12[3 * k + i] = x[3 * vid[k] + i];
+        d12[3 * k + i] = dx[3 * vid[k] + i];
+      }
+    amax = std::min(amax, accd(kind, x12, d12, ACCD_S, 1.0));
   }
   for (int v : C.pg) {
     double y0 = x[3 * v + 1] - s->P.ground_y;
@@ -1381,26 +1415,31 @@ double energy_delta(orc_scene* s, const double* q, const double* dq,
   positions(s, q1.data(), x1);
   const double w0 = h2 * s->P.kappa;
   const double dh = s->P.dhat;
-  double a12[12], b12[12], E0, E1;
-  int vid[4];
-  for (int kind = 0; kind < 2; ++kind) {
-    const auto& L = kind == ORC_PT ? C.pt : C.ee;
-    for (const auto& pr : L) {
-      pair_slots(s, kind, pr.first, pr.second, vid);
-      for (int k = 0; k < 4; ++k)
-        for (int i = 0; i < 3; ++i) {
-          a12[3 * k + i] = x[3 * vid[k] + i];
-          b12[3 * k + i] = x1[3 * vid[k] + i];
-        }
-      double w = w0 / pair_kappa_c(s, vid, 4);
-      double ex = kind == ORC_EE ? pair_eps_x(s, pr.first, pr.second) : 0.0;
-      pair_energy(kind, a12, ex, dh, w, false, false, &E0, nullptr, nullptr,
-                  nullptr, nullptr);
-      pair_energy(kind, b12, ex, dh, w, false, false, &E1, nullptr, nullptr,
-                  nullptr, nullptr);
-      dE += E1 - E0;
-    }
+  /* each pair's E1 - E0 on its own (in parallel in the OpenMP build), then
+   * summed in list order */
+  const long npt = (long)C.pt.size(), n = npt + (long)C.ee.size();
+  std::vector<double> de(n);
+#pragma omp parallel for schedule(dynamic, 16)
+  for (long c = 0; c < n; ++c) {
+    const int kind = c < npt ? ORC_PT : ORC_EE;
+    const auto& pr = c < npt ? C.pt[c] : C.ee[c - npt];
+    double a12[12], b12[12], E0, E1;
+    int vid[4];
+    pair_slots(s, kind, pr.first, pr.second, vid);
+    for (int k = 0; k < 4; ++k)
+      for (int i = 0; i < 3; ++i) {
+        a12[3 * k + i] = x[3 * vid[k] + i];
+        b12[3 * k + i] = x1[3 * vid[k] + i];
+      }
+    double w = w0 / pair_kappa_c(s, vid, 4);
+    double ex = kind == ORC_EE ? pair_eps_x(s, pr.first, pr.second) : 0.0;
+    pair_energy(kind, a12, ex, dh, w, false, false, &E0, nullptr, nullptr,
+                nullptr, nullptr);
+    pair_energy(kind, b12, ex, dh, w, false, false, &E1, nullptr, nullptr,
+                nullptr, nullptr);
+    de[c] = E1 - E0;
   }
+  for (long c = 0; c < n; ++c) dE += de[c];
   for (int v : C.pg) {
     double w = w0 / pair_kappa_c(s, &v, 1);
     double b0, b1, c0, c1, t0, t1;
@@ -1675,6 +1714,7 @@ int orc_local_solve(orc_scene* s, orc_stats* st) {
     positions(s, q.data(), x);
     size_t V = s->vbody.size();
     dx.assign(3 * V, 0.0);
+#pragma omp parallel for schedule(static)
     for (size_t v = 0; v < V; ++v) {
       const double* d = &dq[12 * s->vbody[v]];
       const double* xb = &s->xbar[3 * v];
@@ -1821,6 +1861,7 @@ int orc_ccd(orc_scene* s, const double* q, const double* dq,
   positions(s, q, x);
   size_t V = s->vbody.size();
   dx.assign(3 * V, 0.0);
+#pragma omp parallel for schedule(static)
   for (size_t v = 0; v < V; ++v) {
     const double* d = dq + 12 * s->vbody[v];
     const double* xb = &s->xbar[3 * v];
@@ -1840,6 +1881,7 @@ int orc_energy_delta(orc_scene* s, const double* q, const double* dq,
   positions(s, q, x);
   size_t V = s->vbody.size();
   dx.assign(3 * V, 0.0);
+#pragma omp parallel for schedule(static)
   for (size_t v = 0; v < V; ++v) {
     const double* d = dq + 12 * s->vbody[v];
     const double* xb = &s->xbar[3 * v];
@@ -1870,6 +1912,8 @@ int orc_penetration(orc_scene* s, const double* x, double pad,
     for (int k = 0; k < n; ++k) box_add(b, x + 3 * ids[k]);
     return b;
   };
+  /* a count and a minimum: the same in any order of the body pairs */
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : nc) reduction(min : md)
   for (size_t a = 0; a < nb; ++a)
     for (size_t c = a + 1; c < nb; ++c) {
       const orc_body& A = s->B[a];

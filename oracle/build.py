@@ -1,9 +1,13 @@
-"""Build the CPU oracle shared library (test infrastructure only).
+"""Build the CPU oracle shared libraries (test infrastructure only).
 
     python oracle/build.py
 
 Compiles abd_oracle.cpp with g++ at -O2 and -ffp-contract=off, so no
-multiply-add is fused and the arithmetic is what the source says.
+multiply-add is fused and the arithmetic is what the source says:
+liboracle.so single-threaded, and liboracle_omp.so with OpenMP over
+vertices, bodies and candidate pairs (every parallel loop either writes
+per-element results that are then combined in list order, or takes a
+minimum or a count, so both libraries compute bit-identical results).
 """
 import os
 import subprocess
@@ -11,17 +15,19 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
+LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
 
 
 def build(verbose: bool = False) -> str:
     src = os.path.join(HERE, "abd_oracle.cpp")
-    cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off", "-fno-fast-math",
-           "-fPIC", "-shared", "-Wall", "-Wno-unused-function", src, "-o",
-           LIB + ".tmp"]
-    if verbose:
-        print(" ".join(cmd))
-    subprocess.check_call(cmd)
-    os.replace(LIB + ".tmp", LIB)
+    for out, extra in ((LIB, ["-Wno-unknown-pragmas"]), (LIB_OMP, ["-fopenmp"])):
+        cmd = ["g++", "-std=c++17", "-O2", "-ffp-contract=off",
+               "-fno-fast-math", "-fPIC", "-shared", "-Wall",
+               "-Wno-unused-function", *extra, src, "-o", out + ".tmp"]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.check_call(cmd)
+        os.replace(out + ".tmp", out)
     return LIB
 
 

@@ -13,6 +13,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
+LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 
 PT, EE, PG = 0, 1, 2
 OK = 0
@@ -40,16 +41,18 @@ class OrcStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(omp: bool = False):
+    """The single-threaded oracle library, or (omp) its OpenMP build, which
+    computes bit-identical results on several threads."""
+    if omp not in _libs:
+        path = LIB_OMP_PATH if omp else LIB_PATH
+        if not os.path.exists(path):
             from . import build as _b  # type: ignore
             _b.build()
-        L = C.CDLL(LIB_PATH)
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         ip = C.POINTER(C.c_int32)
         lp = C.POINTER(C.c_int64)
@@ -101,8 +104,8 @@ def lib():
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args
-        _lib = L
-    return _lib
+        _libs[omp] = L
+    return _libs[omp]
 
 
 def _d(a):
@@ -154,8 +157,9 @@ class Oracle:
     """One oracle scene built from a scenes.Scene."""
 
     def __init__(self, scene, dense_max_dof: int = 2400, finalize=True,
-                 **param_over):
-        L = lib()
+                 omp: bool = False, **param_over):
+        """omp: run on the OpenMP build (same results, several threads)."""
+        L = self._L = lib(omp)
         p = dict(scene.params)
         p.update(param_over)
         self.params = p
@@ -181,13 +185,13 @@ class Oracle:
     def __del__(self):
         try:
             if getattr(self, "h", None):
-                lib().orc_destroy(self.h)
+                self._L.orc_destroy(self.h)
                 self.h = None
         except Exception:
             pass
 
     def error(self):
-        return lib().orc_last_error(self.h).decode()
+        return self._L.orc_last_error(self.h).decode()
 
     def _check(self, rc):
         if rc != OK:
@@ -197,13 +201,13 @@ class Oracle:
     # ---- state ----
     def edges(self):
         out = np.zeros((self.E, 2), dtype=np.int32)
-        lib().orc_edges(self.h, _i(out))
+        self._L.orc_edges(self.h, _i(out))
         return out
 
     def body_mass(self):
         M = np.zeros((self.B, 4, 4))
         v = np.zeros(self.B)
-        lib().orc_body_mass(self.h, _d(M), _d(v))
+        self._L.orc_body_mass(self.h, _d(M), _d(v))
         return M, v
 
     def set_shared(self, ids, z, u, rho, kappa_b):
@@ -212,28 +216,28 @@ class Oracle:
         u = _f64(u, (-1, 12)) if len(ids) else np.zeros((0, 12))
         rho = _f64(rho)
         kb = np.ascontiguousarray(kappa_b, dtype=np.int32)
-        return self._check(lib().orc_set_shared(self.h, _i(ids), len(ids),
+        return self._check(self._L.orc_set_shared(self.h, _i(ids), len(ids),
                                                 _d(z), _d(u), _d(rho),
                                                 _i(kb)))
 
     def set_pair_replication(self, mode):
-        return self._check(lib().orc_set_pair_replication(self.h, mode))
+        return self._check(self._L.orc_set_pair_replication(self.h, mode))
 
     def set_projection(self, on):
-        return self._check(lib().orc_set_projection(self.h, int(on)))
+        return self._check(self._L.orc_set_projection(self.h, int(on)))
 
     def begin_step(self):
-        return self._check(lib().orc_begin_step(self.h))
+        return self._check(self._L.orc_begin_step(self.h))
 
     def local_solve(self, check=True):
         st = OrcStats()
-        rc = lib().orc_local_solve(self.h, C.byref(st))
+        rc = self._L.orc_local_solve(self.h, C.byref(st))
         if check:
             self._check(rc)
         return st.as_dict()
 
     def end_step(self):
-        return self._check(lib().orc_end_step(self.h))
+        return self._check(self._L.orc_end_step(self.h))
 
     def step(self):
         self.begin_step()
@@ -244,37 +248,37 @@ class Oracle:
     def get_state(self):
         q = np.zeros((self.B, 12))
         qd = np.zeros((self.B, 12))
-        lib().orc_get_state(self.h, _d(q), _d(qd))
+        self._L.orc_get_state(self.h, _d(q), _d(qd))
         return q, qd
 
     def set_state(self, q, qdot=None):
         q = _f64(q, (-1, 12))
         qd = _f64(qdot, (-1, 12)) if qdot is not None else None
-        lib().orc_set_state(self.h, _d(q),
+        self._L.orc_set_state(self.h, _d(q),
                             _d(qd) if qd is not None else None)
 
     def qtilde(self):
         out = np.zeros((self.B, 12))
-        lib().orc_get_qtilde(self.h, _d(out))
+        self._L.orc_get_qtilde(self.h, _d(out))
         return out
 
     def set_step(self, qt, qtilde, scale):
         qt = _f64(qt, (-1, 12))
         qtilde = _f64(qtilde, (-1, 12))
-        lib().orc_set_step(self.h, _d(qt), _d(qtilde), float(scale))
+        self._L.orc_set_step(self.h, _d(qt), _d(qtilde), float(scale))
 
     # ---- hooks ----
     def vertices(self, q=None):
         x = np.zeros((self.V, 3))
         qq = _f64(q, (-1, 12)) if q is not None else None
-        lib().orc_vertices(self.h, _d(qq) if qq is not None else None, _d(x))
+        self._L.orc_vertices(self.h, _d(qq) if qq is not None else None, _d(x))
         return x
 
     def candidates(self, kind, x, dx=None):
         x = _f64(x, (-1, 3))
         dxa = _f64(dx, (-1, 3)) if dx is not None else None
         n = np.zeros(1, dtype=np.int64)
-        L = lib()
+        L = self._L
         L.orc_candidates(self.h, kind, _d(x),
                          _d(dxa) if dxa is not None else None, None, 0, _l(n))
         w = 1 if kind == PG else 2
@@ -292,7 +296,7 @@ class Oracle:
         Hd = np.zeros((self.B, 12, 12))
         n = np.zeros(1, dtype=np.int64)
         na = np.zeros(1, dtype=np.int64)
-        L = lib()
+        L = self._L
         L.orc_eval(self.h, _d(q), _d(E), _d(g), _d(Hd), 0, _l(n), None, None,
                    _l(na))
         cap = max(int(n[0]), 1)
@@ -308,21 +312,21 @@ class Oracle:
         q = _f64(q, (-1, 12))
         dq = np.zeros((self.B, 12))
         it = np.zeros(1, dtype=np.int32)
-        self._check(lib().orc_direction(self.h, _d(q), _d(dq), _i(it)))
+        self._check(self._L.orc_direction(self.h, _d(q), _d(dq), _i(it)))
         return dq, int(it[0])
 
     def ccd(self, q, dq):
         q = _f64(q, (-1, 12))
         dq = _f64(dq, (-1, 12))
         a = np.zeros(1)
-        self._check(lib().orc_ccd(self.h, _d(q), _d(dq), _d(a)))
+        self._check(self._L.orc_ccd(self.h, _d(q), _d(dq), _d(a)))
         return float(a[0])
 
     def energy_delta(self, q, dq, alpha):
         q = _f64(q, (-1, 12))
         dq = _f64(dq, (-1, 12))
         e = np.zeros(1)
-        self._check(lib().orc_energy_delta(self.h, _d(q), _d(dq),
+        self._check(self._L.orc_energy_delta(self.h, _d(q), _d(dq),
                                            float(alpha), _d(e)))
         return float(e[0])
 
@@ -331,7 +335,7 @@ class Oracle:
         nc = np.zeros(1, dtype=np.int64)
         md = np.zeros(1)
         pad = self.params["dhat"] if pad is None else pad
-        lib().orc_penetration(self.h, _d(x), float(pad), _l(nc), _d(md))
+        self._L.orc_penetration(self.h, _d(x), float(pad), _l(nc), _d(md))
         return int(nc[0]), float(md[0])
 
 

@@ -30,7 +30,8 @@ class Params(C.Structure):
                 ("max_newton", C.c_int32), ("max_pcg", C.c_int32),
                 ("max_ls", C.c_int32), ("has_ground", C.c_int32),
                 ("mollify_ee", C.c_int32), ("precision", C.c_int32),
-                ("list_capacity", C.c_int64)]
+                ("list_capacity", C.c_int64), ("mixed_switch", C.c_int32),
+                ("pad_", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -75,7 +76,7 @@ class Stats(C.Structure):
                 ("n_body_pairs", C.c_int64), ("n_chunk_pairs", C.c_int64),
                 ("n_body_pairs_swept", C.c_int64),
                 ("n_chunk_pairs_swept", C.c_int64),
-                ("fp64_fallback", C.c_int32)]
+                ("fp64_fallback", C.c_int32), ("newton_fp32", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -102,7 +103,8 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_consensus_begin", "abd_consensus_update",
            "abd_consensus_adapt", "abd_consensus_merge", "abd_consensus_get",
            "abd_admm_step", "abd_bind_workspace", "abd_workspace_info",
-           "abd_balance_update"]
+           "abd_balance_update", "abd_check_penetration",
+           "abd_get_timing_flops"]
 
 
 TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
@@ -152,6 +154,8 @@ def lib():
         "abd_set_timing": (C.c_int, [vp, C.c_int32]),
         "abd_get_timing": (C.c_int, [vp, C.c_int32, dp, lp, dp]),
         "abd_reset_timing": (C.c_int, [vp]),
+        "abd_get_timing_flops": (C.c_int, [vp, C.c_int32, dp]),
+        "abd_check_penetration": (C.c_int, [vp, lp, dp]),
         "abd_batch_create": (C.c_int, [C.POINTER(vp), C.c_int32,
                                        C.POINTER(vp)]),
         "abd_batch_run": (C.c_int, [vp, C.POINTER(Stats)]),
@@ -211,6 +215,7 @@ def make_params(p: dict) -> Params:
     o.mollify_ee = int(p.get("mollify_ee", 1))
     o.precision = int(p.get("precision", 0))
     o.list_capacity = int(p.get("list_capacity", 0))
+    o.mixed_switch = int(p.get("mixed_switch", 0))
     return o
 
 
@@ -449,9 +454,19 @@ class Solver:
             n = np.zeros(1, dtype=np.int64)
             by = np.zeros(1)
             self._check(lib().abd_get_timing(self.h, s, _d(ms), _l(n), _d(by)))
+            fl = np.zeros(1)
+            self._check(lib().abd_get_timing_flops(self.h, s, _d(fl)))
             out[name] = dict(ms=float(ms[0]), launches=int(n[0]),
-                             bytes=float(by[0]))
+                             bytes=float(by[0]), flops=float(fl[0]))
         return out
+
+    def check_penetration(self):
+        """(edge-triangle crossings, smallest candidate distance) of the
+        current state; penetration free iff (0, > 0)."""
+        nc = np.zeros(1, dtype=np.int64)
+        md = np.zeros(1)
+        self._check(lib().abd_check_penetration(self.h, _l(nc), _d(md)))
+        return int(nc[0]), float(md[0])
 
 
 class Batch:

@@ -43,8 +43,10 @@ struct Counters {
    * block: this pass took them (the static broad phase is skipped); redo:
    * a pass launched without the static broad phase found nothing to take
    * over, so it changes no state (the next pass can take over its swept
-   * lists, which cover the unchanged state). */
-  int sweep_ok, reuse, redo, pad_;
+   * lists, which cover the unchanged state).  want64 (static block): a
+   * mixed-precision problem stalled in this pass and asks for FP64
+   * Hessians for the rest of its solve. */
+  int sweep_ok, reuse, redo, want64;
   /* arrivals of the workgroups of the kernels whose last workgroup runs
    * the controller or ends the pass */
   unsigned fin[4];
@@ -75,7 +77,17 @@ struct ProbState {
   unsigned long long max_dq, min_toi;
   int state, status, newton, halvings, ls_count;
   int pcg_done, pcg_iters, pcg_total;
+  /* progress of the Newton stop measure: the best eps_N so far and the
+   * Newton iterations since it last fell to half the previous best; the
+   * iterations taken with FP32 Hessians (mixed precision) */
+  double best_eps;
+  int since_best, newton32;
 };
+
+/* a mixed-precision solve asks for FP64 Hessians once eps_N has not
+ * halved for MIXED_STALL_ITERS Newton iterations, or after mixed_switch
+ * Newton iterations (Scene) */
+#define MIXED_STALL_ITERS 16
 
 struct Scene {
   int B, V, T, E, NC;
@@ -137,6 +149,7 @@ struct Scene {
   int grid_blocks, assemble_blocks; /* launch sizes (tuning) */
   double theta;   /* Newton tolerance */
   int max_newton, max_ls, max_pcg;
+  int mixed_switch; /* Newton iterations before FP64 Hessians in any case */
   double eta;
 };
 

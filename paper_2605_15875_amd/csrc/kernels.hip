@@ -2599,7 +2599,7 @@ __device__ __forceinline__ bool wave_uniform(int p) {
 }
 
 __device__ __forceinline__ void ctrl_newton_check(const Scene& S, ProbState& P,
-                                                  const Counters& c0);
+                                                  Counters& c0);
 __device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n);
 /* |dq|_inf per problem over workgroup blk of nblk (256 bodies each) into
  * the counter block c0, then the Newton stop test in the last of them */
@@ -3054,12 +3054,15 @@ __global__ void k_ctrl_start(Scene S) {
   P.min_alpha = 1.0;
   P.final_eps = 0.0;
   P.alpha_acc = 0.0;
+  P.best_eps = INFINITY;
+  P.since_best = P.newton32 = 0;
 }
 __device__ __forceinline__ void ctrl_newton_check(const Scene& S, ProbState& P,
-                                                  const Counters& c0) {
+                                                  Counters& c0) {
   if (P.state != PS_NEWTON || static_overflow(c0, S) || c0.err || c0.redo) return;
   P.newton += 1;
   P.pcg_total += P.pcg_iters;
+  if (S.mixed) P.newton32 += 1;
   const double eps = __longlong_as_double((long long)P.max_dq) / (S.dt * P.scale);
   P.final_eps = eps;
   if (!isfinite(eps)) {
@@ -3068,6 +3071,18 @@ __device__ __forceinline__ void ctrl_newton_check(const Scene& S, ProbState& P,
   } else if (eps < S.theta) {
     P.state = PS_DONE;
     P.status = 0;
+  } else {
+    if (eps <= 0.5 * P.best_eps) {
+      P.best_eps = eps;
+      P.since_best = 0;
+    } else {
+      P.since_best += 1;
+    }
+    /* a mixed-precision problem that stopped making progress asks the
+     * host for FP64 Hessians (all problems of the scene switch) */
+    if (S.mixed && (P.since_best >= MIXED_STALL_ITERS ||
+                    P.newton >= S.mixed_switch))
+      c0.want64 = 1;
   }
 }
 __device__ __forceinline__ void ctrl_first_trial(ProbState& P) {

@@ -78,7 +78,7 @@ struct abd_ctx {
   Counters* h_ring = nullptr; /* pinned [2][2]: counters of passes in flight */
   Counters* d_ring = nullptr; /* the same memory as the device sees it */
   unsigned* d_pass = nullptr; /* device pass counter (ring slot parity) */
-  double* q_start = nullptr;  /* iterate at solve entry (mixed fallback) */
+  bool switched64 = false;    /* this solve switched to FP64 Hessians */
   hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
   std::vector<void*> allocs; /* device memory of our own (hipMalloc) */
@@ -118,7 +118,7 @@ struct abd_ctx {
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
-  double t_ms[7] = {0}, t_bytes[7] = {0};
+  double t_ms[7] = {0}, t_bytes[7] = {0}, t_flops[7] = {0};
   int64_t t_n[7] = {0};
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_pool;
@@ -577,6 +577,31 @@ void account_pcg_bytes(abd_ctx* ctx) {
   ctx->t_bytes[3] += per * ctx->h_cnt[0].pcg_iters;
 }
 
+/* Algorithmic work of the barrier stage (distance filter and assembly) of
+ * one pass, from the pass's static counters.  Bytes, each access counted
+ * once with no cache reuse: per PT/EE candidate its 12-byte list entry and
+ * four vertices (rest position 24 B and body id 4 B each), per ground
+ * candidate 4 + 28 B; per active pair its 16-byte entry written and read,
+ * its four vertices read again, three 12x12 blocks and two 12-gradients
+ * read and written; per body pair its off-diagonal block and used flag
+ * cleared.  Flops: about 100 per candidate distance and 22,300 per active
+ * PT/EE pair (the distance derivatives and the 9x9 projection, about 20k,
+ * and the mapping to three body blocks, about 2.3k), 30 per ground pair. */
+void account_s5(abd_ctx* ctx) {
+  if (ctx->timing != ABD_TIMING_ALL) return;
+  const Counters& c = ctx->h_cnt[0];
+  const Scene& S = ctx->S;
+  const double hs = (double)hess_elem(ctx);
+  const double cand = (double)std::min(c.n_pt, S.cap_pt) + std::min(c.n_ee, S.cap_ee);
+  const double pg = std::min(c.n_pg, S.cap_pg);
+  const double act = std::min(c.n_act, S.cap_act);
+  const double nbp = std::min(c.n_bp, S.cap_bp);
+  ctx->t_bytes[2] += cand * (12.0 + 4 * 28.0) + pg * 32.0 +
+                     act * (2 * 16.0 + 4 * 28.0 + 3 * 144.0 * hs * 2 + 2 * 96.0 * 2) +
+                     nbp * (144.0 * hs + 4.0);
+  ctx->t_flops[2] += cand * 100.0 + pg * 10.0 + act * 22300.0;
+}
+
 /* swept phase on the stream: broad phase over [q, q + dq], CCD, and the
  * energy difference at alpha_scale * min(1, TOI) */
 void launch_swept(abd_ctx* ctx, bool ccd, bool energy_at_toi) {
@@ -865,7 +890,19 @@ int device_solve(abd_ctx* ctx) {
       k = queued;
       continue;
     }
-    if (ctx->pass_timed[k & 1]) account_pcg_bytes(ctx);
+    if (ctx->pass_timed[k & 1]) {
+      account_pcg_bytes(ctx);
+      account_s5(ctx);
+    }
+    if (ctx->S.mixed && ctx->h_cnt[0].want64 && ctx->h_cnt[1].active != 0) {
+      /* a stalled mixed-precision problem: drain the queued pass and run
+       * the rest of the solve with FP64 Hessians (same buffers, which are
+       * sized for FP64); every problem keeps its state */
+      HIPCHK(hipStreamSynchronize(ctx->st));
+      drop_graphs(ctx);
+      ctx->S.mixed = 0;
+      ctx->switched64 = true;
+    }
     if (ctx->h_cnt[1].active == 0) {
       HIPCHK(hipStreamSynchronize(ctx->st));
       resolve_timing(ctx);
@@ -877,31 +914,22 @@ int device_solve(abd_ctx* ctx) {
   return fail(ctx, ABD_E_NOCONV, "device loop did not finish");
 }
 
-/* The local solve; a mixed-precision solve whose FP32 Hessian could not
- * take every problem to the Newton tolerance (NOCONV, LINESEARCH) is
- * repeated from its start iterate with FP64 Hessians in the same buffers.
- * *fell_back reports the repeat. */
+/* The local solve.  A mixed-precision solve in which a problem stops
+ * making progress with FP32 Hessians (eps_N not halving for
+ * MIXED_STALL_ITERS Newton iterations, or a third of the Newton cap spent)
+ * continues from where it is with FP64 Hessians in the same buffers for
+ * the rest of the solve; *fell_back reports the switch.  The scene is
+ * mixed again for the next solve. */
 int solve_with_fallback(abd_ctx* ctx, bool* fell_back) {
   Scene& S = ctx->S;
-  *fell_back = false;
-  const size_t nb = sizeof(double) * 12 * S.B;
-  if (S.mixed)
-    HIPCHK(hipMemcpyAsync(ctx->q_start, S.q, nb, hipMemcpyDeviceToDevice, ctx->st));
+  const int mixed = S.mixed;
+  ctx->switched64 = false;
   int rc = device_solve(ctx);
-  if (!S.mixed || (rc && rc != ABD_E_NOCONV)) return rc;
-  std::vector<ProbState> P(S.NP);
-  HIPCHK(hipMemcpy(P.data(), S.ps, sizeof(ProbState) * S.NP, hipMemcpyDeviceToHost));
-  bool bad = rc == ABD_E_NOCONV;
-  for (const ProbState& x : P)
-    bad |= x.status == ABD_E_NOCONV || x.status == ABD_E_LINESEARCH;
-  if (!bad) return ABD_OK;
-  HIPCHK(hipMemcpyAsync(S.q, ctx->q_start, nb, hipMemcpyDeviceToDevice, ctx->st));
-  drop_graphs(ctx);
-  S.mixed = 0;
-  rc = device_solve(ctx);
-  drop_graphs(ctx);
-  S.mixed = 1;
-  *fell_back = true;
+  *fell_back = ctx->switched64;
+  if (ctx->switched64) {
+    drop_graphs(ctx);
+    S.mixed = mixed;
+  }
   return rc;
 }
 
@@ -926,7 +954,8 @@ int abd_create(abd_ctx** out, const abd_params* p) {
   if (!(p->dt > 0) || !(p->dhat > 0) || !(p->kappa > 0) || !(p->kappa_A >= 0) ||
       p->max_newton < 1 || p->max_pcg < 1 || p->max_ls < 0 ||
       !(p->newton_theta > 0) || !(p->pcg_eta > 0) ||
-      (p->precision != ABD_FP64 && p->precision != ABD_MIXED) || p->list_capacity < 0)
+      (p->precision != ABD_FP64 && p->precision != ABD_MIXED) || p->list_capacity < 0 ||
+      p->mixed_switch < 0)
     return ABD_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1210,7 +1239,6 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.acc, 16))) return rc;
   if ((rc = dalloc(ctx, &S.pw, 5 * 12L * B))) return rc;
   if ((rc = dalloc(ctx, &ctx->d_pass, 1))) return rc;
-  if ((rc = dalloc(ctx, &ctx->q_start, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.pcg_rec, 2L * ((B + 15) / 16)))) return rc;
   HIPCHK(hipMemset(S.pcg_rec, 0, sizeof(PcgRec) * 2 * ((B + 15) / 16)));
   {
@@ -1235,6 +1263,9 @@ int abd_finalize(abd_ctx* ctx) {
   S.max_newton = ctx->P.max_newton;
   S.max_ls = ctx->P.max_ls;
   S.max_pcg = ctx->P.max_pcg;
+  S.mixed_switch = ctx->P.mixed_switch > 0
+                       ? ctx->P.mixed_switch
+                       : std::max(1, ctx->P.max_newton / 3);
   S.iter_mode = 0;
   {
     std::vector<int> bp0(B, 0);
@@ -1283,6 +1314,22 @@ int abd_finalize(abd_ctx* ctx) {
     ctx->finalized = false;
     return fail(ctx, ABD_E_INFEASIBLE, "initial state has intersecting bodies");
   }
+  return ABD_OK;
+}
+
+int abd_check_penetration(abd_ctx* ctx, int64_t* n_cross, double* min_dist) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (!n_cross || !min_dist) return fail(ctx, ABD_E_INVALID_ARG, "check_penetration");
+  Scene& S = ctx->S;
+  S.iter_mode = 0;
+  if ((rc = assemble(ctx))) return rc;
+  *min_dist = bits_to_double(ctx->h_cnt[0].min_dist);
+  if ((rc = reset_counters(ctx, 0))) return rc;
+  broad_phase(ctx, S, 0);
+  launch_crossings(S, ctx->st);
+  if ((rc = read_counters(ctx, 0))) return rc;
+  *n_cross = ctx->h_cnt[0].n_act;
   return ABD_OK;
 }
 
@@ -1426,6 +1473,7 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
   }
   const Counters& c = ctx->h_cnt[0];
   st.newton_iters = P.newton;
+  st.newton_fp32 = P.newton32;
   st.pcg_iters_total = P.pcg_total;
   st.ls_halvings = P.halvings;
   st.final_eps_N = P.final_eps;
@@ -1934,6 +1982,7 @@ int abd_batch_run(abd_batch* bt, abd_stats* out) {
       abd_stats& st = out[i];
       std::memset(&st, 0, sizeof(st));
       st.newton_iters = P[i].newton;
+      st.newton_fp32 = P[i].newton32;
       st.pcg_iters_total = P[i].pcg_total;
       st.ls_halvings = P[i].halvings;
       st.status = status ? status : P[i].status;
@@ -2356,11 +2405,20 @@ int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
   return ABD_OK;
 }
 
+int abd_get_timing_flops(abd_ctx* ctx, int32_t stage, double* flops) {
+  if (!ctx || stage < 0 || stage > 6 || !flops) return ABD_E_INVALID_ARG;
+  (void)hipStreamSynchronize(ctx->st);
+  resolve_timing(ctx);
+  *flops = ctx->t_flops[stage];
+  return ABD_OK;
+}
+
 int abd_reset_timing(abd_ctx* ctx) {
   if (!ctx) return ABD_E_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->st);
   resolve_timing(ctx);
-  for (int i = 0; i < 7; ++i) ctx->t_ms[i] = ctx->t_bytes[i] = 0.0, ctx->t_n[i] = 0;
+  for (int i = 0; i < 7; ++i)
+    ctx->t_ms[i] = ctx->t_bytes[i] = ctx->t_flops[i] = 0.0, ctx->t_n[i] = 0;
   return ABD_OK;
 }
 

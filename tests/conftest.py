@@ -16,6 +16,6 @@ def pytest_configure(config):
 @pytest.fixture(scope="session", autouse=True)
 def _oracle_built():
     from oracle import build
-    if not os.path.exists(build.LIB):
+    if not (os.path.exists(build.LIB) and os.path.exists(build.LIB_OMP)):
         build.build()
     yield

@@ -76,20 +76,40 @@ def test_mixed_spheres_converge_without_penetration():
     gpu.close()
 
 
-def test_mixed_fallback_to_fp64_is_reported():
-    """A mixed solve that cannot reach the tolerance (one Newton iteration
-    allowed) is repeated with FP64 Hessians, which reports the repeat and
-    the final status; a solvable step needs no repeat."""
-    sc = scenes.config(0, newton_theta=1e-6)
-    ok = abd.Solver(sc, precision=1)
-    st = ok.step()
-    assert st["status"] == 0 and st["fp64_fallback"] == 0
-    s1 = abd.Solver(sc, precision=1, max_newton=1)
-    s1.begin_step()
-    st = s1.local_solve(check=False)
+def test_mixed_switch_to_fp64_continues_the_solve():
+    """A mixed solve that is told to switch after two Newton iterations
+    continues from its current iterate with FP64 Hessians: the switch and
+    the FP32 share of the iterations are reported, no work is repeated, and
+    the step lands on the oracle's step from the same state.  A solvable
+    step with the default rule needs no switch, and the context is mixed
+    again for its next solve."""
+    sc = scenes.config(0, newton_theta=1e-9, pcg_eta=1e-12)
+    ref = O.Oracle(sc, newton_theta=1e-9, pcg_eta=1e-12)
+    for _ in range(10):  # contact starts at step 9
+        ref.step()
+    q, qd = ref.get_state()
+    gpu = abd.Solver(sc, precision=1, mixed_switch=2)
+    gpu.set_state(q, qd)
+    st = gpu.step()
+    sr = ref.step()
+    assert st["status"] == 0
     assert st["fp64_fallback"] == 1
-    assert st["status"] == -4  # NOCONV in FP64 as well
-    # the context keeps working in mixed precision afterwards
-    s2 = abd.Solver(sc, precision=1)
+    assert 2 <= st["newton_fp32"] < st["newton_iters"], st
+    err = np.abs(gpu.vertices() - ref.vertices()).max() / st["scene_scale"]
+    assert err < 1e-9, err
+    assert sr["newton_iters"] > 3
+    # the default rule: no switch on a solvable step, all iterations FP32,
+    # and the next solve starts in mixed precision again
+    ok = abd.Solver(sc, precision=1)
+    ok.set_state(q, qd)
     for _ in range(3):
-        assert s2.step()["status"] == 0
+        st = ok.step()
+        assert st["status"] == 0 and st["fp64_fallback"] == 0
+        assert st["newton_fp32"] == st["newton_iters"]
+    gpu.set_state(q, qd)
+    st = gpu.step()
+    assert st["status"] == 0 and st["fp64_fallback"] == 1
+    assert 2 <= st["newton_fp32"] < st["newton_iters"]
+    gpu.close()
+    ok.close()
+
