@@ -50,7 +50,18 @@ struct Counters {
   /* arrivals of the workgroups of the kernels whose last workgroup runs
    * the controller or ends the pass */
   unsigned fin[4];
+  /* connected components of the pass's linear system (static block; set by
+   * the block-row build when it labels them, plan = 1): components of
+   * DIR_MAX bodies or fewer solved directly (n_dir of 2 bodies or more),
+   * bodies of larger components left to the PCG (n_big) */
+  int plan, n_dir, n_big, pad2_;
 };
+
+/* largest component (bodies) solved by a dense Cholesky factorisation */
+#define DIR_MAX 8
+/* scenes of at most this many bodies build their block rows (and label
+ * the components of the system) in one workgroup */
+#define BSR_LDS_ROWS 12288
 
 /* per-problem state of the device-driven Newton loop; a plain context is
  * one problem, a batch merges several */
@@ -126,6 +137,13 @@ struct Scene {
   int *slot_used;
   int *row_ptr, *row_cnt, *col_slot, *col_body, *col_trans;
   int cap_col;
+  /* components of the system: bmode [B] (0 alone, 1 in a component solved
+   * directly, 2 in a component left to the PCG), the bodies of each
+   * directly solved component dir_body [B/2 + 1][DIR_MAX] (ascending) and
+   * their number dir_n [B/2 + 1]; comp_solve: label components in this
+   * scene's block-row build (the PCG form in use masks the rest) */
+  int *bmode, *dir_body, *dir_n;
+  int comp_solve;
   /* PCG work */
   double *r, *zv, *p0, *p1, *Ap, *acc; /* acc: [4][4] ring of dots */
   double *pw; /* single-reduction PCG: [5][12B] w, m0, m1, t0, t1 */

@@ -1297,10 +1297,21 @@ __global__ void k_bsr_scan(Scene S) {
 }
 /* the three steps in one workgroup when the block-row counts fit in LDS:
  * counts by LDS atomics, the same scan, then the counts become the fill
- * cursors */
-#define BSR_LDS_ROWS 12288
+ * cursors.  With comp_solve the same workgroup then labels the connected
+ * components of the system (bodies joined by a used off-diagonal block)
+ * and sorts them for the linear solve: a body alone is solved with its
+ * block inverse, a component of 2..DIR_MAX bodies by a dense Cholesky
+ * factorisation, a larger one by the PCG.  Labelling: every body starts as
+ * its own root; each round, every used block whose two bodies have
+ * different roots links the larger root under the smaller (an LDS atomic
+ * minimum, so links only ever point to smaller indices), then every body
+ * takes its root; rounds repeat until a round links nothing. */
+#define DIR_SLOTS (BSR_LDS_ROWS / 2 + 1)
 __global__ __launch_bounds__(1024) void k_bsr_small(Scene S) {
   __shared__ int cnt[BSR_LDS_ROWS + 1];
+  __shared__ int par[BSR_LDS_ROWS];
+  __shared__ int cur[DIR_SLOTS];
+  __shared__ int s_changed, s_ndir, s_nbig;
   __shared__ int wsum[16];
   const int n = S.B;
   for (int i = threadIdx.x; i <= n; i += blockDim.x) cnt[i] = 0;
@@ -1358,6 +1369,74 @@ __global__ __launch_bounds__(1024) void k_bsr_small(Scene S) {
       S.col_slot[k] = p; S.col_body[k] = ab.x; S.col_trans[k] = 1;
     }
   }
+  if (!S.comp_solve) return;
+  /* ---- connected components ---- */
+  volatile int* vp = par;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) par[i] = i;
+  __syncthreads();
+  bool settled = false;
+  for (int round = 0; round < 64 && !settled; ++round) {
+    if (threadIdx.x == 0) s_changed = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
+      if (!S.slot_used[p]) continue;
+      const int2 ab = S.bp[p];
+      int ra = ab.x, rb = ab.y;
+      while (vp[ra] != ra) ra = vp[ra];
+      while (vp[rb] != rb) rb = vp[rb];
+      if (ra != rb) {
+        atomicMin(&par[max(ra, rb)], min(ra, rb));
+        s_changed = 1;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      int r = vp[i];
+      while (vp[r] != r) r = vp[r];
+      vp[i] = r;
+    }
+    __syncthreads();
+    settled = s_changed == 0;
+  }
+  /* a graph that did not settle in the bounded rounds stays with the PCG */
+  if (!settled) return;
+  /* component sizes (the fill cursors are free again) */
+  for (int i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
+  if (threadIdx.x == 0) s_ndir = s_nbig = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[par[i]], 1);
+  __syncthreads();
+  int nbig = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int c = cnt[par[i]];
+    const int mode = c == 1 ? 0 : (c <= DIR_MAX ? 1 : 2);
+    S.bmode[i] = mode;
+    nbig += mode == 2;
+  }
+  if (nbig) atomicAdd(&s_nbig, nbig);
+  __syncthreads();
+  /* a slot per directly solved component, kept (negated) at its root */
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (par[i] == i && cnt[i] >= 2 && cnt[i] <= DIR_MAX) {
+      const int k = atomicAdd(&s_ndir, 1);
+      cur[k] = 0;
+      cnt[i] = -1 - k;
+    }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int c = cnt[par[i]];
+    if (c < 0) {
+      const int k = -1 - c;
+      S.dir_body[k * DIR_MAX + atomicAdd(&cur[k], 1)] = i;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < s_ndir; k += blockDim.x) S.dir_n[k] = cur[k];
+  if (threadIdx.x == 0) {
+    S.cnt->n_dir = s_ndir;
+    S.cnt->n_big = s_nbig;
+    S.cnt->plan = 1;
+  }
 }
 __global__ void k_bsr_fill(Scene S) {
   int nbp = min(S.cnt->n_bp, S.cap_bp);
@@ -1379,7 +1458,9 @@ __global__ void k_bsr_fill(Scene S) {
 /* inverse of every diagonal block by Gauss-Jordan (SPD, no pivoting):
  * twelve lanes per body, one row (with its identity half) per lane, five
  * bodies per wavefront; the pivot row reaches the other lanes of its body
- * by cross-lane shuffles, so no barrier is needed */
+ * by cross-lane shuffles, so no barrier is needed.  A body that the
+ * block-row build found alone in the system (no used off-diagonal block)
+ * is solved here: dq = -H^-1 g, exactly (its block is its whole system). */
 template <typename HT>
 __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
   const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -1415,6 +1496,124 @@ __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
     HT* Pi = (HT*)S.Pinv;
 #pragma unroll
     for (int c = 0; c < 12; ++c) Pi[144 * b + 12 * r + c] = (HT)row[12 + c];
+  }
+  /* a body alone: dq = -H^-1 g (FP64 from the stored Hessian) */
+  if (S.cnt->plan) {
+    const bool alone = act && S.bmode[b] == 0 &&
+                       (S.iter_mode == 0 || S.ps[S.bprob[b]].state == PS_NEWTON);
+    const double gr = alone ? S.g[12 * b + r] : 0.0;
+    double v = 0.0;
+#pragma unroll
+    for (int c = 0; c < 12; ++c) {
+      const int src = slot < 5 ? base + c : lane;
+      v += row[12 + c] * __shfl(gr, src, 64);
+    }
+    if (alone) S.dq[12 * b + r] = -v;
+  }
+}
+
+/* Components of 2..DIR_MAX bodies, one wavefront each: the component's
+ * system (its diagonal blocks and the used off-diagonal blocks between its
+ * bodies, bodies in ascending order) is formed as a dense lower triangle in
+ * LDS, factorised H = L L^T by right-looking Cholesky (FP64, from the
+ * stored Hessian of either precision) and solved for dq = -H^-1 g by two
+ * triangular substitutions: the exact solution of the component's system.
+ * Lower triangle packed by rows: (i, j), j <= i, at i (i + 1) / 2 + j. */
+#define DIR_WAVES 2
+#define DIR_N (12 * DIR_MAX)
+__device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
+template <typename HT>
+__global__ __launch_bounds__(64 * DIR_WAVES) void k_direct(Scene S) {
+  __shared__ double Ls[DIR_WAVES][DIR_N * (DIR_N + 1) / 2];
+  __shared__ double xs[DIR_WAVES][DIR_N];
+  __shared__ int bod[DIR_WAVES][DIR_MAX];
+  if (!S.cnt->plan) return;
+  const int ndir = S.cnt->n_dir;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  double* const L = Ls[wave];
+  double* const x = xs[wave];
+  int* const bw = bod[wave];
+  for (int k = blockIdx.x * DIR_WAVES + wave; k < ndir; k += gridDim.x * DIR_WAVES) {
+    const int m = S.dir_n[k];
+    /* the bodies in ascending order (rank = number of smaller ids) */
+    const int mine = lane < m ? S.dir_body[k * DIR_MAX + lane] : 0x7fffffff;
+    int rank = 0;
+    for (int t = 0; t < m; ++t) rank += __shfl(mine, t, 64) < mine ? 1 : 0;
+    if (lane < m) bw[rank] = mine;
+    wave_lds_sync();
+    if (S.iter_mode != 0 && S.ps[S.bprob[bw[0]]].state != PS_NEWTON) {
+      wave_lds_sync();
+      continue;
+    }
+    const int n = 12 * m, ntri = n * (n + 1) / 2;
+    for (int e = lane; e < ntri; e += 64) L[e] = 0.0;
+    wave_lds_sync();
+    for (int i = 0; i < m; ++i) {
+      const int b = bw[i];
+      const HT* Hd = (const HT*)S.Hdiag + 144 * (size_t)b;
+      for (int e = lane; e < 144; e += 64) {
+        const int r = e / 12, c = e % 12;
+        if (r >= c) L[pk(12 * i + r, 12 * i + c)] = (double)Hd[e];
+      }
+      /* blocks (i, j) with j < i from body i's block row */
+      for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
+        const int nb = S.col_body[e];
+        int j = 0;
+        while (j < m && bw[j] != nb) ++j;
+        if (j >= i) continue;
+        const HT* blk = (const HT*)S.Hoff + 144 * (size_t)S.col_slot[e];
+        const int tr = S.col_trans[e];
+        for (int t = lane; t < 144; t += 64) {
+          const int r = t / 12, c = t % 12;
+          L[pk(12 * i + r, 12 * j + c)] = (double)(tr ? blk[12 * c + r] : blk[12 * r + c]);
+        }
+      }
+      for (int t = lane; t < 12; t += 64) x[12 * i + t] = -S.g[12 * b + t];
+    }
+    wave_lds_sync();
+    /* H = L L^T, column by column */
+    for (int kk = 0; kk < n; ++kk) {
+      const double d = sqrt(L[pk(kk, kk)]);
+      const double id = 1.0 / d;
+      for (int i = kk + 1 + lane; i < n; i += 64) L[pk(i, kk)] *= id;
+      wave_lds_sync();
+      if (lane == 0) L[pk(kk, kk)] = d;
+      /* trailing lower triangle (i, j), kk < j <= i: element t of it is at
+       * row ii, column jj of the trailing block, advanced 64 at a time */
+      const int nt = n - kk - 1, tot = nt * (nt + 1) / 2;
+      int ii = 0, jj = lane;
+      while (jj > ii) {
+        jj -= ii + 1;
+        ++ii;
+      }
+      for (int t = lane; t < tot; t += 64) {
+        const int i = kk + 1 + ii, j = kk + 1 + jj;
+        L[pk(i, j)] -= L[pk(i, kk)] * L[pk(j, kk)];
+        jj += 64;
+        while (jj > ii) {
+          jj -= ii + 1;
+          ++ii;
+        }
+      }
+      wave_lds_sync();
+    }
+    /* L y = -g, then L^T dq = y */
+    for (int kk = 0; kk < n; ++kk) {
+      const double y = x[kk] / L[pk(kk, kk)];
+      wave_lds_sync();
+      if (lane == 0) x[kk] = y;
+      for (int i = kk + 1 + lane; i < n; i += 64) x[i] -= L[pk(i, kk)] * y;
+      wave_lds_sync();
+    }
+    for (int kk = n - 1; kk >= 0; --kk) {
+      const double v = x[kk] / L[pk(kk, kk)];
+      wave_lds_sync();
+      if (lane == 0) x[kk] = v;
+      for (int i = lane; i < kk; i += 64) x[i] -= L[pk(kk, i)] * v;
+      wave_lds_sync();
+    }
+    for (int t = lane; t < n; t += 64) S.dq[12 * bw[t / 12] + t % 12] = x[t];
+    wave_lds_sync();
   }
 }
 
@@ -2067,6 +2266,11 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   const int ngroups = (S.B + 15) / 16;
   const int gr = blockIdx.x;
   if (gr >= ngroups) return;
+  /* with labelled components only the bodies of components larger than
+   * DIR_MAX are solved here (the others directly); none: nothing to do */
+  const bool planned = S.cnt->plan != 0;
+  if (planned && S.cnt->n_big == 0) return;
+  auto in_pcg = [&](int body) { return !planned || S.bmode[body] == 2; };
   const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
   const int g0 = gr * 16, gend = min(S.B, g0 + 16);
   const int b = g0 + lb;
@@ -2271,7 +2475,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
         double v = 0.0;
         if (q >= 0 && q < nloc && !ldone[q]) {
           const int on = 12 * nb + c;
-          v = init ? -S.g[on]
+          v = init ? (in_pcg(nb) ? -S.g[on] : 0.0)
                    : Rb[cur][on] - alp[q] * (Wb[cur][on] + bet[q] * Sb[(ph) & 1][on]);
         }
         rnb[le][c] = v;
@@ -2315,7 +2519,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   range();
   if (!s_more) return;
   /* phase 0: r = b = -g, x = p = s = 0, u = P^-1 r, w = A u */
-  rr = real && !ldone[j] ? -S.g[o] : 0.0;
+  rr = real && !ldone[j] && in_pcg(b) ? -S.g[o] : 0.0;
   double ur = phase(0, true);
   if (threadIdx.x < 64) {
     bool live = false;
@@ -2374,7 +2578,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   }
   if ((int)threadIdx.x < nloc && !ldone[threadIdx.x] && q_first[threadIdx.x])
     ps[plo + threadIdx.x].pcg_iters = it;
-  if (real && !(S.iter_mode != 0 && ps[p].state != PS_NEWTON)) S.dq[o] = xr;
+  if (real && in_pcg(b) && !(S.iter_mode != 0 && ps[p].state != PS_NEWTON)) S.dq[o] = xr;
   if (threadIdx.x == 0) atomicMax(&S.cnt->pcg_iters, it);
 }
 
@@ -3528,6 +3732,15 @@ void launch_block_inverse(const Scene& S, hipStream_t st) {
     hipLaunchKernelGGL(k_block_inverse<float>, dim3(cdiv(S.B, 15)), dim3(192), 0, st, S);
   else
     hipLaunchKernelGGL(k_block_inverse<double>, dim3(cdiv(S.B, 15)), dim3(192), 0, st, S);
+  /* the components solved directly (none unless the block-row build
+   * labelled them) */
+  if (S.comp_solve) {
+    const unsigned g = std::min(256u, cdiv(S.B / 2 + 1, DIR_WAVES));
+    if (S.mixed)
+      hipLaunchKernelGGL(k_direct<float>, dim3(g), dim3(64 * DIR_WAVES), 0, st, S);
+    else
+      hipLaunchKernelGGL(k_direct<double>, dim3(g), dim3(64 * DIR_WAVES), 0, st, S);
+  }
 }
 int pcg_max_grid() {
   int dev = 0, ncu = 0, per = 0;

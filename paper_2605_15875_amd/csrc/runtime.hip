@@ -541,8 +541,19 @@ int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
   return std::max(1, std::min(ctx->pcg_grid, want));
 }
 
+/* whether the block-row build labels the components of the system, so
+ * that bodies alone and components of at most DIR_MAX bodies are solved
+ * directly and only larger ones by the PCG (the problem-local
+ * one-exchange form, which masks the others; scenes whose block rows are
+ * built in one workgroup) */
+int comp_solve_on(const abd_ctx* ctx, const Scene& S) {
+  return S.B <= BSR_LDS_ROWS && pcg_variant(ctx, S) == ABD_PCG_LOCAL1 ? 1 : 0;
+}
+
 /* block-Jacobi PCG and the Newton stop norm on the stream */
-int launch_solve(abd_ctx* ctx, const Scene& S, bool in_loop) {
+int launch_solve(abd_ctx* ctx, const Scene& S0, bool in_loop) {
+  Scene S = S0;
+  S.comp_solve = comp_solve_on(ctx, S);
   {
     StageTimer t(ctx, 6);
     if (!in_loop) {
@@ -704,6 +715,7 @@ void pass_pre(abd_ctx* ctx, bool take_over) {
   const Counters fresh = fresh_counters();
   launch_static(ctx, S1, take_over, &fresh);
   StageTimer t(ctx, 6);
+  S1.comp_solve = comp_solve_on(ctx, S1);
   launch_bsr(S1, ctx->st);
   launch_block_inverse(S1, ctx->st);
 }
@@ -1231,6 +1243,9 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.col_slot, S.cap_col))) return rc;
   if ((rc = dalloc(ctx, &S.col_body, S.cap_col))) return rc;
   if ((rc = dalloc(ctx, &S.col_trans, S.cap_col))) return rc;
+  if ((rc = dalloc(ctx, &S.bmode, B))) return rc;
+  if ((rc = dalloc(ctx, &S.dir_body, (long)(B / 2 + 1) * DIR_MAX))) return rc;
+  if ((rc = dalloc(ctx, &S.dir_n, B / 2 + 1))) return rc;
   if ((rc = dalloc(ctx, &S.r, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.zv, 12L * B))) return rc;
   if ((rc = dalloc(ctx, &S.p0, 12L * B))) return rc;
