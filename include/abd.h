@@ -180,6 +180,28 @@ int abd_begin_step(abd_ctx* ctx);
  * Errors: NOCONV, LINESEARCH, DEVICE, OOM. */
 int abd_local_solve(abd_ctx* ctx, abd_stats* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * solve as abd_local_solve, with the same results, that allocates nothing.
+ * The per-pass lists of the solve (body pairs with their off-diagonal
+ * blocks and block-row columns, chunk pairs, candidate and active pairs)
+ * live in a static device array of the library (64 MiB on every GPU it
+ * runs on, held until the process ends) instead of the context's buffers,
+ * at fixed maximum sizes: 32768 body pairs, 262144 chunk pairs, 524288
+ * point-triangle and 524288 edge-edge candidates, 262144 point-ground
+ * candidates and 262144 active pairs.  A solve whose lists would exceed a
+ * maximum stops with ABD_E_CAPACITY (abd_last_error names the list and
+ * its maximum; q is the last accepted iterate, feasible like every
+ * iterate) instead of growing them.  Passes are launched directly (no
+ * graph replay) and stage timing is off during the call; no device memory
+ * is allocated or freed.  The context's own buffers must exist
+ * (abd_finalize).  The context's device must be current (INVALID_ARG
+ * otherwise).  All calls on one GPU share its array: two such calls that
+ * overlap in time on one GPU (from several threads, or on contexts whose
+ * streams run concurrently) race and give undefined results.  Errors:
+ * NOCONV, LINESEARCH, CAPACITY, DEVICE, INVALID_ARG. */
+int abd_local_solve_static(abd_ctx* ctx, abd_stats* out);
+
 /* Finish the step: qdot = (q - q^t) / h. */
 int abd_end_step(abd_ctx* ctx);
 

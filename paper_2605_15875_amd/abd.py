@@ -104,7 +104,7 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_consensus_adapt", "abd_consensus_merge", "abd_consensus_get",
            "abd_admm_step", "abd_bind_workspace", "abd_workspace_info",
            "abd_balance_update", "abd_check_penetration",
-           "abd_get_timing_flops"]
+           "abd_get_timing_flops", "abd_local_solve_static"]
 
 
 TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
@@ -134,6 +134,7 @@ def lib():
         "abd_set_pair_replication": (C.c_int, [vp, C.c_int32]),
         "abd_begin_step": (C.c_int, [vp]),
         "abd_local_solve": (C.c_int, [vp, C.POINTER(Stats)]),
+        "abd_local_solve_static": (C.c_int, [vp, C.POINTER(Stats)]),
         "abd_end_step": (C.c_int, [vp]),
         "abd_get_state": (C.c_int, [vp, dp, dp]),
         "abd_set_state": (C.c_int, [vp, dp, dp]),
@@ -316,6 +317,15 @@ class Solver:
     def local_solve(self, check=True):
         st = Stats()
         rc = lib().abd_local_solve(self.h, C.byref(st))
+        if check:
+            self._check(rc)
+        return st.as_dict()
+
+    def local_solve_static(self, check=True):
+        """The allocation-free solve: lists in the library's static device
+        scratch (see abd_local_solve_static)."""
+        st = Stats()
+        rc = lib().abd_local_solve_static(self.h, C.byref(st))
         if check:
             self._check(rc)
         return st.as_dict()

@@ -31,6 +31,18 @@
 
 using namespace abd;
 
+/* Static device scratch of the allocation-free solve
+ * (abd_local_solve_static): the per-pass lists of a solve (body pairs with
+ * their off-diagonal blocks and block-row columns, chunk pairs, candidate
+ * and active pairs) live in this array instead of buffers of the context.
+ * Every GPU the library runs on holds its own copy until the process ends.
+ * Host code never passes the array's name to a kernel: the device address
+ * of the current device's copy is looked up once per device with
+ * hipGetSymbolAddress (scratch_ptr) and only that address is used. */
+#define ABD_SCRATCH_BYTES (64u << 20)
+#define ABD_SCRATCH_DEVICES 64
+static __device__ __align__(256) unsigned char scratch[ABD_SCRATCH_BYTES];
+
 namespace {
 
 struct HBody {
@@ -79,6 +91,8 @@ struct abd_ctx {
   Counters* d_ring = nullptr; /* the same memory as the device sees it */
   unsigned* d_pass = nullptr; /* device pass counter (ring slot parity) */
   bool switched64 = false;    /* this solve switched to FP64 Hessians */
+  bool no_alloc = false;      /* a solve in the static scratch is running */
+  int device = 0;             /* HIP device of the context */
   hipEvent_t ring_ev[2] = {nullptr, nullptr};
   double* h_buf = nullptr;   /* pinned scratch, 64 doubles */
   std::vector<void*> allocs; /* device memory of our own (hipMalloc) */
@@ -129,6 +143,24 @@ namespace {
 int fail(abd_ctx* c, int code, const std::string& m) {
   if (c) c->err = m;
   return code;
+}
+
+/* device address of the scratch copy of device dev (nullptr until
+ * scratch_init ran on that device) */
+std::atomic<void*> g_scratch[ABD_SCRATCH_DEVICES];
+
+/* look up the current device's scratch address once (the device must be
+ * current); ABD_OK or ABD_E_DEVICE */
+int scratch_init(int dev) {
+  if (dev < 0 || dev >= ABD_SCRATCH_DEVICES) return ABD_E_DEVICE;
+  if (g_scratch[dev].load()) return ABD_OK;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return ABD_E_DEVICE;
+  }
+  g_scratch[dev].store(p);
+  return ABD_OK;
 }
 
 void drop_graphs(abd_ctx* c) {
@@ -421,6 +453,25 @@ bool over_cap(const Scene& S, const Counters& c) {
   return c.n_bp > S.cap_bp || c.n_cp > S.cap_cp || c.n_pt > S.cap_pt ||
          c.n_ee > S.cap_ee || c.n_pg > S.cap_pg || c.n_act > S.cap_act;
 }
+/* the list that outgrew the static scratch, as an error */
+int static_overflow_error(abd_ctx* ctx) {
+  const Scene& S = ctx->S;
+  const char* names[6] = {"body pairs", "chunk pairs", "point-triangle candidates",
+                          "edge-edge candidates", "point-ground candidates",
+                          "active pairs"};
+  const int caps[6] = {S.cap_bp, S.cap_cp, S.cap_pt, S.cap_ee, S.cap_pg, S.cap_act};
+  for (int b = 0; b < 2; ++b) {
+    const Counters& c = ctx->h_cnt[b];
+    const int n[6] = {c.n_bp, c.n_cp, c.n_pt, c.n_ee, c.n_pg, c.n_act};
+    for (int i = 0; i < 6; ++i)
+      if (n[i] > caps[i])
+        return fail(ctx, ABD_E_CAPACITY,
+                    std::string("static scratch: ") + std::to_string(n[i]) + " " +
+                        names[i] + " exceed its maximum of " + std::to_string(caps[i]));
+  }
+  return fail(ctx, ABD_E_CAPACITY, "static scratch: a list overflowed");
+}
+
 void drop_graphs_if(abd_ctx* ctx, const Counters& c) {
   if (over_cap(ctx->S, c)) drop_graphs(ctx);
 }
@@ -893,6 +944,7 @@ int device_solve(abd_ctx* ctx) {
       /* drain, grow, and start over from the state the overflowing pass
        * left unchanged */
       HIPCHK(hipStreamSynchronize(ctx->st));
+      if (ctx->no_alloc) return static_overflow_error(ctx);
       bool ch0 = false, ch1 = false;
       if ((rc = grow(ctx, ctx->h_cnt[0], &ch0))) return rc;
       if ((rc = grow(ctx, ctx->h_cnt[1], &ch1))) return rc;
@@ -911,7 +963,7 @@ int device_solve(abd_ctx* ctx) {
        * the rest of the solve with FP64 Hessians (same buffers, which are
        * sized for FP64); every problem keeps its state */
       HIPCHK(hipStreamSynchronize(ctx->st));
-      drop_graphs(ctx);
+      if (!ctx->no_alloc) drop_graphs(ctx); /* no graphs run without allocation */
       ctx->S.mixed = 0;
       ctx->switched64 = true;
     }
@@ -939,7 +991,7 @@ int solve_with_fallback(abd_ctx* ctx, bool* fell_back) {
   int rc = device_solve(ctx);
   *fell_back = ctx->switched64;
   if (ctx->switched64) {
-    drop_graphs(ctx);
+    if (!ctx->no_alloc) drop_graphs(ctx);
     S.mixed = mixed;
   }
   return rc;
@@ -975,8 +1027,16 @@ int abd_create(abd_ctx** out, const abd_params* p) {
     return ABD_E_DEVICE;
   }
   static std::atomic<uint64_t> next_serial{1};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return ABD_E_DEVICE;
+  }
+  /* the static scratch of this device, for abd_local_solve_static */
+  if (scratch_init(dev)) return ABD_E_DEVICE;
   abd_ctx* c = new abd_ctx();
   c->serial = next_serial.fetch_add(1);
+  c->device = dev;
   c->P = *p;
   std::memset(&c->S, 0, sizeof(Scene));
   *out = c;
@@ -1507,6 +1567,91 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
       std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   if (out) *out = st;
   return status;
+}
+
+/* Maximum list sizes of the allocation-free solve: the static scratch
+ * holds every list of a solve at these capacities (about 61 MB of the
+ * 64 MiB array). */
+#define ABD_STATIC_BP (32 << 10)
+#define ABD_STATIC_CP (256 << 10)
+#define ABD_STATIC_PT (512 << 10)
+#define ABD_STATIC_EE (512 << 10)
+#define ABD_STATIC_PG (256 << 10)
+#define ABD_STATIC_ACT (256 << 10)
+
+int abd_local_solve_static(abd_ctx* ctx, abd_stats* out) {
+  int rc = check_ctx(ctx, true);
+  if (rc) return rc;
+  if (ctx->capturing) return fail(ctx, ABD_E_INVALID_ARG, "solve during capture");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != ctx->device)
+    return fail(ctx, ABD_E_INVALID_ARG, "the context's device is not current");
+  unsigned char* base = (unsigned char*)g_scratch[ctx->device].load();
+  if (!base) return fail(ctx, ABD_E_DEVICE, "static scratch not available");
+  Scene& S = ctx->S;
+  /* the lists of this solve, carved from the scratch at fixed capacities */
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    unsigned char* p = base + off;
+    off += (bytes + 255) & ~(size_t)255;
+    return (void*)p;
+  };
+  Scene L = S;
+  L.cap_bp = ABD_STATIC_BP;
+  L.cap_col = 2 * L.cap_bp;
+  L.cap_cp = ABD_STATIC_CP;
+  L.cap_pt = ABD_STATIC_PT;
+  L.cap_ee = ABD_STATIC_EE;
+  L.cap_pg = ABD_STATIC_PG;
+  L.cap_act = ABD_STATIC_ACT;
+  L.bp = (int2*)take(sizeof(int2) * (size_t)L.cap_bp);
+  L.Hoff = take(144 * sizeof(double) * (size_t)L.cap_bp);
+  L.slot_used = (int*)take(sizeof(int) * (size_t)L.cap_bp);
+  L.col_slot = (int*)take(sizeof(int) * (size_t)L.cap_col);
+  L.col_body = (int*)take(sizeof(int) * (size_t)L.cap_col);
+  L.col_trans = (int*)take(sizeof(int) * (size_t)L.cap_col);
+  L.cp = (int4*)take(sizeof(int4) * (size_t)L.cap_cp);
+  L.cand_pt = (int*)take(3 * sizeof(int) * (size_t)L.cap_pt);
+  L.cand_ee = (int*)take(3 * sizeof(int) * (size_t)L.cap_ee);
+  L.cand_pg = (int*)take(sizeof(int) * (size_t)L.cap_pg);
+  L.act = (int4*)take(sizeof(int4) * (size_t)L.cap_act);
+  if (off > ABD_SCRATCH_BYTES)
+    return fail(ctx, ABD_E_DEVICE, "static scratch layout exceeds the array");
+  /* swap the context's lists for the scratch ones for this call: direct
+   * launches (no graph replay, whose captured launches hold the context's
+   * own lists) and no stage timing (its events are created on demand) */
+  const Scene saved = S;
+  const int timing = ctx->timing, graphs = ctx->tune.use_graphs;
+  S = L;
+  ctx->no_alloc = true;
+  ctx->timing = ABD_TIMING_OFF;
+  ctx->tune.use_graphs = 0;
+  rc = abd_local_solve(ctx, out);
+  /* back to the context's own lists: only the list fields were swapped, so
+   * everything else of the scene (mixed flag, state pointers) is kept */
+  S.bp = saved.bp;
+  S.Hoff = saved.Hoff;
+  S.slot_used = saved.slot_used;
+  S.col_slot = saved.col_slot;
+  S.col_body = saved.col_body;
+  S.col_trans = saved.col_trans;
+  S.cp = saved.cp;
+  S.cand_pt = saved.cand_pt;
+  S.cand_ee = saved.cand_ee;
+  S.cand_pg = saved.cand_pg;
+  S.act = saved.act;
+  S.cap_bp = saved.cap_bp;
+  S.cap_col = saved.cap_col;
+  S.cap_cp = saved.cap_cp;
+  S.cap_pt = saved.cap_pt;
+  S.cap_ee = saved.cap_ee;
+  S.cap_pg = saved.cap_pg;
+  S.cap_act = saved.cap_act;
+  ctx->no_alloc = false;
+  ctx->timing = timing;
+  ctx->tune.use_graphs = graphs;
+  return rc;
 }
 
 int abd_end_step(abd_ctx* ctx) {
