@@ -57,8 +57,9 @@ struct Counters {
   int plan, n_dir, n_big, pad2_;
 };
 
-/* largest component (bodies) solved by a dense Cholesky factorisation */
-#define DIR_MAX 8
+/* largest component (bodies) solved directly (a dense elimination of up to
+ * 60 rows, one wavefront) */
+#define DIR_MAX 5
 /* scenes of at most this many bodies build their block rows (and label
  * the components of the system) in one workgroup */
 #define BSR_LDS_ROWS 12288

@@ -1300,8 +1300,8 @@ __global__ void k_bsr_scan(Scene S) {
  * cursors.  With comp_solve the same workgroup then labels the connected
  * components of the system (bodies joined by a used off-diagonal block)
  * and sorts them for the linear solve: a body alone is solved with its
- * block inverse, a component of 2..DIR_MAX bodies by a dense Cholesky
- * factorisation, a larger one by the PCG.  Labelling: every body starts as
+ * block inverse, a component of 2..DIR_MAX bodies by dense elimination,
+ * a larger one by the PCG.  Labelling: every body starts as
  * its own root; each round, every used block whose two bodies have
  * different roots links the larger root under the smaller (an LDS atomic
  * minimum, so links only ever point to smaller indices), then every body
@@ -1514,24 +1514,53 @@ __global__ __launch_bounds__(192) void k_block_inverse(Scene S) {
 
 /* Components of 2..DIR_MAX bodies, one wavefront each: the component's
  * system (its diagonal blocks and the used off-diagonal blocks between its
- * bodies, bodies in ascending order) is formed as a dense lower triangle in
- * LDS, factorised H = L L^T by right-looking Cholesky (FP64, from the
- * stored Hessian of either precision) and solved for dq = -H^-1 g by two
- * triangular substitutions: the exact solution of the component's system.
- * Lower triangle packed by rows: (i, j), j <= i, at i (i + 1) / 2 + j. */
+ * bodies, bodies in ascending order) is formed densely in LDS with -g as
+ * an extra column, then each lane takes one row into registers and the
+ * system is reduced by Gauss-Jordan elimination without pivoting (it is
+ * symmetric positive definite): step k takes row k, unchanged, as the
+ * pivot row (read lane by lane with readlane) and removes column k from
+ * every other row; at the end dq_i = rhs_i / a_ii.  The steps are unrolled
+ * for each size (12 rows per body), so every register index is static.
+ * FP64 from the stored Hessian of either precision; the exact solution of
+ * the component's system. */
 #define DIR_WAVES 2
 #define DIR_N (12 * DIR_MAX)
-__device__ __forceinline__ int pk(int i, int j) { return i * (i + 1) / 2 + j; }
+#define DIR_LD (DIR_N + 1)          /* row stride: n columns and the rhs */
+#define DIR_NE (DIR_MAX * (DIR_MAX - 1))
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane((unsigned)u, lane);
+  const unsigned hi = __builtin_amdgcn_readlane((unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+/* n rows in lanes 0..n-1 of the wavefront, row r of A (stride DIR_LD, rhs
+ * in column n); returns this lane's solution entry (lanes below n) */
+template <int n>
+__device__ __forceinline__ double gj_solve(const double* A, int lane) {
+  double row[n + 1];
+#pragma unroll
+  for (int c = 0; c <= n; ++c) row[c] = lane < n ? A[lane * DIR_LD + c] : 0.0;
+  double diag = 1.0;
+#pragma unroll
+  for (int k = 0; k < n; ++k) {
+    const double ip = 1.0 / readlane_d(row[k], k);
+    const double f = lane == k ? 0.0 : row[k] * ip;
+    if (lane == k) diag = row[k];
+#pragma unroll
+    for (int c = k + 1; c <= n; ++c) row[c] = __fma_rn(-f, readlane_d(row[c], k), row[c]);
+  }
+  return row[n] / diag;
+}
 template <typename HT>
 __global__ __launch_bounds__(64 * DIR_WAVES) void k_direct(Scene S) {
-  __shared__ double Ls[DIR_WAVES][DIR_N * (DIR_N + 1) / 2];
-  __shared__ double xs[DIR_WAVES][DIR_N];
+  __shared__ double As[DIR_WAVES][DIR_N * DIR_LD];
   __shared__ int bod[DIR_WAVES][DIR_MAX];
+  __shared__ int ent[DIR_WAVES][DIR_NE][3]; /* (i * DIR_MAX + j, slot, trans) */
+  __shared__ int nent[DIR_WAVES];
   if (!S.cnt->plan) return;
   const int ndir = S.cnt->n_dir;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  double* const L = Ls[wave];
-  double* const x = xs[wave];
+  double* const A = As[wave];
   int* const bw = bod[wave];
   for (int k = blockIdx.x * DIR_WAVES + wave; k < ndir; k += gridDim.x * DIR_WAVES) {
     const int m = S.dir_n[k];
@@ -1540,79 +1569,54 @@ __global__ __launch_bounds__(64 * DIR_WAVES) void k_direct(Scene S) {
     int rank = 0;
     for (int t = 0; t < m; ++t) rank += __shfl(mine, t, 64) < mine ? 1 : 0;
     if (lane < m) bw[rank] = mine;
+    if (lane == 0) nent[wave] = 0;
     wave_lds_sync();
-    if (S.iter_mode != 0 && S.ps[S.bprob[bw[0]]].state != PS_NEWTON) {
-      wave_lds_sync();
-      continue;
-    }
-    const int n = 12 * m, ntri = n * (n + 1) / 2;
-    for (int e = lane; e < ntri; e += 64) L[e] = 0.0;
-    wave_lds_sync();
-    for (int i = 0; i < m; ++i) {
-      const int b = bw[i];
-      const HT* Hd = (const HT*)S.Hdiag + 144 * (size_t)b;
-      for (int e = lane; e < 144; e += 64) {
-        const int r = e / 12, c = e % 12;
-        if (r >= c) L[pk(12 * i + r, 12 * i + c)] = (double)Hd[e];
-      }
-      /* blocks (i, j) with j < i from body i's block row */
-      for (int e = S.row_ptr[b]; e < S.row_ptr[b + 1]; ++e) {
+    /* the problem's state is read alongside the system; a problem outside
+     * this pass keeps its dq */
+    const bool run = S.iter_mode == 0 || S.ps[S.bprob[bw[0]]].state == PS_NEWTON;
+    const int n = 12 * m;
+    /* block-row entries (i, j > i) of the component, one lane per body */
+    if (lane < m) {
+      const int b = bw[lane];
+      for (int e = S.row_ptr[b], e1 = S.row_ptr[b + 1]; e < e1; ++e) {
         const int nb = S.col_body[e];
         int j = 0;
         while (j < m && bw[j] != nb) ++j;
-        if (j >= i) continue;
-        const HT* blk = (const HT*)S.Hoff + 144 * (size_t)S.col_slot[e];
-        const int tr = S.col_trans[e];
-        for (int t = lane; t < 144; t += 64) {
-          const int r = t / 12, c = t % 12;
-          L[pk(12 * i + r, 12 * j + c)] = (double)(tr ? blk[12 * c + r] : blk[12 * r + c]);
+        if (j <= lane || j >= m) continue;
+        const int q = atomicAdd(&nent[wave], 1);
+        if (q < DIR_NE) {
+          ent[wave][q][0] = lane * DIR_MAX + j;
+          ent[wave][q][1] = S.col_slot[e];
+          ent[wave][q][2] = S.col_trans[e];
         }
       }
-      for (int t = lane; t < 12; t += 64) x[12 * i + t] = -S.g[12 * b + t];
     }
+    for (int t = lane; t < n * DIR_LD; t += 64) A[t] = 0.0;
     wave_lds_sync();
-    /* H = L L^T, column by column */
-    for (int kk = 0; kk < n; ++kk) {
-      const double d = sqrt(L[pk(kk, kk)]);
-      const double id = 1.0 / d;
-      for (int i = kk + 1 + lane; i < n; i += 64) L[pk(i, kk)] *= id;
-      wave_lds_sync();
-      if (lane == 0) L[pk(kk, kk)] = d;
-      /* trailing lower triangle (i, j), kk < j <= i: element t of it is at
-       * row ii, column jj of the trailing block, advanced 64 at a time */
-      const int nt = n - kk - 1, tot = nt * (nt + 1) / 2;
-      int ii = 0, jj = lane;
-      while (jj > ii) {
-        jj -= ii + 1;
-        ++ii;
-      }
-      for (int t = lane; t < tot; t += 64) {
-        const int i = kk + 1 + ii, j = kk + 1 + jj;
-        L[pk(i, j)] -= L[pk(i, kk)] * L[pk(j, kk)];
-        jj += 64;
-        while (jj > ii) {
-          jj -= ii + 1;
-          ++ii;
-        }
-      }
-      wave_lds_sync();
+    const int ne = min(nent[wave], DIR_NE);
+    /* diagonal blocks, off-diagonal blocks (both triangles), -g */
+    for (int t = lane; t < 144 * m; t += 64) {
+      const int i = t / 144, e = t % 144, r = e / 12, c = e % 12;
+      A[(12 * i + r) * DIR_LD + 12 * i + c] =
+          (double)((const HT*)S.Hdiag)[144 * (size_t)bw[i] + e];
     }
-    /* L y = -g, then L^T dq = y */
-    for (int kk = 0; kk < n; ++kk) {
-      const double y = x[kk] / L[pk(kk, kk)];
-      wave_lds_sync();
-      if (lane == 0) x[kk] = y;
-      for (int i = kk + 1 + lane; i < n; i += 64) x[i] -= L[pk(i, kk)] * y;
-      wave_lds_sync();
+    for (int t = lane; t < 144 * ne; t += 64) {
+      const int q = t / 144, e = t % 144, r = e / 12, c = e % 12;
+      const int i = ent[wave][q][0] / DIR_MAX, j = ent[wave][q][0] % DIR_MAX;
+      const HT* blk = (const HT*)S.Hoff + 144 * (size_t)ent[wave][q][1];
+      /* block (i, j): rows of body i; stored rows belong to the lower id */
+      const double v = (double)(ent[wave][q][2] ? blk[12 * c + r] : blk[e]);
+      A[(12 * i + r) * DIR_LD + 12 * j + c] = v;
+      A[(12 * j + c) * DIR_LD + 12 * i + r] = v;
     }
-    for (int kk = n - 1; kk >= 0; --kk) {
-      const double v = x[kk] / L[pk(kk, kk)];
-      wave_lds_sync();
-      if (lane == 0) x[kk] = v;
-      for (int i = lane; i < kk; i += 64) x[i] -= L[pk(kk, i)] * v;
-      wave_lds_sync();
-    }
-    for (int t = lane; t < n; t += 64) S.dq[12 * bw[t / 12] + t % 12] = x[t];
+    for (int t = lane; t < n; t += 64) A[t * DIR_LD + n] = -S.g[12 * bw[t / 12] + t % 12];
+    wave_lds_sync();
+    double x = 0.0;
+    if (m == 2) x = gj_solve<24>(A, lane);
+    else if (m == 3) x = gj_solve<36>(A, lane);
+    else if (m == 4) x = gj_solve<48>(A, lane);
+    else x = gj_solve<60>(A, lane);
+    if (run && lane < n) S.dq[12 * bw[lane / 12] + lane % 12] = x;
     wave_lds_sync();
   }
 }

@@ -68,7 +68,7 @@ class Scene:
 def default_params(**over) -> Dict[str, float]:
     p = dict(dt=0.01, dhat=1e-3, kappa=1e5, kappa_A=1e8,
              gravity=(0.0, -9.8, 0.0), newton_theta=1e-6, pcg_eta=1e-4,
-             max_newton=300, max_pcg=2000, max_ls=40, has_ground=0,
+             max_newton=1000, max_pcg=2000, max_ls=40, has_ground=0,
              ground_y=0.0, mollify_ee=1, precision=0)
     p.update(over)
     return p
