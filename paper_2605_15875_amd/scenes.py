@@ -110,11 +110,13 @@ def _orient_outward(v: np.ndarray, tris: np.ndarray) -> np.ndarray:
     """Flip triangles of a star-shaped closed mesh so normals point away
     from the vertex centroid."""
     c = v.mean(axis=0)
+    a, b, d = v[tris[:, 0]], v[tris[:, 1]], v[tris[:, 2]]
+    n = np.cross(b - a, d - a)
+    m = (a + b + d) / 3.0 - c
+    flip = n[:, 0] * m[:, 0] + n[:, 1] * m[:, 1] + n[:, 2] * m[:, 2] < 0
     out = tris.copy()
-    for i, (a, b, d) in enumerate(tris):
-        n = np.cross(v[b] - v[a], v[d] - v[a])
-        if np.dot(n, (v[a] + v[b] + v[d]) / 3.0 - c) < 0:
-            out[i] = (a, d, b)
+    out[flip, 1] = tris[flip, 2]
+    out[flip, 2] = tris[flip, 1]
     return out
 
 
