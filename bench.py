@@ -11,9 +11,9 @@ untimed first, then K steps are timed.  value = Newton iterations per
 second over the timed steps, inputs resident on the device throughout.
 
 Also on the line:
-  roofline      the dominant kernel (the PCG launch), its launch duration
-                measured with HIP events on the library's stream inside the
-                timed region;
+  roofline      the dominant kernel (the barrier assembly, k_assemble), its
+                launch duration measured with HIP events on the library's
+                stream inside the timed region (every fourth pass);
   roofline_s5   the barrier stage (distance filter and assembly) against
                 both the HBM and the FP64 roofline, from extra steps with
                 every stage timed;
@@ -43,15 +43,17 @@ FP64_PEAK_TFS = 78.6
 # benchmark (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each divided
 # by what the same counter reads per byte for a plain device copy of known
 # size (python bench.py --copy-probe).  Valid only for the kernel source it
-# was measured on (sha256 of the PCG section of the kernel source);
+# was measured on (sha256 of the kernel's section of the kernel source);
 # otherwise traffic is null.
 PMC_TRAFFIC = {
-    "kernel": "k_pcg_cg1<double>",
-    "fetch_kib": 2473.1,       # FETCH_SIZE per dispatch, 90 dispatches
-    "write_kib": 5346.0,       # WRITE_SIZE per dispatch, 90 dispatches
-    "fetch_per_byte": 131086.5 / 262144.0,  # copy of 256 MiB reads 0.5
+    "kernel": "k_assemble<double>",
+    "section": ("/* S5 barrier: narrow phase filter and assembly",
+                "/* S7 block-Jacobi PCG"),
+    "fetch_kib": 534.9,        # FETCH_SIZE per dispatch, 91 dispatches
+    "write_kib": 322.5,        # WRITE_SIZE per dispatch, 91 dispatches
+    "fetch_per_byte": 131086.8 / 262144.0,  # copy of 256 MiB reads 0.5
     "write_per_byte": 262144.0 / 262144.0,  # copy of 256 MiB writes 1.0
-    "sha256": "6eaa85fabf0744a19da079fdfb0d3f500eee447519f4a32017c3fef0a441c2bb",
+    "sha256": "d55596f7f60f4056bc4efb87b041b418004bc119c98304d462fb6cb7f6074d86",
 }
 
 METRIC = ("local Newton iters/s at ~1M tris; mixed vs FP64 speedup at 1e-6 "
@@ -93,21 +95,22 @@ def copy_probe():
     print(json.dumps({"copy_probe_bytes": n, "copies": 3}), flush=True)
 
 
-def kernel_sha():
-    """sha256 of the PCG section of the kernel source (the block-Jacobi PCG
-    kernels and their helpers), which the traffic figures belong to."""
+def kernel_sha(section):
+    """sha256 of a section of the kernel source (between two banner
+    comments), which a kernel's traffic figures belong to."""
     import hashlib
     path = os.path.join(ROOT, "paper_2605_15875_amd", "csrc", "kernels.hip")
     with open(path, "r") as f:
         src = f.read()
-    a = src.index("/* S7 block-Jacobi PCG")
-    b = src.index("/* Single-reduction (pipelined) block-Jacobi PCG")
+    a = src.index(section[0])
+    b = src.index(section[1])
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
 def pmc_traffic(kernel):
     t = PMC_TRAFFIC
-    if not t or t["kernel"] != kernel or t["sha256"] != kernel_sha():
+    if (not t or t["kernel"] != kernel or t["sha256"] is None or
+            t["sha256"] != kernel_sha(t["section"])):
         return None
     return (t["fetch_kib"] * 1024.0 / t["fetch_per_byte"] +
             t["write_kib"] * 1024.0 / t["write_per_byte"])
@@ -291,10 +294,10 @@ def main():
         log(f"autotuned: {solver.autotune()}")
     tuning = solver.tuning()
     q_first, qd_first = solver.get_state()  # state at the first timed step
-    # timed region: the PCG launch of every fourth pass is bracketed by
-    # events, so the PCG kernel's launch duration is measured on a sample of
-    # the timed region's own launches
-    solver.set_timing(abd.TIMING_PCG)
+    # timed region: the assembly launch of every fourth pass (the dominant
+    # kernel) is bracketed by events, so its launch duration is measured on
+    # a sample of the timed region's own launches
+    solver.set_timing(abd.TIMING_ASM)
     solver.reset_timing()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -324,20 +327,23 @@ def main():
     solver.set_timing(abd.TIMING_OFF)
     if not any(v["launches"] for v in tm.values()):
         tm = tm_timed
-    pcg_kernel = {abd.PCG_LOCAL: "k_pcg_local", abd.PCG_TWO_BARRIER: "k_pcg",
-                  abd.PCG_PIPELINED: "k_pcg1",
-                  abd.PCG_LOCAL1: "k_pcg_cg1"}[tuning["pcg_variant"]] + "<double>"
     roof = None
-    d = tm_timed["pcg"]
+    d = tm_timed["assemble"]
     if d["bytes"] > 0 and d["launches"]:
+        # HBM-nominal (about 3 flops per algorithmic byte, below the FP64
+        # ridge of 9.8); its FP64 fraction rides along
         achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        tfs = d["flops"] / (d["ms"] * 1e-3) / 1e12
+        kname = "k_assemble<double>"
         roof = dict(bound="hbm", achieved=achieved, peak=HBM_PEAK_GBS,
                     unit="GB/s", frac=achieved / HBM_PEAK_GBS,
-                    traffic=pmc_traffic(pcg_kernel), kernel=pcg_kernel,
+                    traffic=pmc_traffic(kname), kernel=kname,
                     bytes_per_launch=d["bytes"] / d["launches"],
+                    flops_per_launch=d["flops"] / d["launches"],
+                    fp64_achieved_TFs=tfs, fp64_frac=tfs / FP64_PEAK_TFS,
                     launches=d["launches"],
                     avg_launch_ms=d["ms"] / d["launches"],
-                    measured="timed region")
+                    measured="timed region, every fourth pass")
     roof5 = None
     d5 = tm["barrier"]
     if d5["launches"] and d5["ms"] > 0:

@@ -444,8 +444,10 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
                      double* dE);
 
 /* Per-stage device timing with HIP events on the bound stream.  Stage ids:
- * 0 body terms, 1 broad phase, 2 barrier assembly, 3 PCG, 4 CCD,
- * 5 line search, 6 other.  abd_get_timing returns the summed milliseconds,
+ * 0 body terms, 1 broad phase, 2 barrier assembly (distance filter and
+ * assembly), 3 PCG, 4 CCD, 5 line search, 6 other (block rows, block
+ * inverses and the direct component solves), 7 the assembly kernel alone
+ * (ABD_TIMING_ASM).  abd_get_timing returns the summed milliseconds,
  * the number of timed launches and the algorithmic bytes those launches
  * had to move (sizes as launched).  Modes: ABD_TIMING_OFF (default);
  * ABD_TIMING_ALL times every stage, which replaces the captured graphs by
@@ -456,12 +458,16 @@ int abd_energy_delta(abd_ctx* ctx, const double* dq, double alpha,
 #define ABD_TIMING_OFF 0
 #define ABD_TIMING_ALL 1
 #define ABD_TIMING_PCG 2
+#define ABD_TIMING_ASM 3 /* as ABD_TIMING_PCG for the assembly kernel (stage 7,
+                            with its algorithmic bytes and flops); the
+                            sampled passes launch their kernels directly */
 int abd_set_timing(abd_ctx* ctx, int32_t on);
 int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms,
                    int64_t* launches, double* bytes);
 int abd_reset_timing(abd_ctx* ctx);
-/* Algorithmic FP64 flops of the timed launches of a stage (ABD_TIMING_ALL;
- * counted for the barrier stage 2 only, 0 for the others).  With the bytes
+/* Algorithmic FP64 flops of the timed launches of a stage (counted for the
+ * barrier stage 2 with ABD_TIMING_ALL and the assembly kernel, stage 7,
+ * with ABD_TIMING_ASM; 0 for the others).  With the bytes
  * of abd_get_timing this places stage 2 against both the HBM and the FP64
  * roofline.  Per pass: about 100 flops per candidate distance and 22,300
  * per active point-triangle or edge-edge pair (distance derivatives, 9x9

@@ -19,7 +19,8 @@ E_LINESEARCH, E_CAPACITY, E_DEVICE, E_OOM = -5, -6, -7, -8
 PT, EE, PG = 0, 1, 2
 DYNAMIC, STATIC = 0, 1
 PAIRS_ALL_ONE, PAIRS_BY_SHARED = 0, 1
-STAGES = ("body", "broad", "barrier", "pcg", "ccd", "linesearch", "other")
+STAGES = ("body", "broad", "barrier", "pcg", "ccd", "linesearch", "other",
+          "assemble")
 
 
 class Params(C.Structure):
@@ -107,7 +108,7 @@ EXPORTS = ["abd_create", "abd_destroy", "abd_last_error", "abd_add_body",
            "abd_get_timing_flops", "abd_local_solve_static"]
 
 
-TIMING_OFF, TIMING_ALL, TIMING_PCG = 0, 1, 2
+TIMING_OFF, TIMING_ALL, TIMING_PCG, TIMING_ASM = 0, 1, 2, 3
 
 
 def lib():

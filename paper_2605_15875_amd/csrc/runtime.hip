@@ -31,6 +31,11 @@
 
 using namespace abd;
 
+/* timing stages: 0 body terms, 1 broad phase, 2 barrier (filter and
+ * assembly), 3 PCG, 4 CCD, 5 line search, 6 other, 7 the assembly kernel
+ * alone (ABD_TIMING_ASM) */
+#define ABD_STAGES 8
+
 /* Static device scratch of the allocation-free solve
  * (abd_local_solve_static): the per-pass lists of a solve (body pairs with
  * their off-diagonal blocks and block-row columns, chunk pairs, candidate
@@ -132,8 +137,8 @@ struct abd_ctx {
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
-  double t_ms[7] = {0}, t_bytes[7] = {0}, t_flops[7] = {0};
-  int64_t t_n[7] = {0};
+  double t_ms[ABD_STAGES] = {0}, t_bytes[ABD_STAGES] = {0}, t_flops[ABD_STAGES] = {0};
+  int64_t t_n[ABD_STAGES] = {0};
   std::vector<Pending> pending;
   std::vector<hipEvent_t> ev_pool;
 };
@@ -276,7 +281,8 @@ struct StageTimer {
      * is not part of the captured graphs */
     active = !ctx->capturing &&
              (ctx->timing == ABD_TIMING_ALL ||
-              (ctx->timing == ABD_TIMING_PCG && stage == 3 && ctx->pcg_timed_now));
+              (ctx->timing == ABD_TIMING_PCG && stage == 3 && ctx->pcg_timed_now) ||
+              (ctx->timing == ABD_TIMING_ASM && stage == 7 && ctx->pcg_timed_now));
     if (active) {
       a = get_event(ctx);
       (void)hipEventRecord(a, stream);
@@ -570,6 +576,7 @@ void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
     StageTimer t(ctx, 2);
     launch_filter(S, ctx->st);
     if (ctx->tune.overlap_body) (void)hipStreamWaitEvent(ctx->st, ctx->ev_join, 0);
+    StageTimer ta(ctx, 7);
     launch_assemble(S, 0, ctx->st);
   }
 }
@@ -662,6 +669,23 @@ void account_s5(abd_ctx* ctx) {
                      act * (2 * 16.0 + 4 * 28.0 + 3 * 144.0 * hs * 2 + 2 * 96.0 * 2) +
                      nbp * (144.0 * hs + 4.0);
   ctx->t_flops[2] += cand * 100.0 + pg * 10.0 + act * 22300.0;
+}
+
+/* Algorithmic work of the assembly kernel alone (stage 7, ABD_TIMING_ASM)
+ * for one pass: per active pair its 16-byte entry and four vertices (rest
+ * position 24 B and body id 4 B each) read, three 12x12 blocks and two
+ * 12-gradients read and written (atomic additions), each counted once
+ * with no cache reuse; 22,300 flops per active pair (the distance
+ * derivatives and 9x9 projection of a PT/EE pair, about 20k, and the
+ * mapping to three body blocks, about 2.3k; ground pairs need far fewer,
+ * so scenes with a ground plane are overcounted). */
+void account_asm(abd_ctx* ctx) {
+  if (ctx->timing != ABD_TIMING_ASM) return;
+  const Scene& S = ctx->S;
+  const double hs = (double)hess_elem(ctx);
+  const double act = std::min(ctx->h_cnt[0].n_act, S.cap_act);
+  ctx->t_bytes[7] += act * (16.0 + 4 * 28.0 + 3 * 144.0 * hs * 2 + 2 * 96.0 * 2);
+  ctx->t_flops[7] += act * 22300.0;
 }
 
 /* swept phase on the stream: broad phase over [q, q + dq], CCD, and the
@@ -872,6 +896,14 @@ int run_pass(abd_ctx* ctx, bool take_over, bool timed) {
       ctx->whole_ok = false;
     }
   }
+  /* a pass whose assembly launch is timed runs its kernels directly */
+  if (timed && ctx->timing == ABD_TIMING_ASM) {
+    pass_pre(ctx, take_over);
+    int rc = pass_pcg(ctx);
+    if (rc) return rc;
+    pass_post(ctx);
+    return ABD_OK;
+  }
   if (graphs && ctx->graphs_ok && !timed && ctx->pass_graph[3] && ctx->pass_graph[4]) {
     HIPCHK(hipGraphLaunch(ctx->pass_graph[take_over ? 4 : 3], ctx->st));
     return ABD_OK;
@@ -917,7 +949,7 @@ int device_solve(abd_ctx* ctx) {
   auto enqueue = [&]() -> int {
     /* the sample runs over all passes of the context, so it does not
      * favour the first passes of a solve */
-    const bool timed = ctx->timing == ABD_TIMING_PCG &&
+    const bool timed = (ctx->timing == ABD_TIMING_PCG || ctx->timing == ABD_TIMING_ASM) &&
                        ctx->pass_seq++ % std::max(1, ctx->pcg_sample) == 0;
     ctx->pass_timed[queued & 1] = timed || ctx->timing == ABD_TIMING_ALL;
     int rc = run_pass(ctx, !full, timed); /* ends by writing its counters to the ring */
@@ -957,6 +989,7 @@ int device_solve(abd_ctx* ctx) {
     if (ctx->pass_timed[k & 1]) {
       account_pcg_bytes(ctx);
       account_s5(ctx);
+      account_asm(ctx);
     }
     if (ctx->S.mixed && ctx->h_cnt[0].want64 && ctx->h_cnt[1].active != 0) {
       /* a stalled mixed-precision problem: drain the queued pass and run
@@ -2548,7 +2581,8 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
 
 int abd_set_timing(abd_ctx* ctx, int32_t on) {
   if (!ctx) return ABD_E_INVALID_ARG;
-  if (on != ABD_TIMING_OFF && on != ABD_TIMING_ALL && on != ABD_TIMING_PCG)
+  if (on != ABD_TIMING_OFF && on != ABD_TIMING_ALL && on != ABD_TIMING_PCG &&
+      on != ABD_TIMING_ASM)
     return fail(ctx, ABD_E_INVALID_ARG, "timing mode");
   ctx->timing = on;
   return ABD_OK;
@@ -2556,7 +2590,7 @@ int abd_set_timing(abd_ctx* ctx, int32_t on) {
 
 int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
                    double* bytes) {
-  if (!ctx || stage < 0 || stage > 6) return ABD_E_INVALID_ARG;
+  if (!ctx || stage < 0 || stage >= ABD_STAGES) return ABD_E_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->st);
   resolve_timing(ctx);
   if (ms) *ms = ctx->t_ms[stage];
@@ -2566,7 +2600,7 @@ int abd_get_timing(abd_ctx* ctx, int32_t stage, double* ms, int64_t* launches,
 }
 
 int abd_get_timing_flops(abd_ctx* ctx, int32_t stage, double* flops) {
-  if (!ctx || stage < 0 || stage > 6 || !flops) return ABD_E_INVALID_ARG;
+  if (!ctx || stage < 0 || stage >= ABD_STAGES || !flops) return ABD_E_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->st);
   resolve_timing(ctx);
   *flops = ctx->t_flops[stage];
@@ -2577,7 +2611,7 @@ int abd_reset_timing(abd_ctx* ctx) {
   if (!ctx) return ABD_E_INVALID_ARG;
   (void)hipStreamSynchronize(ctx->st);
   resolve_timing(ctx);
-  for (int i = 0; i < 7; ++i)
+  for (int i = 0; i < ABD_STAGES; ++i)
     ctx->t_ms[i] = ctx->t_bytes[i] = ctx->t_flops[i] = 0.0, ctx->t_n[i] = 0;
   return ABD_OK;
 }

@@ -20,6 +20,7 @@ MODES = [
     ("every stage timed", dict(timing=abd.TIMING_ALL)),
     ("direct launches", dict(timing=abd.TIMING_OFF, use_graphs=0)),
     ("direct, sampled PCG timing", dict(timing=abd.TIMING_PCG, use_graphs=0)),
+    ("graphs, sampled assembly timing", dict(timing=abd.TIMING_ASM, use_graphs=1)),
 ]
 
 
@@ -58,6 +59,12 @@ def test_launch_paths_match_oracle(name, mode):
         assert 2 <= tm["pcg"]["launches"] < newton
         assert tm["pcg"]["ms"] > 0.0 and tm["pcg"]["bytes"] >= 0.0
         assert all(v["launches"] == 0 for s, v in tm.items() if s != "pcg")
+    elif mode["timing"] == abd.TIMING_ASM:
+        # a sample of the passes' assembly launches, with their work
+        assert 2 <= tm["assemble"]["launches"] < newton
+        assert tm["assemble"]["ms"] > 0.0
+        assert tm["assemble"]["bytes"] > 0.0 and tm["assemble"]["flops"] > 0.0
+        assert all(v["launches"] == 0 for s, v in tm.items() if s != "assemble")
     else:
         assert tm["pcg"]["launches"] >= newton
         assert tm["broad"]["launches"] > 0 and tm["barrier"]["launches"] > 0
