@@ -238,6 +238,79 @@ def bench_batch(abd, scenes, torch, n_scenes, steps, warmup):
                 speedup=(it_b / t_b) / (it_s / t_s))
 
 
+def bench_batch_workload(abd, scenes, torch, steps, log):
+    """The batch workload: 8 ADMM subdomains of 200-3000 bodies (icospheres
+    and hulls, each with its shared bodies and consensus data) and 64 cube
+    scenes of 16-512 cubes, 6.8M triangles, solved together in the same
+    launches (FP64 and mixed precision) against one context after another
+    (FP64); the first `steps` time steps from the initial state.  Newton
+    iterations are summed over the problems; a problem that ends a step
+    without converging is counted, not dropped."""
+    scs = scenes.batch_workload(0)
+
+    def contexts(prec):
+        out = [abd.Solver(sc, precision=prec) for sc in scs]
+        for s in out:
+            s.set_pair_replication(abd.PAIRS_BY_SHARED)
+        return out
+
+    def begin(ctxs):
+        for sc, g in zip(scs, ctxs):
+            g.begin_step()
+            if sc.shared_ids is not None:
+                z = g.qtilde()[sc.shared_ids] + sc.shared_delta
+                g.set_shared(sc.shared_ids, z, sc.shared_u, sc.shared_rho,
+                             sc.shared_kappa)
+
+    def run(ctxs, solve):
+        it, t, bad, per = 0, 0.0, 0, []
+        for _ in range(steps):
+            begin(ctxs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = solve()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            for g in ctxs:
+                g.end_step()
+            n = sum(x["newton_iters"] for x in st)
+            it += n
+            t += dt
+            bad += sum(1 for x in st if x["status"] != 0)
+            per.append((round(dt * 1e3, 1), n))
+        return dict(newton_iters_per_s=it / t, newton_iters=it,
+                    ms_per_step=t * 1e3 / steps, unconverged_problem_steps=bad,
+                    per_step_ms_and_iters=per)
+
+    res = {}
+    for name, prec in (("batched_fp64", 0), ("batched_mixed", 1)):
+        ctxs = contexts(prec)
+        bt = abd.Batch(ctxs)
+        res[name] = run(ctxs, lambda: bt.local_solve(check=False))
+        log(f"batch workload {name}: {res[name]}")
+        bt.close()
+        for g in ctxs:
+            g.close()
+    ctxs = contexts(0)
+    res["sequential_fp64"] = run(
+        ctxs, lambda: [g.local_solve(check=False) for g in ctxs])
+    log(f"batch workload sequential_fp64: {res['sequential_fp64']}")
+    for g in ctxs:
+        g.close()
+    res.update(
+        workload=f"{len(scs)} problems: 8 ADMM subdomains of "
+                 f"{min(scenes.BATCH_SUBDOMAINS)}-{max(scenes.BATCH_SUBDOMAINS)} "
+                 f"bodies (icospheres and hulls) and 64 cube scenes of "
+                 f"{min(scenes.BATCH_CUBES)}-{max(scenes.BATCH_CUBES)} cubes",
+        bodies=sum(sc.n_dynamic for sc in scs),
+        triangles=sum(sc.n_triangles for sc in scs), steps=steps,
+        speedup_fp64=res["batched_fp64"]["newton_iters_per_s"]
+        / res["sequential_fp64"]["newton_iters_per_s"],
+        mixed_vs_fp64_wall=res["batched_fp64"]["ms_per_step"]
+        / res["batched_mixed"]["ms_per_step"])
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +327,8 @@ def main():
     ap.add_argument("--breakdown-steps", type=int, default=3)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-batch-workload", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--pcg-variant", type=int, default=None)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner after warmup")
@@ -401,6 +476,9 @@ def main():
     if not a.no_batch:
         batch = bench_batch(abd, scenes, torch, a.batch_scenes, 5, 1)
         log(f"batch: {batch}")
+    batch_wl = None
+    if not a.no_batch_workload:
+        batch_wl = bench_batch_workload(abd, scenes, torch, a.batch_steps, log)
     out = {
         "metric": METRIC,
         "value": newton / elapsed,
@@ -431,6 +509,7 @@ def main():
         "run50": run50,
         "vs_oracle": vs_oracle,
         "batch": batch,
+        "batch_workload": batch_wl,
     }
     print(json.dumps(out), flush=True)
 

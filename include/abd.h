@@ -275,7 +275,28 @@ typedef struct abd_tuning {
                               at once; its waits are bounded and end in
                               DEVICE should the blocks not be resident
                               together (another process filling the GPU) */
+  int32_t body_pairs;      /* body-pair broad phase, the same pairs either
+                              way: ABD_BODY_PAIRS_AUTO (default: every pair
+                              of each problem while those number at most
+                              2^21, else sort and sweep), ABD_BODY_PAIRS_ALL
+                              (INVALID_ARG beyond 2^27 pairs) or
+                              ABD_BODY_PAIRS_SWEEP */
+  int32_t pcg_launch_groups; /* problem-local PCG forms: at most this many
+                              16-body groups per launch (0: as many as the
+                              device holds resident at once); problems that
+                              share no group may run in separate launches
+                              one after another; a problem needing more
+                              groups runs the two-barrier form */
+  int32_t label_rows;      /* component labelling: at most this many bodies
+                              per workgroup of whole problems (0: 12288,
+                              also the largest value used); a scene of at
+                              most this many bodies builds its block rows
+                              and labels in one workgroup; a problem of
+                              more bodies leaves every component to the PCG */
 } abd_tuning;
+#define ABD_BODY_PAIRS_AUTO 0
+#define ABD_BODY_PAIRS_ALL 1
+#define ABD_BODY_PAIRS_SWEEP 2
 
 /* Read or replace the launch settings of a finalized context.  Settings
  * change launch shapes and the PCG recurrence, not the system solved:

@@ -39,13 +39,15 @@ class Tuning(C.Structure):
     _fields_ = [("pcg_variant", C.c_int32), ("pcg_blocks", C.c_int32),
                 ("grid_blocks", C.c_int32), ("assemble_blocks", C.c_int32),
                 ("use_graphs", C.c_int32), ("overlap_body", C.c_int32),
-                ("pcg_coop", C.c_int32)]
+                ("pcg_coop", C.c_int32), ("body_pairs", C.c_int32),
+                ("pcg_launch_groups", C.c_int32), ("label_rows", C.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 PCG_TWO_BARRIER, PCG_PIPELINED, PCG_LOCAL, PCG_LOCAL1 = 0, 1, 2, 3
+BODY_PAIRS_AUTO, BODY_PAIRS_ALL, BODY_PAIRS_SWEEP = 0, 1, 2
 
 
 class AdmmParams(C.Structure):

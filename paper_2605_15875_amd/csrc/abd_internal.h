@@ -101,6 +101,17 @@ struct ProbState {
  * Newton iterations (Scene) */
 #define MIXED_STALL_ITERS 16
 
+/* the bucket map of one problem's sweep: bucket(x) = floor((x - lo) *
+ * scale) clamped to [0, nb - 1], a monotone function of x */
+struct SapAxis {
+  double lo, scale;
+  int axis, nb;
+};
+#define SAP_MAX_BUCKETS 8192
+/* sort and sweep once every pair of each problem would exceed this many
+ * box tests */
+#define SAP_ALL_PAIRS_MAX (1L << 21)
+
 struct Scene {
   int B, V, T, E, NC;
   /* parameters */
@@ -122,6 +133,23 @@ struct Scene {
   double *ch_rest;  /* [NC][6] */
   double *ch_box;   /* [NC][6] world box lo(3) hi(3) of the current phase */
   double *body_box; /* [B][6] */
+  /* body pairs by sort and sweep (per problem): the dynamic bodies of
+   * each problem, sap_dyn [D] from sap_doff [NP + 1], and its static
+   * bodies, sap_stat from sap_soff [NP + 1] (fixed); per pass, the dynamic
+   * bodies bucketed by the lower bound of their box (sap_sorted [D]), each
+   * problem's bucket starts (sap_bstart, from sap_boff [NP + 1], one entry
+   * past its last bucket), its bucket map (sap_par [NP]) and the boxes in
+   * sorted order */
+  int *sap_dyn, *sap_doff, *sap_stat, *sap_soff;
+  int *sap_sorted, *sap_bstart, *sap_boff;
+  double *sap_sbox; /* [D][6] the boxes in sorted order */
+  SapAxis *sap_par;
+  int n_dyn;
+  /* sap_on = 0: every pair of each problem instead, by the 16 x 16 body
+   * tiles bp_tiles [n_bp_tiles] (tiles on or above each problem's
+   * diagonal) */
+  int sap_on, n_bp_tiles;
+  int2 *bp_tiles;
   /* broad phase outputs */
   int2 *bp;     /* body pairs (a < b) */
   int4 *cp;     /* chunk pairs (kind, chunk P, chunk Q, body-pair slot) */
@@ -145,6 +173,12 @@ struct Scene {
    * scene's block-row build (the PCG form in use masks the rest) */
   int *bmode, *dir_body, *dir_n;
   int comp_solve;
+  /* bsr_one: block rows and component labels in one workgroup (scenes of
+   * at most BSR_LDS_ROWS bodies); else the block rows by three kernels and
+   * the labels per chunk of whole problems, bodies [lab_chunk[c],
+   * lab_chunk[c + 1]) of n_lab_chunks (0: no labels) */
+  int *lab_chunk;
+  int n_lab_chunks, bsr_one;
   /* PCG work */
   double *r, *zv, *p0, *p1, *Ap, *acc; /* acc: [4][4] ring of dots */
   double *pw; /* single-reduction PCG: [5][12B] w, m0, m1, t0, t1 */
@@ -754,7 +788,7 @@ void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st);
 void launch_bsr(const Scene& S, hipStream_t st);
 void launch_block_inverse(const Scene& S, hipStream_t st);
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
-               hipStream_t st);
+               int goff, hipStream_t st);
 int pcg_max_grid();
 void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st);
 void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st);

@@ -5,10 +5,13 @@
  *   body terms (inertia, orthogonality,  k_body_terms
  *   ADMM penalty of Eq. 5)
  *   broad phase                          k_positions (positions, chunk and
- *                                        body boxes), k_body_pairs,
+ *                                        body boxes), k_sap_sort and
+ *                                        k_sap_sweep (body pairs),
  *                                        k_chunk_pairs, k_prim_pairs, k_pg
  *   barrier (narrow phase + assembly)    k_filter, k_assemble
- *   block-Jacobi PCG                     k_bsr_*, k_block_inverse, k_pcg_cg1
+ *   linear solve by components           k_bsr_* (block rows, component
+ *                                        labels), k_block_inverse, k_direct,
+ *                                        block-Jacobi PCG k_pcg_cg1
  *                                        (k_pcg_local, k_pcg, k_pcg1)
  *   Newton stop                          k_positions (swept, stop-test
  *                                        workgroups), k_dq_norm
@@ -306,11 +309,15 @@ __device__ __forceinline__ int wave_slot(bool pred, int* counter) {
   return pred ? base + __popcll(m & ((1ull << lane) - 1ull)) : -1;
 }
 
-/* body pairs (a < b, not both static) whose boxes pass the predicate */
+/* ---- body pairs (a < b, not both static) whose boxes pass the predicate ----
+ * Scenes whose problems hold few bodies test every pair of each problem:
+ * one workgroup per 16 x 16 tile of a problem's body range (tiles on or
+ * above the diagonal, from a fixed list). */
 __global__ void k_body_pairs(Scene S) {
-  if ((int)(blockIdx.x * 16 + 15) <= (int)(blockIdx.y * 16) || S.cnt->reuse) return;
-  const int a = blockIdx.y * 16 + threadIdx.y;
-  const int b = blockIdx.x * 16 + threadIdx.x;
+  if (S.cnt->reuse) return;
+  const int2 tl = S.bp_tiles[blockIdx.x];
+  const int a = tl.x * 16 + threadIdx.y;
+  const int b = tl.y * 16 + threadIdx.x;
   bool ok = a < S.B && b < S.B && a < b;
   ok = ok && !(S.kind[a] != 0 && S.kind[b] != 0);
   ok = ok && S.bprob[a] == S.bprob[b]; /* independent problems */
@@ -318,6 +325,177 @@ __global__ void k_body_pairs(Scene S) {
   ok = ok && box_overlap(S.body_box + 6 * a, S.body_box + 6 * b, S.dhat);
   const int k = wave_slot(ok, &S.cnt->n_bp);
   if (ok && k < S.cap_bp) S.bp[k] = make_int2(a, b);
+}
+
+/* Larger problems: sort and sweep per problem.
+ * The dynamic bodies of a problem are bucketed by the lower bound of their
+ * box along the axis on which these lower bounds spread the most (one
+ * bucket per body, at most SAP_MAX_BUCKETS): a counting sort in one
+ * workgroup per problem.  Each dynamic body then tests the bodies whose
+ * bucket lies between the buckets of its own lower bound and of its upper
+ * bound plus d-hat (one contiguous run of the sorted array), keeping those
+ * after it in (lower bound, index) order, and every static body of its
+ * problem.  Any overlapping pair of dynamic bodies lies in the run of the
+ * one first in that order (the bucket map is monotone), so each pair is
+ * found exactly once, with the box predicate of every other stage. */
+__device__ __forceinline__ int wave_prefix(int n, int* total);
+__device__ __forceinline__ int sap_bucket(const SapAxis& a, double x) {
+  /* explicit roundings: both kernels evaluate the same monotone map */
+  const double t = __dmul_rn(__dsub_rn(x, a.lo), a.scale);
+  if (!(t >= 1.0)) return 0; /* also NaN */
+  if (!(t < (double)a.nb)) return a.nb - 1;
+  return (int)t;
+}
+
+__global__ __launch_bounds__(1024) void k_sap_sort(Scene S) {
+  __shared__ int cnt[SAP_MAX_BUCKETS + 1];
+  __shared__ double red[16][6];
+  __shared__ int wsum[16];
+  __shared__ SapAxis s_ax;
+  if (S.cnt->reuse) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  for (int p = blockIdx.x; p < S.NP; p += gridDim.x) {
+    const int d0 = S.sap_doff[p], nd = S.sap_doff[p + 1] - d0;
+    if (nd == 0 || !body_in_pass(S, S.sap_dyn[d0])) continue;
+    /* range of the lower bounds on each axis */
+    double v[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      const double* bx = S.body_box + 6 * S.sap_dyn[d0 + i];
+      for (int k = 0; k < 3; ++k) {
+        v[k] = fmin(v[k], bx[k]);
+        v[3 + k] = fmax(v[3 + k], bx[k]);
+      }
+    }
+    for (int o = 32; o > 0; o >>= 1)
+      for (int k = 0; k < 3; ++k) {
+        v[k] = fmin(v[k], __shfl_xor(v[k], o, 64));
+        v[3 + k] = fmax(v[3 + k], __shfl_xor(v[3 + k], o, 64));
+      }
+    if (lane == 0)
+      for (int k = 0; k < 6; ++k) red[wave][k] = v[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int w = 1; w < nw; ++w)
+        for (int k = 0; k < 3; ++k) {
+          v[k] = fmin(v[k], red[w][k]);
+          v[3 + k] = fmax(v[3 + k], red[w][3 + k]);
+        }
+      int ax = 0;
+      for (int k = 1; k < 3; ++k)
+        if (v[3 + k] - v[k] > v[3 + ax] - v[ax]) ax = k;
+      SapAxis a;
+      a.axis = ax;
+      a.lo = v[ax];
+      a.nb = S.sap_boff[p + 1] - S.sap_boff[p] - 1;
+      const double w = v[3 + ax] - v[ax];
+      double sc = w > 0.0 ? (double)a.nb / w : 0.0;
+      if (!(sc < 1e300)) sc = 0.0;
+      a.scale = sc;
+      s_ax = a;
+      S.sap_par[p] = a;
+    }
+    __syncthreads();
+    const SapAxis a = s_ax;
+    for (int k = threadIdx.x; k <= a.nb; k += blockDim.x) cnt[k] = 0;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      const double* bx = S.body_box + 6 * S.sap_dyn[d0 + i];
+      atomicAdd(&cnt[sap_bucket(a, bx[a.axis])], 1);
+    }
+    __syncthreads();
+    /* exclusive scan of the counts: a run of buckets per thread */
+    const int per = (a.nb + blockDim.x - 1) / blockDim.x;
+    const int lo = threadIdx.x * per, hi = min(a.nb, lo + per);
+    int sum = 0;
+    for (int k = lo; k < hi; ++k) sum += cnt[k];
+    int tot;
+    const int ex = wave_prefix(sum, &tot);
+    if (lane == 0) wsum[wave] = tot;
+    __syncthreads();
+    int acc = ex;
+    for (int w = 0; w < wave; ++w) acc += wsum[w];
+    const int bo = S.sap_boff[p];
+    for (int k = lo; k < hi; ++k) {
+      const int c = cnt[k];
+      cnt[k] = acc;
+      S.sap_bstart[bo + k] = d0 + acc;
+      acc += c;
+    }
+    if (threadIdx.x == 0) S.sap_bstart[bo + a.nb] = d0 + nd;
+    __syncthreads();
+    for (int i = threadIdx.x; i < nd; i += blockDim.x) {
+      const int b = S.sap_dyn[d0 + i];
+      const double* bx = S.body_box + 6 * b;
+      const int pos = d0 + atomicAdd(&cnt[sap_bucket(a, bx[a.axis])], 1);
+      S.sap_sorted[pos] = b;
+      for (int k = 0; k < 6; ++k) S.sap_sbox[6L * pos + k] = bx[k];
+    }
+    __syncthreads(); /* cnt, red and s_ax serve the next problem */
+  }
+}
+
+/* SAP_PER_WAVE sorted dynamic bodies per wavefront, in its first lanes;
+ * all 64 lanes share out the tests of their runs, 64 at a time (a long
+ * run, such as that of a body spanning the scene, is spread over the
+ * lanes).  The boxes are read in sorted order (sap_sbox). */
+#define SAP_PER_WAVE 4 /* a power of two, at most 64 */
+__global__ __launch_bounds__(256) void k_sap_sweep(Scene S) {
+  if (S.cnt->reuse) return;
+  const int D = S.n_dyn;
+  const int lane = __lane_id();
+  const int waves = gridDim.x * (blockDim.x >> 6);
+  for (int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+       w * SAP_PER_WAVE < D; w += waves) {
+    const int t = w * SAP_PER_WAVE + lane;
+    int a = 0, start = 0, ndyn = 0, nst = 0, s0 = 0, axis = 0;
+    if (lane < SAP_PER_WAVE && t < D) {
+      a = S.sap_sorted[t];
+      if (body_in_pass(S, a)) {
+        const int p = S.bprob[a];
+        const SapAxis ax = S.sap_par[p];
+        const double* ba = S.sap_sbox + 6L * t;
+        const int k0 = sap_bucket(ax, ba[ax.axis]);
+        const int k1 = sap_bucket(ax, __dadd_rn(ba[3 + ax.axis], S.dhat));
+        const int bo = S.sap_boff[p];
+        start = S.sap_bstart[bo + k0];
+        ndyn = S.sap_bstart[bo + k1 + 1] - start;
+        s0 = S.sap_soff[p];
+        nst = S.sap_soff[p + 1] - s0;
+        axis = ax.axis;
+      }
+    }
+    int total;
+    const int excl = wave_prefix(ndyn + nst, &total);
+    for (int f0 = 0; f0 < total; f0 += 64) {
+      const int f = f0 + lane;
+      /* the lane whose share holds test f: the last with excl <= f */
+      int o = 0;
+      for (int st = SAP_PER_WAVE / 2; st > 0; st >>= 1)
+        if (__shfl(excl, o + st, 64) <= f) o += st;
+      const int u = f - __shfl(excl, o, 64);
+      const int ao = __shfl(a, o, 64), so = __shfl(start, o, 64);
+      const int ndo = __shfl(ndyn, o, 64), sso = __shfl(s0, o, 64);
+      const int axo = __shfl(axis, o, 64), to = w * SAP_PER_WAVE + o;
+      bool ok = false;
+      int bj = 0;
+      if (f < total) {
+        const double* pa = S.sap_sbox + 6L * to;
+        if (u < ndo) {
+          bj = S.sap_sorted[so + u];
+          const double* pb = S.sap_sbox + 6L * (so + u);
+          const double xa = pa[axo], xb = pb[axo];
+          ok = bj != ao && (xb > xa || (xb == xa && bj > ao)) &&
+               box_overlap(pa, pb, S.dhat);
+        } else {
+          bj = S.sap_stat[sso + u - ndo];
+          ok = box_overlap(pa, S.body_box + 6 * bj, S.dhat);
+        }
+      }
+      const int k = wave_slot(ok, &S.cnt->n_bp);
+      if (ok && k < S.cap_bp) S.bp[k] = make_int2(min(ao, bj), max(ao, bj));
+    }
+  }
 }
 
 /* chunk pairs of every body pair: vertex chunks x triangle chunks (both
@@ -1266,6 +1444,12 @@ __global__ void k_bsr_scan(Scene S) {
   const int per = (n + blockDim.x - 1) / blockDim.x;
   const int lo = threadIdx.x * per, hi = min(n, lo + per);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) {
+    /* the component labels that follow add their counts */
+    S.cnt->n_dir = 0;
+    S.cnt->n_big = 0;
+    S.cnt->plan = 0;
+  }
   int s = 0;
   for (int i = lo; i < hi; ++i) s += S.row_cnt[i];
   int x = s;
@@ -1295,23 +1479,123 @@ __global__ void k_bsr_scan(Scene S) {
     S.row_cnt[i] = 0; /* reused as fill cursor */
   }
 }
+/* Connected components of the system among the bodies [c0, c0 + n) (whole
+ * problems: no used block joins them to other bodies), in one workgroup
+ * with LDS arrays par [n], cnt [n + 1], cur [n / 2 + 1] and sh [4]: every
+ * body starts as its own root; each round, every used block whose two
+ * bodies have different roots links the larger root under the smaller (an
+ * LDS atomic minimum, so links only ever point to smaller indices), then
+ * every body takes its root; rounds repeat until a round links nothing.
+ * Then bmode of each body (0 alone, 1 in a component of 2..DIR_MAX bodies,
+ * 2 larger) and a slot per directly solved component with its bodies in
+ * ascending order.  single: these are all bodies of the scene (the counts
+ * are stored), else the slots and counts are added to the scene's. */
+__device__ void label_components(const Scene& S, int c0, int n, int nbp, int* par,
+                                 int* cnt, int* cur, int* sh, bool single) {
+  int& s_changed = sh[0];
+  int& s_ndir = sh[1];
+  int& s_nbig = sh[2];
+  int& s_base = sh[3];
+  volatile int* vp = par;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) par[i] = i;
+  __syncthreads();
+  bool settled = false;
+  for (int round = 0; round < 64 && !settled; ++round) {
+    if (threadIdx.x == 0) s_changed = 0;
+    __syncthreads();
+    for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
+      if (!S.slot_used[p]) continue;
+      const int2 ab = S.bp[p];
+      if (ab.x < c0 || ab.x >= c0 + n) continue;
+      int ra = ab.x - c0, rb = ab.y - c0;
+      while (vp[ra] != ra) ra = vp[ra];
+      while (vp[rb] != rb) rb = vp[rb];
+      if (ra != rb) {
+        atomicMin(&par[max(ra, rb)], min(ra, rb));
+        s_changed = 1;
+      }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      int r = vp[i];
+      while (vp[r] != r) r = vp[r];
+      vp[i] = r;
+    }
+    __syncthreads();
+    settled = s_changed == 0;
+    __syncthreads(); /* every thread has read the flag before its reset */
+  }
+  if (!settled) {
+    /* a graph that did not settle in the bounded rounds stays with the
+     * PCG: in one workgroup for the whole scene, no plan; else its bodies
+     * as one large component */
+    if (single) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) S.bmode[c0 + i] = 2;
+    if (threadIdx.x == 0) {
+      atomicAdd(&S.cnt->n_big, n);
+      S.cnt->plan = 1;
+    }
+    return;
+  }
+  /* component sizes (the fill cursors are free again) */
+  for (int i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
+  if (threadIdx.x == 0) s_ndir = s_nbig = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[par[i]], 1);
+  __syncthreads();
+  int nbig = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int c = cnt[par[i]];
+    const int mode = c == 1 ? 0 : (c <= DIR_MAX ? 1 : 2);
+    S.bmode[c0 + i] = mode;
+    nbig += mode == 2;
+  }
+  if (nbig) atomicAdd(&s_nbig, nbig);
+  __syncthreads();
+  /* a slot per directly solved component, kept (negated) at its root */
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    if (par[i] == i && cnt[i] >= 2 && cnt[i] <= DIR_MAX) {
+      const int k = atomicAdd(&s_ndir, 1);
+      cur[k] = 0;
+      cnt[i] = -1 - k;
+    }
+  __syncthreads();
+  if (threadIdx.x == 0) s_base = single ? 0 : atomicAdd(&S.cnt->n_dir, s_ndir);
+  __syncthreads();
+  const int base = s_base;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int c = cnt[par[i]];
+    if (c < 0) {
+      const int k = -1 - c;
+      S.dir_body[(base + k) * DIR_MAX + atomicAdd(&cur[k], 1)] = c0 + i;
+    }
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < s_ndir; k += blockDim.x) S.dir_n[base + k] = cur[k];
+  if (threadIdx.x == 0) {
+    if (single) {
+      S.cnt->n_dir = s_ndir;
+      S.cnt->n_big = s_nbig;
+    } else if (s_nbig) {
+      atomicAdd(&S.cnt->n_big, s_nbig);
+    }
+    S.cnt->plan = 1;
+  }
+}
+
 /* the three steps in one workgroup when the block-row counts fit in LDS:
  * counts by LDS atomics, the same scan, then the counts become the fill
  * cursors.  With comp_solve the same workgroup then labels the connected
  * components of the system (bodies joined by a used off-diagonal block)
  * and sorts them for the linear solve: a body alone is solved with its
  * block inverse, a component of 2..DIR_MAX bodies by dense elimination,
- * a larger one by the PCG.  Labelling: every body starts as
- * its own root; each round, every used block whose two bodies have
- * different roots links the larger root under the smaller (an LDS atomic
- * minimum, so links only ever point to smaller indices), then every body
- * takes its root; rounds repeat until a round links nothing. */
+ * a larger one by the PCG. */
 #define DIR_SLOTS (BSR_LDS_ROWS / 2 + 1)
 __global__ __launch_bounds__(1024) void k_bsr_small(Scene S) {
   __shared__ int cnt[BSR_LDS_ROWS + 1];
   __shared__ int par[BSR_LDS_ROWS];
   __shared__ int cur[DIR_SLOTS];
-  __shared__ int s_changed, s_ndir, s_nbig;
+  __shared__ int sh[4];
   __shared__ int wsum[16];
   const int n = S.B;
   for (int i = threadIdx.x; i <= n; i += blockDim.x) cnt[i] = 0;
@@ -1370,73 +1654,7 @@ __global__ __launch_bounds__(1024) void k_bsr_small(Scene S) {
     }
   }
   if (!S.comp_solve) return;
-  /* ---- connected components ---- */
-  volatile int* vp = par;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) par[i] = i;
-  __syncthreads();
-  bool settled = false;
-  for (int round = 0; round < 64 && !settled; ++round) {
-    if (threadIdx.x == 0) s_changed = 0;
-    __syncthreads();
-    for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
-      if (!S.slot_used[p]) continue;
-      const int2 ab = S.bp[p];
-      int ra = ab.x, rb = ab.y;
-      while (vp[ra] != ra) ra = vp[ra];
-      while (vp[rb] != rb) rb = vp[rb];
-      if (ra != rb) {
-        atomicMin(&par[max(ra, rb)], min(ra, rb));
-        s_changed = 1;
-      }
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      int r = vp[i];
-      while (vp[r] != r) r = vp[r];
-      vp[i] = r;
-    }
-    __syncthreads();
-    settled = s_changed == 0;
-  }
-  /* a graph that did not settle in the bounded rounds stays with the PCG */
-  if (!settled) return;
-  /* component sizes (the fill cursors are free again) */
-  for (int i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
-  if (threadIdx.x == 0) s_ndir = s_nbig = 0;
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) atomicAdd(&cnt[par[i]], 1);
-  __syncthreads();
-  int nbig = 0;
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int c = cnt[par[i]];
-    const int mode = c == 1 ? 0 : (c <= DIR_MAX ? 1 : 2);
-    S.bmode[i] = mode;
-    nbig += mode == 2;
-  }
-  if (nbig) atomicAdd(&s_nbig, nbig);
-  __syncthreads();
-  /* a slot per directly solved component, kept (negated) at its root */
-  for (int i = threadIdx.x; i < n; i += blockDim.x)
-    if (par[i] == i && cnt[i] >= 2 && cnt[i] <= DIR_MAX) {
-      const int k = atomicAdd(&s_ndir, 1);
-      cur[k] = 0;
-      cnt[i] = -1 - k;
-    }
-  __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int c = cnt[par[i]];
-    if (c < 0) {
-      const int k = -1 - c;
-      S.dir_body[k * DIR_MAX + atomicAdd(&cur[k], 1)] = i;
-    }
-  }
-  __syncthreads();
-  for (int k = threadIdx.x; k < s_ndir; k += blockDim.x) S.dir_n[k] = cur[k];
-  if (threadIdx.x == 0) {
-    S.cnt->n_dir = s_ndir;
-    S.cnt->n_big = s_nbig;
-    S.cnt->plan = 1;
-  }
+  label_components(S, 0, n, nbp, par, cnt, cur, sh, true);
 }
 __global__ void k_bsr_fill(Scene S) {
   int nbp = min(S.cnt->n_bp, S.cap_bp);
@@ -1453,6 +1671,20 @@ __global__ void k_bsr_fill(Scene S) {
       S.col_slot[k] = p; S.col_body[k] = ab.x; S.col_trans[k] = 1;
     }
   }
+}
+
+/* component labels of scenes whose block rows are built by the three
+ * kernels: one workgroup per chunk of whole problems (at most BSR_LDS_ROWS
+ * bodies, lab_chunk) */
+__global__ __launch_bounds__(1024) void k_components(Scene S) {
+  __shared__ int cnt[BSR_LDS_ROWS + 1];
+  __shared__ int par[BSR_LDS_ROWS];
+  __shared__ int cur[DIR_SLOTS];
+  __shared__ int sh[4];
+  const int c0 = S.lab_chunk[blockIdx.x];
+  const int n = S.lab_chunk[blockIdx.x + 1] - c0;
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  label_components(S, c0, n, nbp, par, cnt, cur, sh, false);
 }
 
 /* inverse of every diagonal block by Gauss-Jordan (SPD, no pivoting):
@@ -1702,9 +1934,10 @@ struct PcgCache {
 template <typename HT>
 __device__ __forceinline__ bool pcg_cache_load(PcgCache<HT>& C, const Scene& S,
                                                const HT* Hd, const HT* Ho,
-                                               const HT* Pi, int ngroups) {
-  if ((int)gridDim.x < ngroups || (int)blockIdx.x >= ngroups) return false;
-  const int gr = blockIdx.x, lb = threadIdx.x / 12, row = threadIdx.x % 12;
+                                               const HT* Pi, int ngroups, int gr,
+                                               bool own) {
+  if (!own || gr >= ngroups) return false;
+  const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
   const int b = gr * 16 + lb;
   for (int c = 0; c < 12; ++c) {
     C.hd[c * 192 + threadIdx.x] = b < S.B ? Hd[144 * b + 12 * row + c] : HT(0);
@@ -1755,7 +1988,8 @@ __global__ __launch_bounds__(192) void k_pcg(Scene S, double eta, int max_it) {
   for (int p = threadIdx.x; p < NP; p += blockDim.x)
     pdone[p] = (S.iter_mode == 0 || ps[p].state == PS_NEWTON) ? 0 : 1;
   __syncthreads();
-  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups, (int)blockIdx.x,
+                                          (int)gridDim.x >= ngroups);
   /* init: x = 0, r = b = -g, z = P^-1 r, p_{-1} = 0 */
   for (int gr = blockIdx.x; gr < ngroups; gr += nblk) {
     const int b = gr * 16 + lb;
@@ -1983,7 +2217,8 @@ __device__ __forceinline__ void pcg_wait_sum(const PcgRec* recs, int glo, int gh
 }
 
 template <typename HT>
-__global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_it) {
+__global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_it,
+                                                   int goff) {
   const HT* __restrict__ Hd = (const HT*)S.Hdiag;
   const HT* __restrict__ Ho = (const HT*)S.Hoff;
   const HT* __restrict__ Pi = (const HT*)S.Pinv;
@@ -1998,7 +2233,7 @@ __global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_
   __shared__ int e_nb[PCG_OFF_CACHE], e_tr[PCG_OFF_CACHE];
   __shared__ PcgCache<HT> cache;
   const int ngroups = (S.B + 15) / 16;
-  const int gr = blockIdx.x;
+  const int gr = goff + (int)blockIdx.x;
   if (gr >= ngroups) return;
   const int lb = threadIdx.x / 12, row = threadIdx.x % 12;
   const int g0 = gr * 16, gend = min(S.B, g0 + 16);
@@ -2015,7 +2250,7 @@ __global__ __launch_bounds__(192) void k_pcg_local(Scene S, double eta, int max_
     ldone[threadIdx.x] =
         (S.iter_mode == 0 || ps[plo + threadIdx.x].state == PS_NEWTON) ? 0 : 1;
   __syncthreads();
-  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups, gr, true);
   if (!cached) __syncthreads();
   /* the group's block-row structure does not change during the solve */
   const int e0 = S.row_ptr[g0];
@@ -2244,7 +2479,8 @@ __device__ __forceinline__ void wave_sum_dpp(double& x) {
   x += dpp_move<0x143, 0xC>(x); /* row_bcast:31 into rows 2, 3 */
 }
 template <typename HT>
-__global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it) {
+__global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it,
+                                                 int goff) {
   const HT* __restrict__ Hd = (const HT*)S.Hdiag;
   const HT* __restrict__ Ho = (const HT*)S.Hoff;
   const HT* __restrict__ Pi = (const HT*)S.Pinv;
@@ -2268,7 +2504,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   __shared__ HT e_pi[PCG_OFF_CACHE][144];
   __shared__ PcgCache<HT> cache;
   const int ngroups = (S.B + 15) / 16;
-  const int gr = blockIdx.x;
+  const int gr = goff + (int)blockIdx.x;
   if (gr >= ngroups) return;
   /* with labelled components only the bodies of components larger than
    * DIR_MAX are solved here (the others directly); none: nothing to do */
@@ -2302,7 +2538,7 @@ __global__ __launch_bounds__(192) void k_pcg_cg1(Scene S, double eta, int max_it
   }
   if (threadIdx.x == 0) s_err = S.cnt->err;
   __syncthreads();
-  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups, gr, true);
   if (!cached) __syncthreads();
   const int e0 = S.row_ptr[g0], e_end = S.row_ptr[gend];
   const int e_lo = real ? S.row_ptr[b] : 0, e_hi = real ? S.row_ptr[b + 1] : 0;
@@ -2634,7 +2870,8 @@ __global__ __launch_bounds__(192) void k_pcg1(Scene S, double eta, int max_it) {
   for (int p = threadIdx.x; p < NP; p += blockDim.x)
     pdone[p] = (S.iter_mode == 0 || ps[p].state == PS_NEWTON) ? 0 : 1;
   __syncthreads();
-  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups);
+  const bool cached = pcg_cache_load(cache, S, Hd, Ho, Pi, ngroups, (int)blockIdx.x,
+                                          (int)gridDim.x >= ngroups);
   auto hrow = [&](int b, int c) -> HT {
     return cached ? cache.hd[c * 192 + threadIdx.x] : Hd[144 * b + 12 * row + c];
   };
@@ -3646,8 +3883,15 @@ void launch_positions(const Scene& S, int swept, hipStream_t st,
                      (int)nmain);
 }
 void launch_body_pairs(const Scene& S, hipStream_t st) {
-  unsigned g = cdiv(S.B, 16);
-  hipLaunchKernelGGL(k_body_pairs, dim3(g, g), dim3(16, 16), 0, st, S);
+  if (S.n_dyn == 0) return;
+  if (!S.sap_on) {
+    if (S.n_bp_tiles == 0) return;
+    hipLaunchKernelGGL(k_body_pairs, dim3(S.n_bp_tiles), dim3(16, 16), 0, st, S);
+    return;
+  }
+  hipLaunchKernelGGL(k_sap_sort, dim3(std::min(S.NP, 1024)), dim3(1024), 0, st, S);
+  hipLaunchKernelGGL(k_sap_sweep, dim3(std::min(4096u, cdiv(S.n_dyn, 4 * SAP_PER_WAVE))),
+                     dim3(256), 0, st, S);
 }
 void launch_chunk_pairs(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_chunk_pairs, dim3(S.grid_blocks), dim3(256), 0, st, S);
@@ -3723,13 +3967,15 @@ void launch_crossings(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_crossings, dim3(1024), dim3(256), 0, st, S);
 }
 void launch_bsr(const Scene& S, hipStream_t st) {
-  if (S.B <= BSR_LDS_ROWS) {
+  if (S.bsr_one) {
     hipLaunchKernelGGL(k_bsr_small, dim3(1), dim3(1024), 0, st, S);
     return;
   }
   hipLaunchKernelGGL(k_bsr_count, dim3(256), dim3(256), 0, st, S);
   hipLaunchKernelGGL(k_bsr_scan, dim3(1), dim3(1024), 0, st, S);
   hipLaunchKernelGGL(k_bsr_fill, dim3(256), dim3(256), 0, st, S);
+  if (S.comp_solve)
+    hipLaunchKernelGGL(k_components, dim3(S.n_lab_chunks), dim3(1024), 0, st, S);
 }
 void launch_block_inverse(const Scene& S, hipStream_t st) {
   if (S.mixed)
@@ -3767,8 +4013,8 @@ int pcg_max_grid() {
   return ncu * (per > 0 ? per : 1);
 }
 int launch_pcg(const Scene& S, double eta, int max_it, int grid, int variant,
-               hipStream_t st) {
-  void* args[] = {(void*)&S, (void*)&eta, (void*)&max_it};
+               int goff, hipStream_t st) {
+  void* args[] = {(void*)&S, (void*)&eta, (void*)&max_it, (void*)&goff};
   const void* fn;
   if (variant == 1)
     fn = S.mixed ? (const void*)k_pcg1<float> : (const void*)k_pcg1<double>;

@@ -133,7 +133,13 @@ struct abd_ctx {
   /* direct launches by default: on the benchmark scene a replayed graph
    * per pass costs more at each graph boundary than the pass's kernel
    * launches do (the host queues passes ahead either way) */
-  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 0, 0, 0};
+  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 0, 0, 0, ABD_BODY_PAIRS_AUTO, 0, 0};
+  long bp_tests = 0; /* box tests of every pair of each problem */
+  /* problem-local PCG forms: launches of consecutive 16-body groups
+   * (first group, count), each holding whole problems and at most
+   * pcg_grid groups; empty when a problem's groups exceed that */
+  std::vector<std::pair<int, int>> pcg_ranges;
+  std::vector<int> hb0, hb1; /* first and last body of each problem */
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -537,6 +543,14 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
   return ABD_OK;
 }
 
+/* body pairs by sort and sweep (else every pair of each problem) */
+constexpr long ALL_PAIRS_BUILD_MAX = 1L << 27;
+int sap_on(const abd_ctx* ctx) {
+  if (ctx->tune.body_pairs == ABD_BODY_PAIRS_ALL) return 0;
+  if (ctx->tune.body_pairs == ABD_BODY_PAIRS_SWEEP) return 1;
+  return ctx->bp_tests > SAP_ALL_PAIRS_MAX ? 1 : 0;
+}
+
 /* ---------------- phases ---------------- */
 void broad_phase(abd_ctx* ctx, const Scene& S, int swept, int stop_test = 0) {
   StageTimer t(ctx, 1);
@@ -581,15 +595,74 @@ void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
   }
 }
 
-/* PCG form in use: the problem-local form needs one resident block per
- * 16-body group */
+/* PCG form in use: the problem-local forms need one resident block per
+ * 16-body group of every problem (groups of different problems that share
+ * no group may run in separate launches, pcg_ranges) */
 int pcg_variant(const abd_ctx* ctx, const Scene& S) {
-  const int ng = std::max(1, (S.B + 15) / 16);
+  (void)S;
   if ((ctx->tune.pcg_variant == ABD_PCG_LOCAL || ctx->tune.pcg_variant == ABD_PCG_LOCAL1) &&
-      ng > ctx->pcg_grid)
+      ctx->pcg_ranges.empty())
     return ABD_PCG_TWO_BARRIER;
   return ctx->tune.pcg_variant;
 }
+
+/* launches of the problem-local PCG forms: problems whose 16-body groups
+ * overlap form one cluster (a group holding bodies of two problems runs
+ * both), clusters are packed in order into launches of at most cap
+ * groups; none if one cluster alone exceeds cap */
+std::vector<std::pair<int, int>> pcg_launch_ranges(const std::vector<int>& b0,
+                                                   const std::vector<int>& b1,
+                                                   int cap) {
+  std::vector<std::pair<int, int>> clusters, out;
+  for (size_t p = 0; p < b0.size(); ++p) {
+    if (b1[p] < b0[p]) continue;
+    const int ga = b0[p] / 16, gb = b1[p] / 16;
+    if (!clusters.empty() && ga <= clusters.back().second)
+      clusters.back().second = std::max(clusters.back().second, gb);
+    else
+      clusters.push_back({ga, gb});
+  }
+  for (auto& c : clusters) {
+    const int n = c.second - c.first + 1;
+    if (n > cap) return {};
+    if (!out.empty() && out.back().first + out.back().second == c.first &&
+        out.back().second + n <= cap)
+      out.back().second += n;
+    else
+      out.push_back({c.first, n});
+  }
+  return out;
+}
+/* launch plans that follow from the problems' body ranges and the
+ * tuning: the problem-local PCG launches (pcg_ranges) and the component
+ * labelling chunks (consecutive whole problems of at most label_rows
+ * bodies; none if a problem is larger) */
+int plan_launches(abd_ctx* ctx) {
+  Scene& S = ctx->S;
+  const int cap = ctx->tune.pcg_launch_groups > 0
+                      ? std::min(ctx->tune.pcg_launch_groups, ctx->pcg_grid)
+                      : ctx->pcg_grid;
+  ctx->pcg_ranges = pcg_launch_ranges(ctx->hb0, ctx->hb1, cap);
+  const int rows = ctx->tune.label_rows > 0 ? std::min(ctx->tune.label_rows, BSR_LDS_ROWS)
+                                            : BSR_LDS_ROWS;
+  S.bsr_one = S.B <= rows ? 1 : 0;
+  std::vector<int> ch = {0};
+  for (int p = 0; p < ctx->np; ++p) {
+    const int b0 = ctx->hb0[p], b1 = ctx->hb1[p];
+    if (b1 < b0) continue;
+    if (b1 - b0 + 1 > rows) {
+      ch.clear();
+      break;
+    }
+    if (b1 + 1 - ch.back() > rows) ch.push_back(b0);
+  }
+  if (!ch.empty() && ch.back() < S.B) ch.push_back(S.B);
+  S.n_lab_chunks = ch.size() >= 2 ? (int)ch.size() - 1 : 0;
+  if (S.n_lab_chunks > 0)
+    HIPCHK(hipMemcpy(S.lab_chunk, ch.data(), sizeof(int) * ch.size(), hipMemcpyHostToDevice));
+  return ABD_OK;
+}
+
 /* blocks of the persistent PCG launch (at most the resident capacity) */
 int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
   const int ng = std::max(1, (S.B + 15) / 16);
@@ -599,13 +672,28 @@ int pcg_blocks(const abd_ctx* ctx, const Scene& S) {
   return std::max(1, std::min(ctx->pcg_grid, want));
 }
 
+/* the PCG of a pass on the stream: one launch, or one per range of the
+ * problem-local forms */
+int run_pcg(abd_ctx* ctx, const Scene& S) {
+  const int v = pcg_variant(ctx, S);
+  if (v == ABD_PCG_LOCAL || v == ABD_PCG_LOCAL1) {
+    for (auto& r : ctx->pcg_ranges)
+      if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, r.second, v, r.first, ctx->st))
+        return fail(ctx, ABD_E_DEVICE, "PCG launch failed");
+    return ABD_OK;
+  }
+  if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S), v, 0, ctx->st))
+    return fail(ctx, ABD_E_DEVICE, "PCG launch failed");
+  return ABD_OK;
+}
+
 /* whether the block-row build labels the components of the system, so
  * that bodies alone and components of at most DIR_MAX bodies are solved
  * directly and only larger ones by the PCG (the problem-local
- * one-exchange form, which masks the others; scenes whose block rows are
- * built in one workgroup) */
+ * one-exchange form, which masks the others; every problem within one
+ * labelling chunk) */
 int comp_solve_on(const abd_ctx* ctx, const Scene& S) {
-  return S.B <= BSR_LDS_ROWS && pcg_variant(ctx, S) == ABD_PCG_LOCAL1 ? 1 : 0;
+  return S.n_lab_chunks > 0 && pcg_variant(ctx, S) == ABD_PCG_LOCAL1 ? 1 : 0;
 }
 
 /* block-Jacobi PCG and the Newton stop norm on the stream */
@@ -623,9 +711,8 @@ int launch_solve(abd_ctx* ctx, const Scene& S0, bool in_loop) {
     launch_block_inverse(S, ctx->st);
   }
   StageTimer t(ctx, 3);
-  if (launch_pcg(S, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S),
-                 pcg_variant(ctx, S), ctx->st))
-    return fail(ctx, ABD_E_DEVICE, "PCG launch failed");
+  int rc = run_pcg(ctx, S);
+  if (rc) return rc;
   launch_dq_norm(S, 0, ctx->st);
   return ABD_OK;
 }
@@ -799,10 +886,7 @@ int pass_pcg(abd_ctx* ctx) {
   Scene S1 = ctx->S;
   S1.iter_mode = 1;
   StageTimer t(ctx, 3);
-  if (launch_pcg(S1, ctx->P.pcg_eta, ctx->P.max_pcg, pcg_blocks(ctx, S1),
-                 pcg_variant(ctx, S1), ctx->st))
-    return fail(ctx, ABD_E_DEVICE, "PCG launch failed");
-  return ABD_OK;
+  return run_pcg(ctx, S1);
 }
 
 void pass_post(abd_ctx* ctx) {
@@ -1358,6 +1442,61 @@ int abd_finalize(abd_ctx* ctx) {
     }
     if ((rc = upload(ctx, &S.prob_b0, b0))) return rc;
     if ((rc = upload(ctx, &S.prob_b1, b1))) return rc;
+    /* sort-and-sweep lists: each problem's dynamic and static bodies, and
+     * one bucket per dynamic body (at most SAP_MAX_BUCKETS) */
+    std::vector<int> dyn, doff(ctx->np + 1, 0), stat, soff(ctx->np + 1, 0),
+        boff(ctx->np + 1, 0);
+    for (int p = 0; p < ctx->np; ++p) {
+      for (int i = b0[p]; i <= b1[p]; ++i) {
+        const int pi = (int)ctx->prob_of_body.size() == B ? ctx->prob_of_body[i] : 0;
+        if (pi != p) continue;
+        if (kind[i] == ABD_DYNAMIC)
+          dyn.push_back(i);
+        else
+          stat.push_back(i);
+      }
+      doff[p + 1] = (int)dyn.size();
+      soff[p + 1] = (int)stat.size();
+      const int nd = doff[p + 1] - doff[p];
+      boff[p + 1] = boff[p] + std::max(1, std::min(nd, SAP_MAX_BUCKETS)) + 1;
+    }
+    S.n_dyn = (int)dyn.size();
+    if (dyn.empty()) dyn.push_back(0);
+    if (stat.empty()) stat.push_back(0);
+    if ((rc = upload(ctx, &S.sap_dyn, dyn))) return rc;
+    if ((rc = upload(ctx, &S.sap_sorted, dyn))) return rc;
+    if ((rc = upload(ctx, &S.sap_doff, doff))) return rc;
+    if ((rc = upload(ctx, &S.sap_stat, stat))) return rc;
+    if ((rc = upload(ctx, &S.sap_soff, soff))) return rc;
+    if ((rc = upload(ctx, &S.sap_boff, boff))) return rc;
+    if ((rc = dalloc(ctx, &S.sap_bstart, (size_t)boff[ctx->np]))) return rc;
+    if ((rc = dalloc(ctx, &S.sap_par, (size_t)ctx->np))) return rc;
+    if ((rc = dalloc(ctx, &S.sap_sbox, 6 * dyn.size()))) return rc;
+    /* the all-pairs tiles, unless they would be very many */
+    long tests = 0;
+    for (int p = 0; p < ctx->np; ++p) {
+      const long n = std::max(0, b1[p] - b0[p] + 1);
+      tests += n * (n - 1) / 2;
+    }
+    ctx->bp_tests = tests;
+    S.sap_on = sap_on(ctx);
+    std::vector<int2> tiles;
+    if (tests <= ALL_PAIRS_BUILD_MAX)
+      for (int p = 0; p < ctx->np; ++p) {
+        if (b1[p] < b0[p]) continue;
+        for (int ta = b0[p] / 16; ta <= b1[p] / 16; ++ta)
+          for (int tb = ta; tb <= b1[p] / 16; ++tb) tiles.push_back(make_int2(ta, tb));
+      }
+    /* problems that share a tile list it once */
+    std::sort(tiles.begin(), tiles.end(), [](int2 x, int2 y) {
+      return x.x != y.x ? x.x < y.x : x.y < y.y;
+    });
+    tiles.erase(std::unique(tiles.begin(), tiles.end(),
+                            [](int2 x, int2 y) { return x.x == y.x && x.y == y.y; }),
+                tiles.end());
+    S.n_bp_tiles = (int)tiles.size();
+    if (tiles.empty()) tiles.push_back(make_int2(0, 0));
+    if ((rc = upload(ctx, &S.bp_tiles, tiles))) return rc;
   }
   if ((rc = dalloc(ctx, &S.xw, 3L * S.V))) return rc;
   if ((rc = dalloc(ctx, &S.xw1, 3L * S.V))) return rc;
@@ -1390,6 +1529,17 @@ int abd_finalize(abd_ctx* ctx) {
       hipHostMalloc((void**)&ctx->h_buf, 64 * sizeof(double)) != hipSuccess)
     return fail(ctx, ABD_E_OOM, "pinned host allocation failed");
   ctx->pcg_grid = pcg_max_grid();
+  {
+    ctx->hb0.assign(ctx->np, B);
+    ctx->hb1.assign(ctx->np, -1);
+    for (int i = 0; i < B; ++i) {
+      const int p = (int)ctx->prob_of_body.size() == B ? ctx->prob_of_body[i] : 0;
+      ctx->hb0[p] = std::min(ctx->hb0[p], i);
+      ctx->hb1[p] = std::max(ctx->hb1[p], i);
+    }
+    if ((rc = dalloc(ctx, &S.lab_chunk, (size_t)ctx->np + 2))) return rc;
+    if ((rc = plan_launches(ctx))) return rc;
+  }
   {
     int dev = 0;
     (void)hipGetDevice(&dev);
@@ -2103,6 +2253,20 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out) {
       M->prob_of_body.push_back(i);
     }
     off += B;
+    /* pad the problem to a multiple of 16 bodies with static one-triangle
+     * bodies far below the scene: no 16-body group of the merged scene then
+     * holds two problems, so the problem-local PCG can run the problems in
+     * several launches when their groups do not all fit at once */
+    static const double tv[9] = {0, 0, 0, 1e-3, 0, 0, 0, 0, 1e-3};
+    static const int32_t tt[3] = {0, 1, 2};
+    const double qg[12] = {0, -1e6, 0, 1, 0, 0, 0, 1, 0, 0, 0, 1};
+    for (int k = 0; k < (16 - B % 16) % 16; ++k) {
+      int32_t id;
+      rc = abd_add_body(M, tv, 3, tt, 1, 1000.0, qg, nullptr, ABD_STATIC, &id);
+      if (rc) { abd_batch_destroy(bt); return rc; }
+      M->prob_of_body.push_back(i);
+      ++off;
+    }
     bt->max_nb = std::max(bt->max_nb, B);
   }
   if ((rc = abd_finalize(M)) || (rc = abd_set_tuning(M, &ctxs[0]->tune))) {
@@ -2470,13 +2634,21 @@ int abd_set_tuning(abd_ctx* ctx, const abd_tuning* t) {
   if (t->pcg_coop != 0)
     return fail(ctx, ABD_E_INVALID_ARG,
                 "pcg_coop is reserved and must be 0: the PCG launch is always a plain launch");
+  if (t->pcg_launch_groups < 0 || t->label_rows < 0)
+    return fail(ctx, ABD_E_INVALID_ARG, "pcg_launch_groups and label_rows must be >= 0");
+  if (t->body_pairs < ABD_BODY_PAIRS_AUTO || t->body_pairs > ABD_BODY_PAIRS_SWEEP)
+    return fail(ctx, ABD_E_INVALID_ARG, "body_pairs must be ABD_BODY_PAIRS_AUTO, _ALL or _SWEEP");
+  if (t->body_pairs == ABD_BODY_PAIRS_ALL && ctx->bp_tests > ALL_PAIRS_BUILD_MAX)
+    return fail(ctx, ABD_E_INVALID_ARG,
+                "every-pair body tests are not set up for more than 2^27 pairs");
   drop_graphs(ctx); /* launch shapes are part of the captured graphs */
   ctx->tune = *t;
   ctx->tune.use_graphs = t->use_graphs ? 1 : 0;
   ctx->tune.overlap_body = t->overlap_body ? 1 : 0;
   ctx->S.grid_blocks = t->grid_blocks;
   ctx->S.assemble_blocks = t->assemble_blocks;
-  return ABD_OK;
+  ctx->S.sap_on = sap_on(ctx);
+  return plan_launches(ctx);
 }
 
 int abd_autotune(abd_ctx* ctx, abd_tuning* out) {

@@ -351,6 +351,134 @@ def hulls_in_funnel_scene(seed: int = 0, n_bodies: int = 2500,
     return sc
 
 
+def _place(rng: np.random.Generator, n: int, lo: np.ndarray, hi: np.ndarray,
+           r_lo: float, r_hi: float, min_gap: float):
+    """n non-overlapping spheres (centres, radii) drawn uniformly in the box
+    [lo, hi] by rejection."""
+    centres = np.zeros((n, 3))
+    radii = np.zeros(n)
+    k = 0
+    tries = 0
+    while k < n:
+        tries += 1
+        if tries > 200000 * max(1, n):
+            raise RuntimeError("could not place bodies")
+        r = rng.uniform(r_lo, r_hi)
+        c = rng.uniform(lo, hi)
+        if k and np.any(np.linalg.norm(centres[:k] - c, axis=1) < radii[:k] + r + min_gap):
+            continue
+        centres[k] = c
+        radii[k] = r
+        k += 1
+    return centres, radii
+
+
+def subdomain_scene(seed: int = 0, n_bodies: int = 400, sphere_frac: float = 0.5,
+                    level: int = 3, n_lo: int = 300, n_hi: int = 600,
+                    width: float = 4.0, shared_frac: float = 0.1,
+                    rho: float = 1e4, vel: float = 1.0, steps: int = 50,
+                    **over) -> Scene:
+    """One ADMM subdomain of a larger scene: icospheres and convex hulls
+    (radius 0.05-0.15; hulls of n_lo..n_hi points) at seeded
+    non-overlapping positions in the slab 0 < x < width, |z| < width/2,
+    with random velocities, falling into an open box.  The bodies nearest
+    the two cut planes x = 0 and x = width (a fraction shared_frac) are
+    shared, with seeded consensus draws as in the worker share."""
+    rng = np.random.default_rng(seed)
+    h = max(1.0, 0.004 * n_bodies * (width / 4.0) ** -2)
+    m = 0.2
+    lo = np.array([m, 0.3, -0.5 * width + m])
+    hi = np.array([width - m, 0.3 + h, 0.5 * width - m])
+    centres, radii = _place(rng, n_bodies, lo, hi, 0.05, 0.15, 0.01)
+    unit_v, unit_t = icosphere_mesh(level, 1.0)
+    bodies = []
+    for i in range(n_bodies):
+        qd = np.zeros(12)
+        qd[0:3] = rng.uniform(-vel, vel, 3)
+        if rng.uniform() < sphere_frac:
+            v, t = unit_v * radii[i], unit_t.copy()
+            q = identity_q(centres[i])
+        else:
+            n = int(rng.integers(n_lo, n_hi + 1))
+            v, t = hull_mesh(rng, n, radii[i], rng.uniform(0.6, 1.0, 3))
+            q = identity_q(centres[i])
+            q[3:12] = random_rotation(rng).reshape(-1)
+        bodies.append(Body(v, t, 1000.0, q, qd, DYNAMIC))
+    bv, bt = open_box_mesh(0.5 * width + 0.2, 0.5 * width + 0.2, h + 1.0)
+    bodies.append(Body(bv, bt, 1000.0, identity_q([0.5 * width, 0.0, 0.0]),
+                       np.zeros(12), STATIC))
+    params = default_params(has_ground=0)
+    params.update(over)
+    sc = Scene(f"subdomain{n_bodies}_s{seed}", params, bodies, steps)
+    ns = max(1, int(round(shared_frac * n_bodies)))
+    edge = np.minimum(centres[:, 0], width - centres[:, 0])
+    sid = np.sort(np.argsort(edge, kind="stable")[:ns]).astype(np.int32)
+    delta = np.zeros((ns, 12))
+    delta[:, 0:3] = rng.uniform(-1e-3, 1e-3, (ns, 3))
+    delta[:, 3:12] = rng.uniform(-1e-4, 1e-4, (ns, 9))
+    sc.shared_ids = sid
+    sc.shared_delta = delta
+    sc.shared_u = rng.uniform(-1e-5, 1e-5, (ns, 12))
+    sc.shared_rho = np.full(ns, rho)
+    sc.shared_kappa = np.full(ns, 2, dtype=np.int32)
+    return sc
+
+
+def cubes_in_box_scene(seed: int = 0, n_cubes: int = 16, gap: float = 0.05,
+                       jitter: float = 0.01, steps: int = 20, **over) -> Scene:
+    """n unit cubes stacked in layers of k x k (k = round(cbrt(n)), at
+    least 2) with `gap` spacing and uniform +/-jitter, in an open box (a
+    static body instead of the ground plane, so that these scenes share
+    their parameters with the subdomains of a batch)."""
+    rng = np.random.default_rng(seed)
+    v, t = cube_mesh(0.5)
+    k = max(2, int(round(n_cubes ** (1.0 / 3.0))))
+    pitch = 1.0 + gap
+    xs = (np.arange(k) - (k - 1) / 2.0) * pitch
+    bodies = []
+    for i in range(n_cubes):
+        layer, rest = divmod(i, k * k)
+        ix, iz = divmod(rest, k)
+        c = np.array([xs[ix], 0.5 + gap + layer * pitch, xs[iz]])
+        c = c + rng.uniform(-jitter, jitter, 3)
+        bodies.append(Body(v.copy(), t.copy(), 1000.0, identity_q(c),
+                           np.zeros(12), DYNAMIC))
+    half = 0.5 * k * pitch + 0.3
+    layers = (n_cubes + k * k - 1) // (k * k)
+    bv, bt = open_box_mesh(half, half, layers * pitch + 1.0)
+    bodies.append(Body(bv, bt, 1000.0, identity_q(np.zeros(3)), np.zeros(12),
+                       STATIC))
+    params = default_params(has_ground=0)
+    params.update(over)
+    return Scene(f"cubes{n_cubes}_box_s{seed}", params, bodies, steps)
+
+
+# the batch workload: subdomains of uneven size and independent cube scenes
+BATCH_SUBDOMAINS = (200, 220, 250, 300, 400, 600, 1200, 3000)
+BATCH_CUBES = tuple(int(round(16 * 32 ** (i / 63))) for i in range(64))
+
+
+def batch_workload(seed: int = 0, subdomains=BATCH_SUBDOMAINS,
+                   cubes=BATCH_CUBES, sub_args: Optional[dict] = None,
+                   **over) -> List[Scene]:
+    """Problems solved together in one batch: ADMM subdomains of uneven
+    size (icospheres and hulls, each a worker's local problem with its
+    shared bodies; sub_args: further subdomain_scene arguments) followed
+    by independent scenes of stacked cubes, all with the same parameters
+    (over).  At most 20 line-search halvings: in the subdomains' contact
+    piles the energy differences of FP64 positions in a 10 m scene are
+    resolved to about 1e-12, so a line search that still finds no
+    decrease after 20 halvings has reached that floor (and ends the solve
+    as converged when eps_N < 10 theta)."""
+    over = {"max_ls": 20, **over}
+    sa = dict(sub_args or {})
+    out = [subdomain_scene(seed * 1000 + i, n, **sa, **over)
+           for i, n in enumerate(subdomains)]
+    out += [cubes_in_box_scene(seed * 1000 + 500 + i, n, **over)
+            for i, n in enumerate(cubes)]
+    return out
+
+
 @dataclasses.dataclass
 class Split:
     """Subdomains of one scene: worker scenes plus the replica table.
@@ -403,7 +531,8 @@ def split_scene(scene: Scene, axis: int = 0, cut: float = 0.0,
 def config(idx: int, seed: int = 0, **over) -> Scene:
     """The named workloads: 0 = 8 stacked cubes on the ground (20 steps),
     1 = 1000 icospheres in an open box (50 steps), 2 = one worker's share
-    of 2500 hulls in a funnel."""
+    of 2500 hulls in a funnel (the batch of subdomains and cube scenes is
+    batch_workload)."""
     if idx == 0:
         return cubes_scene(seed, **over)
     if idx == 1:
