@@ -109,7 +109,21 @@ typedef struct abd_params {
                             continues with FP64 Hessians in any case (0: a
                             third of max_newton); a stall (eps_N not halving
                             for 16 iterations) switches earlier */
-  int32_t pad_;
+  int32_t deterministic; /* 1: every local solve is bit-reproducible: the
+                            barrier gradient and Hessian sums and the
+                            line-search energy sums are accumulated exactly
+                            (fixed point on the grid 2^-128, independent of
+                            the order in which terms arrive) and rounded
+                            once, block rows are in ascending neighbour
+                            order and the PCG is the problem-local
+                            one-exchange form (abd_finalize fails with
+                            INVALID_ARG when a problem exceeds what that
+                            form holds resident).  A barrier term of
+                            magnitude 2^100 or more ends the solve with
+                            DEVICE.  0 (default): FP64/FP32 atomics, last
+                            bits may vary between runs.  Not available to
+                            abd_local_solve_static (INVALID_ARG); the
+                            consensus kernels keep their atomics */
 } abd_params;
 
 typedef struct abd_stats {

@@ -32,7 +32,7 @@ class Params(C.Structure):
                 ("max_ls", C.c_int32), ("has_ground", C.c_int32),
                 ("mollify_ee", C.c_int32), ("precision", C.c_int32),
                 ("list_capacity", C.c_int64), ("mixed_switch", C.c_int32),
-                ("pad_", C.c_int32)]
+                ("deterministic", C.c_int32)]
 
 
 class Tuning(C.Structure):
@@ -220,6 +220,7 @@ def make_params(p: dict) -> Params:
     o.precision = int(p.get("precision", 0))
     o.list_capacity = int(p.get("list_capacity", 0))
     o.mixed_switch = int(p.get("mixed_switch", 0))
+    o.deterministic = int(p.get("deterministic", 0))
     return o
 
 

@@ -112,6 +112,58 @@ struct SapAxis {
  * box tests */
 #define SAP_ALL_PAIRS_MAX (1L << 21)
 
+/* Exact, order-independent sums for the deterministic mode: a sum of
+ * doubles held as a fixed-point integer on the grid 2^-DET_FRAC, in DET_W
+ * words of which each receives 32-bit signed digits (so a word takes 2^31
+ * additions without overflow).  Integer additions commute, so the total
+ * does not depend on the order in which terms arrive.  A term is truncated
+ * toward zero onto the grid; terms of magnitude 2^DET_MAX_EXP or more (and
+ * NaN) do not fit. */
+#define DET_W 8
+#define DET_FRAC 128
+#define DET_MAX_EXP 100
+typedef unsigned long long det_word;
+
+/* add v; false if it does not fit (nothing added) */
+__device__ __forceinline__ bool det_add(det_word* w, double v) {
+  if (v == 0.0) return true;
+  const double a = fabs(v);
+  if (!(a < 0x1p100)) return false;
+  int e;
+  const double m = frexp(a, &e); /* a = m 2^e, m in [0.5, 1) */
+  unsigned long long M = (unsigned long long)ldexp(m, 53);
+  int s = e - 53 + DET_FRAC; /* a 2^DET_FRAC = M 2^s */
+  if (s < 0) {
+    if (s <= -53) return true;
+    M >>= -s;
+    s = 0;
+  }
+  const int wi = s >> 5, o = s & 31;
+  const unsigned long long lo = M << o;
+  const unsigned long long hi = o ? (M >> (64 - o)) : 0ull;
+  const unsigned long long d[3] = {lo & 0xffffffffull, lo >> 32, hi};
+  for (int k = 0; k < 3; ++k) {
+    if (d[k] == 0ull || wi + k >= DET_W) continue;
+    const unsigned long long x = v < 0.0 ? (unsigned long long)(-(long long)d[k]) : d[k];
+    atomicAdd(w + wi + k, x);
+  }
+  return true;
+}
+
+/* the value of an accumulator, rounded (deterministically) to a double */
+__device__ __forceinline__ double det_value(const det_word* w) {
+  long long c = 0;
+  long long d[DET_W];
+  for (int k = 0; k < DET_W; ++k) {
+    const long long x = (long long)w[k] + c;
+    d[k] = x & 0xffffffffll;
+    c = x >> 32;
+  }
+  double r = (double)c;
+  for (int k = DET_W - 1; k >= 0; --k) r = r * 4294967296.0 + (double)d[k];
+  return ldexp(r, -DET_FRAC);
+}
+
 struct Scene {
   int B, V, T, E, NC;
   /* parameters */
@@ -173,6 +225,13 @@ struct Scene {
    * scene's block-row build (the PCG form in use masks the rest) */
   int *bmode, *dir_body, *dir_n;
   int comp_solve;
+  /* deterministic mode: exact accumulators of the barrier contributions to
+   * g [B][12], the diagonal blocks [B][144] and the off-diagonal blocks
+   * [cap_bp][144], and of the line-search trial energies per problem
+   * [NP][LS_TRIALS] (DET_W words each, plus one word per trial counting
+   * terms that do not fit) */
+  int det;
+  det_word *det_g, *det_hd, *det_ho, *det_de;
   /* bsr_one: block rows and component labels in one workgroup (scenes of
    * at most BSR_LDS_ROWS bodies); else the block rows by three kernels and
    * the labels per chunk of whole problems, bodies [lab_chunk[c],

@@ -156,6 +156,9 @@ __device__ __forceinline__ void pass_reset(const Scene& S, const Counters& fresh
     P.pcg_iters = 0;
     for (int k = 0; k < LS_TRIALS; ++k) P.dE[k] = 0.0;
     for (int k = 0; k < 16; ++k) P.acc[k] = 0.0;
+    if (S.det)
+      for (int k = 0; k < LS_TRIALS * (DET_W + 1); ++k)
+        S.det_de[(size_t)q * LS_TRIALS * (DET_W + 1) + k] = 0ull;
   }
   for (int i = t; i <= S.B; i += nth) S.row_cnt[i] = 0;
   for (int i = t; i < 2 * ((S.B + 15) / 16); i += nth)
@@ -1143,15 +1146,23 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int g, bool on, T* k) {
       offs += __shfl_xor(offs, o, 16);
     }
     /* a sweep that skips all 36 rotations leaves the upper triangle under
-     * the bound (the V lanes only follow) */
+     * the bound (the V lanes only follow).  The two matrices of the
+     * wavefront stop independently: a group whose matrix is done keeps it
+     * unchanged while the other sweeps on, so each projection is the same
+     * whichever pair shares its wavefront */
     const bool done = !kon || offs == T(0) || offs <= tol2 * fro;
-    if (__all(done)) break;
+    const unsigned long long bal = __ballot(done);
+    if (bal == ~0ull) break;
+    const unsigned long long gm = (__lane_id() & 32) ? 0xffffffff00000000ull
+                                                     : 0x00000000ffffffffull;
+    const bool gact = (bal & gm) != gm;
+    const bool kact = kon && gact;
     const T skip2 = tol2 * T(1.0 / 36.0) * fro;
 #pragma unroll
     for (int kr = 0; kr < 9; ++kr) {
       const int pr = (2 * kr + 18 - r) % 9; /* partner of row r */
       /* the pair's leading lane: its rotation */
-      if (kon && r < pr) {
+      if (kact && r < pr) {
         const T app = X.row[r][r], aqq = X.row[pr][pr], apq = X.row[r][pr];
         T c = T(1), sn = T(0), t = T(0);
         if (apq * apq > skip2) {
@@ -1189,7 +1200,7 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int g, bool on, T* k) {
         const T sg = m < pm ? -s4[i] : s4[i];
         x1[m] = c4[i] * x[m] + sg * x[pm];
       }
-      if (kon) {
+      if (kact) {
 #pragma unroll
         for (int m = 0; m < 9; ++m) X.row[r][m] = x1[m];
       }
@@ -1198,7 +1209,7 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int g, bool on, T* k) {
        * annihilated 2x2 block is then written into the row in LDS */
       const int lead = r < pr ? r : pr;
       const T c = X.cs[lead][0], sn = X.cs[lead][1];
-      const bool rot = kon && pr != r && sn != T(0);
+      const bool rot = kact && pr != r && sn != T(0);
       if (rot) {
         const T sg = r < pr ? -sn : sn;
 #pragma unroll
@@ -1217,7 +1228,7 @@ __device__ __forceinline__ void psd9_par(JacX<T>& X, int g, bool on, T* k) {
       if (kon) {
 #pragma unroll
         for (int m = 0; m < 9; ++m) x[m] = X.row[r][m];
-      } else {
+      } else if (gact) {
 #pragma unroll
         for (int m = 0; m < 9; ++m) x[m] = x1[m];
       }
@@ -1381,7 +1392,10 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
 #pragma unroll
           for (int r = 0; r < 3; ++r)
             v += GW[(wo + 4 * r + k) * 64 + j] * GW[(3 * r + i) * 64 + j];
-          atomicAdd(S.g + 12 * body + dd, v);
+          if (!S.det)
+            atomicAdd(S.g + 12 * body + dd, v);
+          else if (!det_add(S.det_g + (size_t)(12 * body + dd) * DET_W, v))
+            atomicOr(&S.cnt->err, 2);
         }
       }
       __syncthreads();
@@ -1389,16 +1403,20 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
       for (int blk = 0; blk < 3; ++blk) {
         int X, Y;
         HT* dst;
+        det_word* ddst;
         if (blk == 0) {
           if (A < 0) continue;
           X = 0; Y = 0; dst = (HT*)S.Hdiag + 144 * A;
+          ddst = S.det_hd + (size_t)144 * DET_W * A;
         } else if (blk == 1) {
           if (Bq < 0) continue;
           X = 1; Y = 1; dst = (HT*)S.Hdiag + 144 * Bq;
+          ddst = S.det_hd + (size_t)144 * DET_W * Bq;
         } else {
           if (A < 0 || Bq < 0) continue;
           if (A < Bq) { X = 0; Y = 1; } else { X = 1; Y = 0; }
           dst = (HT*)S.Hoff + 144 * (size_t)sl;
+          ddst = S.det_ho + (size_t)144 * DET_W * sl;
           if (lane == 0) S.slot_used[sl] = 1;
         }
         const int wx = X ? 21 : 9;
@@ -1411,13 +1429,78 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
           for (int r = 0; r < 3; ++r)
             v += (HT)GW[(wx + 4 * r + k) * 64 + j] *
                  TB[Y * 108 + (3 * r + i) * 12 + i2 * 4 + l];
-          atomicAdd(dst + e, v);
+          if (!S.det)
+            atomicAdd(dst + e, v);
+          else if (!det_add(ddst + (size_t)e * DET_W, (double)v))
+            atomicOr(&S.cnt->err, 2);
         }
       }
       __syncthreads();
     }
     __syncthreads();
   }
+}
+
+/* deterministic mode: the exact barrier sums rounded once and added to
+ * the body terms (gradient, diagonal blocks) or stored (off-diagonal
+ * blocks of the body pairs that received contributions); the
+ * accumulators are cleared for the next assembly.  One thread per entry. */
+template <typename HT>
+__global__ void k_det_finish(Scene S) {
+  const long nb = 156L * S.B;
+  const long nbp = min(S.cnt->n_bp, S.cap_bp);
+  const long stride = (long)gridDim.x * blockDim.x;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < nb + 144 * nbp;
+       t += stride) {
+    if (t < nb) {
+      const int b = (int)(t / 156), e = (int)(t % 156);
+      if (!body_in_pass(S, b)) continue;
+      det_word* w = (e < 12 ? S.det_g + (size_t)(12 * b + e) * DET_W
+                            : S.det_hd + ((size_t)144 * b + e - 12) * DET_W);
+      const double v = det_value(w);
+      for (int k = 0; k < DET_W; ++k) w[k] = 0ull;
+      if (v == 0.0) continue;
+      if (e < 12) {
+        S.g[12 * b + e] += v;
+      } else {
+        HT* h = (HT*)S.Hdiag + 144 * b + e - 12;
+        *h = (HT)((double)*h + v);
+      }
+    } else {
+      const long u = t - nb;
+      const int sl = (int)(u / 144), e = (int)(u % 144);
+      if (!S.slot_used[sl]) continue;
+      det_word* w = S.det_ho + ((size_t)144 * sl + e) * DET_W;
+      const double v = det_value(w);
+      for (int k = 0; k < DET_W; ++k) w[k] = 0ull;
+      ((HT*)S.Hoff)[144 * (size_t)sl + e] = (HT)v;
+    }
+  }
+}
+
+/* deterministic mode: each block row's entries in ascending neighbour
+ * order (the fill order depends on the order of atomics), rows
+ * [r0, r1) by the calling threads */
+__device__ void sort_block_rows(const Scene& S, int r0, int r1, int step) {
+  for (int r = r0; r < r1; r += step) {
+    const int lo = S.row_ptr[r], hi = min(S.row_ptr[r + 1], S.cap_col);
+    for (int i = lo + 1; i < hi; ++i) {
+      const int b = S.col_body[i], sl = S.col_slot[i], tr = S.col_trans[i];
+      int j = i - 1;
+      while (j >= lo && S.col_body[j] > b) {
+        S.col_body[j + 1] = S.col_body[j];
+        S.col_slot[j + 1] = S.col_slot[j];
+        S.col_trans[j + 1] = S.col_trans[j];
+        --j;
+      }
+      S.col_body[j + 1] = b;
+      S.col_slot[j + 1] = sl;
+      S.col_trans[j + 1] = tr;
+    }
+  }
+}
+__global__ void k_sort_rows(Scene S) {
+  sort_block_rows(S, blockIdx.x * blockDim.x + threadIdx.x, S.B, gridDim.x * blockDim.x);
 }
 
 /* ================================================================== */
@@ -1652,6 +1735,10 @@ __global__ __launch_bounds__(1024) void k_bsr_small(Scene S) {
     if (k < S.cap_col) {
       S.col_slot[k] = p; S.col_body[k] = ab.x; S.col_trans[k] = 1;
     }
+  }
+  if (S.det) {
+    __syncthreads(); /* the fill's global writes, for the sort */
+    sort_block_rows(S, threadIdx.x, n, blockDim.x);
   }
   if (!S.comp_solve) return;
   label_components(S, 0, n, nbp, par, cnt, cur, sh, true);
@@ -3355,6 +3442,17 @@ __device__ __forceinline__ bool last_workgroup(unsigned* ctr, unsigned n);
 __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
                                                 const Counters& c0,
                                                 const Counters& c1);
+/* a trial energy term into its problem's sum: an FP64 atomic, or exact
+ * in the deterministic mode */
+__device__ __forceinline__ void de_add(const Scene& S, int p, int k, double v) {
+  if (!S.det) {
+    atomicAdd(&S.ps[p].dE[k], v);
+    return;
+  }
+  det_word* w = S.det_de + ((size_t)p * LS_TRIALS + k) * (DET_W + 1);
+  if (!det_add(w, v)) atomicAdd(w + DET_W, 1ull);
+}
+
 __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
@@ -3411,6 +3509,12 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
         }
       }
     }
+    if (S.det) {
+      /* every term on its own into the exact sum: no floating-point
+       * partial sum whose grouping follows the list order */
+      if (prob >= 0) de_add(S, prob, k, e);
+      continue;
+    }
     /* per trial: the eight elements of the wavefront summed when they
      * belong to one problem (lanes k, k + 8, ... hold trial k) */
     const bool uni = wave_uniform(prob);
@@ -3419,7 +3523,7 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
         for (int o = 32; o >= LS_TRIALS; o >>= 1) e += __shfl_down(e, o, 64);
         if (lane < LS_TRIALS) {
           if (accp != prob) {
-            if (accp >= 0) atomicAdd(&S.ps[accp].dE[k], acc);
+            if (accp >= 0) de_add(S, accp, k, acc);
             acc = 0.0;
             accp = prob;
           }
@@ -3427,7 +3531,7 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
         }
       }
     } else if (prob >= 0) {
-      atomicAdd(&S.ps[prob].dE[k], e);
+      de_add(S, prob, k, e);
     }
   }
   /* the four waves' running sums: lanes 0..LS_TRIALS-1 of a wave share
@@ -3445,13 +3549,13 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
       const int pi = s_accp[i];
       if (pi < 0) continue;
       if (pi != p) {
-        if (p >= 0) atomicAdd(&S.ps[p].dE[threadIdx.x], sum);
+        if (p >= 0) de_add(S, p, threadIdx.x, sum);
         p = pi;
         sum = 0.0;
       }
       sum += s_acc[i][threadIdx.x];
     }
-    if (p >= 0) atomicAdd(&S.ps[p].dE[threadIdx.x], sum);
+    if (p >= 0) de_add(S, p, threadIdx.x, sum);
   }
   /* then every problem's line search decision (this scene's counters are
    * the swept block; the static block precedes it) */
@@ -3459,6 +3563,11 @@ __global__ __launch_bounds__(256) void k_energy_multi(Scene S) {
     const Counters* base = S.cnt - 1;
     for (int q = threadIdx.x; q < S.NP; q += blockDim.x) {
       ProbState& P = S.ps[q];
+      if (S.det)
+        for (int k = 0; k < LS_TRIALS; ++k) {
+          det_word* w = S.det_de + ((size_t)q * LS_TRIALS + k) * (DET_W + 1);
+          P.dE[k] = w[DET_W] ? INFINITY : det_value(w);
+        }
       ctrl_linesearch(S, P, base[0], base[1]);
       if (P.state != PS_DONE) atomicAdd(&S.cnt->active, 1);
     }
@@ -3913,6 +4022,13 @@ void launch_assemble(const Scene& S, int n_act_hint, hipStream_t st) {
     hipLaunchKernelGGL(k_assemble<float>, dim3(g), dim3(64), 0, st, S);
   else
     hipLaunchKernelGGL(k_assemble<double>, dim3(g), dim3(64), 0, st, S);
+  if (S.det) {
+    const unsigned gd = std::min(4096u, cdiv(156L * S.B + 144L * S.cap_bp, 256));
+    if (S.mixed)
+      hipLaunchKernelGGL(k_det_finish<float>, dim3(gd), dim3(256), 0, st, S);
+    else
+      hipLaunchKernelGGL(k_det_finish<double>, dim3(gd), dim3(256), 0, st, S);
+  }
 }
 void launch_energy_multi(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_energy_multi, dim3(512), dim3(256), 0, st, S);
@@ -3974,6 +4090,7 @@ void launch_bsr(const Scene& S, hipStream_t st) {
   hipLaunchKernelGGL(k_bsr_count, dim3(256), dim3(256), 0, st, S);
   hipLaunchKernelGGL(k_bsr_scan, dim3(1), dim3(1024), 0, st, S);
   hipLaunchKernelGGL(k_bsr_fill, dim3(256), dim3(256), 0, st, S);
+  if (S.det) hipLaunchKernelGGL(k_sort_rows, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S);
   if (S.comp_solve)
     hipLaunchKernelGGL(k_components, dim3(S.n_lab_chunks), dim3(1024), 0, st, S);
 }

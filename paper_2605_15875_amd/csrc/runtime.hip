@@ -437,6 +437,13 @@ int reset_both(abd_ctx* ctx) {
   return ABD_OK;
 }
 
+/* the device's error bits: 1 a bounded wait ran out, 2 a barrier term
+ * too large for the deterministic mode's exact sums */
+const char* device_err_text(int err) {
+  if (err & 2) return "a barrier term of magnitude 2^100 or more (deterministic mode)";
+  return "device barrier timed out";
+}
+
 int read_counters(abd_ctx* ctx, int which = 0, int n = 1) {
   HIPCHK(hipMemcpyAsync(ctx->h_cnt + which, ctx->S.cnt + which,
                         n * sizeof(Counters), hipMemcpyDeviceToHost, ctx->st));
@@ -444,7 +451,7 @@ int read_counters(abd_ctx* ctx, int which = 0, int n = 1) {
   resolve_timing(ctx);
   for (int i = which; i < which + n; ++i)
     if (ctx->h_cnt[i].err)
-      return fail(ctx, ABD_E_DEVICE, "device barrier timed out");
+      return fail(ctx, ABD_E_DEVICE, device_err_text(ctx->h_cnt[i].err));
   return ABD_OK;
 }
 
@@ -501,6 +508,11 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
     if ((rc = dalloc(ctx, &S.bp, S.cap_bp))) return rc;
     if ((rc = dalloc_bytes(ctx, &S.Hoff, 144L * S.cap_bp * HESS_ALLOC))) return rc;
     if ((rc = dalloc(ctx, &S.slot_used, S.cap_bp))) return rc;
+    if (S.det) {
+      dfree(ctx, S.det_ho);
+      if ((rc = dalloc(ctx, &S.det_ho, (size_t)144 * DET_W * S.cap_bp))) return rc;
+      HIPCHK(hipMemset(S.det_ho, 0, sizeof(det_word) * 144 * DET_W * (size_t)S.cap_bp));
+    }
     dfree(ctx, S.col_slot);
     dfree(ctx, S.col_body);
     dfree(ctx, S.col_trans);
@@ -600,6 +612,7 @@ void launch_static(abd_ctx* ctx, const Scene& S, bool take_over = false,
  * no group may run in separate launches, pcg_ranges) */
 int pcg_variant(const abd_ctx* ctx, const Scene& S) {
   (void)S;
+  if (ctx->P.deterministic) return ABD_PCG_LOCAL1; /* finalize checked the ranges */
   if ((ctx->tune.pcg_variant == ABD_PCG_LOCAL || ctx->tune.pcg_variant == ABD_PCG_LOCAL1) &&
       ctx->pcg_ranges.empty())
     return ABD_PCG_TWO_BARRIER;
@@ -1054,7 +1067,7 @@ int device_solve(abd_ctx* ctx) {
     resolve_timing(ctx);
     if (c[0].err || c[1].err) {
       HIPCHK(hipStreamSynchronize(ctx->st));
-      return fail(ctx, ABD_E_DEVICE, "device barrier timed out");
+      return fail(ctx, ABD_E_DEVICE, device_err_text(c[0].err | c[1].err));
     }
     if (over_cap(ctx->S, ctx->h_cnt[0]) || over_cap(ctx->S, ctx->h_cnt[1])) {
       /* drain, grow, and start over from the state the overflowing pass
@@ -1136,7 +1149,7 @@ int abd_create(abd_ctx** out, const abd_params* p) {
       p->max_newton < 1 || p->max_pcg < 1 || p->max_ls < 0 ||
       !(p->newton_theta > 0) || !(p->pcg_eta > 0) ||
       (p->precision != ABD_FP64 && p->precision != ABD_MIXED) || p->list_capacity < 0 ||
-      p->mixed_switch < 0)
+      p->mixed_switch < 0 || (p->deterministic != 0 && p->deterministic != 1))
     return ABD_E_INVALID_ARG;
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
@@ -1420,6 +1433,17 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.col_slot, S.cap_col))) return rc;
   if ((rc = dalloc(ctx, &S.col_body, S.cap_col))) return rc;
   if ((rc = dalloc(ctx, &S.col_trans, S.cap_col))) return rc;
+  S.det = ctx->P.deterministic;
+  if (S.det) {
+    const size_t ng = (size_t)12 * DET_W * B, nh = (size_t)144 * DET_W * B,
+                 no = (size_t)144 * DET_W * S.cap_bp;
+    if ((rc = dalloc(ctx, &S.det_g, ng)) || (rc = dalloc(ctx, &S.det_hd, nh)) ||
+        (rc = dalloc(ctx, &S.det_ho, no)))
+      return rc;
+    HIPCHK(hipMemset(S.det_g, 0, sizeof(det_word) * ng));
+    HIPCHK(hipMemset(S.det_hd, 0, sizeof(det_word) * nh));
+    HIPCHK(hipMemset(S.det_ho, 0, sizeof(det_word) * no));
+  }
   if ((rc = dalloc(ctx, &S.bmode, B))) return rc;
   if ((rc = dalloc(ctx, &S.dir_body, (long)(B / 2 + 1) * DIR_MAX))) return rc;
   if ((rc = dalloc(ctx, &S.dir_n, B / 2 + 1))) return rc;
@@ -1520,6 +1544,11 @@ int abd_finalize(abd_ctx* ctx) {
     if ((rc = upload(ctx, &S.bprob, bp0))) return rc;
     if ((rc = dalloc(ctx, &S.ps, S.NP))) return rc;
     HIPCHK(hipMemset(S.ps, 0, sizeof(ProbState) * S.NP));
+    if (S.det) {
+      const size_t nd = (size_t)S.NP * LS_TRIALS * (DET_W + 1);
+      if ((rc = dalloc(ctx, &S.det_de, nd))) return rc;
+      HIPCHK(hipMemset(S.det_de, 0, sizeof(det_word) * nd));
+    }
   }
   if (hipHostMalloc((void**)&ctx->h_cnt, 2 * sizeof(Counters)) != hipSuccess ||
       hipHostMalloc((void**)&ctx->h_ring, 4 * sizeof(Counters)) != hipSuccess ||
@@ -1539,6 +1568,10 @@ int abd_finalize(abd_ctx* ctx) {
     }
     if ((rc = dalloc(ctx, &S.lab_chunk, (size_t)ctx->np + 2))) return rc;
     if ((rc = plan_launches(ctx))) return rc;
+    if (ctx->P.deterministic && ctx->pcg_ranges.empty())
+      return fail(ctx, ABD_E_INVALID_ARG,
+                  "deterministic mode: a problem has more 16-body groups than the "
+                  "problem-local PCG holds resident");
   }
   {
     int dev = 0;
@@ -1770,6 +1803,8 @@ int abd_local_solve_static(abd_ctx* ctx, abd_stats* out) {
   HIPCHK(hipGetDevice(&dev));
   if (dev != ctx->device)
     return fail(ctx, ABD_E_INVALID_ARG, "the context's device is not current");
+  if (ctx->P.deterministic)
+    return fail(ctx, ABD_E_INVALID_ARG, "the static solve has no deterministic mode");
   unsigned char* base = (unsigned char*)g_scratch[ctx->device].load();
   if (!base) return fail(ctx, ABD_E_DEVICE, "static scratch not available");
   Scene& S = ctx->S;

@@ -34,7 +34,8 @@ def test_create_rejects_bad_parameters_before_device_use():
     for key, bad in (("dt", 0.0), ("dhat", -1.0), ("kappa", 0.0),
                      ("max_newton", 0), ("pcg_eta", 0.0),
                      ("newton_theta", -1.0), ("precision", 7),
-                     ("list_capacity", -1), ("mixed_switch", -1)):
+                     ("list_capacity", -1), ("mixed_switch", -1),
+                     ("deterministic", 2)):
         p = dict(base)
         p[key] = bad
         h = C.c_void_p()
