@@ -323,6 +323,10 @@ def main():
                          "baseline (the first timed steps)")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--no-run50", action="store_true")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="bit-reproducible solves (exact sums)")
+    ap.add_argument("--max-ls", type=int, default=None,
+                    help="line-search halvings (scene default if unset)")
     ap.add_argument("--run-steps", type=int, default=50)
     ap.add_argument("--breakdown-steps", type=int, default=3)
     ap.add_argument("--batch-scenes", type=int, default=64)
@@ -355,7 +359,12 @@ def main():
         if not a.quiet:
             print(*m, file=sys.stderr, flush=True)
 
-    sc = scenes.config(1, a.seed)
+    over = {}
+    if a.deterministic:
+        over["deterministic"] = 1
+    if a.max_ls is not None:
+        over["max_ls"] = a.max_ls
+    sc = scenes.config(1, a.seed, **over)
     log(f"scene: {len(sc.bodies)} bodies, {sc.n_vertices} verts, "
         f"{sc.n_triangles} tris")
     solver = abd.Solver(sc)

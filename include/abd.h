@@ -203,7 +203,8 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out);
  * runs on, held until the process ends) instead of the context's buffers,
  * at fixed maximum sizes: 32768 body pairs, 262144 chunk pairs, 524288
  * point-triangle and 524288 edge-edge candidates, 262144 point-ground
- * candidates and 262144 active pairs.  A solve whose lists would exceed a
+ * candidates, 262144 active pairs and 16384 pairs whose CCD continues in
+ * blocked steps.  A solve whose lists would exceed a
  * maximum stops with ABD_E_CAPACITY (abd_last_error names the list and
  * its maximum; q is the last accepted iterate, feasible like every
  * iterate) instead of growing them.  Passes are launched directly (no

@@ -47,7 +47,10 @@
 namespace {
 
 const double ACCD_S = 0.1;         /* ACCD: target gap fraction s */
-const int ACCD_MAX_IT = 100000;    /* ACCD: iteration cap (returns safe t) */
+const int ACCD_MAX_IT = 100000;    /* ACCD: distance evaluations cap (returns safe t) */
+const int ACCD_SERIAL_IT = 32;     /* ACCD: one-point steps before blocked steps */
+const int ACCD_BLOCK = 64;         /* ACCD: points per blocked step */
+const int LS_FLOOR_HALVINGS = 10;  /* line search at the energy's rounding floor */
 const double MOLLIFIER_EPS = 1e-3; /* eps_x = 1e-3 |ea_rest|^2 |eb_rest|^2 */
 
 /* ------------------------------------------------------------------ */
@@ -1175,14 +1178,43 @@ double accd(int kind, const double* x, const double* dx, double s,
   double t = 0.0;
   double tl = (1.0 - s) * d0 / lp;
   double xt[12];
-  for (int it = 0; it < ACCD_MAX_IT; ++it) {
+  double d = d0;
+  int it = 0;
+  for (; it < ACCD_SERIAL_IT; ++it) {
     double tn = t + tl;
     for (int i = 0; i < 12; ++i) xt[i] = x[i] + tn * r[i];
-    double d = pair_distance(kind, xt);
+    d = pair_distance(kind, xt);
     if (t > 0.0 && d < gap) return t;
     t = tn;
     if (t > tmax) return tmax;
     tl = 0.9 * d / lp;
+  }
+  /* then steps of ACCD_BLOCK points t + j delta that share the step
+   * length delta = 0.5 da / lp of their anchor (t, da): point j is
+   * reached when it keeps the gap and every point before it keeps the
+   * distance at least 0.6 da, so each accepted segment keeps
+   * d >= 0.6 da - lp delta = 0.1 da > 0 along it.  A pair that slides at a
+   * small distance, or closes it slowly, advances up to ACCD_BLOCK points
+   * per step (each point half the one-point step) */
+  double da = d;
+  for (; it < ACCD_MAX_IT; it += ACCD_BLOCK) {
+    const double delta = 0.5 * da / lp;
+    const double keep = 0.6 * da;
+    int J = 0;
+    double dJ = da;
+    for (int j = 1; j <= ACCD_BLOCK; ++j) {
+      const double tj = t + (double)j * delta;
+      for (int i = 0; i < 12; ++i) xt[i] = x[i] + tj * r[i];
+      const double dj = pair_distance(kind, xt);
+      if (dj < gap) break;
+      J = j;
+      dJ = dj;
+      if (dj < keep) break;
+    }
+    if (J == 0) return t;
+    t = t + (double)J * delta;
+    if (t > tmax) return tmax;
+    da = dJ;
   }
   return t;
 }
@@ -1744,6 +1776,14 @@ int orc_local_solve(orc_scene* s, orc_stats* st) {
     }
     S.min_alpha = std::min(S.min_alpha, alpha);
     for (size_t i = 0; i < q.size(); ++i) q[i] += alpha * dq[i];
+    /* a decrease that only a step halved more than LS_FLOOR_HALVINGS times
+     * finds, with eps within 10 theta, is rounding noise of the energy
+     * difference: the iterate is converged to the precision the energy
+     * resolves */
+    if (nh > LS_FLOOR_HALVINGS && eps < 10.0 * s->P.newton_theta) {
+      status = ORC_OK;
+      break;
+    }
   }
   for (size_t b = 0; b < s->B.size(); ++b)
     std::memcpy(s->B[b].q, &q[12 * b], 12 * sizeof(double));

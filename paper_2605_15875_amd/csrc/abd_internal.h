@@ -18,7 +18,9 @@
 
 #define ABD_CHUNK 64
 #define ACCD_S 0.1
-#define ACCD_MAX_IT 100000
+#define ACCD_MAX_IT 100000  /* distance evaluations of one pair's ACCD */
+#define ACCD_SERIAL_IT 32   /* one-point steps, by the pair's own lane */
+#define ACCD_BLOCK 64       /* then steps of 64 points, one wavefront per pair */
 #define MOLL_EPS 1e-3
 #define BOX_PAD_REL 1e-12
 
@@ -36,6 +38,7 @@ struct Counters {
   unsigned long long max_dq;    /* bits of a non-negative double */
   unsigned int bar;             /* grid barrier arrivals */
   int n_rows_used;
+  int n_long; /* swept block: pairs whose ACCD continues in blocked steps */
   int active; /* problems not done after a pass of the device loop */
   double pcg_rr, pcg_bb;
   /* swept block: the pass's lists are complete (no overflow in either
@@ -54,7 +57,9 @@ struct Counters {
    * the block-row build when it labels them, plan = 1): components of
    * DIR_MAX bodies or fewer solved directly (n_dir of 2 bodies or more),
    * bodies of larger components left to the PCG (n_big) */
-  int plan, n_dir, n_big, pad2_;
+  int plan, n_dir, n_big;
+  int stat_ran; /* static block: the pass had a problem in its Newton
+                   step, so these are the counters of its static phase */
 };
 
 /* largest component (bodies) solved directly (a dense elimination of up to
@@ -68,6 +73,10 @@ struct Counters {
  * one problem, a batch merges several */
 enum { PS_NEWTON = 0, PS_LINESEARCH = 1, PS_DONE = 2 };
 #define LS_TRIALS 8
+/* a step accepted after more than this many halvings while eps_N < 10
+ * theta ends the solve as converged (the line search at the rounding floor
+ * of the energy) */
+#define LS_FLOOR_HALVINGS 10
 /* per-group record of the problem-local PCG: the group's partial sums of
  * one phase for each of its (at most 16) problems, published with the
  * phase number as a flag */
@@ -164,6 +173,13 @@ __device__ __forceinline__ double det_value(const det_word* w) {
   return ldexp(r, -DET_FRAC);
 }
 
+/* a pair whose ACCD continues past its one-point steps: the anchor time
+ * and distance, its candidate index in the current lists, its problem */
+struct CcdLong {
+  double t, da;
+  int cand, prob;
+};
+
 struct Scene {
   int B, V, T, E, NC;
   /* parameters */
@@ -210,6 +226,8 @@ struct Scene {
   int *cand_pg; /* [cap] v */
   int4 *act;    /* active pairs (kind, i, j, slot) */
   int cap_bp, cap_cp, cap_pt, cap_ee, cap_pg, cap_act;
+  CcdLong *ccd_long; /* pairs of the swept lists in blocked ACCD steps */
+  int cap_long;
   /* system: gradient FP64; Hessian blocks, their inverses and the PCG
    * matvec in FP64 (mixed = 0) or FP32 (mixed = 1) */
   double *g;
@@ -770,14 +788,20 @@ __device__ __forceinline__ void orth_hessian_psd(const double* A, double* K) {
 /* bound (may be null): bits of a TOI another pair of the same problem has
  * already reached; once t passes it this pair cannot lower the minimum,
  * so the advance stops there and returns t (a lower bound of its TOI) */
-__device__ __forceinline__ double accd(int kind, const double* x, const double* dx,
-                              double tmax,
-                              const unsigned long long* bound = nullptr) {
+/* Additive CCD (R11) of a pair moving on x + t dx, t in [0, tmax]: the
+ * relative displacements r (each point's dx less the pair's mean), the
+ * bound lp on how fast the distance can shrink, then one-point steps
+ * (1 - s) d0 / lp and 0.9 d / lp while the gap s d0 holds.  Returns true
+ * with the time of impact bound in *t, or false after ACCD_SERIAL_IT steps
+ * with the anchor (*t, *da) from which the blocked steps continue (the
+ * second phase, a wavefront per pair).  bound: stop once t passes it (the
+ * problem's smallest TOI so far, which this pair can then no longer lower). */
+__device__ __forceinline__ void accd_setup(int kind, const double* dx, double* r,
+                                           double* lp) {
   double m[3];
 #pragma unroll
   for (int i = 0; i < 3; ++i)
     m[i] = 0.25 * (dx[i] + dx[3 + i] + dx[6 + i] + dx[9 + i]);
-  double r[12];
 #pragma unroll
   for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -785,30 +809,51 @@ __device__ __forceinline__ double accd(int kind, const double* x, const double* 
   double n[4];
 #pragma unroll
   for (int k = 0; k < 4; ++k) n[k] = sqrt(dot3(r + 3 * k, r + 3 * k));
-  double lp = (kind == C_PT) ? n[0] + fmax(n[1], fmax(n[2], n[3]))
-                             : fmax(n[0], n[1]) + fmax(n[2], n[3]);
-  if (lp == 0.0) return tmax;
+  *lp = (kind == C_PT) ? n[0] + fmax(n[1], fmax(n[2], n[3]))
+                       : fmax(n[0], n[1]) + fmax(n[2], n[3]);
+}
+__device__ __forceinline__ double bound_of(const unsigned long long* bound) {
+  return __longlong_as_double((long long)__hip_atomic_load(
+      bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+}
+__device__ __forceinline__ bool accd_begin(int kind, const double* x, const double* dx,
+                                           double tmax, const unsigned long long* bound,
+                                           double* t_out, double* da_out) {
+  double r[12], lp;
+  accd_setup(kind, dx, r, &lp);
+  *t_out = tmax;
+  if (lp == 0.0) return true;
   double d0 = pair_dist(kind, x);
-  if (!(d0 > 0.0)) return 0.0;
+  *t_out = 0.0;
+  if (!(d0 > 0.0)) return true;
   double gap = ACCD_S * d0;
   double t = 0.0;
   double tl = (1.0 - ACCD_S) * d0 / lp;
   double xt[12];
-  for (int it = 0; it < ACCD_MAX_IT; ++it) {
+  double d = d0;
+  for (int it = 0; it < ACCD_SERIAL_IT; ++it) {
     double tn = t + tl;
 #pragma unroll
     for (int i = 0; i < 12; ++i) xt[i] = x[i] + tn * r[i];
-    double d = pair_dist(kind, xt);
-    if (t > 0.0 && d < gap) return t;
+    d = pair_dist(kind, xt);
+    if (t > 0.0 && d < gap) {
+      *t_out = t;
+      return true;
+    }
     t = tn;
-    if (t > tmax) return tmax;
-    if (bound && (it & 3) == 3 &&
-        t >= __longlong_as_double((long long)__hip_atomic_load(
-                 bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)))
-      return t;
+    if (t > tmax) {
+      *t_out = tmax;
+      return true;
+    }
+    if (bound && (it & 3) == 3 && t >= bound_of(bound)) {
+      *t_out = t;
+      return true;
+    }
     tl = 0.9 * d / lp;
   }
-  return t;
+  *t_out = t; /* d: the distance at t */
+  *da_out = d;
+  return false;
 }
 
 /* ------------------------------------------------------------------ */

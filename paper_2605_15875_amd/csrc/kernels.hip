@@ -15,7 +15,7 @@
  *                                        (k_pcg_local, k_pcg, k_pcg1)
  *   Newton stop                          k_positions (swept, stop-test
  *                                        workgroups), k_dq_norm
- *   CCD step bound                       k_ccd (k_ccd_pairs: each pair's TOI)
+ *   CCD step bound                       k_ccd, k_ccd_long (blocked steps)
  *   line search energy                   k_energy_multi, k_energy, k_reduce
  *   device loop                          k_ctrl_start, k_update_multi
  */
@@ -807,6 +807,11 @@ __device__ __forceinline__ double pair_weight(const Scene& S, const int* vid,
 
 /* hoff_words: 8-byte words per off-diagonal block (144 FP64, 72 FP32) */
 __global__ void k_filter(Scene S, int hoff_words) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int ran = S.iter_mode == 0;
+    for (int q = 0; q < S.NP && !ran; ++q) ran = S.ps[q].state == PS_NEWTON;
+    S.cnt->stat_ran = ran;
+  }
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
@@ -3186,49 +3191,60 @@ __global__ void k_dq_norm(Scene S, int with_ctrl) {
 /* S9 CCD                                                              */
 /* ================================================================== */
 __device__ __forceinline__ void ctrl_first_trial(ProbState& P);
-/* with_ctrl: then the first trial step of every problem */
+/* a PT or EE candidate's points at q and their motion over dq */
+__device__ __forceinline__ int candidate_geom(const Scene& S, int t, int npt, double* x,
+                                              double* dx, int* prob) {
+  const int* c = t < npt ? S.cand_pt + 3 * t : S.cand_ee + 3 * (t - npt);
+  const int kind = t < npt ? C_PT : C_EE;
+  int vid[4];
+  pair_vertices(S, kind, c[0], c[1], vid);
+  for (int k = 0; k < 4; ++k) {
+    int v = vid[k], b = S.vbody[v];
+    double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
+    xform(S.q + 12 * b, b0, b1, b2, x + 3 * k);
+    xform(S.dq + 12 * b, b0, b1, b2, dx + 3 * k);
+  }
+  *prob = S.bprob[S.vbody[vid[0]]];
+  return kind;
+}
+
 /* TOI of candidate t of the list (PT, then EE, then PG), clamped to
  * [0, 1]; *prob receives its problem.  With use_bound the advance of a PT
  * or EE pair stops once it passes the smallest TOI its problem has reached
- * (a lower bound of the pair's TOI that cannot lower the minimum). */
-__device__ __forceinline__ double candidate_toi(const Scene& S, int t, int npt,
-                                                int nee, bool use_bound,
-                                                int* prob) {
-  double toi = 1.0;
+ * (a lower bound of the pair's TOI that cannot lower the minimum).  false:
+ * the pair's ACCD continues in blocked steps from the anchor (*toi, *da) */
+__device__ __forceinline__ bool candidate_toi(const Scene& S, int t, int npt, int nee,
+                                              bool use_bound, int* prob, double* toi,
+                                              double* da) {
+  *toi = 1.0;
   if (t < npt + nee) {
-    const int* c = t < npt ? S.cand_pt + 3 * t : S.cand_ee + 3 * (t - npt);
-    int kind = t < npt ? C_PT : C_EE;
-    int vid[4];
-    pair_vertices(S, kind, c[0], c[1], vid);
     double x[12], dx[12];
-    for (int k = 0; k < 4; ++k) {
-      int v = vid[k], b = S.vbody[v];
-      double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
-      xform(S.q + 12 * b, b0, b1, b2, x + 3 * k);
-      xform(S.dq + 12 * b, b0, b1, b2, dx + 3 * k);
-    }
-    *prob = S.bprob[S.vbody[vid[0]]];
-    toi = accd(kind, x, dx, 1.0, use_bound ? &S.ps[*prob].min_toi : nullptr);
+    const int kind = candidate_geom(S, t, npt, x, dx, prob);
+    if (!accd_begin(kind, x, dx, 1.0, use_bound ? &S.ps[*prob].min_toi : nullptr, toi, da))
+      return false;
   } else {
     int v = S.cand_pg[t - npt - nee], b = S.vbody[v];
     double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
     double x[3], dx[3];
     xform(S.q + 12 * b, b0, b1, b2, x);
     xform(S.dq + 12 * b, b0, b1, b2, dx);
-    if (dx[1] < 0.0) toi = (1.0 - ACCD_S) * (x[1] - S.ground_y) / (-dx[1]);
+    if (dx[1] < 0.0) *toi = (1.0 - ACCD_S) * (x[1] - S.ground_y) / (-dx[1]);
     *prob = S.bprob[b];
   }
-  return fmax(fmin(toi, 1.0), 0.0);
+  *toi = fmax(fmin(*toi, 1.0), 0.0);
+  return true;
 }
 
-__global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
+/* CCD of the swept candidates, first phase: a lane per candidate takes the
+ * one-point ACCD steps; a pair still advancing goes to the long list (a
+ * count beyond cap_long redoes the pass with a larger list).  toi_out:
+ * every candidate's own TOI (no early stop) for the hooks, else the
+ * problems' minima */
+__global__ __launch_bounds__(256) void k_ccd(Scene S, double* toi_out) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nee = min(S.cnt->n_ee, S.cap_ee);
   const int npg = min(S.cnt->n_pg, S.cap_pg);
   const int tot = npt + nee + npg;
-  /* workgroups with candidates (at least one, to run the controller) */
-  const unsigned nwork = max(1u, min(gridDim.x, (unsigned)((tot + 255) / 256)));
-  if (blockIdx.x >= nwork) return;
   double tmin = 1.0;
   const int lane = threadIdx.x & 63;
   /* whole workgroups step through the list together, so every lane of a
@@ -3236,8 +3252,18 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
   for (int base = blockIdx.x * blockDim.x; base < tot; base += gridDim.x * blockDim.x) {
     const int t = base + threadIdx.x;
     int prob = -1;
-    double toi = 1.0;
-    if (t < tot) toi = candidate_toi(S, t, npt, nee, true, &prob);
+    double toi = 1.0, da = 0.0;
+    bool fin = true;
+    if (t < tot) fin = candidate_toi(S, t, npt, nee, !toi_out, &prob, &toi, &da);
+    const int k = wave_slot(!fin, &S.cnt->n_long);
+    if (!fin) {
+      if (k < S.cap_long) S.ccd_long[k] = CcdLong{toi, da, t, prob};
+      toi = 1.0; /* the second phase takes the pair's TOI */
+    }
+    if (toi_out) {
+      if (t < tot && fin) toi_out[t] = toi;
+      continue;
+    }
     tmin = fmin(tmin, toi);
     /* the wavefront's smallest TOI below 1 of its first such lane's problem
      * with one atomic; lanes of other problems add theirs directly */
@@ -3257,22 +3283,65 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S, int with_ctrl) {
    * min(1, .)), which keeps empty waves off the shared counter */
   if ((threadIdx.x & 63) == 0 && tmin < 1.0)
     atomic_min_pos(&S.cnt->min_toi, fmax(tmin, 0.0));
-  if (with_ctrl && last_workgroup(&S.cnt->fin[1], nwork))
-    for (int q = threadIdx.x; q < S.NP; q += blockDim.x) ctrl_first_trial(S.ps[q]);
 }
 
-/* every candidate's own TOI, without the early stop (a test hook):
- * toi[t] for the t-th candidate of the list */
-__global__ __launch_bounds__(256) void k_ccd_pairs(Scene S, double* toi) {
+/* CCD, second phase: one wavefront per pair of the long list.  From the
+ * anchor (t, da) the lanes evaluate the points t + j delta, j = 1..64,
+ * delta = 0.5 da / lp; the step goes to the last point j such that every
+ * point up to j keeps the gap and every point before j keeps the distance
+ * at least 0.6 da (so the distance stays above 0.6 da - lp delta = 0.1 da
+ * along each segment), and the point reached is the next anchor.  A pair
+ * that slides at a small distance, or closes it slowly, advances up to 64
+ * half steps at once.  Then, in the last workgroup, the controller's first
+ * trial step (with_ctrl). */
+#define CCD_LONG_BLOCKS 256
+__global__ __launch_bounds__(256) void k_ccd_long(Scene S, int with_ctrl, double* toi_out) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
-  const int nee = min(S.cnt->n_ee, S.cap_ee);
-  const int npg = min(S.cnt->n_pg, S.cap_pg);
-  const int tot = npt + nee + npg;
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < tot;
-       t += gridDim.x * blockDim.x) {
+  const int nl = min(S.cnt->n_long, S.cap_long);
+  const int lane = threadIdx.x & 63;
+  const int nw = gridDim.x * (blockDim.x >> 6);
+  for (int w = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); w < nl; w += nw) {
+    const CcdLong L = S.ccd_long[w];
+    double x[12], dx[12], r[12], lp;
     int prob;
-    toi[t] = candidate_toi(S, t, npt, nee, false, &prob);
+    const int kind = candidate_geom(S, L.cand, npt, x, dx, &prob);
+    accd_setup(kind, dx, r, &lp);
+    const double gap = ACCD_S * pair_dist(kind, x);
+    double t = L.t, da = L.da;
+    for (int it = ACCD_SERIAL_IT; it < ACCD_MAX_IT; it += ACCD_BLOCK) {
+      const double delta = __ddiv_rn(__dmul_rn(0.5, da), lp);
+      const double keep = __dmul_rn(0.6, da);
+      const double tj = __dadd_rn(t, __dmul_rn((double)(lane + 1), delta));
+      double xt[12];
+#pragma unroll
+      for (int i = 0; i < 12; ++i) xt[i] = __dadd_rn(x[i], __dmul_rn(tj, r[i]));
+      const double d = pair_dist(kind, xt);
+      const unsigned long long fg = __ballot(d < gap), fc = __ballot(d < keep);
+      const int A = fg ? __ffsll((long long)fg) : ACCD_BLOCK + 1;
+      const int C = fc ? __ffsll((long long)fc) : ACCD_BLOCK;
+      const int J = min(A - 1, C);
+      if (J == 0) break;
+      const double dJ = __shfl(d, J - 1, 64);
+      t = __dadd_rn(t, __dmul_rn((double)J, delta));
+      if (t > 1.0) {
+        t = 1.0;
+        break;
+      }
+      da = dJ;
+      if (!toi_out && t >= bound_of(&S.ps[L.prob].min_toi)) break;
+    }
+    const double toi = fmax(fmin(t, 1.0), 0.0);
+    if (lane == 0) {
+      if (toi_out) {
+        toi_out[L.cand] = toi;
+      } else if (toi < 1.0) {
+        atomic_min_pos(&S.ps[L.prob].min_toi, toi);
+        atomic_min_pos(&S.cnt->min_toi, toi);
+      }
+    }
   }
+  if (with_ctrl && last_workgroup(&S.cnt->fin[1], gridDim.x))
+    for (int q = threadIdx.x; q < S.NP; q += blockDim.x) ctrl_first_trial(S.ps[q]);
 }
 
 /* ================================================================== */
@@ -3580,7 +3649,7 @@ __device__ __forceinline__ bool static_overflow(const Counters& c, const Scene& 
 }
 __device__ __forceinline__ bool swept_overflow(const Counters& c, const Scene& S) {
   return c.n_bp > S.cap_bp || c.n_cp > S.cap_cp || c.n_pt > S.cap_pt ||
-         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg;
+         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg || c.n_long > S.cap_long;
 }
 
 __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
@@ -3689,12 +3758,18 @@ __device__ __forceinline__ void ctrl_linesearch(const Scene& S, ProbState& P,
   while (k < LS_TRIALS && !(P.dE[k] <= 0.0)) ++k;
   if (k < LS_TRIALS && P.ls_count + k <= S.max_ls) {
     const double a = P.alpha_base * ldexp(1.0, -k);
+    const int nh = P.ls_count + k;
     P.alpha_acc = a;
-    P.halvings += P.ls_count + k;
+    P.halvings += nh;
     P.ls_count = 0;
     P.min_alpha = fmin(P.min_alpha, a);
     P.state = PS_NEWTON;
-    if (P.newton >= S.max_newton) {
+    if (nh > LS_FLOOR_HALVINGS && P.final_eps < 10.0 * S.theta) {
+      /* a decrease found only this deep, this close to the tolerance, is
+       * the rounding floor of the energy: converged with this step */
+      P.state = PS_DONE;
+      P.status = 0;
+    } else if (P.newton >= S.max_newton) {
       P.state = PS_DONE;
       P.status = -4;
     }
@@ -4152,11 +4227,14 @@ void launch_dq_norm(const Scene& S, int with_ctrl, hipStream_t st) {
   hipLaunchKernelGGL(k_dq_norm, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S, with_ctrl);
 }
 void launch_ccd(const Scene& S, int with_ctrl, hipStream_t st) {
-  hipLaunchKernelGGL(k_ccd, dim3(S.grid_blocks), dim3(256), 0, st, S, with_ctrl);
+  hipLaunchKernelGGL(k_ccd, dim3(S.grid_blocks), dim3(256), 0, st, S, (double*)nullptr);
+  hipLaunchKernelGGL(k_ccd_long, dim3(CCD_LONG_BLOCKS), dim3(256), 0, st, S, with_ctrl,
+                     (double*)nullptr);
 }
 void launch_ccd_pairs(const Scene& S, double* toi, int64_t n, hipStream_t st) {
   const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096));
-  hipLaunchKernelGGL(k_ccd_pairs, dim3(blocks), dim3(256), 0, st, S, toi);
+  hipLaunchKernelGGL(k_ccd, dim3(blocks), dim3(256), 0, st, S, toi);
+  hipLaunchKernelGGL(k_ccd_long, dim3(CCD_LONG_BLOCKS), dim3(256), 0, st, S, 0, toi);
 }
 void launch_energy(const Scene& S, double alpha, int mode_with_pairs,
                    int alpha_from_toi, double* out, hipStream_t st) {

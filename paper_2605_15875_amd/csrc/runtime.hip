@@ -92,6 +92,10 @@ struct abd_ctx {
   unsigned sh_version = 0;
   Scene S;
   Counters* h_cnt = nullptr; /* pinned */
+  /* the last static and swept counters of a device-loop pass that ran a
+   * Newton step (a pass that only continues a line search has no static
+   * phase): the list sizes a solve reports */
+  Counters h_last[2] = {};
   Counters* h_ring = nullptr; /* pinned [2][2]: counters of passes in flight */
   Counters* d_ring = nullptr; /* the same memory as the device sees it */
   unsigned* d_pass = nullptr; /* device pass counter (ring slot parity) */
@@ -466,23 +470,30 @@ double bits_to_double(unsigned long long b) {
   std::memcpy(&d, &b, 8);
   return d;
 }
+unsigned long long double_to_bits(double d) {
+  unsigned long long b;
+  std::memcpy(&b, &d, 8);
+  return b;
+}
 
 /* ---------------- capacities ---------------- */
 bool over_cap(const Scene& S, const Counters& c) {
   return c.n_bp > S.cap_bp || c.n_cp > S.cap_cp || c.n_pt > S.cap_pt ||
-         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg || c.n_act > S.cap_act;
+         c.n_ee > S.cap_ee || c.n_pg > S.cap_pg || c.n_act > S.cap_act ||
+         c.n_long > S.cap_long;
 }
 /* the list that outgrew the static scratch, as an error */
 int static_overflow_error(abd_ctx* ctx) {
   const Scene& S = ctx->S;
-  const char* names[6] = {"body pairs", "chunk pairs", "point-triangle candidates",
+  const char* names[7] = {"body pairs", "chunk pairs", "point-triangle candidates",
                           "edge-edge candidates", "point-ground candidates",
-                          "active pairs"};
-  const int caps[6] = {S.cap_bp, S.cap_cp, S.cap_pt, S.cap_ee, S.cap_pg, S.cap_act};
+                          "active pairs", "pairs in blocked CCD steps"};
+  const int caps[7] = {S.cap_bp, S.cap_cp, S.cap_pt, S.cap_ee, S.cap_pg, S.cap_act,
+                       S.cap_long};
   for (int b = 0; b < 2; ++b) {
     const Counters& c = ctx->h_cnt[b];
-    const int n[6] = {c.n_bp, c.n_cp, c.n_pt, c.n_ee, c.n_pg, c.n_act};
-    for (int i = 0; i < 6; ++i)
+    const int n[7] = {c.n_bp, c.n_cp, c.n_pt, c.n_ee, c.n_pg, c.n_act, c.n_long};
+    for (int i = 0; i < 7; ++i)
       if (n[i] > caps[i])
         return fail(ctx, ABD_E_CAPACITY,
                     std::string("static scratch: ") + std::to_string(n[i]) + " " +
@@ -550,6 +561,14 @@ int grow(abd_ctx* ctx, const Counters& c, bool* changed) {
     dfree(ctx, S.act);
     S.cap_act = (int)std::min<long>(2L * c.n_act + 1024, 1L << 30);
     if ((rc = dalloc(ctx, &S.act, S.cap_act))) return rc;
+    *changed = true;
+  }
+  /* the long CCD list holds every PT and EE candidate (its own overflow
+   * is only possible with caller-fixed capacities) */
+  if (S.cap_long < S.cap_pt + S.cap_ee || need(S.cap_long, c.n_long)) {
+    dfree(ctx, S.ccd_long);
+    S.cap_long = std::max(S.cap_pt + S.cap_ee, 2 * c.n_long + 1024);
+    if ((rc = dalloc(ctx, &S.ccd_long, S.cap_long))) return rc;
     *changed = true;
   }
   return ABD_OK;
@@ -1033,6 +1052,9 @@ int device_solve(abd_ctx* ctx) {
     ~TimedAgain() { c->pcg_timed_now = true; }
   } timed_again{ctx};
   launch_ctrl_start(ctx->S, ctx->st);
+  ctx->h_last[0] = Counters{};
+  ctx->h_last[1] = Counters{};
+  ctx->h_last[0].min_dist = double_to_bits(INFINITY);
   const int max_pass =
       ctx->P.max_newton * (2 + (ctx->P.max_ls + LS_TRIALS) / LS_TRIALS) + 8;
   int queued = 0;
@@ -1064,6 +1086,10 @@ int device_solve(abd_ctx* ctx) {
     const Counters* c = ctx->h_ring + 2 * (k & 1);
     ctx->h_cnt[0] = c[0];
     ctx->h_cnt[1] = c[1];
+    if (c[0].stat_ran) {
+      ctx->h_last[0] = c[0];
+      ctx->h_last[1] = c[1];
+    }
     resolve_timing(ctx);
     if (c[0].err || c[1].err) {
       HIPCHK(hipStreamSynchronize(ctx->st));
@@ -1422,6 +1448,8 @@ int abd_finalize(abd_ctx* ctx) {
   if ((rc = dalloc(ctx, &S.cand_ee, 3L * S.cap_ee))) return rc;
   if ((rc = dalloc(ctx, &S.cand_pg, S.cap_pg))) return rc;
   if ((rc = dalloc(ctx, &S.act, S.cap_act))) return rc;
+  S.cap_long = S.cap_pt + S.cap_ee;
+  if ((rc = dalloc(ctx, &S.ccd_long, S.cap_long))) return rc;
   if ((rc = dalloc(ctx, &S.g, 12L * B))) return rc;
   S.mixed = ctx->P.precision == ABD_MIXED;
   if ((rc = dalloc_bytes(ctx, &S.Hdiag, 144L * B * HESS_ALLOC))) return rc;
@@ -1762,7 +1790,7 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
     if (status == ABD_E_NOCONV) ctx->err = "Newton did not converge";
     if (status == ABD_E_LINESEARCH) ctx->err = "line search exhausted";
   }
-  const Counters& c = ctx->h_cnt[0];
+  const Counters& c = ctx->h_last[0];
   st.newton_iters = P.newton;
   st.newton_fp32 = P.newton32;
   st.pcg_iters_total = P.pcg_total;
@@ -1775,8 +1803,8 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
   st.n_active = c.n_act;
   st.n_body_pairs = c.n_bp;
   st.n_chunk_pairs = c.n_cp;
-  st.n_body_pairs_swept = ctx->h_cnt[1].n_bp;
-  st.n_chunk_pairs_swept = ctx->h_cnt[1].n_cp;
+  st.n_body_pairs_swept = ctx->h_last[1].n_bp;
+  st.n_chunk_pairs_swept = ctx->h_last[1].n_cp;
   st.min_dist = bits_to_double(c.min_dist);
   st.status = status;
   st.t_solve_ms =
@@ -1794,6 +1822,7 @@ int abd_local_solve(abd_ctx* ctx, abd_stats* out) {
 #define ABD_STATIC_EE (512 << 10)
 #define ABD_STATIC_PG (256 << 10)
 #define ABD_STATIC_ACT (256 << 10)
+#define ABD_STATIC_LONG (16 << 10)
 
 int abd_local_solve_static(abd_ctx* ctx, abd_stats* out) {
   int rc = check_ctx(ctx, true);
@@ -1834,6 +1863,8 @@ int abd_local_solve_static(abd_ctx* ctx, abd_stats* out) {
   L.cand_ee = (int*)take(3 * sizeof(int) * (size_t)L.cap_ee);
   L.cand_pg = (int*)take(sizeof(int) * (size_t)L.cap_pg);
   L.act = (int4*)take(sizeof(int4) * (size_t)L.cap_act);
+  L.cap_long = ABD_STATIC_LONG;
+  L.ccd_long = (CcdLong*)take(sizeof(CcdLong) * (size_t)L.cap_long);
   if (off > ABD_SCRATCH_BYTES)
     return fail(ctx, ABD_E_DEVICE, "static scratch layout exceeds the array");
   /* swap the context's lists for the scratch ones for this call: direct
@@ -1859,6 +1890,8 @@ int abd_local_solve_static(abd_ctx* ctx, abd_stats* out) {
   S.cand_ee = saved.cand_ee;
   S.cand_pg = saved.cand_pg;
   S.act = saved.act;
+  S.ccd_long = saved.ccd_long;
+  S.cap_long = saved.cap_long;
   S.cap_bp = saved.cap_bp;
   S.cap_col = saved.cap_col;
   S.cap_cp = saved.cap_cp;
@@ -2148,6 +2181,7 @@ int toi_in_export_order(abd_ctx* ctx, double* d_toi, int64_t npt, int64_t nee,
                         int64_t npg, double* toi) {
   const Scene& S = ctx->S;
   const int64_t n = npt + nee + npg;
+  HIPCHK(hipMemsetAsync(&S.cnt[1].n_long, 0, sizeof(int), ctx->st));
   launch_ccd_pairs(swept_scene(ctx), d_toi, n, ctx->st);
   std::vector<double> t(n);
   std::vector<int> pt(3 * npt), ee(3 * nee), pg(npg);
@@ -2381,7 +2415,7 @@ int abd_batch_run(abd_batch* bt, abd_stats* out) {
       st.final_eps_N = P[i].final_eps;
       st.min_alpha = P[i].min_alpha;
       st.scene_scale = bt->h_scales[i];
-      st.min_dist = bits_to_double(M->h_cnt[0].min_dist);
+      st.min_dist = bits_to_double(M->h_last[0].min_dist);
       st.t_solve_ms = ms;
       st.fp64_fallback = fell_back ? 1 : 0;
     }

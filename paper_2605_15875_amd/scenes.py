@@ -465,12 +465,7 @@ def batch_workload(seed: int = 0, subdomains=BATCH_SUBDOMAINS,
     size (icospheres and hulls, each a worker's local problem with its
     shared bodies; sub_args: further subdomain_scene arguments) followed
     by independent scenes of stacked cubes, all with the same parameters
-    (over).  At most 20 line-search halvings: in the subdomains' contact
-    piles the energy differences of FP64 positions in a 10 m scene are
-    resolved to about 1e-12, so a line search that still finds no
-    decrease after 20 halvings has reached that floor (and ends the solve
-    as converged when eps_N < 10 theta)."""
-    over = {"max_ls": 20, **over}
+    (over)."""
     sa = dict(sub_args or {})
     out = [subdomain_scene(seed * 1000 + i, n, **sa, **over)
            for i, n in enumerate(subdomains)]

@@ -279,3 +279,29 @@ def test_eps_N_of_one_free_fall_iteration():
     want = np.abs(h * qd[:3] + h * h * g).max() / (h * l)
     assert st["final_eps_N"] == pytest.approx(want, rel=1e-10)
     assert st["newton_iters"] == 1
+
+
+def test_accd_of_a_pair_sliding_into_contact():
+    # a point 1e-4 above a wide triangle in y = 0 that slides 2 along x while
+    # closing the gap at 2e-4 per unit t: first contact at t = 0.5 (x = 0.5,
+    # inside the triangle).  The one-point steps of ACCD shrink the distance
+    # by 1e-4 of itself each, so this pair runs well past the one-point
+    # phase; its blocked steps must stay below the contact, end within the
+    # gap rule's last tenth of the distance, and need far fewer distance
+    # evaluations than the cap
+    d0 = 1e-4
+    x = np.array([-0.5, d0, 0.0, -1.0, 0.0, -1.0, 3.0, 0.0, -1.0, -1.0, 0.0, 3.0])
+    dx = np.zeros(12)
+    dx[0:3] = [2.0, -2.0 * d0, 0.0]
+    toi = O.exact_toi(O.PT, x, dx)
+    assert toi == pytest.approx(0.5, rel=1e-12)
+    t = O.accd(O.PT, x, dx, 0.1, 1.0)
+    assert t <= toi
+    # the gap rule stops once the distance would drop below 0.1 d0, whose
+    # time is 0.45; the last accepted point lies beyond the previous one
+    assert 0.44 < t < 0.5
+    # sliding at a constant distance over the triangle: no contact, the
+    # blocked steps reach the end of the step
+    dx[0:3] = [2.0, 0.0, 0.0]
+    x[0] = -0.9
+    assert O.accd(O.PT, x, dx, 0.1, 1.0) == 1.0
