@@ -3294,7 +3294,7 @@ __global__ __launch_bounds__(256) void k_ccd(Scene S, double* toi_out) {
  * that slides at a small distance, or closes it slowly, advances up to 64
  * half steps at once.  Then, in the last workgroup, the controller's first
  * trial step (with_ctrl). */
-#define CCD_LONG_BLOCKS 256
+#define CCD_LONG_BLOCKS 64
 __global__ __launch_bounds__(256) void k_ccd_long(Scene S, int with_ctrl, double* toi_out) {
   const int npt = min(S.cnt->n_pt, S.cap_pt);
   const int nl = min(S.cnt->n_long, S.cap_long);
