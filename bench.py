@@ -49,11 +49,11 @@ PMC_TRAFFIC = {
     "kernel": "k_assemble<double>",
     "section": ("/* S5 barrier: narrow phase filter and assembly",
                 "/* S7 block-Jacobi PCG"),
-    "fetch_kib": 534.9,        # FETCH_SIZE per dispatch, 91 dispatches
-    "write_kib": 322.5,        # WRITE_SIZE per dispatch, 91 dispatches
-    "fetch_per_byte": 131086.8 / 262144.0,  # copy of 256 MiB reads 0.5
+    "fetch_kib": 545.0,        # FETCH_SIZE per dispatch, 91 dispatches
+    "write_kib": 322.6,        # WRITE_SIZE per dispatch, 91 dispatches
+    "fetch_per_byte": 131085.25 / 262144.0,  # copy of 256 MiB reads 0.5
     "write_per_byte": 262144.0 / 262144.0,  # copy of 256 MiB writes 1.0
-    "sha256": "d55596f7f60f4056bc4efb87b041b418004bc119c98304d462fb6cb7f6074d86",
+    "sha256": "7a406879269d5a3a01a65443534b88e49a5df6a73ba6f172b5c27a8cf71daa93",
 }
 
 METRIC = ("local Newton iters/s at ~1M tris; mixed vs FP64 speedup at 1e-6 "
@@ -333,6 +333,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-batch-workload", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-workload-only", action="store_true",
+                    help="only the batch workload leg (its JSON on stdout)")
     ap.add_argument("--pcg-variant", type=int, default=None)
     ap.add_argument("--autotune", action="store_true",
                     help="run the library autotuner after warmup")
@@ -358,6 +360,11 @@ def main():
     def log(*m):
         if not a.quiet:
             print(*m, file=sys.stderr, flush=True)
+
+    if a.batch_workload_only:
+        print(json.dumps(bench_batch_workload(abd, scenes, torch, a.batch_steps, log)),
+              flush=True)
+        return
 
     over = {}
     if a.deterministic:
