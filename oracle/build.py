@@ -16,6 +16,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB = os.path.join(HERE, "liboracle.so")
 LIB_OMP = os.path.join(HERE, "liboracle_omp.so")
+LIB_SAN = os.path.join(HERE, "liboracle_san.so")
 
 
 def build(verbose: bool = False) -> str:
@@ -31,6 +32,26 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(verbose: bool = False) -> str:
+    """liboracle_san.so: the single-threaded oracle with AddressSanitizer
+    and UndefinedBehaviorSanitizer (any undefined-behaviour report aborts);
+    load it with the sanitizer runtime preloaded (LD_PRELOAD of libasan)
+    and ORACLE_LIB pointing at it."""
+    src = os.path.join(HERE, "abd_oracle.cpp")
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-ffp-contract=off",
+           "-fno-fast-math", "-fPIC", "-shared", "-Wall",
+           "-Wno-unused-function", "-Wno-unknown-pragmas",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+           "-fno-omit-frame-pointer", src, "-o", LIB_SAN + ".tmp"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.check_call(cmd)
+    os.replace(LIB_SAN + ".tmp", LIB_SAN)
+    return LIB_SAN
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    if "--sanitize" in sys.argv:
+        build_sanitized(verbose=True)
     sys.exit(0)

@@ -12,7 +12,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liboracle.so")
+# ORACLE_LIB: another build of the single-threaded library (the sanitized
+# one of build.build_sanitized)
+LIB_PATH = os.environ.get("ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 LIB_OMP_PATH = os.path.join(HERE, "liboracle_omp.so")
 
 PT, EE, PG = 0, 1, 2

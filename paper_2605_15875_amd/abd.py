@@ -11,7 +11,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libabd.so")
+# ABD_LIB: another build of the library (libabd_san.so, the host-code
+# sanitizer build); the HIP library is required either way
+LIB_PATH = os.environ.get("ABD_LIB") or os.path.join(HERE, "libabd.so")
 
 OK = 0
 E_INVALID_ARG, E_MESH, E_INFEASIBLE, E_NOCONV = -1, -2, -3, -4

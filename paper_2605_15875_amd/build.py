@@ -24,30 +24,45 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Wno-unused-result"]
 
 
-def _compile(src):
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# host-code sanitizer for libabd_san.so: UndefinedBehaviorSanitizer on the
+# host pass only (the GPU code is built as in libabd.so).  The clang
+# AddressSanitizer runtime intercepts the HSA memory-pool allocator and
+# fails its first device allocation with the ROCm runtime of this image,
+# so the host runtime runs under UBSan only
+SAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=undefined", "-Xarch_host",
+             "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+LIB_SAN = os.path.join(HERE, "libabd_san.so")
+
+
+def _compile(src, san=False):
+    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ("_san.o" if san else ".o"))
+    cmd = [HIPCC, *FLAGS, *(SAN_FLAGS if san else []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """libabd.so, or (sanitize) libabd_san.so with UndefinedBehaviorSanitizer
+    on the host code (run with the clang UBSan runtime preloaded and ABD_LIB
+    pointing at it)."""
     os.makedirs(BUILD, exist_ok=True)
     with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    out = LIB_SAN if sanitize else LIB
+    tmp = out + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv)
     sys.exit(0)
