@@ -345,8 +345,10 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out);
 /* Solve Eq. 5 for every problem of the batch in one device loop: the
  * current q, q^t, q-tilde, qdot, scene scale and shared-body data of each
  * context are gathered in, every Newton pass runs all problems in the same
- * kernel launches (replayed from captured graphs), and the solutions are
- * scattered back to the contexts.  out: [n] stats (may be NULL).  Returns
+ * kernel launches (direct launches, or replayed from captured graphs when
+ * the first context's tuning sets use_graphs; the batch takes that
+ * context's tuning), and the solutions are scattered back to the
+ * contexts.  out: [n] stats (may be NULL).  Returns
  * ABD_OK or the first non-OK problem status. */
 int abd_batch_run(abd_batch* batch, abd_stats* out);
 

@@ -255,6 +255,7 @@ struct Scene {
    * the labels per chunk of whole problems, bodies [lab_chunk[c],
    * lab_chunk[c + 1]) of n_lab_chunks (0: no labels) */
   int *lab_chunk;
+  int *chunk_tot; /* [n_lab_chunks] block-row entries of each chunk */
   int n_lab_chunks, bsr_one;
   /* PCG work */
   double *r, *zv, *p0, *p1, *Ap, *acc; /* acc: [4][4] ring of dots */

@@ -1765,17 +1765,107 @@ __global__ void k_bsr_fill(Scene S) {
   }
 }
 
-/* component labels of scenes whose block rows are built by the three
- * kernels: one workgroup per chunk of whole problems (at most BSR_LDS_ROWS
- * bodies, lab_chunk) */
-__global__ __launch_bounds__(1024) void k_components(Scene S) {
+/* block rows (and component labels) of scenes above one workgroup's LDS,
+ * one workgroup per chunk of whole problems (bodies [lab_chunk[c],
+ * lab_chunk[c + 1]), at most BSR_LDS_ROWS; no used block joins two
+ * chunks).  First the counts of the chunk's rows by LDS atomics, their
+ * exclusive scan into row_ptr relative to the chunk, and the chunk's
+ * total; then (k_bsr_chunk_fill) the chunk's offset, the sum of the totals
+ * before it, the fill through LDS cursors, and the labels. */
+__device__ int block_scan_1024(int* cnt, int n, int* wsum, int* row_out, int base) {
+  /* exclusive scan of cnt[0..n) by 1024 threads (runs of ceil(n/1024) per
+   * thread, then the wavefront and workgroup prefix); row_out[i] = base +
+   * prefix, cnt[i] = the same; returns the total (valid in every thread) */
+  const int per = (n + blockDim.x - 1) / blockDim.x;
+  const int lo = threadIdx.x * per, hi = min(n, lo + per);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += cnt[i];
+  int tot;
+  const int ex = wave_prefix(s, &tot);
+  if (lane == 0) wsum[wave] = tot;
+  __syncthreads();
+  int acc = ex, all = 0;
+  for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+    if (w < wave) acc += wsum[w];
+    all += wsum[w];
+  }
+  for (int i = lo; i < hi; ++i) {
+    const int c = cnt[i];
+    cnt[i] = base + acc;
+    row_out[i] = base + acc;
+    acc += c;
+  }
+  return all;
+}
+__global__ __launch_bounds__(1024) void k_bsr_chunk_count(Scene S) {
+  __shared__ int cnt[BSR_LDS_ROWS + 1];
+  __shared__ int wsum[16];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    /* the component labels that follow add their counts */
+    S.cnt->n_dir = 0;
+    S.cnt->n_big = 0;
+    S.cnt->plan = 0;
+  }
+  const int c0 = S.lab_chunk[blockIdx.x], n = S.lab_chunk[blockIdx.x + 1] - c0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) cnt[i] = 0;
+  __syncthreads();
+  const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
+    if (!S.slot_used[p]) continue;
+    const int2 ab = S.bp[p];
+    if (ab.x < c0 || ab.x >= c0 + n) continue;
+    atomicAdd(&cnt[ab.x - c0], 1);
+    atomicAdd(&cnt[ab.y - c0], 1);
+  }
+  __syncthreads();
+  const int tot = block_scan_1024(cnt, n, wsum, S.row_ptr + c0, 0);
+  if (threadIdx.x == 0) S.chunk_tot[blockIdx.x] = tot;
+}
+__global__ __launch_bounds__(1024) void k_bsr_chunk_fill(Scene S) {
   __shared__ int cnt[BSR_LDS_ROWS + 1];
   __shared__ int par[BSR_LDS_ROWS];
   __shared__ int cur[DIR_SLOTS];
   __shared__ int sh[4];
-  const int c0 = S.lab_chunk[blockIdx.x];
-  const int n = S.lab_chunk[blockIdx.x + 1] - c0;
+  __shared__ int s_base;
+  const int c0 = S.lab_chunk[blockIdx.x], n = S.lab_chunk[blockIdx.x + 1] - c0;
+  if (threadIdx.x == 0) {
+    int b = 0;
+    for (int c = 0; c < (int)blockIdx.x; ++c) b += S.chunk_tot[c];
+    s_base = b;
+    if (blockIdx.x + 1 == gridDim.x) {
+      S.row_ptr[S.B] = b + S.chunk_tot[blockIdx.x];
+      S.cnt->n_rows_used = b + S.chunk_tot[blockIdx.x];
+    }
+  }
+  __syncthreads();
+  const int base = s_base;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int r = S.row_ptr[c0 + i] + base;
+    S.row_ptr[c0 + i] = r;
+    cnt[i] = r; /* the fill cursor of the row */
+  }
+  __syncthreads();
   const int nbp = min(S.cnt->n_bp, S.cap_bp);
+  for (int p = threadIdx.x; p < nbp; p += blockDim.x) {
+    if (!S.slot_used[p]) continue;
+    const int2 ab = S.bp[p];
+    if (ab.x < c0 || ab.x >= c0 + n) continue;
+    int k = atomicAdd(&cnt[ab.x - c0], 1);
+    if (k < S.cap_col) {
+      S.col_slot[k] = p; S.col_body[k] = ab.y; S.col_trans[k] = 0;
+    }
+    k = atomicAdd(&cnt[ab.y - c0], 1);
+    if (k < S.cap_col) {
+      S.col_slot[k] = p; S.col_body[k] = ab.x; S.col_trans[k] = 1;
+    }
+  }
+  if (S.det) {
+    __syncthreads(); /* the fill's global writes, for the sort */
+    sort_block_rows(S, c0 + threadIdx.x, c0 + n, blockDim.x);
+  }
+  if (!S.comp_solve) return;
+  __syncthreads();
   label_components(S, c0, n, nbp, par, cnt, cur, sh, false);
 }
 
@@ -4162,12 +4252,15 @@ void launch_bsr(const Scene& S, hipStream_t st) {
     hipLaunchKernelGGL(k_bsr_small, dim3(1), dim3(1024), 0, st, S);
     return;
   }
+  if (S.n_lab_chunks > 0) {
+    hipLaunchKernelGGL(k_bsr_chunk_count, dim3(S.n_lab_chunks), dim3(1024), 0, st, S);
+    hipLaunchKernelGGL(k_bsr_chunk_fill, dim3(S.n_lab_chunks), dim3(1024), 0, st, S);
+    return;
+  }
   hipLaunchKernelGGL(k_bsr_count, dim3(256), dim3(256), 0, st, S);
   hipLaunchKernelGGL(k_bsr_scan, dim3(1), dim3(1024), 0, st, S);
   hipLaunchKernelGGL(k_bsr_fill, dim3(256), dim3(256), 0, st, S);
   if (S.det) hipLaunchKernelGGL(k_sort_rows, dim3(cdiv(S.B, 256)), dim3(256), 0, st, S);
-  if (S.comp_solve)
-    hipLaunchKernelGGL(k_components, dim3(S.n_lab_chunks), dim3(1024), 0, st, S);
 }
 void launch_block_inverse(const Scene& S, hipStream_t st) {
   if (S.mixed)

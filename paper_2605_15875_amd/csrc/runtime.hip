@@ -144,6 +144,7 @@ struct abd_ctx {
    * pcg_grid groups; empty when a problem's groups exceed that */
   std::vector<std::pair<int, int>> pcg_ranges;
   std::vector<int> hb0, hb1; /* first and last body of each problem */
+  std::vector<char> padding;  /* [B] bodies a batch adds to align problems */
   /* timing */
   int timing = 0;      /* ABD_TIMING_* */
   bool capturing = false;
@@ -1504,8 +1505,8 @@ int abd_finalize(abd_ctx* ctx) {
         if (pi != p) continue;
         if (kind[i] == ABD_DYNAMIC)
           dyn.push_back(i);
-        else
-          stat.push_back(i);
+        else if (i >= (int)ctx->padding.size() || !ctx->padding[i])
+          stat.push_back(i); /* padding bodies are far from every other */
       }
       doff[p + 1] = (int)dyn.size();
       soff[p + 1] = (int)stat.size();
@@ -1595,6 +1596,7 @@ int abd_finalize(abd_ctx* ctx) {
       ctx->hb1[p] = std::max(ctx->hb1[p], i);
     }
     if ((rc = dalloc(ctx, &S.lab_chunk, (size_t)ctx->np + 2))) return rc;
+    if ((rc = dalloc(ctx, &S.chunk_tot, (size_t)ctx->np + 2))) return rc;
     if ((rc = plan_launches(ctx))) return rc;
     if (ctx->P.deterministic && ctx->pcg_ranges.empty())
       return fail(ctx, ABD_E_INVALID_ARG,
@@ -2334,6 +2336,8 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out) {
       rc = abd_add_body(M, tv, 3, tt, 1, 1000.0, qg, nullptr, ABD_STATIC, &id);
       if (rc) { abd_batch_destroy(bt); return rc; }
       M->prob_of_body.push_back(i);
+      M->padding.resize(M->prob_of_body.size(), 0);
+      M->padding.back() = 1;
       ++off;
     }
     bt->max_nb = std::max(bt->max_nb, B);
