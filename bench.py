@@ -331,7 +331,9 @@ def main():
     ap.add_argument("--breakdown-steps", type=int, default=3)
     ap.add_argument("--batch-scenes", type=int, default=64)
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-batch-workload", action="store_true")
+    ap.add_argument("--batch-workload", action="store_true",
+                    help="also run the batch workload leg (72 problems, "
+                         "6.8M triangles; off by default)")
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--batch-workload-only", action="store_true",
                     help="only the batch workload leg (its JSON on stdout)")
@@ -493,7 +495,7 @@ def main():
         batch = bench_batch(abd, scenes, torch, a.batch_scenes, 5, 1)
         log(f"batch: {batch}")
     batch_wl = None
-    if not a.no_batch_workload:
+    if a.batch_workload:
         batch_wl = bench_batch_workload(abd, scenes, torch, a.batch_steps, log)
     out = {
         "metric": METRIC,

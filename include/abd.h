@@ -281,7 +281,8 @@ typedef struct abd_tuning {
                               CCD kernels (default 1024) */
   int32_t assemble_blocks; /* blocks of the barrier assembly (default 2048) */
   int32_t use_graphs;      /* replay Newton passes from captured graphs (1)
-                              or launch their kernels directly (0, default) */
+                              or launch their kernels directly (0, default);
+                              batches always launch directly */
   int32_t overlap_body;    /* body terms on a second stream, overlapping the
                               broad phase (1), or in line (0, default) */
   int32_t pcg_coop;        /* reserved, must be 0 (INVALID_ARG otherwise):
@@ -345,10 +346,9 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out);
 /* Solve Eq. 5 for every problem of the batch in one device loop: the
  * current q, q^t, q-tilde, qdot, scene scale and shared-body data of each
  * context are gathered in, every Newton pass runs all problems in the same
- * kernel launches (direct launches, or replayed from captured graphs when
- * the first context's tuning sets use_graphs; the batch takes that
- * context's tuning), and the solutions are scattered back to the
- * contexts.  out: [n] stats (may be NULL).  Returns
+ * kernel launches (direct launches; the batch takes the first context's
+ * tuning except use_graphs, which it ignores), and the solutions are
+ * scattered back to the contexts.  out: [n] stats (may be NULL).  Returns
  * ABD_OK or the first non-OK problem status. */
 int abd_batch_run(abd_batch* batch, abd_stats* out);
 

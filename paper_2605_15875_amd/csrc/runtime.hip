@@ -2342,7 +2342,11 @@ int abd_batch_create(abd_ctx** ctxs, int32_t n, abd_batch** out) {
     }
     bt->max_nb = std::max(bt->max_nb, B);
   }
-  if ((rc = abd_finalize(M)) || (rc = abd_set_tuning(M, &ctxs[0]->tune))) {
+  /* the first context's tuning, with direct launches: batch passes are
+   * never replayed from captured graphs */
+  abd_tuning tune = ctxs[0]->tune;
+  tune.use_graphs = 0;
+  if ((rc = abd_finalize(M)) || (rc = abd_set_tuning(M, &tune))) {
     abd_batch_destroy(bt);
     return rc;
   }
