@@ -633,13 +633,6 @@ __host__ __device__ constexpr int sidx(int p, int q) {
 /* off-diagonal mass below tol2 of the total (1e-30 in FP64, 1e-12 in   */
 /* FP32, i.e. about the square of each precision)                       */
 /* ------------------------------------------------------------------ */
-template <typename T> struct JacobiTol;
-template <> struct JacobiTol<double> {
-  static constexpr double tol2 = 1e-30;
-};
-template <> struct JacobiTol<float> {
-  static constexpr float tol2 = 1e-12f;
-};
 __device__ __forceinline__ double rsq(double x) { return rsqrt(x); }
 __device__ __forceinline__ float rsq(float x) { return rsqrtf(x); }
 
@@ -663,6 +656,13 @@ __device__ __forceinline__ double rsq_nr(double x) {
   }
   return y;
 }
+/* one Newton step: relative error about 1e-14 */
+__device__ __forceinline__ double rsq_nr1(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x * y;
+  return __fma_rn(-h, y * y, 1.5 * y);
+}
+__device__ __forceinline__ float rsq_nr1(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ float rcp_nr(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ float rsq_nr(float x) { return __builtin_amdgcn_rsqf(x); }
 

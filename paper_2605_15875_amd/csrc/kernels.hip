@@ -1099,160 +1099,146 @@ __device__ __forceinline__ void pair_frame_derivs(const Scene& S, int kind, int 
  * T = H_y W_Y, then the body-space gradient and 12x12 blocks W_X^T T,
  * accumulated with FP64 atomics into g, Hdiag and Hoff. */
 #define PAIRS_PER_WG 16
-/* PSD projection of a symmetric 9x9 matrix by cyclic Jacobi with the
- * rotations of a sweep run in parallel: one matrix per group of 32 lanes,
- * lane r (< 9) holding row r of the matrix and lane 16 + r row r of the
- * accumulated rotation V, so that one column update serves both.  A sweep
- * has nine rounds; round k pairs index a with (2k - a) mod 9 (the
- * round-robin order, index k rests), so each round's four rotations touch
- * disjoint rows and columns and commute, and every pair is visited once
- * per sweep.  Each rotation is the serial step: the tangent
- * t = sgn(a) b / (|a| + hypot(a, b)) with a = aqq - app, b = 2 apq,
- * c = 1 / sqrt(1 + t^2), s = t c, columns then rows, and the annihilated
- * 2x2 block set to (app - t apq, aqq + t apq, 0).  The lane of the lower
- * index of a pair computes its rotation and shares it through LDS.
- * Rotations whose apq^2 is below 1/36 of the stopping bound are skipped; a
- * sweep starts only while the mass of the upper triangle (rounding leaves
- * the two triangles slightly different) exceeds tol2 of the total.  The
- * result, V max(D,0) V^T, replaces row r in place (matrix lanes). */
-template <typename T>
-struct JacX {
-  T row[9][10]; /* rows of the matrix between rounds */
-  T vrow[9][9]; /* rows of V at the end */
-  T lam[9];     /* max(D, 0) */
-  T cs[9][6];   /* rotation of the pair led by each index: c s t app aqq apq */
+/* PSD projection of a symmetric 9x9 matrix K by one-sided (Hestenes)
+ * Jacobi on the shifted matrix A = K' + mu I, where K' = 2^-e K with 2^e
+ * the power of two at or above the largest |K| entry (exact scaling) and
+ * mu = 2 |K'|_F, so that A is symmetric positive definite with eigenvalues
+ * in [|K'|_F, 3 |K'|_F].  One matrix per group of 16 lanes, lane j (< 9)
+ * holding column j of A.  A sweep has nine rounds; round k pairs index a
+ * with (2k - a) mod 9 (the round-robin order, index k rests), so every pair
+ * of columns meets once per sweep.  The two lanes of a pair swap columns
+ * (cross-lane reads, no LDS) and form, in the same order, the same dot
+ * products al = a_p.a_p, be = a_q.a_q, ga = a_p.a_q and the same rotation
+ * making the two columns orthogonal: t = sgn(be - al) 2ga /
+ * (|be - al| + hypot(be - al, 2ga)), c = 1 / sqrt(1 + t^2), s = t c
+ * (evaluated with two reciprocal square roots of one Newton step each),
+ * a_p <- c a_p - s a_q, a_q <- s a_p + c a_q.  A rotation is applied while
+ * ga^2 > rot2 al be; a group stops after a sweep in which every pair had
+ * ga^2 <= stop2 al be, independently of the other groups of the wavefront
+ * (a projection does not depend on the matrices sharing its wavefront).
+ * The columns are then A's eigenvectors scaled by its eigenvalues
+ * sigma_j = |a_j| (A's condition number is at most 3, so the accumulated
+ * rotation is not needed), K''s eigenvalues are sigma_j - mu, and
+ * K+ = 2^e sum_j max(sigma_j - mu, 0) / sigma_j^2 a_j a_j^T, whose row r
+ * replaces k on lane r.  Per round: one exchange of nine values and a
+ * short chain (three dot products, two reciprocal square roots). */
+template <typename T> struct OsjTol;
+template <> struct OsjTol<double> {
+  static constexpr double rot2 = 1e-28, stop2 = 1e-22;
+};
+template <> struct OsjTol<float> {
+  static constexpr float rot2 = 1e-12f, stop2 = 1.6e-11f;
 };
 template <typename T>
-__device__ __forceinline__ void psd9_par(JacX<T>& X, int g, bool on, T* k) {
-  constexpr T tol2 = JacobiTol<T>::tol2;
-  const bool is_k = g < 16;
-  const int r = is_k ? g : g - 16;
-  const bool kon = on && is_k && r < 9; /* a row of the matrix */
-  const bool von = on && !is_k && r < 9; /* a row of V */
-  T x[9];
+struct OsjX {
+  T col[4][9][9]; /* the converged columns of each group */
+  T w[4][9];      /* max(sigma - mu, 0) / sigma^2 */
+};
+__device__ __forceinline__ double scale2(double x, int e) { return ldexp(x, e); }
+__device__ __forceinline__ float scale2(float x, int e) { return ldexpf(x, e); }
+__device__ __forceinline__ int exp2_above(double x) {
+  int e;
+  (void)frexp(x, &e);
+  return e;
+}
+__device__ __forceinline__ int exp2_above(float x) {
+  int e;
+  (void)frexpf(x, &e);
+  return e;
+}
+template <typename T>
+__device__ __forceinline__ void psd9_osj(OsjX<T>& X, int g, bool on, T* k) {
+  constexpr T rot2 = OsjTol<T>::rot2, stop2 = OsjTol<T>::stop2;
+  const int lane = __lane_id();
+  const int base = lane & ~15, grp = lane >> 4;
+  const bool mine = on && g < 9; /* a column of the matrix */
+  /* exact power-of-two scaling by the group's largest entry */
+  T mx = T(0);
 #pragma unroll
-  for (int m = 0; m < 9; ++m) x[m] = kon ? k[m] : ((m == r) ? T(1) : T(0));
-  if (kon) {
+  for (int m = 0; m < 9; ++m) mx = fmax(mx, mine ? fabs(k[m]) : T(0));
 #pragma unroll
-    for (int m = 0; m < 9; ++m) X.row[r][m] = x[m];
+  for (int o = 8; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o, 16));
+  const int e = mx > T(0) ? exp2_above(mx) : 0;
+  T a[9];
+  T ss = T(0);
+#pragma unroll
+  for (int m = 0; m < 9; ++m) {
+    a[m] = mine ? scale2(k[m], -e) : T(0);
+    ss += a[m] * a[m];
   }
-  wave_lds_sync();
-  for (int sweep = 0; sweep < 60; ++sweep) {
-    T fro = 0, offs = 0;
 #pragma unroll
-    for (int m = 0; m < 9; ++m) {
-      const T v = kon ? x[m] : T(0);
-      fro += v * v;
-      offs += (m > r) ? v * v : T(0);
-    }
+  for (int o = 8; o > 0; o >>= 1) ss += __shfl_xor(ss, o, 16);
+  const T mu = ss > T(0) ? T(2) * (ss * rsq_nr(ss)) : T(0);
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-      fro += __shfl_xor(fro, o, 16);
-      offs += __shfl_xor(offs, o, 16);
-    }
-    /* a sweep that skips all 36 rotations leaves the upper triangle under
-     * the bound (the V lanes only follow).  The two matrices of the
-     * wavefront stop independently: a group whose matrix is done keeps it
-     * unchanged while the other sweeps on, so each projection is the same
-     * whichever pair shares its wavefront */
-    const bool done = !kon || offs == T(0) || offs <= tol2 * fro;
-    const unsigned long long bal = __ballot(done);
-    if (bal == ~0ull) break;
-    const unsigned long long gm = (__lane_id() & 32) ? 0xffffffff00000000ull
-                                                     : 0x00000000ffffffffull;
-    const bool gact = (bal & gm) != gm;
-    const bool kact = kon && gact;
-    const T skip2 = tol2 * T(1.0 / 36.0) * fro;
-#pragma unroll
+  for (int m = 0; m < 9; ++m)
+    if (m == g) a[m] += mu;
+  /* group-uniform: a group without a matrix, or with K = 0, is done */
+  bool gdone = !on || !(mu > T(0));
+  for (int sweep = 0; sweep < 30; ++sweep) {
+    if (__ballot(!gdone) == 0ull) break;
+    bool big = false;
+#pragma unroll 1
     for (int kr = 0; kr < 9; ++kr) {
-      const int pr = (2 * kr + 18 - r) % 9; /* partner of row r */
-      /* the pair's leading lane: its rotation */
-      if (kact && r < pr) {
-        const T app = X.row[r][r], aqq = X.row[pr][pr], apq = X.row[r][pr];
-        T c = T(1), sn = T(0), t = T(0);
-        if (apq * apq > skip2) {
-          const T aa = aqq - app, bb = T(2) * apq;
+      const int q = g < 9 ? (2 * kr + 18 - g) % 9 : g;
+      T b[9];
+#pragma unroll
+      for (int m = 0; m < 9; ++m) b[m] = __shfl(a[m], base + q, 64);
+      if (!gdone && mine && q != g) {
+        const bool lo = g < q;
+        /* own = a.a, oth = b.b, ga = a.b: the partner lane forms the same
+         * three sums in the same order (its own is this lane's oth) */
+        T own = T(0), oth = T(0), ga = T(0);
+#pragma unroll
+        for (int m = 0; m < 9; ++m) {
+          own = fma(a[m], a[m], own);
+          oth = fma(b[m], b[m], oth);
+          ga = fma(a[m], b[m], ga);
+        }
+        const T al = lo ? own : oth, be = lo ? oth : own;
+        const T g2 = ga * ga, ab = al * be;
+        big = big || g2 > stop2 * ab;
+        if (g2 > rot2 * ab) {
+          /* with r = hypot(aa, bb) and u = |aa| + r: t = sgn(aa) bb / u,
+           * 1 + t^2 = 2 r u / u^2, so c = u / sqrt(2 r u) and
+           * s = sgn(aa) bb / sqrt(2 r u); one Newton step on each
+           * reciprocal square root leaves c^2 + s^2 within about 1e-14 of
+           * 1 (the columns' scale drifts by about that per rotation) */
+          const T aa = be - al, bb = T(2) * ga;
           const T h2 = aa * aa + bb * bb;
-          t = bb * rcp_nr(fabs(aa) + h2 * rsq_nr(h2));
-          t = aa < T(0) ? -t : t;
-          c = rsq_nr(t * t + T(1));
-          sn = t * c;
+          const T r = h2 * rsq_nr1(h2);
+          const T u = fabs(aa) + r;
+          const T y = rsq_nr1(T(2) * r * u);
+          const T c = u * y;
+          const T sn = (aa < T(0) ? -bb : bb) * y;
+          /* a_p <- c a_p - s a_q on the lane of p, a_q <- c a_q + s a_p */
+          const T sl = lo ? -sn : sn;
+#pragma unroll
+          for (int m = 0; m < 9; ++m) a[m] = fma(c, a[m], sl * b[m]);
         }
-        X.cs[r][0] = c; X.cs[r][1] = sn; X.cs[r][2] = t;
-        X.cs[r][3] = app; X.cs[r][4] = aqq; X.cs[r][5] = apq;
-      }
-      wave_lds_sync();
-      T c4[4], s4[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const int a = (kr + i + 1) % 9, b = (kr + 8 - i) % 9;
-        const int p = a < b ? a : b;
-        c4[i] = X.cs[p][0];
-        s4[i] = X.cs[p][1];
-      }
-      /* columns: K J on the matrix lanes, V J on the V lanes */
-      T x1[9];
-#pragma unroll
-      for (int m = 0; m < 9; ++m) {
-        const int pm = (2 * kr + 9 - m) % 9;
-        if (pm == m) {
-          x1[m] = x[m];
-          continue;
-        }
-        /* the pair of column m: m = kr +- (i + 1) mod 9 */
-        const int d = (m + 9 - kr) % 9;
-        const int i = (d <= 4 ? d : 9 - d) - 1;
-        const T sg = m < pm ? -s4[i] : s4[i];
-        x1[m] = c4[i] * x[m] + sg * x[pm];
-      }
-      if (kact) {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) X.row[r][m] = x1[m];
-      }
-      wave_lds_sync();
-      /* rows of the matrix: J^T (K J), with the partner row from LDS; the
-       * annihilated 2x2 block is then written into the row in LDS */
-      const int lead = r < pr ? r : pr;
-      const T c = X.cs[lead][0], sn = X.cs[lead][1];
-      const bool rot = kact && pr != r && sn != T(0);
-      if (rot) {
-        const T sg = r < pr ? -sn : sn;
-#pragma unroll
-        for (int m = 0; m < 9; ++m) x[m] = c * x1[m] + sg * X.row[pr][m];
-      }
-      wave_lds_sync();
-      if (rot) {
-        const T t = X.cs[lead][2], app = X.cs[lead][3], aqq = X.cs[lead][4],
-                apq = X.cs[lead][5];
-#pragma unroll
-        for (int m = 0; m < 9; ++m) X.row[r][m] = x[m];
-        X.row[r][r] = r < pr ? app - t * apq : aqq + t * apq;
-        X.row[r][pr] = T(0);
-      }
-      wave_lds_sync();
-      if (kon) {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) x[m] = X.row[r][m];
-      } else if (gact) {
-#pragma unroll
-        for (int m = 0; m < 9; ++m) x[m] = x1[m];
       }
     }
+    const unsigned long long gm = 0xFFFFull << base;
+    if ((__ballot(big) & gm) == 0ull) gdone = true;
   }
-  /* V max(D, 0) V^T, row r */
-  if (kon) X.lam[r] = fmax(X.row[r][r], T(0));
-  if (von) {
+  /* K+ row by row from the converged columns */
+  if (mine) {
+    T s2 = T(0);
 #pragma unroll
-    for (int m = 0; m < 9; ++m) X.vrow[r][m] = x[m];
+    for (int m = 0; m < 9; ++m) s2 += a[m] * a[m];
+    const T sig = s2 * rsq_nr(s2);
+    const T lam = sig - mu;
+    X.w[grp][g] = lam > T(0) ? lam * rcp_nr(s2) : T(0);
+#pragma unroll
+    for (int m = 0; m < 9; ++m) X.col[grp][g][m] = a[m];
   }
   wave_lds_sync();
-  if (kon) {
+  if (mine) {
 #pragma unroll
     for (int m = 0; m < 9; ++m) {
-      T acc = 0;
+      T acc = T(0);
 #pragma unroll
-      for (int j = 0; j < 9; ++j) acc += X.vrow[r][j] * X.lam[j] * X.vrow[m][j];
-      k[m] = acc;
+      for (int j = 0; j < 9; ++j) acc += X.w[grp][j] * X.col[grp][j][g] * X.col[grp][j][m];
+      k[m] = scale2(acc, e);
     }
   }
   wave_lds_sync();
@@ -1264,7 +1250,7 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
   __shared__ double GW[33 * 64]; /* rows 0..8 g_y, 9..20 W_A, 21..32 W_B */
   __shared__ HT TB[216];
   __shared__ int meta[3 * 64];
-  __shared__ JacX<HT> JX[2];         /* Jacobi exchange, one per lane group */
+  __shared__ OsjX<HT> JX;            /* converged Jacobi columns */
   __shared__ HT IG[9 * 64];         /* inverse frame scales of each pair */
   __shared__ unsigned char proj[64]; /* the pair's 9x9 needs the projection */
   const int lane = threadIdx.x;
@@ -1353,16 +1339,16 @@ __global__ __launch_bounds__(64) void k_assemble(Scene S) {
     meta[128 + lane] = slot;
     __syncthreads();
     const int npairs = min(ppw, nact - base);
-    /* PSD projection of the PT/EE frame Hessians, two pairs at a time */
-    for (int j0 = 0; j0 < npairs; j0 += 2) {
-      const int j = j0 + lane / 32, g = lane % 32, r = g;
+    /* PSD projection of the PT/EE frame Hessians, four pairs at a time */
+    for (int j0 = 0; j0 < npairs; j0 += 4) {
+      const int j = j0 + lane / 16, g = lane % 16, r = g;
       const bool on = j < npairs && proj[j];
       const bool kon = on && g < 9; /* the lanes holding the matrix rows */
       HT k[9];
 #pragma unroll
       for (int m = 0; m < 9; ++m) k[m] = kon ? KL[sidx(r, m) * 64 + j] : HT(0);
       __syncthreads();
-      psd9_par<HT>(JX[lane / 32], g, on, k);
+      psd9_osj<HT>(JX, g, on, k);
       if (kon) {
         const HT ir = IG[r * 64 + j];
 #pragma unroll
