@@ -49,11 +49,11 @@ PMC_TRAFFIC = {
     "kernel": "k_assemble<double>",
     "section": ("/* S5 barrier: narrow phase filter and assembly",
                 "/* S7 block-Jacobi PCG"),
-    "fetch_kib": 545.0,        # FETCH_SIZE per dispatch, 91 dispatches
-    "write_kib": 322.6,        # WRITE_SIZE per dispatch, 91 dispatches
-    "fetch_per_byte": 131085.25 / 262144.0,  # copy of 256 MiB reads 0.5
+    "fetch_kib": 441.96,       # FETCH_SIZE per dispatch, 91 dispatches
+    "write_kib": 322.5,        # WRITE_SIZE per dispatch, 91 dispatches
+    "fetch_per_byte": 131086.77 / 262144.0,  # copy of 256 MiB reads 0.5
     "write_per_byte": 262144.0 / 262144.0,  # copy of 256 MiB writes 1.0
-    "sha256": "7a406879269d5a3a01a65443534b88e49a5df6a73ba6f172b5c27a8cf71daa93",
+    "sha256": "c147b8b6b6ae0f2818e3e3d1a71e5e8307c04fc8cd784f95831cf938f27f5506",
 }
 
 METRIC = ("local Newton iters/s at ~1M tris; mixed vs FP64 speedup at 1e-6 "
