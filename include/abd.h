@@ -278,7 +278,7 @@ typedef struct abd_tuning {
                               each per pass; 0 = one block per 16 bodies up to
                               the co-resident limit */
   int32_t grid_blocks;     /* blocks of the grid-stride broad-phase, filter and
-                              CCD kernels (default 1024) */
+                              CCD kernels (default 2048) */
   int32_t assemble_blocks; /* blocks of the barrier assembly (default 2048) */
   int32_t use_graphs;      /* replay Newton passes from captured graphs (1)
                               or launch their kernels directly (0, default);

@@ -137,7 +137,7 @@ struct abd_ctx {
   /* direct launches by default: on the benchmark scene a replayed graph
    * per pass costs more at each graph boundary than the pass's kernel
    * launches do (the host queues passes ahead either way) */
-  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 1024, 2048, 0, 0, 0, ABD_BODY_PAIRS_AUTO, 0, 0};
+  abd_tuning tune = {ABD_PCG_LOCAL1, 0, 2048, 2048, 0, 0, 0, ABD_BODY_PAIRS_AUTO, 0, 0};
   long bp_tests = 0; /* box tests of every pair of each problem */
   /* problem-local PCG forms: launches of consecutive 16-body groups
    * (first group, count), each holding whole problems and at most
@@ -2794,7 +2794,7 @@ int abd_autotune(abd_ctx* ctx, abd_tuning* out) {
       consider(t);
     }
   const abd_tuning after_pcg = best;
-  for (int g : {256, 512, 2048, 4096}) {
+  for (int g : {512, 1024, 2048, 4096}) {
     abd_tuning t = after_pcg;
     t.grid_blocks = g;
     if (g != orig.grid_blocks) consider(t);
