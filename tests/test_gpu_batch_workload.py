@@ -11,6 +11,8 @@ scenes of 16-512 cubes, 6.8M triangles, the launch configuration the
 benchmark times): two batched steps, every problem converged and
 penetration free, and sampled problems against the oracle from the same
 state."""
+import time
+
 import numpy as np
 import pytest
 
@@ -133,7 +135,12 @@ def test_full_batch_workload():
                     r.set_shared(scs[i].shared_ids, z, scs[i].shared_u,
                                  scs[i].shared_rho, scs[i].shared_kappa)
                 refs[i] = r
+        t0 = time.perf_counter()
         stats = bt.local_solve()
+        ms = (time.perf_counter() - t0) * 1e3
+        print(f"batched step {step}: {ms:.1f} ms, "
+              f"{sum(st['newton_iters'] for st in stats)} Newton iterations "
+              f"over {len(stats)} problems", flush=True)
         assert all(st["status"] == 0 for st in stats), step
         if step == 1:
             for i in sample:
