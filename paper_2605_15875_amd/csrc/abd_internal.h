@@ -262,10 +262,6 @@ struct Scene {
   double *pw; /* single-reduction PCG: [5][12B] w, m0, m1, t0, t1 */
   PcgRec *pcg_rec;         /* [2][groups] problem-local PCG records */
   int *prob_b0, *prob_b1;  /* [NP] first and last body of each problem */
-  /* world positions of the current broad phase, [3][V] each: xw at q,
-   * xw1 at q + dq (swept phase); written by k_positions with the canonical
-   * transform, read by the primitive tests and the distance filter */
-  double *xw, *xw1;
   /* reductions */
   double *partials; /* [cap_partials] */
   int cap_partials;
@@ -880,9 +876,11 @@ void launch_body_terms(const Scene& S, hipStream_t st, const Counters* fresh = n
 /* the pass reset of the device loop alone */
 void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
                        hipStream_t st);
-void launch_positions(const Scene& S, int swept, hipStream_t st,
-                      const Counters* fresh = nullptr, int expect_reuse = 0,
-                      int stop_test = 0);
+/* chunk and body boxes of a broad phase (with stop_test, the Newton stop
+ * test in extra workgroups) */
+void launch_boxes(const Scene& S, int swept, hipStream_t st,
+                  const Counters* fresh = nullptr, int expect_reuse = 0,
+                  int stop_test = 0);
 void launch_body_pairs(const Scene& S, hipStream_t st);
 void launch_chunk_pairs(const Scene& S, hipStream_t st);
 void launch_prim_pairs(const Scene& S, int swept, hipStream_t st);

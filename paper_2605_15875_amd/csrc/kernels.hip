@@ -4,8 +4,8 @@
  *   prediction of Eq. 1 and commit      k_predict, k_commit
  *   body terms (inertia, orthogonality,  k_body_terms
  *   ADMM penalty of Eq. 5)
- *   broad phase                          k_positions (positions, chunk and
- *                                        body boxes), k_sap_sort and
+ *   broad phase                          k_boxes (chunk and body boxes),
+ *                                        k_body_pairs or k_sap_sort and
  *                                        k_sap_sweep (body pairs),
  *                                        k_chunk_pairs, k_prim_pairs, k_pg
  *   barrier (narrow phase + assembly)    k_filter, k_assemble
@@ -13,7 +13,7 @@
  *                                        labels), k_block_inverse, k_direct,
  *                                        block-Jacobi PCG k_pcg_cg1
  *                                        (k_pcg_local, k_pcg, k_pcg1)
- *   Newton stop                          k_positions (swept, stop-test
+ *   Newton stop                          k_boxes (swept, stop-test
  *                                        workgroups), k_dq_norm
  *   CCD step bound                       k_ccd, k_ccd_long (blocked steps)
  *   line search energy                   k_energy_multi, k_energy, k_reduce
@@ -587,71 +587,64 @@ __global__ __launch_bounds__(256) void k_chunk_pairs(Scene S) {
   }
 }
 
-/* world positions for the broad phase: x at q, and x + dx at q + dq for
- * the swept phase (the same canonical transforms as every other kernel) */
+/* First kernel of a broad phase: the chunk and body boxes of the phase
+ * (conservative images of the rest boxes under the bodies' maps, one
+ * thread each).  The primitive tests transform their vertices themselves
+ * (vert_box).  With stop_test, the workgroups from nmain on run the Newton
+ * stop test of the device loop (|dq|_inf per problem, then the controller
+ * in the last of them).  reset_mode as for the body terms; swept < 0: the
+ * reset only. */
 __device__ void newton_stop_test(const Scene& S, Counters* c0, int blk, int nblk);
-/* reset_mode as for the body terms; swept < 0: the reset only.  Threads
- * past the vertices compute the chunk and body boxes of the phase (from
- * the rest boxes, independent of the positions).  With stop_test, the
- * workgroups from nmain on run the Newton stop test of the device loop
- * (|dq|_inf per problem, then the controller in the last of them); the
- * swept positions of a problem that stops here are not used. */
-__global__ void k_positions(Scene S, int swept, Counters fresh, int reset_mode,
-                            int stop_test, int nmain) {
+__global__ void k_boxes(Scene S, int swept, Counters fresh, int reset_mode,
+                        int stop_test, int nmain) {
   if (stop_test && (int)blockIdx.x >= nmain) {
     /* this scene's counters are the swept block; the static one precedes */
     newton_stop_test(S, S.cnt - 1, blockIdx.x - nmain, gridDim.x - nmain);
     return;
   }
-  const int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (reset_mode) pass_reset(S, fresh, reset_mode == 2, v, gridDim.x * blockDim.x);
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (reset_mode) pass_reset(S, fresh, reset_mode == 2, t, gridDim.x * blockDim.x);
   if (swept < 0) return;
-  if (v >= S.V) {
-    if (!S.cnt->reuse) chunk_or_body_box(S, swept, v - S.V);
-    return;
-  }
-  if (!body_in_pass(S, S.vbody[v])) return;
-  double x[3], x1[3];
-  if (swept) {
-    vertex_pos_swept(S, v, x, x1);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) S.xw1[k * S.V + v] = x1[k];
-  } else {
-    vertex_pos(S, v, x);
-  }
-#pragma unroll
-  for (int k = 0; k < 3; ++k) S.xw[k * S.V + v] = x[k];
+  if (!S.cnt->reuse) chunk_or_body_box(S, swept, t);
 }
 
-/* exact box of one primitive (static, or swept over the step) from the
- * positions of the current phase */
-__device__ __forceinline__ void vert_box(const Scene& S, int v, int swept,
-                                         double* box) {
+/* exact box of one vertex of a body, static at q or swept over
+ * [q, q + dq]: its positions by the canonical transform of every other
+ * kernel (vertex_pos, vertex_pos_swept) from the body's qb and db */
+__device__ __forceinline__ void vert_box(const Scene& S, int v, const double* qb,
+                                         const double* db, int swept, double* box) {
+  const double b0 = S.xbar[v], b1 = S.xbar[S.V + v], b2 = S.xbar[2 * S.V + v];
+  double x[3];
+  xform(qb, b0, b1, b2, x);
   if (swept) {
+    double dx[3];
+    xform(db, b0, b1, b2, dx);
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      const double a = S.xw[k * S.V + v], b = S.xw1[k * S.V + v];
-      box[k] = fmin(a, b);
-      box[3 + k] = fmax(a, b);
+      const double x1 = __dadd_rn(x[k], dx[k]);
+      box[k] = fmin(x[k], x1);
+      box[3 + k] = fmax(x[k], x1);
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < 3; ++k) box[k] = box[3 + k] = S.xw[k * S.V + v];
+    for (int k = 0; k < 3; ++k) box[k] = box[3 + k] = x[k];
   }
 }
+/* exact box of one primitive of a body (a chunk's primitives share it) */
 __device__ __forceinline__ void prim_box(const Scene& S, int kind, int id,
+                                         const double* qb, const double* db,
                                          int swept, double* box) {
   if (kind == K_VERT) {
-    vert_box(S, id, swept, box);
+    vert_box(S, id, qb, db, swept, box);
     return;
   }
   int n = kind == K_TRI ? 3 : 2;
   const int* ids = kind == K_TRI ? S.tri : S.edge;
   int stride = kind == K_TRI ? S.T : S.E;
-  vert_box(S, ids[id], swept, box);
+  vert_box(S, ids[id], qb, db, swept, box);
   for (int j = 1; j < n; ++j) {
     double b2[6];
-    vert_box(S, ids[j * stride + id], swept, b2);
+    vert_box(S, ids[j * stride + id], qb, db, swept, b2);
     for (int k = 0; k < 3; ++k) {
       box[k] = fmin(box[k], b2[k]);
       box[3 + k] = fmax(box[3 + k], b2[3 + k]);
@@ -677,22 +670,28 @@ __global__ __launch_bounds__(256) void k_prim_pairs(Scene S, int swept) {
   /* every wavefront works through its own chunk pairs */
   for (int c = blockIdx.x * 4 + wave; c < ncp; c += gridDim.x * 4) {
     const int4 cp = S.cp[c];
-    const int P = cp.y, Q = cp.z;
+    /* uniform over the wavefront: the chunks' data in scalar loads */
+    const int P = __builtin_amdgcn_readfirstlane(cp.y);
+    const int Q = __builtin_amdgcn_readfirstlane(cp.z);
     const int kindP = cp.x == C_PT ? K_VERT : K_EDGE;
     const int kindQ = cp.x == C_PT ? K_TRI : K_EDGE;
     const int nP = S.ch_count[P];
     const int nQ = S.ch_count[Q];
+    /* every primitive of a chunk belongs to the chunk's body */
+    const int bP = S.ch_body[P], bQ = S.ch_body[Q];
+    const double *qP = S.q + 12 * bP, *dP = S.dq + 12 * bP;
+    const double *qQ = S.q + 12 * bQ, *dQ = S.dq + 12 * bQ;
     /* both sides' primitives are loaded together (independent gathers) */
     bool keep = false, mine = false;
     int id = 0, pid = 0;
     double qb[6], box[6];
     if (lane < nQ) {
       id = S.ch_prims[S.ch_start[Q] + lane];
-      prim_box(S, kindQ, id, swept, qb);
+      prim_box(S, kindQ, id, qQ, dQ, swept, qb);
     }
     if (lane < nP) {
       pid = S.ch_prims[S.ch_start[P] + lane];
-      prim_box(S, kindP, pid, swept, box);
+      prim_box(S, kindP, pid, qP, dP, swept, box);
     }
     if (lane < nQ) keep = box_overlap(qb, S.ch_box + 6 * P, S.dhat);
     if (lane < nP) mine = box_overlap(box, S.ch_box + 6 * Q, S.dhat);
@@ -767,8 +766,9 @@ __global__ void k_pg(Scene S, int swept) {
     int v = 0;
     if (lane < S.ch_count[c]) {
       v = S.ch_prims[S.ch_start[c] + lane];
+      const int b = S.ch_body[c];
       double box[6];
-      vert_box(S, v, swept, box);
+      vert_box(S, v, S.q + 12 * b, S.dq + 12 * b, swept, box);
       ok = box[1] <= top;
     }
     const int k = wave_slot(ok, &S.cnt->n_pg);
@@ -4130,16 +4130,16 @@ void launch_body_terms(const Scene& S, hipStream_t st, const Counters* fresh,
 void launch_pass_reset(const Scene& S, const Counters& fresh, int expect_reuse,
                        hipStream_t st) {
   const long n = std::max<long>(std::max<long>(S.B + 1, S.NP), 2L * ((S.B + 15) / 16));
-  hipLaunchKernelGGL(k_positions, dim3(cdiv(n, 256)), dim3(256), 0, st, S, -1, fresh,
+  hipLaunchKernelGGL(k_boxes, dim3(cdiv(n, 256)), dim3(256), 0, st, S, -1, fresh,
                      expect_reuse ? 2 : 1, 0, 0);
 }
-void launch_positions(const Scene& S, int swept, hipStream_t st,
-                      const Counters* fresh, int expect_reuse, int stop_test) {
+void launch_boxes(const Scene& S, int swept, hipStream_t st,
+                  const Counters* fresh, int expect_reuse, int stop_test) {
   const Counters f = fresh ? *fresh : Counters{};
   const int mode = fresh ? (expect_reuse ? 2 : 1) : 0;
-  const unsigned nmain = cdiv((long)S.V + S.NC + S.B, 256);
+  const unsigned nmain = std::max(1u, cdiv((long)S.NC + S.B, 256));
   const unsigned g = nmain + (stop_test ? cdiv(S.B, 256) : 0u);
-  hipLaunchKernelGGL(k_positions, dim3(g), dim3(256), 0, st, S, swept, f, mode, stop_test,
+  hipLaunchKernelGGL(k_boxes, dim3(g), dim3(256), 0, st, S, swept, f, mode, stop_test,
                      (int)nmain);
 }
 void launch_body_pairs(const Scene& S, hipStream_t st) {

@@ -586,7 +586,7 @@ int sap_on(const abd_ctx* ctx) {
 /* ---------------- phases ---------------- */
 void broad_phase(abd_ctx* ctx, const Scene& S, int swept, int stop_test = 0) {
   StageTimer t(ctx, 1);
-  launch_positions(S, swept, ctx->st, nullptr, 0, stop_test);
+  launch_boxes(S, swept, ctx->st, nullptr, 0, stop_test);
   launch_body_pairs(S, ctx->st);
   launch_chunk_pairs(S, ctx->st);
   launch_prim_pairs(S, swept, ctx->st);
@@ -1551,8 +1551,6 @@ int abd_finalize(abd_ctx* ctx) {
     if (tiles.empty()) tiles.push_back(make_int2(0, 0));
     if ((rc = upload(ctx, &S.bp_tiles, tiles))) return rc;
   }
-  if ((rc = dalloc(ctx, &S.xw, 3L * S.V))) return rc;
-  if ((rc = dalloc(ctx, &S.xw1, 3L * S.V))) return rc;
   S.grid_blocks = ctx->tune.grid_blocks;
   S.assemble_blocks = ctx->tune.assemble_blocks;
   if ((rc = dalloc(ctx, &S.partials, S.cap_partials))) return rc;
