@@ -54,7 +54,10 @@ def test_oracle_under_address_and_undefined_behaviour_sanitizers():
         pytest.skip("no libasan for g++")
     from oracle import build
     lib = build.build_sanitized()
-    env = dict(os.environ, LD_PRELOAD=asan, ORACLE_LIB=lib,
+    # the sanitizer runtime goes first; whatever the environment already
+    # preloads stays preloaded after it
+    pre = os.environ.get("LD_PRELOAD", "")
+    env = dict(os.environ, LD_PRELOAD=asan + (":" + pre if pre else ""), ORACLE_LIB=lib,
                ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
                PYTHONPATH=ROOT)
