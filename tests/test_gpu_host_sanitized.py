@@ -64,10 +64,10 @@ def test_host_runtime_under_ubsan():
                           "libclang_rt.ubsan_standalone-x86_64.so"))
     if not rt:
         pytest.skip("no UBSan runtime")
-    # the UBSan runtime is added in front of whatever the environment
-    # already preloads, which stays preloaded
+    # the UBSan runtime is added after whatever the environment already
+    # preloads, which stays preloaded as it is
     pre = os.environ.get("LD_PRELOAD", "")
-    env = dict(os.environ, LD_PRELOAD=rt[-1] + (":" + pre if pre else ""), ABD_LIB=lib,
+    env = dict(os.environ, LD_PRELOAD=(pre + ":" if pre else "") + rt[-1], ABD_LIB=lib,
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
                PYTHONPATH=ROOT)
     r = subprocess.run([sys.executable, "-u", "-c", SCRIPT], env=env, cwd=ROOT,
