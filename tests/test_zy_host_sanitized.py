@@ -6,7 +6,9 @@ launches, the hooks, a batch, the deterministic and mixed modes and the
 allocation-free solve, in a child process with the UBSan runtime
 preloaded.  (The AddressSanitizer runtime of this toolchain intercepts the
 HSA allocator and fails its first device allocation, so the host runtime
-has no ASan run; the oracle has one, tests/test_oracle_sanitized.py.)"""
+has no ASan run; the oracle has one, tests/test_oracle_sanitized.py.)
+It is collected after the other GPU parity tests, since unlike them it
+depends on the process environment (the preloaded runtime)."""
 import glob
 import os
 import subprocess
